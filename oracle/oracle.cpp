@@ -1,0 +1,559 @@
+// ICP oracle: plain, slow, FP64 CPU implementation of the registration loop.
+//
+// TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+// benchmark's CPU-baseline leg may load this library.  It shares no code,
+// header, table or helper with the GPU library; the product path never calls
+// it.
+//
+// What it computes (paper: Open3D, Sec. 3.3 "Registration" and Sec. 4
+// "Optimization"):
+//   * ICP refinement of a source cloud onto a target cloud given an initial
+//     transform and a maximum correspondence distance (Sec. 3.3, the
+//     registration_icp example), point-to-plane or point-to-point [2, 4].
+//   * Each iteration is one Gauss-Newton step of the least-squares objective
+//     L(x) = sum_i r_i(x)^2 (Sec. 4, eq. (1)): x <- x - (J^T J)^{-1} J^T r
+//     (eq. (2)), with J^T J and J^T r formed as a reduction over per-record
+//     contributions (Sec. 4, the OpenMP reduction over a per-record lambda).
+//   * Nearest neighbours come from a k-d tree (the paper delegates NN search to
+//     FLANN, Sec. 2) or brute force on small inputs.
+//
+// Readings where the paper is silent (all shared with the GPU path by
+// definition, not by code):
+//   - selection: PINNED_FP32 mode transforms s in FP64 without FMA
+//     (((R00*sx + R01*sy) + R02*sz) + tx), rounds to FP32, and takes the FP32
+//     squared distance ((dx*dx + dy*dy) + dz*dz) without FMA; FP64 mode uses the
+//     unrounded FP64 distance.  Nearest = lexicographic minimum of
+//     (distance, original target index); inlier iff distance <= r^2, with
+//     r2_32 = (float)(r*r) in PINNED_FP32 mode.
+//   - update: xi = (omega, v) rotation first, left perturbation
+//     T <- Exp(xi) * T, xi solves A xi = -b (no damping, no line search).
+//   - fitness = inliers / N_src, inlier_rmse = sqrt(sum |T s - p|^2 / inliers)
+//     with the FP64 Euclidean distance, both at the returned T.
+//   - convergence: relative change of both the inlier count and the rmse
+//     between consecutive passes <= rel_tol.
+//   - degeneracy: no inliers, or a Cholesky pivot <= 1e-12 * max(diag A).
+//
+// Build: g++ -std=c++17 -O2 -ffp-contract=off -fopenmp -shared -fPIC.
+// Every function here is plain scalar code so it can be checked by eye.
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <vector>
+
+#include <omp.h>
+
+namespace {
+
+constexpr int kSelPinnedF32 = 0;
+constexpr int kSelF64 = 1;
+constexpr int kPointToPoint = 0;
+constexpr int kPointToPlane = 1;
+constexpr int kStatusOk = 0;
+constexpr int kStatusConverged = 1;
+constexpr int kStatusDegenerate = 2;
+constexpr int kLeafSize = 16;
+constexpr int64_t kChunk = 4096;  // fixed summation chunk: order independent of threads
+
+// ---------------------------------------------------------------- transform
+// q64 = R s + t, evaluated term by term in the pinned order, no FMA.
+inline void transform64(const double T[16], const float s[3], double q[3]) {
+  const double sx = s[0], sy = s[1], sz = s[2];
+  for (int a = 0; a < 3; ++a) {
+    double acc = T[4 * a + 0] * sx;
+    acc = acc + T[4 * a + 1] * sy;
+    acc = acc + T[4 * a + 2] * sz;
+    q[a] = acc + T[4 * a + 3];
+  }
+}
+
+// FP32 squared distance in the pinned order, no FMA.
+inline float pinned_d2(const float q[3], const float p[3]) {
+  const float dx = q[0] - p[0];
+  const float dy = q[1] - p[1];
+  const float dz = q[2] - p[2];
+  float d2 = dx * dx + dy * dy;
+  d2 = d2 + dz * dz;
+  return d2;
+}
+
+inline double d2_64(const double q[3], const float p[3]) {
+  const double dx = q[0] - (double)p[0];
+  const double dy = q[1] - (double)p[1];
+  const double dz = q[2] - (double)p[2];
+  return (dx * dx + dy * dy) + dz * dz;
+}
+
+// ---------------------------------------------------------------- k-d tree
+struct KdNode {
+  int64_t lo, hi;      // range in idx[]
+  int dim;             // split dimension (-1 = leaf)
+  double split;
+  int64_t left, right;
+};
+
+struct KdTree {
+  const float* pts = nullptr;  // (n, 3) original target points
+  int64_t n = 0;
+  std::vector<int64_t> idx;
+  std::vector<KdNode> nodes;
+
+  void build(const float* p, int64_t count) {
+    pts = p;
+    n = count;
+    idx.resize(n);
+    for (int64_t i = 0; i < n; ++i) idx[i] = i;
+    nodes.clear();
+    nodes.reserve(2 * (n / kLeafSize + 1) + 1);
+    if (n > 0) make(0, n);
+  }
+
+  int64_t make(int64_t lo, int64_t hi) {
+    const int64_t id = (int64_t)nodes.size();
+    nodes.push_back(KdNode{lo, hi, -1, 0.0, -1, -1});
+    if (hi - lo <= kLeafSize) return id;
+    double mn[3] = {HUGE_VAL, HUGE_VAL, HUGE_VAL};
+    double mx[3] = {-HUGE_VAL, -HUGE_VAL, -HUGE_VAL};
+    for (int64_t k = lo; k < hi; ++k)
+      for (int a = 0; a < 3; ++a) {
+        const double v = pts[3 * idx[k] + a];
+        mn[a] = std::min(mn[a], v);
+        mx[a] = std::max(mx[a], v);
+      }
+    int dim = 0;
+    for (int a = 1; a < 3; ++a)
+      if (mx[a] - mn[a] > mx[dim] - mn[dim]) dim = a;
+    if (mx[dim] - mn[dim] <= 0.0) return id;  // all coincident: keep as a leaf
+    const int64_t mid = lo + (hi - lo) / 2;
+    std::nth_element(idx.begin() + lo, idx.begin() + mid, idx.begin() + hi,
+                     [&](int64_t a, int64_t b) { return pts[3 * a + dim] < pts[3 * b + dim]; });
+    const double split = pts[3 * idx[mid] + dim];
+    const int64_t l = make(lo, mid);
+    const int64_t r = make(mid, hi);
+    nodes[id].dim = dim;
+    nodes[id].split = split;
+    nodes[id].left = l;
+    nodes[id].right = r;
+    return id;
+  }
+
+  // Calls f(j) for every point j with squared distance to c possibly <= R2
+  // (a superset: the caller applies the exact test).  Left subtrees hold
+  // coordinates <= split, right subtrees >= split.
+  template <class F>
+  void range(const double c[3], double R2, F&& f) const {
+    if (n == 0) return;
+    int64_t stack[128];
+    int top = 0;
+    stack[top++] = 0;
+    while (top > 0) {
+      const KdNode& nd = nodes[stack[--top]];
+      if (nd.dim < 0) {
+        for (int64_t k = nd.lo; k < nd.hi; ++k) f(idx[k]);
+        continue;
+      }
+      const double diff = c[nd.dim] - nd.split;
+      const int64_t near_child = diff <= 0.0 ? nd.left : nd.right;
+      const int64_t far_child = diff <= 0.0 ? nd.right : nd.left;
+      if (diff * diff <= R2) stack[top++] = far_child;
+      stack[top++] = near_child;
+    }
+  }
+};
+
+// ---------------------------------------------------------------- selection
+struct Match {
+  int64_t j;      // original target index, -1 if none
+  float d2f;      // pinned FP32 squared distance (PINNED_FP32 mode)
+  double d2d;     // FP64 squared distance |q64 - p|^2
+};
+
+struct Selector {
+  const float* tgt;
+  int64_t n_tgt;
+  double r;
+  int mode;
+  bool use_tree;
+  KdTree tree;
+
+  Selector(const float* t, int64_t nt, double radius, int m, bool tree_search)
+      : tgt(t), n_tgt(nt), r(radius), mode(m), use_tree(tree_search) {
+    if (use_tree) tree.build(tgt, n_tgt);
+  }
+
+  Match select(const double q64[3]) const {
+    Match best{-1, std::numeric_limits<float>::infinity(), std::numeric_limits<double>::infinity()};
+    if (mode == kSelPinnedF32) {
+      const float q32[3] = {(float)q64[0], (float)q64[1], (float)q64[2]};
+      const float r2f = (float)(r * r);
+      auto visit = [&](int64_t j) {
+        const float d = pinned_d2(q32, tgt + 3 * j);
+        if (!(d <= r2f)) return;
+        if (d < best.d2f || (d == best.d2f && j < best.j)) {
+          best.j = j;
+          best.d2f = d;
+        }
+      };
+      if (use_tree) {
+        const double c[3] = {(double)q32[0], (double)q32[1], (double)q32[2]};
+        tree.range(c, r * r * (1.0 + 1e-5), visit);
+      } else {
+        for (int64_t j = 0; j < n_tgt; ++j) visit(j);
+      }
+    } else {
+      const double r2 = r * r;
+      auto visit = [&](int64_t j) {
+        const double d = d2_64(q64, tgt + 3 * j);
+        if (!(d <= r2)) return;
+        if (d < best.d2d || (d == best.d2d && j < best.j)) {
+          best.j = j;
+          best.d2d = d;
+        }
+      };
+      if (use_tree) {
+        tree.range(q64, r2 * (1.0 + 1e-9), visit);
+      } else {
+        for (int64_t j = 0; j < n_tgt; ++j) visit(j);
+      }
+    }
+    if (best.j >= 0) best.d2d = d2_64(q64, tgt + 3 * best.j);
+    return best;
+  }
+};
+
+// ---------------------------------------------------------------- per record
+// Residual(s) and Jacobian rows at q for target point p with normal n.
+// Point-to-plane [4]: r = n . (q - p),  J = [ (q x n)^T , n^T ].
+// Point-to-point [2]: r = q - p,        J = [ -[q]_x , I ].
+// Returns the number of residual rows (1 or 3); J is row-major rows x 6.
+int residual_jacobian(int variant, const double q[3], const double p[3], const double n[3],
+                      double res[3], double J[18]) {
+  const double d[3] = {q[0] - p[0], q[1] - p[1], q[2] - p[2]};
+  if (variant == kPointToPlane) {
+    res[0] = (n[0] * d[0] + n[1] * d[1]) + n[2] * d[2];
+    J[0] = q[1] * n[2] - q[2] * n[1];
+    J[1] = q[2] * n[0] - q[0] * n[2];
+    J[2] = q[0] * n[1] - q[1] * n[0];
+    J[3] = n[0];
+    J[4] = n[1];
+    J[5] = n[2];
+    return 1;
+  }
+  // -[q]_x rows
+  const double mq[3][3] = {{0.0, q[2], -q[1]}, {-q[2], 0.0, q[0]}, {q[1], -q[0], 0.0}};
+  for (int a = 0; a < 3; ++a) {
+    res[a] = d[a];
+    for (int c = 0; c < 3; ++c) {
+      J[6 * a + c] = mq[a][c];
+      J[6 * a + 3 + c] = (a == c) ? 1.0 : 0.0;
+    }
+  }
+  return 3;
+}
+
+// Accumulator of one chunk: upper triangle of A (21), b (6), sum d2, count.
+struct Sums {
+  double A[36];
+  double b[6];
+  double sd2;
+  int64_t n;
+  void clear() {
+    std::memset(A, 0, sizeof A);
+    std::memset(b, 0, sizeof b);
+    sd2 = 0.0;
+    n = 0;
+  }
+  void add(const Sums& o) {
+    for (int k = 0; k < 36; ++k) A[k] += o.A[k];
+    for (int k = 0; k < 6; ++k) b[k] += o.b[k];
+    sd2 += o.sd2;
+    n += o.n;
+  }
+};
+
+struct PassResult {
+  Sums s;
+};
+
+// One correspondence pass at T: fills per-source matches (optional) and the
+// normal-equation sums.  Summation is in fixed chunks of kChunk source points,
+// chunk partials are added in chunk order, so the result does not depend on
+// the number of threads.
+void pass(const Selector& sel, const float* src, int64_t n_src, const float* tgt_n,
+          const double T[16], int variant, Sums* out, int64_t* idx_out, float* d2f_out,
+          double* d2d_out) {
+  const int64_t n_chunks = (n_src + kChunk - 1) / kChunk;
+  std::vector<Sums> part((size_t)n_chunks);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t c = 0; c < n_chunks; ++c) {
+    Sums& S = part[(size_t)c];
+    S.clear();
+    const int64_t i0 = c * kChunk, i1 = std::min(n_src, i0 + kChunk);
+    for (int64_t i = i0; i < i1; ++i) {
+      double q[3];
+      transform64(T, src + 3 * i, q);
+      const Match m = sel.select(q);
+      if (idx_out) idx_out[i] = m.j;
+      if (d2f_out) d2f_out[i] = m.d2f;
+      if (d2d_out) d2d_out[i] = m.d2d;
+      if (m.j < 0) continue;
+      const float* pf = sel.tgt + 3 * m.j;
+      const double p[3] = {pf[0], pf[1], pf[2]};
+      double nrm[3] = {0.0, 0.0, 0.0};
+      if (variant == kPointToPlane) {
+        const float* nf = tgt_n + 3 * m.j;
+        nrm[0] = nf[0]; nrm[1] = nf[1]; nrm[2] = nf[2];
+      }
+      double res[3], J[18];
+      const int rows = residual_jacobian(variant, q, p, nrm, res, J);
+      for (int a = 0; a < rows; ++a) {
+        const double* Ja = J + 6 * a;
+        for (int u = 0; u < 6; ++u) {
+          for (int v = u; v < 6; ++v) S.A[6 * u + v] += Ja[u] * Ja[v];
+          S.b[u] += Ja[u] * res[a];
+        }
+      }
+      S.sd2 += m.d2d;
+      S.n += 1;
+    }
+  }
+  out->clear();
+  for (int64_t c = 0; c < n_chunks; ++c) out->add(part[(size_t)c]);
+}
+
+// ---------------------------------------------------------------- solve
+// Cholesky of the symmetric 6x6 A (upper triangle given), then xi = -A^{-1} b.
+// Returns false if a pivot is <= 1e-12 * max(diag A).
+bool solve6(const double Aup[36], const double b[6], double xi[6]) {
+  double A[6][6];
+  for (int u = 0; u < 6; ++u)
+    for (int v = u; v < 6; ++v) A[u][v] = A[v][u] = Aup[6 * u + v];
+  double dmax = 0.0;
+  for (int u = 0; u < 6; ++u) dmax = std::max(dmax, A[u][u]);
+  const double tol = 1e-12 * dmax;
+  double L[6][6] = {};
+  for (int j = 0; j < 6; ++j) {
+    double piv = A[j][j];
+    for (int k = 0; k < j; ++k) piv -= L[j][k] * L[j][k];
+    if (!(piv > tol)) return false;
+    L[j][j] = std::sqrt(piv);
+    for (int i = j + 1; i < 6; ++i) {
+      double s = A[i][j];
+      for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
+      L[i][j] = s / L[j][j];
+    }
+  }
+  double y[6];
+  for (int i = 0; i < 6; ++i) {
+    double s = -b[i];
+    for (int k = 0; k < i; ++k) s -= L[i][k] * y[k];
+    y[i] = s / L[i][i];
+  }
+  for (int i = 5; i >= 0; --i) {
+    double s = y[i];
+    for (int k = i + 1; k < 6; ++k) s -= L[k][i] * xi[k];
+    xi[i] = s / L[i][i];
+  }
+  return true;
+}
+
+// Exp of the twist xi = (omega, v) as a 4x4 row-major matrix:
+//   R = I + A W + B W^2,  V = I + B W + C W^2,  t = V v,  W = [omega]_x,
+//   A = sin(th)/th, B = (1 - cos th)/th^2 = 2 sin^2(th/2)/th^2 (half-angle form,
+//   free of cancellation), C = (th - sin th)/th^3, with three-term Taylor
+//   series below th = 1e-4.
+void se3_exp(const double xi[6], double E[16]) {
+  const double w[3] = {xi[0], xi[1], xi[2]};
+  const double th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+  const double th = std::sqrt(th2);
+  double A, B, C;
+  if (th < 1e-4) {
+    A = 1.0 - th2 / 6.0 + th2 * th2 / 120.0;
+    B = 0.5 - th2 / 24.0 + th2 * th2 / 720.0;
+    C = 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0;
+  } else {
+    const double s = std::sin(th), sh = std::sin(0.5 * th);
+    A = s / th;
+    B = 2.0 * sh * sh / th2;
+    C = (th - s) / (th2 * th);
+  }
+  const double W[3][3] = {{0.0, -w[2], w[1]}, {w[2], 0.0, -w[0]}, {-w[1], w[0], 0.0}};
+  double W2[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += W[i][k] * W[k][j];
+      W2[i][j] = s;
+    }
+  double R[3][3], V[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      const double I = (i == j) ? 1.0 : 0.0;
+      R[i][j] = I + A * W[i][j] + B * W2[i][j];
+      V[i][j] = I + B * W[i][j] + C * W2[i][j];
+    }
+  std::memset(E, 0, 16 * sizeof(double));
+  for (int i = 0; i < 3; ++i) {
+    for (int j = 0; j < 3; ++j) E[4 * i + j] = R[i][j];
+    E[4 * i + 3] = V[i][0] * xi[3] + V[i][1] * xi[4] + V[i][2] * xi[5];
+  }
+  E[15] = 1.0;
+}
+
+void matmul4(const double X[16], const double Y[16], double Z[16]) {
+  double tmp[16];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 4; ++k) s += X[4 * i + k] * Y[4 * k + j];
+      tmp[4 * i + j] = s;
+    }
+  std::memcpy(Z, tmp, sizeof tmp);
+}
+
+void pack21(const Sums& S, double A21[21], double b6[6]) {
+  int k = 0;
+  for (int u = 0; u < 6; ++u)
+    for (int v = u; v < 6; ++v) A21[k++] = S.A[6 * u + v];
+  for (int u = 0; u < 6; ++u) b6[u] = S.b[u];
+}
+
+bool bad_args(const float* src, int64_t n_src, const float* tgt, int64_t n_tgt, double r) {
+  return !src || !tgt || n_src < 1 || n_tgt < 1 || !(r > 0.0) || !std::isfinite(r);
+}
+
+}  // namespace
+
+extern "C" {
+
+int oracle_num_threads(void) { return omp_get_max_threads(); }
+void oracle_set_num_threads(int n) {
+  if (n > 0) omp_set_num_threads(n);
+}
+
+// Pinned FP32 squared distances of n (s, p) pairs under T (test of the
+// pinned expression itself).
+void oracle_pinned_d2(const double T[16], const float* s, const float* p, int64_t n, float* out) {
+  for (int64_t i = 0; i < n; ++i) {
+    double q[3];
+    transform64(T, s + 3 * i, q);
+    const float q32[3] = {(float)q[0], (float)q[1], (float)q[2]};
+    out[i] = pinned_d2(q32, p + 3 * i);
+  }
+}
+
+void oracle_transform64(const double T[16], const float* s, int64_t n, double* q_out) {
+  for (int64_t i = 0; i < n; ++i) transform64(T, s + 3 * i, q_out + 3 * i);
+}
+
+void oracle_se3_exp(const double xi[6], double E[16]) { se3_exp(xi, E); }
+
+int oracle_residual_jacobian(int variant, const double q[3], const double p[3], const double n[3],
+                             double res[3], double J[18]) {
+  return residual_jacobian(variant, q, p, n, res, J);
+}
+
+int oracle_solve6(const double A21[21], const double b6[6], double xi[6]) {
+  double Aup[36] = {};
+  int k = 0;
+  for (int u = 0; u < 6; ++u)
+    for (int v = u; v < 6; ++v) Aup[6 * u + v] = A21[k++];
+  return solve6(Aup, b6, xi) ? 0 : 1;
+}
+
+// Correspondences at T.  search: 0 = automatic (brute force when
+// n_src * n_tgt <= 2e7), 1 = brute force, 2 = k-d tree.  idx = -1 when no
+// target point lies within r.  d2f = pinned FP32 distance (PINNED_FP32 mode,
+// +inf otherwise or when none), d2d = FP64 distance of the match.
+int oracle_correspondences(const float* src, int64_t n_src, const double T[16], const float* tgt,
+                           int64_t n_tgt, double r, int selection, int search, int64_t* idx_out,
+                           float* d2f_out, double* d2d_out) {
+  if (bad_args(src, n_src, tgt, n_tgt, r)) return -1;
+  const bool tree = search == 2 || (search == 0 && (double)n_src * (double)n_tgt > 2e7);
+  Selector sel(tgt, n_tgt, r, selection, tree);
+  Sums S;
+  pass(sel, src, n_src, nullptr, T, kPointToPoint, &S, idx_out, d2f_out, d2d_out);
+  return 0;
+}
+
+// Normal equations at T: A (upper triangle, 21, row-major), b (6), sum of FP64
+// squared distances and the inlier count.
+int oracle_normal_equations(const float* src, int64_t n_src, const double T[16], const float* tgt,
+                            const float* tgt_n, int64_t n_tgt, double r, int variant, int selection,
+                            int search, double A21[21], double b6[6], double* sum_d2,
+                            int64_t* n_in) {
+  if (bad_args(src, n_src, tgt, n_tgt, r)) return -1;
+  if (variant == kPointToPlane && !tgt_n) return -1;
+  const bool tree = search == 2 || (search == 0 && (double)n_src * (double)n_tgt > 2e7);
+  Selector sel(tgt, n_tgt, r, selection, tree);
+  Sums S;
+  pass(sel, src, n_src, tgt_n, T, variant, &S, nullptr, nullptr, nullptr);
+  pack21(S, A21, b6);
+  *sum_d2 = S.sd2;
+  *n_in = S.n;
+  return 0;
+}
+
+// The ICP loop.  Pass k = 0..max_iter computes correspondences at T_k and the
+// metrics (n_k, fitness_k, rmse_k); it stops at no inliers (DEGENERATE), at
+// k == max_iter (OK), or when both relative changes are <= rel_tol (CONVERGED);
+// otherwise it solves the normal equations (DEGENERATE on a failed pivot) and
+// sets T_{k+1} = Exp(xi) T_k.  Optional trajectory outputs hold T_k, n_k and
+// rmse_k for every executed pass (capacity max_iter + 1).
+int oracle_icp_register(const float* src, int64_t n_src, const float* tgt, const float* tgt_n,
+                        int64_t n_tgt, const double T_init[16], double r, int32_t max_iter,
+                        double rel_tol, int variant, int selection, int search, double T_out[16],
+                        double* fitness, double* rmse, int64_t* n_inliers, int32_t* n_iter,
+                        int32_t* status, double* traj_T, int64_t* traj_n, double* traj_rmse) {
+  if (bad_args(src, n_src, tgt, n_tgt, r) || max_iter < 0 || !(rel_tol >= 0.0)) return -1;
+  if (variant == kPointToPlane && !tgt_n) return -1;
+  const bool tree = search == 2 || (search == 0 && (double)n_src * (double)n_tgt > 2e7);
+  Selector sel(tgt, n_tgt, r, selection, tree);
+  double T[16];
+  std::memcpy(T, T_init, sizeof T);
+  int64_t n_prev = 0;
+  double e_prev = 0.0;
+  for (int32_t k = 0;; ++k) {
+    Sums S;
+    pass(sel, src, n_src, tgt_n, T, variant, &S, nullptr, nullptr, nullptr);
+    const int64_t nk = S.n;
+    const double fk = (double)nk / (double)n_src;
+    const double ek = nk > 0 ? std::sqrt(S.sd2 / (double)nk) : 0.0;
+    if (traj_T) std::memcpy(traj_T + 16 * k, T, 16 * sizeof(double));
+    if (traj_n) traj_n[k] = nk;
+    if (traj_rmse) traj_rmse[k] = ek;
+    int st = -1;
+    if (nk == 0) {
+      st = kStatusDegenerate;
+    } else if (k == max_iter) {
+      st = kStatusOk;
+    } else if (k >= 1 && std::fabs((double)(nk - n_prev)) <= rel_tol * (double)n_prev &&
+               std::fabs(ek - e_prev) <= rel_tol * e_prev) {
+      st = kStatusConverged;
+    } else {
+      double xi[6];
+      if (!solve6(S.A, S.b, xi)) {
+        st = kStatusDegenerate;
+      } else {
+        double E[16];
+        se3_exp(xi, E);
+        matmul4(E, T, T);
+      }
+    }
+    if (st >= 0) {
+      std::memcpy(T_out, T, sizeof T);
+      *fitness = fk;
+      *rmse = ek;
+      *n_inliers = nk;
+      *n_iter = k;
+      *status = st;
+      return 0;
+    }
+    n_prev = nk;
+    e_prev = ek;
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,335 @@
+"""Seeded synthetic scan pairs for ICP (inputs only; no registration arithmetic).
+
+Stand-ins for the fragment pairs of the paper's reconstruction workloads
+(Sec. 3.4: fragments built from RGB-D sequences, then registered pairwise with
+ICP, Sec. 3.3).  Those recordings are not available, so two generators emit
+clouds with the same structure: a smooth heightfield and a furnished room.
+
+Every random draw comes from ``numpy.random.Generator(PCG64(seed))``; sub-seeds
+are derived with ``numpy.random.SeedSequence`` so target and source sampling
+are independent but reproducible.  Arithmetic is float64, outputs are float32
+C-contiguous (N, 3) arrays.  The rigid motion G applied to the source is built
+with ``scipy.spatial.transform.Rotation`` (a library routine), so nothing here
+shares code with either ICP implementation.
+
+Returned dict keys (both generators):
+  src, tgt, tgt_normals, src_normals : float32 (N, 3)
+  G       : float64 (4, 4), the motion applied to the source (moved = G @ orig)
+  T_gt    : float64 (4, 4), inverse of G: maps the moved source back onto the target
+  area    : float, sampled surface area of the target in m^2
+  meta    : dict of the drawn parameters
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy.spatial.transform import Rotation
+
+
+def _rng(seed, *tags) -> np.random.Generator:
+    """Generator for ``seed`` and a tuple of string/int tags (stable across runs)."""
+    words = [int(seed)]
+    for t in tags:
+        if isinstance(t, str):
+            words.append(int.from_bytes(t.encode("utf-8")[:8].ljust(8, b"\0"), "little"))
+        else:
+            words.append(int(t))
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence(words)))
+
+
+def unit_vector(rng: np.random.Generator) -> np.ndarray:
+    v = rng.normal(size=3)
+    while np.linalg.norm(v) < 1e-12:
+        v = rng.normal(size=3)
+    return v / np.linalg.norm(v)
+
+
+def random_motion(rng: np.random.Generator, max_deg: float, max_trans: float,
+                  centre: np.ndarray) -> np.ndarray:
+    """Rigid motion: rotation about ``centre`` by U(0, max_deg) degrees around a
+    uniform axis, then a translation of magnitude U(0, max_trans) in a uniform
+    direction.  Returns the 4x4 float64 matrix G."""
+    axis = unit_vector(rng)
+    ang = math.radians(rng.uniform(0.0, max_deg))
+    R = Rotation.from_rotvec(axis * ang).as_matrix()
+    tdir = unit_vector(rng)
+    tmag = rng.uniform(0.0, max_trans)
+    G = np.eye(4)
+    G[:3, :3] = R
+    G[:3, 3] = centre - R @ centre + tdir * tmag
+    return G
+
+
+def apply(G: np.ndarray, pts: np.ndarray) -> np.ndarray:
+    return pts @ G[:3, :3].T + G[:3, 3]
+
+
+def _f32(a: np.ndarray) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+# --------------------------------------------------------------------------
+# Heightfield pair: z = sum_k a_k exp(-|p - c_k|^2 / (2 s_k^2)) on [0,1]^2
+# --------------------------------------------------------------------------
+
+def heightfield_params(seed: int, n_bumps: int = 8) -> dict:
+    rng = _rng(seed, "hf-surface")
+    return {
+        "a": rng.uniform(0.02, 0.1, n_bumps),
+        "s": rng.uniform(0.05, 0.2, n_bumps),
+        "c": rng.uniform(0.0, 1.0, (n_bumps, 2)),
+    }
+
+
+def heightfield_eval(prm: dict, xy: np.ndarray):
+    """Height and unit normal (from the analytic gradient) at (M, 2) points."""
+    dx = xy[:, None, 0] - prm["c"][None, :, 0]
+    dy = xy[:, None, 1] - prm["c"][None, :, 1]
+    s2 = prm["s"][None, :] ** 2
+    e = prm["a"][None, :] * np.exp(-(dx * dx + dy * dy) / (2.0 * s2))
+    z = e.sum(axis=1)
+    fx = (e * (-dx / s2)).sum(axis=1)
+    fy = (e * (-dy / s2)).sum(axis=1)
+    n = np.stack([-fx, -fy, np.ones_like(fx)], axis=1)
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    return z, n
+
+
+def heightfield_surface(seed: int, n: int, tag: str = "tgt"):
+    """``n`` points drawn uniformly in (x, y) on the seed's heightfield."""
+    prm = heightfield_params(seed)
+    rng = _rng(seed, "hf-" + tag)
+    xy = rng.uniform(0.0, 1.0, (n, 2))
+    z, nrm = heightfield_eval(prm, xy)
+    return np.column_stack([xy, z]), nrm
+
+
+def heightfield_pair(seed: int = 0, n_tgt: int = 5000, n_src: int = 5000,
+                     noise: float = 0.001, max_deg: float = 5.0,
+                     max_trans: float = 0.02) -> dict:
+    """Target: ``n_tgt`` points on the heightfield with analytic normals.
+    Source: an independent ``n_src`` resample plus iid N(0, noise^2) per axis,
+    moved by a rigid motion about its centroid."""
+    tgt, tgt_n = heightfield_surface(seed, n_tgt, "tgt")
+    src0, src_n0 = heightfield_surface(seed, n_src, "src")
+    rng = _rng(seed, "hf-motion")
+    src0 = src0 + rng.normal(0.0, noise, src0.shape)
+    G = random_motion(rng, max_deg, max_trans, src0.mean(axis=0))
+    src = apply(G, src0)
+    src_n = src_n0 @ G[:3, :3].T
+    return {
+        "src": _f32(src), "tgt": _f32(tgt), "tgt_normals": _f32(tgt_n),
+        "src_normals": _f32(src_n), "G": G, "T_gt": np.linalg.inv(G),
+        "area": 1.0, "meta": {"kind": "heightfield", "seed": seed},
+    }
+
+
+# --------------------------------------------------------------------------
+# Room pair: a box room with axis-aligned boxes and spheres, surface-sampled
+# --------------------------------------------------------------------------
+
+def room_scene(seed: int, W: float, D: float, H: float, n_box: int, n_sph: int) -> dict:
+    """Scene geometry: boxes resting on the floor (sides U(0.2, 1.0) m per axis)
+    and spheres (radius U(0.1, 0.4) m) lying fully inside the room."""
+    rng = _rng(seed, "room-scene")
+    boxes = []
+    for _ in range(n_box):
+        size = rng.uniform(0.2, 1.0, 3)
+        lo = np.array([rng.uniform(0.0, W - size[0]), rng.uniform(0.0, D - size[1]), 0.0])
+        boxes.append((lo, lo + size))
+    spheres = []
+    for _ in range(n_sph):
+        r = rng.uniform(0.1, 0.4)
+        c = np.array([rng.uniform(r, W - r), rng.uniform(r, D - r), rng.uniform(r, H - r)])
+        spheres.append((c, r))
+    return {"W": W, "D": D, "H": H, "boxes": boxes, "spheres": spheres}
+
+
+def _lattice_rect(rng, u_len, v_len, h):
+    """Points of a lattice of pitch h on [0,u_len]x[0,v_len] with a random offset."""
+    ou, ov = rng.uniform(0.0, h, 2)
+    u = np.arange(ou, u_len, h)
+    v = np.arange(ov, v_len, h)
+    uu, vv = np.meshgrid(u, v, indexing="ij")
+    return uu.ravel(), vv.ravel()
+
+
+def _face(rng, h, axis, value, lo, hi, normal_sign):
+    """Axis-aligned rectangle {x_axis = value} x [lo, hi] on the other two axes."""
+    a1, a2 = [k for k in range(3) if k != axis]
+    u, v = _lattice_rect(rng, hi[a1] - lo[a1], hi[a2] - lo[a2], h)
+    p = np.empty((u.size, 3))
+    p[:, axis] = value
+    p[:, a1] = lo[a1] + u
+    p[:, a2] = lo[a2] + v
+    n = np.zeros_like(p)
+    n[:, axis] = normal_sign
+    return p, n
+
+
+def _fibonacci_sphere(rng, c, r, h):
+    m = max(4, int(math.ceil(4.0 * math.pi * r * r / (h * h))))
+    i = np.arange(m) + 0.5
+    phi = np.arccos(1.0 - 2.0 * i / m)
+    theta = math.pi * (1.0 + 5.0 ** 0.5) * i
+    d = np.column_stack([np.cos(theta) * np.sin(phi), np.sin(theta) * np.sin(phi), np.cos(phi)])
+    d = d @ Rotation.random(random_state=rng).as_matrix().T
+    return c + r * d, d
+
+
+def _inside_any(p, scene, skip_box=-1, skip_sph=-1):
+    """True where p lies strictly inside a solid other than the skipped one.
+    Boxes count their floor contact as inside, so floor samples hidden under a
+    box are removed."""
+    out = np.zeros(len(p), dtype=bool)
+    for bi, (lo, hi) in enumerate(scene["boxes"]):
+        if bi == skip_box:
+            continue
+        m = ((p[:, 0] > lo[0]) & (p[:, 0] < hi[0]) & (p[:, 1] > lo[1]) & (p[:, 1] < hi[1])
+             & (p[:, 2] >= lo[2] - 1e-9) & (p[:, 2] < hi[2]))
+        out |= m
+    for si, (c, r) in enumerate(scene["spheres"]):
+        if si == skip_sph:
+            continue
+        d2 = ((p - c) ** 2).sum(axis=1)
+        out |= d2 < r * r
+    return out
+
+
+def room_surface(scene: dict, rng: np.random.Generator, h: float = 0.01):
+    """All visible surface samples of the scene at lattice pitch ``h`` (exact
+    normals: inward for the room shell, outward for objects)."""
+    W, D, H = scene["W"], scene["D"], scene["H"]
+    pts, nrm = [], []
+    lo0, hi0 = np.zeros(3), np.array([W, D, H])
+    for axis, (a, b) in enumerate(((0.0, W), (0.0, D), (0.0, H))):
+        for value, sign in ((a, +1.0), (b, -1.0)):
+            p, n = _face(rng, h, axis, value, lo0, hi0, sign)
+            keep = ~_inside_any(p, scene)
+            pts.append(p[keep]); nrm.append(n[keep])
+    for bi, (lo, hi) in enumerate(scene["boxes"]):
+        for axis in range(3):
+            for value, sign in ((lo[axis], -1.0), (hi[axis], +1.0)):
+                if axis == 2 and sign < 0:
+                    continue  # bottom face rests on the floor
+                p, n = _face(rng, h, axis, value, lo, hi, sign)
+                keep = ~_inside_any(p, scene, skip_box=bi)
+                pts.append(p[keep]); nrm.append(n[keep])
+    for si, (c, r) in enumerate(scene["spheres"]):
+        p, n = _fibonacci_sphere(rng, c, r, h)
+        keep = ~_inside_any(p, scene, skip_sph=si)
+        pts.append(p[keep]); nrm.append(n[keep])
+    return np.concatenate(pts), np.concatenate(nrm)
+
+
+def room_pair(seed: int = 0, n_tgt: int = 300_000, n_src: int = 300_000,
+              W: float = 6.0, D: float = 4.0, H: float = 3.0, n_box: int = 20,
+              n_sph: int = 10, overlap: float = 0.7, noise: float = 0.002,
+              max_deg: float = 10.0, max_trans: float = 0.10, h: float = 0.01) -> dict:
+    """Target: the whole room sampled at pitch ``h`` plus N(0, noise^2) position
+    noise, subsampled to ``n_tgt``.  Source: an independent sampling cropped to an
+    x-slab that starts at a random end wall and holds a fraction ``overlap`` of
+    the target's samples, subsampled to ``n_src``, then moved by a rigid motion
+    about its centroid.  Normals are exact (never perturbed)."""
+    scene = room_scene(seed, W, D, H, n_box, n_sph)
+    rt, rs, rm = _rng(seed, "tgt"), _rng(seed, "src"), _rng(seed, "motion")
+
+    tp, tn = room_surface(scene, rt, h)
+    area = tp.shape[0] * h * h
+    tp = tp + rt.normal(0.0, noise, tp.shape)
+    sp, sn = room_surface(scene, rs, h)
+    sp = sp + rs.normal(0.0, noise, sp.shape)
+
+    # x-slab holding a fraction `overlap` of the target's samples
+    from_low = bool(rm.integers(0, 2))
+    xs = np.sort(tp[:, 0])
+    k = min(len(xs) - 1, max(0, int(round(overlap * len(xs))) - 1))
+    if from_low:
+        cut = xs[k]
+        keep = sp[:, 0] <= cut
+    else:
+        cut = xs[len(xs) - 1 - k]
+        keep = sp[:, 0] >= cut
+    sp, sn = sp[keep], sn[keep]
+
+    ti = rt.choice(len(tp), size=min(n_tgt, len(tp)), replace=False)
+    si = rs.choice(len(sp), size=min(n_src, len(sp)), replace=False)
+    tp, tn = tp[np.sort(ti)], tn[np.sort(ti)]
+    sp, sn = sp[np.sort(si)], sn[np.sort(si)]
+    # shuffle so that storage order carries no spatial structure
+    tperm, sperm = rt.permutation(len(tp)), rs.permutation(len(sp))
+    tp, tn, sp, sn = tp[tperm], tn[tperm], sp[sperm], sn[sperm]
+
+    G = random_motion(rm, max_deg, max_trans, sp.mean(axis=0))
+    src = apply(G, sp)
+    src_n = sn @ G[:3, :3].T
+    return {
+        "src": _f32(src), "tgt": _f32(tp), "tgt_normals": _f32(tn),
+        "src_normals": _f32(src_n), "G": G, "T_gt": np.linalg.inv(G),
+        "area": float(area),
+        "meta": {"kind": "room", "seed": seed, "W": W, "D": D, "H": H,
+                 "n_box": n_box, "n_sph": n_sph, "overlap": overlap,
+                 "from_low": from_low, "cut": float(cut)},
+    }
+
+
+# --------------------------------------------------------------------------
+# Workload recipes (sizes and parameters of the five benchmark configurations)
+# --------------------------------------------------------------------------
+
+def c1_heightfield(seed: int = 0) -> dict:
+    """5k/5k heightfield pair, point-to-plane, r = 5 cm, 30 iterations."""
+    d = heightfield_pair(seed, 5000, 5000)
+    d.update(max_corr_dist=0.05, max_iter=30, variant="point_to_plane")
+    return d
+
+
+def c2_room(seed: int = 0) -> dict:
+    """300k/300k room pair (6x4x3 m, 20 boxes, 10 spheres), r = 3 cm, 50 iterations."""
+    d = room_pair(seed, 300_000, 300_000, 6.0, 4.0, 3.0, 20, 10, overlap=0.7)
+    d.update(max_corr_dist=0.03, max_iter=50, variant="point_to_plane")
+    return d
+
+
+def c3_room(seed: int = 0) -> dict:
+    """2M/2M room pair (12x8x3 m, 80 boxes, 40 spheres), r = 2 cm, 50 iterations."""
+    d = room_pair(seed, 2_000_000, 2_000_000, 12.0, 8.0, 3.0, 80, 40, overlap=0.7)
+    d.update(max_corr_dist=0.02, max_iter=50, variant="point_to_plane")
+    return d
+
+
+def loguniform_size(rng: np.random.Generator, lo: float, hi: float) -> int:
+    return int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+
+
+def c4_pair(p: int, lo: float = 2e3, hi: float = 2e5) -> dict:
+    """Pair ``p`` of the batched workload: seed 1000+p, size log-uniform in
+    [2k, 200k], overlap U(0.5, 0.9), r = max(3 cm, 2 sqrt(A/N))."""
+    seed = 1000 + p
+    rng = _rng(seed, "c4-size")
+    n = loguniform_size(rng, lo, hi)
+    o = rng.uniform(0.5, 0.9)
+    d = room_pair(seed, n, n, 6.0, 4.0, 3.0, 20, 10, overlap=o)
+    d.update(max_corr_dist=max(0.03, 2.0 * math.sqrt(d["area"] / len(d["tgt"]))),
+             max_iter=30, rel_tol=1e-6, variant="point_to_plane")
+    return d
+
+
+def c5_request_size(q: int, lo: float = 5e3, hi: float = 5e5):
+    """Size and overlap of served request ``q`` (seed 10000+q)."""
+    rng = _rng(10_000 + q, "c5-size")
+    return loguniform_size(rng, lo, hi), rng.uniform(0.5, 0.9)
+
+
+def c5_request(q: int, lo: float = 5e3, hi: float = 5e5) -> dict:
+    n, o = c5_request_size(q, lo, hi)
+    d = room_pair(10_000 + q, n, n, 6.0, 4.0, 3.0, 20, 10, overlap=o)
+    d.update(rel_tol=1e-6, variant="point_to_plane")
+    return d
+
+
+def poisson_arrivals(n: int, rate: float, seed: int = 0) -> np.ndarray:
+    """Arrival times (s) of a Poisson process of ``rate`` requests/s."""
+    rng = _rng(seed, "arrivals")
+    return np.cumsum(rng.exponential(1.0 / rate, n))

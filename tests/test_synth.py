@@ -1,0 +1,45 @@
+"""Generator determinism and shape checks (inputs shared by oracle and GPU tests)."""
+import numpy as np
+
+from paper_1801_09847_amd import synth
+
+
+def test_heightfield_deterministic_and_shaped():
+    a, b = synth.c1_heightfield(0), synth.c1_heightfield(0)
+    for k in ("src", "tgt", "tgt_normals"):
+        assert a[k].dtype == np.float32 and a[k].shape == (5000, 3) and a[k].flags.c_contiguous
+        np.testing.assert_array_equal(a[k], b[k])
+    assert np.abs(np.linalg.norm(a["tgt_normals"], axis=1) - 1).max() < 1e-6
+    c = synth.c1_heightfield(1)
+    assert not np.array_equal(a["src"], c["src"])
+    # the applied motion is a rigid motion within the configured bounds
+    R = a["G"][:3, :3]
+    assert np.abs(R.T @ R - np.eye(3)).max() < 1e-12
+    ang = np.degrees(np.arccos(np.clip((np.trace(R) - 1) / 2, -1, 1)))
+    assert ang <= 5.0
+    np.testing.assert_allclose(a["T_gt"] @ a["G"], np.eye(4), atol=1e-12)
+
+
+def test_room_pair_small():
+    d = synth.room_pair(3, 20000, 15000, 3.0, 2.0, 2.0, 4, 2, overlap=0.6)
+    e = synth.room_pair(3, 20000, 15000, 3.0, 2.0, 2.0, 4, 2, overlap=0.6)
+    np.testing.assert_array_equal(d["src"], e["src"])
+    np.testing.assert_array_equal(d["tgt"], e["tgt"])
+    assert d["tgt"].shape == (20000, 3) and d["src"].shape == (15000, 3)
+    n = np.linalg.norm(d["tgt_normals"], axis=1)
+    assert np.abs(n - 1).max() < 1e-6
+    # target within the room (plus noise), source a slab of it before the motion
+    assert d["tgt"].min() > -0.02 and d["tgt"][:, 0].max() < 3.02
+    back = synth.apply(d["T_gt"], d["src"].astype(np.float64))
+    if d["meta"]["from_low"]:
+        assert back[:, 0].max() <= d["meta"]["cut"] + 1e-5
+    else:
+        assert back[:, 0].min() >= d["meta"]["cut"] - 1e-5
+    assert d["area"] > 0
+
+
+def test_c4_c5_sizes_in_range():
+    rng_sizes = [synth.c5_request_size(q)[0] for q in range(200)]
+    assert min(rng_sizes) >= 5000 and max(rng_sizes) <= 500000
+    t = synth.poisson_arrivals(100, 10.0)
+    assert np.all(np.diff(t) > 0)

@@ -1,0 +1,807 @@
+// HIP kernels of the ICP registration loop for CDNA4 (gfx950, wave64).
+//
+// Method: Open3D paper Sec. 3.3 (ICP refinement with a maximum
+// correspondence distance, point-to-plane / point-to-point) and Sec. 4
+// (Gauss-Newton step of eq. (2) with J^T J and J^T r built by a parallel
+// reduction over per-correspondence terms).  The paper's nearest-neighbour
+// search is a CPU k-d tree; here it is a dense uniform grid over the target
+// (cell edge >= max_corr_dist, 27-cell neighbourhood) built by a counting
+// sort of cell keys, and the source is ordered along a Morton curve so that a
+// wavefront's queries touch the same cells.
+//
+// Every kernel is compiled with floating-point contraction disabled: the
+// correspondence distance must be the exact float32 expression the interface
+// specifies, and the transform the exact float64 one.
+
+#include <float.h>
+#include <math.h>
+
+#include <algorithm>
+#include <utility>
+
+#include "icp_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace icp {
+
+namespace {
+
+constexpr int kWave = 64;
+
+__device__ inline int lane_id() { return __lane_id(); }
+
+// ------------------------------------------------------------------ small helpers
+template <class T>
+__device__ inline T wave_sum_xor(T v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v = v + __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Exact error-free sum: s + e == a + b exactly (Knuth TwoSum).
+__device__ inline void two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  const float bb = s - a;
+  const float aa = s - bb;
+  e = (a - aa) + (b - bb);
+}
+
+struct Mat16 {
+  double v[16];
+};
+
+// ------------------------------------------------------------------ bbox + finiteness
+__global__ __launch_bounds__(256) void bbox_kernel(const float* __restrict__ pts,
+                                                   const float* __restrict__ nrm, int64_t n,
+                                                   float* __restrict__ block_out) {
+  float mn[3] = {INFINITY, INFINITY, INFINITY};
+  float mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+  float bad = 0.0f;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const float x = pts[3 * i + 0], y = pts[3 * i + 1], z = pts[3 * i + 2];
+    if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
+      bad = 1.0f;
+    } else {
+      mn[0] = fminf(mn[0], x); mn[1] = fminf(mn[1], y); mn[2] = fminf(mn[2], z);
+      mx[0] = fmaxf(mx[0], x); mx[1] = fmaxf(mx[1], y); mx[2] = fmaxf(mx[2], z);
+    }
+    if (nrm) {
+      const float a = nrm[3 * i + 0], b = nrm[3 * i + 1], c = nrm[3 * i + 2];
+      if (!(isfinite(a) && isfinite(b) && isfinite(c))) bad = 1.0f;
+    }
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    for (int a = 0; a < 3; ++a) {
+      mn[a] = fminf(mn[a], __shfl_xor(mn[a], off, kWave));
+      mx[a] = fmaxf(mx[a], __shfl_xor(mx[a], off, kWave));
+    }
+    bad = fmaxf(bad, __shfl_xor(bad, off, kWave));
+  }
+  __shared__ float red[4][8];
+  const int w = threadIdx.x / kWave;
+  if (lane_id() == 0) {
+    for (int a = 0; a < 3; ++a) { red[w][a] = mn[a]; red[w][3 + a] = mx[a]; }
+    red[w][6] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x < 7) {
+    const int a = threadIdx.x;
+    float v = red[0][a];
+    for (int k = 1; k < 4; ++k) v = (a < 3) ? fminf(v, red[k][a]) : fmaxf(v, red[k][a]);
+    block_out[blockIdx.x * 8 + a] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void bbox_final_kernel(const float* __restrict__ block_out, int nblk,
+                                                         float* __restrict__ out) {
+  __shared__ float red[7][256];
+  for (int a = 0; a < 7; ++a) {
+    float v = (a < 3) ? INFINITY : -INFINITY;
+    if (a == 6) v = 0.0f;
+    for (int b = threadIdx.x; b < nblk; b += 256) {
+      const float x = block_out[b * 8 + a];
+      v = (a < 3) ? fminf(v, x) : fmaxf(v, x);
+    }
+    red[a][threadIdx.x] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 7) {
+    const int a = threadIdx.x;
+    float v = red[a][0];
+    for (int t = 1; t < 256; ++t) v = (a < 3) ? fminf(v, red[a][t]) : fmaxf(v, red[a][t]);
+    out[a] = v;
+  }
+}
+
+// ------------------------------------------------------------------ exclusive scan (uint32)
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* total) {
+  __shared__ uint32_t wsum[kScanThreads / kWave];
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  uint32_t x = v;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off, kWave);
+    if (lane >= off) x += y;
+  }
+  if (lane == kWave - 1) wsum[w] = x;
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+  for (int k = 0; k < kScanThreads / kWave; ++k) {
+    if (k < w) before += wsum[k];
+    all += wsum[k];
+  }
+  __syncthreads();
+  *total = all;
+  return before + x - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_tile_sums_kernel(const uint32_t* __restrict__ d,
+                                                                      int64_t n,
+                                                                      uint32_t* __restrict__ sums) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k)
+    if (base + k < n) s += d[base + k];
+  uint32_t total;
+  block_exclusive_scan(s, &total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// Single block: exclusive scan of nb tile sums in place.
+__global__ __launch_bounds__(1024) void scan_top_kernel(uint32_t* __restrict__ sums, int64_t nb) {
+  __shared__ uint32_t tsum[1024];
+  const int64_t per = (nb + 1023) / 1024;
+  const int64_t b0 = (int64_t)threadIdx.x * per;
+  uint32_t s = 0;
+  for (int64_t k = 0; k < per; ++k)
+    if (b0 + k < nb) s += sums[b0 + k];
+  tsum[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int t = 0; t < 1024; ++t) {
+      const uint32_t v = tsum[t];
+      tsum[t] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  uint32_t run = tsum[threadIdx.x];
+  for (int64_t k = 0; k < per; ++k)
+    if (b0 + k < nb) {
+      const uint32_t v = sums[b0 + k];
+      sums[b0 + k] = run;
+      run += v;
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(uint32_t* __restrict__ d, int64_t n,
+                                                                  const uint32_t* __restrict__ sums) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = (base + k < n) ? d[base + k] : 0u;
+    s += v[k];
+  }
+  uint32_t total;
+  uint32_t run = block_exclusive_scan(s, &total) + sums[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) d[base + k] = run;
+    run += v[k];
+  }
+}
+
+// ------------------------------------------------------------------ target grid
+__device__ inline int cell_of(float p, double o, double inv_h, int dim) {
+  double u = ((double)p - o) * inv_h;
+  u = fmin(fmax(u, -2.0), (double)dim + 1.0);
+  return (int)floor(u);
+}
+
+__global__ __launch_bounds__(256) void target_key_kernel(const float* __restrict__ tgt, int64_t n,
+                                                         GridDesc g, uint32_t* __restrict__ counts,
+                                                         uint32_t* __restrict__ key,
+                                                         uint32_t* __restrict__ rank) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int cx = min(max(cell_of(tgt[3 * i + 0], g.ox, g.inv_h, g.dx), 0), g.dx - 1);
+  const int cy = min(max(cell_of(tgt[3 * i + 1], g.oy, g.inv_h, g.dy), 0), g.dy - 1);
+  const int cz = min(max(cell_of(tgt[3 * i + 2], g.oz, g.inv_h, g.dz), 0), g.dz - 1);
+  const uint32_t k = ((uint32_t)cz * (uint32_t)g.dy + (uint32_t)cy) * (uint32_t)g.dx + (uint32_t)cx;
+  key[i] = k;
+  rank[i] = atomicAdd(&counts[k], 1u);
+}
+
+__global__ __launch_bounds__(256) void target_scatter_kernel(
+    const float* __restrict__ tgt, const float* __restrict__ tgt_n, int64_t n,
+    const uint32_t* __restrict__ key, const uint32_t* __restrict__ rank,
+    const uint32_t* __restrict__ cs, float4* __restrict__ tp, float4* __restrict__ tn) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t pos = cs[key[i]] + rank[i];
+  tp[pos] = make_float4(tgt[3 * i + 0], tgt[3 * i + 1], tgt[3 * i + 2], __uint_as_float((uint32_t)i));
+  if (tgt_n) tn[pos] = make_float4(tgt_n[3 * i + 0], tgt_n[3 * i + 1], tgt_n[3 * i + 2], 0.0f);
+}
+
+// ------------------------------------------------------------------ LSD radix sort (stable)
+constexpr int kSortThreads = 256;
+constexpr int kSortRounds = 8;
+constexpr int kSortTile = kSortThreads * kSortRounds;
+
+__global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const uint32_t* __restrict__ keys,
+                                                                  int64_t n, int shift,
+                                                                  uint32_t* __restrict__ hist,
+                                                                  int nblk) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t tile = (int64_t)blockIdx.x * kSortTile;
+  for (int k = 0; k < kSortRounds; ++k) {
+    const int64_t i = tile + k * kSortThreads + threadIdx.x;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
+    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals, int64_t n, int shift,
+    const uint32_t* __restrict__ offs, int nblk, uint32_t* __restrict__ keys_out,
+    uint32_t* __restrict__ vals_out) {
+  __shared__ uint32_t base[256];
+  __shared__ uint32_t wcnt[kSortThreads / kWave][256];
+  const int t = threadIdx.x, w = t / kWave, lane = lane_id();
+  base[t] = offs[(int64_t)t * nblk + blockIdx.x];
+  for (int k = 0; k < kSortThreads / kWave; ++k) wcnt[k][t] = 0;
+  __syncthreads();
+  const int64_t tile = (int64_t)blockIdx.x * kSortTile;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int r = 0; r < kSortRounds; ++r) {
+    const int64_t i = tile + r * kSortThreads + t;
+    const bool valid = i < n;
+    const uint32_t key = valid ? keys[i] : 0u;
+    const uint32_t val = valid ? vals[i] : 0u;
+    const uint32_t d = (key >> shift) & 255u;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bb = __ballot(bit);
+      peers &= bit ? bb : ~bb;
+    }
+    const uint32_t rank_w = __popcll(peers & lt_mask);
+    if (valid && rank_w == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t dst = base[d] + rank_w;
+      for (int k = 0; k < w; ++k) dst += wcnt[k][d];
+      keys_out[dst] = key;
+      vals_out[dst] = val;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+    for (int k = 0; k < kSortThreads / kWave; ++k) {
+      add += wcnt[k][t];
+      wcnt[k][t] = 0;
+    }
+    base[t] += add;
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ source ordering
+__device__ inline uint32_t spread10(uint32_t v) {
+  v &= 0x3ffu;
+  v = (v | (v << 16)) & 0x030000ffu;
+  v = (v | (v << 8)) & 0x0300f00fu;
+  v = (v | (v << 4)) & 0x030c30c3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+__global__ __launch_bounds__(256) void source_key_kernel(const float* __restrict__ src, int64_t n,
+                                                         double ox, double oy, double oz,
+                                                         double inv_h, uint32_t* __restrict__ keys,
+                                                         uint32_t* __restrict__ vals) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int cx = min(max(cell_of(src[3 * i + 0], ox, inv_h, 1024), 0), 1023);
+  const int cy = min(max(cell_of(src[3 * i + 1], oy, inv_h, 1024), 0), 1023);
+  const int cz = min(max(cell_of(src[3 * i + 2], oz, inv_h, 1024), 0), 1023);
+  keys[i] = spread10(cx) | (spread10(cy) << 1) | (spread10(cz) << 2);
+  vals[i] = (uint32_t)i;
+}
+
+__global__ __launch_bounds__(256) void source_gather_kernel(const float* __restrict__ src, int64_t n,
+                                                            const uint32_t* __restrict__ perm,
+                                                            float* __restrict__ sx,
+                                                            float* __restrict__ sy,
+                                                            float* __restrict__ sz) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t o = perm[i];
+  sx[i] = src[3 * o + 0];
+  sy[i] = src[3 * o + 1];
+  sz[i] = src[3 * o + 2];
+}
+
+// ------------------------------------------------------------------ loop state
+__global__ void state_init_kernel(IterState* st, Mat16 T) {
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 16; ++k) st->T[k] = T.v[k];
+    st->fitness = 0.0;
+    st->rmse = 0.0;
+    st->e_prev = 0.0;
+    st->n_in = 0;
+    st->n_prev = 0;
+    st->k = 0;
+    st->done = 0;
+    st->status = 0;
+    st->pad = 0;
+  }
+}
+
+// ------------------------------------------------------------------ correspondence + normal equations
+// Per-correspondence terms: 21 entries of J^T J (upper, row-major), 6 of J^T r,
+// the squared distance.  Point-to-plane: one row J = [q x n, n], r = n . d.
+// Point-to-point: three rows J_a = [-[q]_x row a, e_a], r = d, summed in
+// closed form: J^T J = [[|q|^2 I - q q^T, [q]_x], [[q]_x^T, I]],
+// J^T r = [q x d, d].
+template <int VAR, class F>
+__device__ inline void record_terms(F qx, F qy, F qz, F rx, F ry, F rz, F nx, F ny, F nz, F* v) {
+  if (VAR == 1) {
+    const F res = (nx * rx + ny * ry) + nz * rz;
+    const F J[6] = {qy * nz - qz * ny, qz * nx - qx * nz, qx * ny - qy * nx, nx, ny, nz};
+    int k = 0;
+#pragma unroll
+    for (int u = 0; u < 6; ++u)
+#pragma unroll
+      for (int w = u; w < 6; ++w) v[k++] = J[u] * J[w];
+#pragma unroll
+    for (int u = 0; u < 6; ++u) v[21 + u] = J[u] * res;
+  } else {
+    const F xx = qx * qx, yy = qy * qy, zz = qz * qz;
+    const F one = F(1), zero = F(0);
+    // row 0: (yy+zz, -xy, -xz, 0, -z, y)
+    v[0] = yy + zz; v[1] = -(qx * qy); v[2] = -(qx * qz); v[3] = zero; v[4] = -qz; v[5] = qy;
+    // row 1: (xx+zz, -yz, z, 0, -x)
+    v[6] = xx + zz; v[7] = -(qy * qz); v[8] = qz; v[9] = zero; v[10] = -qx;
+    // row 2: (xx+yy, -y, x, 0)
+    v[11] = xx + yy; v[12] = -qy; v[13] = qx; v[14] = zero;
+    // rows 3..5: identity
+    v[15] = one; v[16] = zero; v[17] = zero; v[18] = one; v[19] = zero; v[20] = one;
+    v[21] = qy * rz - qz * ry;
+    v[22] = qz * rx - qx * rz;
+    v[23] = qx * ry - qy * rx;
+    v[24] = rx; v[25] = ry; v[26] = rz;
+  }
+}
+
+template <int VAR, int PREC, bool WRITE>
+__global__ __launch_bounds__(kBlock) void pass_kernel(PassArgs a) {
+  if (a.st->done) return;
+  double T[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) T[k] = a.st->T[k];
+
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  bool inl = false;
+  float bd = INFINITY;
+  uint32_t bo = 0xffffffffu;
+  float4 bp = make_float4(0.f, 0.f, 0.f, 0.f);
+  uint32_t bj = 0;
+  double q64x = 0.0, q64y = 0.0, q64z = 0.0;
+  float q32x = 0.f, q32y = 0.f, q32z = 0.f;
+  if (i < a.n_src) {
+    const double sx = a.sx[i], sy = a.sy[i], sz = a.sz[i];
+    double t;
+    t = T[0] * sx; t = t + T[1] * sy; t = t + T[2] * sz; q64x = t + T[3];
+    t = T[4] * sx; t = t + T[5] * sy; t = t + T[6] * sz; q64y = t + T[7];
+    t = T[8] * sx; t = t + T[9] * sy; t = t + T[10] * sz; q64z = t + T[11];
+    q32x = (float)q64x; q32y = (float)q64y; q32z = (float)q64z;
+    const GridDesc g = a.g;
+    const int cx = cell_of(q32x, g.ox, g.inv_h, g.dx);
+    const int cy = cell_of(q32y, g.oy, g.inv_h, g.dy);
+    const int cz = cell_of(q32z, g.oz, g.inv_h, g.dz);
+    const int x0 = max(cx - 1, 0), x1 = min(cx + 1, g.dx - 1);
+    if (x0 <= x1) {
+      for (int ddz = -1; ddz <= 1; ++ddz) {
+        const int z = cz + ddz;
+        if ((unsigned)z >= (unsigned)g.dz) continue;
+        for (int ddy = -1; ddy <= 1; ++ddy) {
+          const int y = cy + ddy;
+          if ((unsigned)y >= (unsigned)g.dy) continue;
+          const uint32_t row = ((uint32_t)z * (uint32_t)g.dy + (uint32_t)y) * (uint32_t)g.dx;
+          const uint32_t beg = a.cs[row + x0], end = a.cs[row + x1 + 1];
+          for (uint32_t j = beg; j < end; ++j) {
+            const float4 p = a.tp[j];
+            const float dx = q32x - p.x, dy = q32y - p.y, dz = q32z - p.z;
+            float d2 = dx * dx + dy * dy;
+            d2 = d2 + dz * dz;
+            const uint32_t o = __float_as_uint(p.w);
+            if (d2 < bd || (d2 == bd && o < bo)) {
+              bd = d2;
+              bo = o;
+              bp = p;
+              bj = j;
+            }
+          }
+        }
+      }
+    }
+    inl = bd <= a.r2f;
+    if (WRITE) {
+      const uint32_t oi = a.sperm[i];
+      a.idx_out[oi] = inl ? (int32_t)bo : -1;
+      a.d2_out[oi] = inl ? bd : INFINITY;
+    }
+  }
+
+  __shared__ float red_s[kBlock / kWave][kNumSums];
+  __shared__ float red_c[kBlock / kWave][kNumSums];
+  __shared__ double red_d[kBlock / kWave][kNumSums];
+  __shared__ int red_n[kBlock / kWave];
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  int cnt = inl ? 1 : 0;
+  cnt = wave_sum_xor(cnt);
+
+  if (PREC == 0) {
+    float v[28];
+    if (inl) {
+      const double rx = q64x - (double)bp.x, ry = q64y - (double)bp.y, rz = q64z - (double)bp.z;
+      const float fx = (float)rx, fy = (float)ry, fz = (float)rz;
+      float4 n = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (VAR == 1) n = a.tn[bj];
+      record_terms<VAR, float>(q32x, q32y, q32z, fx, fy, fz, n.x, n.y, n.z, v);
+      float d2 = fx * fx + fy * fy;
+      v[27] = d2 + fz * fz;
+    } else {
+#pragma unroll
+      for (int k = 0; k < 28; ++k) v[k] = 0.0f;
+    }
+    float c[28];
+#pragma unroll
+    for (int k = 0; k < 28; ++k) c[k] = 0.0f;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+#pragma unroll
+      for (int k = 0; k < 28; ++k) {
+        const float so = __shfl_xor(v[k], off, kWave);
+        const float co = __shfl_xor(c[k], off, kWave);
+        float s, e;
+        two_sum(v[k], so, s, e);
+        v[k] = s;
+        c[k] = (c[k] + co) + e;
+      }
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < 28; ++k) {
+        red_s[w][k] = v[k];
+        red_c[w][k] = c[k];
+      }
+      red_n[w] = cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x < 28) {
+      const int k = threadIdx.x;
+      float s = red_s[0][k], cc = red_c[0][k];
+      for (int ww = 1; ww < kBlock / kWave; ++ww) {
+        float t2, e;
+        two_sum(s, red_s[ww][k], t2, e);
+        s = t2;
+        cc = (cc + red_c[ww][k]) + e;
+      }
+      a.part[(int64_t)k * a.n_blocks + blockIdx.x] = (double)s + (double)cc;
+    } else if (threadIdx.x == 28) {
+      int nn = 0;
+      for (int ww = 0; ww < kBlock / kWave; ++ww) nn += red_n[ww];
+      a.part[(int64_t)28 * a.n_blocks + blockIdx.x] = (double)nn;
+    }
+  } else {
+    double v[28];
+    if (inl) {
+      const double px = bp.x, py = bp.y, pz = bp.z;
+      const double rx = q64x - px, ry = q64y - py, rz = q64z - pz;
+      double nx = 0.0, ny = 0.0, nz = 0.0;
+      if (VAR == 1) {
+        const float4 n = a.tn[bj];
+        nx = n.x; ny = n.y; nz = n.z;
+      }
+      record_terms<VAR, double>(q64x, q64y, q64z, rx, ry, rz, nx, ny, nz, v);
+      v[27] = (rx * rx + ry * ry) + rz * rz;
+    } else {
+#pragma unroll
+      for (int k = 0; k < 28; ++k) v[k] = 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 28; ++k) v[k] = wave_sum_xor(v[k]);
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < 28; ++k) red_d[w][k] = v[k];
+      red_n[w] = cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x < 28) {
+      const int k = threadIdx.x;
+      double s = red_d[0][k];
+      for (int ww = 1; ww < kBlock / kWave; ++ww) s = s + red_d[ww][k];
+      a.part[(int64_t)k * a.n_blocks + blockIdx.x] = s;
+    } else if (threadIdx.x == 28) {
+      int nn = 0;
+      for (int ww = 0; ww < kBlock / kWave; ++ww) nn += red_n[ww];
+      a.part[(int64_t)28 * a.n_blocks + blockIdx.x] = (double)nn;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ solve + pose update
+// 6x6 Cholesky of A (given by its upper triangle), x = -A^{-1} b.  Fails when
+// a pivot is <= 1e-12 * max(diag A).
+__device__ bool cholesky_solve6(const double* up21, const double* b, double* x) {
+  double A[6][6];
+  int k = 0;
+  for (int r = 0; r < 6; ++r)
+    for (int c = r; c < 6; ++c) {
+      A[r][c] = up21[k];
+      A[c][r] = up21[k];
+      ++k;
+    }
+  double dmax = A[0][0];
+  for (int r = 1; r < 6; ++r) dmax = fmax(dmax, A[r][r]);
+  const double tol = 1e-12 * dmax;
+  double L[6][6];
+  for (int r = 0; r < 6; ++r)
+    for (int c = 0; c < 6; ++c) L[r][c] = 0.0;
+  for (int c = 0; c < 6; ++c) {
+    double d = A[c][c];
+    for (int m = 0; m < c; ++m) d -= L[c][m] * L[c][m];
+    if (!(d > tol)) return false;
+    L[c][c] = sqrt(d);
+    for (int r = c + 1; r < 6; ++r) {
+      double s = A[r][c];
+      for (int m = 0; m < c; ++m) s -= L[r][m] * L[c][m];
+      L[r][c] = s / L[c][c];
+    }
+  }
+  double y[6];
+  for (int r = 0; r < 6; ++r) {
+    double s = -b[r];
+    for (int m = 0; m < r; ++m) s -= L[r][m] * y[m];
+    y[r] = s / L[r][r];
+  }
+  for (int r = 5; r >= 0; --r) {
+    double s = y[r];
+    for (int m = r + 1; m < 6; ++m) s -= L[m][r] * x[m];
+    x[r] = s / L[r][r];
+  }
+  return true;
+}
+
+// T <- Exp(xi) T with xi = (omega, v): R = I + A W + B W^2, V = I + B W + C W^2.
+__device__ void apply_exp(const double* xi, double* T) {
+  const double wx = xi[0], wy = xi[1], wz = xi[2];
+  const double th2 = (wx * wx + wy * wy) + wz * wz;
+  const double th = sqrt(th2);
+  double A, B, C;
+  if (th < 1e-4) {
+    A = 1.0 - th2 / 6.0 + th2 * th2 / 120.0;
+    B = 0.5 - th2 / 24.0 + th2 * th2 / 720.0;
+    C = 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0;
+  } else {
+    const double s = sin(th), sh = sin(0.5 * th);
+    A = s / th;
+    B = 2.0 * sh * sh / th2;
+    C = (th - s) / (th2 * th);
+  }
+  const double W[3][3] = {{0.0, -wz, wy}, {wz, 0.0, -wx}, {-wy, wx, 0.0}};
+  double W2[3][3];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      double s = 0.0;
+      for (int m = 0; m < 3; ++m) s += W[r][m] * W[m][c];
+      W2[r][c] = s;
+    }
+  double E[3][4];
+  for (int r = 0; r < 3; ++r) {
+    double Vr[3];
+    for (int c = 0; c < 3; ++c) {
+      const double I = (r == c) ? 1.0 : 0.0;
+      E[r][c] = I + A * W[r][c] + B * W2[r][c];
+      Vr[c] = I + B * W[r][c] + C * W2[r][c];
+    }
+    E[r][3] = Vr[0] * xi[3] + Vr[1] * xi[4] + Vr[2] * xi[5];
+  }
+  double N[12];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 4; ++c) {
+      double s = 0.0;
+      for (int m = 0; m < 3; ++m) s += E[r][m] * T[4 * m + c];
+      if (c == 3) s += E[r][3];
+      N[4 * r + c] = s;
+    }
+  for (int k = 0; k < 12; ++k) T[k] = N[k];
+}
+
+__global__ __launch_bounds__(1024) void solve_kernel(SolveArgs a) {
+  IterState* st = a.st;
+  if (st->done) return;
+  __shared__ double sums[kNumSums];
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  for (int v = w; v < kNumSums; v += 1024 / kWave) {
+    const double* p = a.part + (int64_t)v * a.n_blocks;
+    double acc = 0.0;
+    for (int b = lane; b < a.n_blocks; b += kWave) acc += p[b];
+    acc = wave_sum_xor(acc);
+    if (lane == 0) sums[v] = acc;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double n = sums[kSumCount];
+  const int64_t nk = (int64_t)n;
+  const double fk = n / (double)a.n_src;
+  const double ek = nk > 0 ? sqrt(sums[kSumD2] / n) : 0.0;
+  if (a.reduce_only) {
+    for (int v = 0; v < kNumSums; ++v) st->sums[v] = sums[v];
+    st->n_in = nk;
+    st->fitness = fk;
+    st->rmse = ek;
+    return;
+  }
+  const int k = st->k;
+  int status = -1;
+  if (nk == 0) {
+    status = 2;
+  } else if (k == a.max_iter) {
+    status = 0;
+  } else if (k >= 1 && fabs((double)(nk - st->n_prev)) <= a.rel_tol * (double)st->n_prev &&
+             fabs(ek - st->e_prev) <= a.rel_tol * st->e_prev) {
+    status = 1;
+  } else {
+    double xi[6];
+    if (!cholesky_solve6(sums, sums + 21, xi)) {
+      status = 2;
+    } else {
+      double T[12];
+      for (int m = 0; m < 12; ++m) T[m] = st->T[m];
+      apply_exp(xi, T);
+      for (int m = 0; m < 12; ++m) st->T[m] = T[m];
+    }
+  }
+  st->fitness = fk;
+  st->rmse = ek;
+  st->n_in = nk;
+  if (status >= 0) {
+    st->status = status;
+    st->done = 1;
+  } else {
+    st->n_prev = nk;
+    st->e_prev = ek;
+    st->k = k + 1;
+  }
+}
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace
+
+// ====================================================================== launchers
+int bbox_blocks(int64_t n) { return (int)std::min<int64_t>(1024, std::max<int64_t>(1, ceil_div(n, 256))); }
+
+hipError_t launch_bbox(const float* pts, const float* nrm, int64_t n, float* block_out, int nblk,
+                       float* final_out, hipStream_t s) {
+  hipLaunchKernelGGL(bbox_kernel, dim3(nblk), dim3(256), 0, s, pts, nrm, n, block_out);
+  hipLaunchKernelGGL(bbox_final_kernel, dim3(1), dim3(256), 0, s, block_out, nblk, final_out);
+  return hipGetLastError();
+}
+
+int64_t scan_block_sums_needed(int64_t n) { return ceil_div(n, kScanTile); }
+
+hipError_t launch_scan_exclusive(uint32_t* data, int64_t n, uint32_t* block_sums, int64_t cap_blocks,
+                                 hipStream_t s) {
+  const int64_t nb = ceil_div(n, kScanTile);
+  if (nb > cap_blocks) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(scan_tile_sums_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n,
+                     block_sums);
+  hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(1024), 0, s, block_sums, nb);
+  hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n,
+                     block_sums);
+  return hipGetLastError();
+}
+
+hipError_t launch_target_grid(const float* tgt, const float* tgt_n, int64_t n, const GridDesc& g,
+                              uint32_t* key, uint32_t* rank, uint32_t* cs, float4* tp, float4* tn,
+                              uint32_t* scan_tmp, int64_t scan_cap, hipStream_t s) {
+  hipError_t e = hipMemsetAsync(cs, 0, ((size_t)g.ncell + 1) * sizeof(uint32_t), s);
+  if (e != hipSuccess) return e;
+  const unsigned nb = (unsigned)ceil_div(n, 256);
+  hipLaunchKernelGGL(target_key_kernel, dim3(nb), dim3(256), 0, s, tgt, n, g, cs, key, rank);
+  e = launch_scan_exclusive(cs, (int64_t)g.ncell + 1, scan_tmp, scan_cap, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(target_scatter_kernel, dim3(nb), dim3(256), 0, s, tgt, tgt_n, n, key, rank, cs,
+                     tp, tn);
+  return hipGetLastError();
+}
+
+int64_t radix_hist_needed(int64_t n) {
+  const int64_t h = 256 * ceil_div(std::max<int64_t>(n, 1), kSortTile);
+  return h + ceil_div(h, kScanTile);
+}
+
+hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
+                             int64_t n, int key_bits, uint32_t* hist, int64_t hist_cap,
+                             uint32_t** keys_out, uint32_t** vals_out, hipStream_t s) {
+  const int nblk = (int)ceil_div(std::max<int64_t>(n, 1), kSortTile);
+  if ((int64_t)256 * nblk > hist_cap) return hipErrorInvalidValue;
+  // the histogram scan needs its own tile sums after the histogram itself
+  uint32_t* scan_tmp = hist + (int64_t)256 * nblk;
+  const int64_t scan_cap = hist_cap - (int64_t)256 * nblk;
+  uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
+  for (int shift = 0; shift < key_bits; shift += 8) {
+    hipLaunchKernelGGL(radix_hist_kernel, dim3(nblk), dim3(kSortThreads), 0, s, ki, n, shift, hist,
+                       nblk);
+    hipError_t e = launch_scan_exclusive(hist, (int64_t)256 * nblk, scan_tmp, scan_cap, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(radix_scatter_kernel, dim3(nblk), dim3(kSortThreads), 0, s, ki, vi, n, shift,
+                       hist, nblk, ko, vo);
+    std::swap(ki, ko);
+    std::swap(vi, vo);
+  }
+  *keys_out = ki;
+  *vals_out = vi;
+  return hipGetLastError();
+}
+
+hipError_t launch_source_order(const float* src, int64_t n, double ox, double oy, double oz,
+                               double inv_h, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
+                               uint32_t* vals_alt, uint32_t* hist, int64_t hist_cap, float* sx,
+                               float* sy, float* sz, uint32_t** perm_out, hipStream_t s) {
+  const unsigned nb = (unsigned)ceil_div(n, 256);
+  hipLaunchKernelGGL(source_key_kernel, dim3(nb), dim3(256), 0, s, src, n, ox, oy, oz, inv_h, keys,
+                     vals);
+  uint32_t *ko = nullptr, *vo = nullptr;
+  hipError_t e = launch_radix_sort(keys, vals, keys_alt, vals_alt, n, 30, hist, hist_cap, &ko, &vo, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(source_gather_kernel, dim3(nb), dim3(256), 0, s, src, n, vo, sx, sy, sz);
+  *perm_out = vo;
+  return hipGetLastError();
+}
+
+hipError_t launch_state_init(IterState* st, const double T[16], hipStream_t s) {
+  Mat16 m;
+  for (int k = 0; k < 16; ++k) m.v[k] = T[k];
+  hipLaunchKernelGGL(state_init_kernel, dim3(1), dim3(64), 0, s, st, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_pass(const PassArgs& a, int variant, int precision, bool write_corr, hipStream_t s) {
+  const dim3 grid((unsigned)a.n_blocks), block(kBlock);
+#define ICP_PASS(V, P, W) hipLaunchKernelGGL((pass_kernel<V, P, W>), grid, block, 0, s, a)
+  if (write_corr) {
+    if (variant == 1) { if (precision == 0) ICP_PASS(1, 0, true); else ICP_PASS(1, 1, true); }
+    else { if (precision == 0) ICP_PASS(0, 0, true); else ICP_PASS(0, 1, true); }
+  } else {
+    if (variant == 1) { if (precision == 0) ICP_PASS(1, 0, false); else ICP_PASS(1, 1, false); }
+    else { if (precision == 0) ICP_PASS(0, 0, false); else ICP_PASS(0, 1, false); }
+  }
+#undef ICP_PASS
+  return hipGetLastError();
+}
+
+hipError_t launch_solve(const SolveArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(solve_kernel, dim3(1), dim3(1024), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace icp

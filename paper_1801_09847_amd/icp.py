@@ -1,0 +1,243 @@
+"""Python binding of libicp.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module converts torch tensors
+and numpy arrays into the pointers and sizes of the C ABI (include/icp.h) and
+raises ``IcpError`` on a negative return code.  Functions named ``icp_*`` take
+raw integers (device pointers) exactly like the C entry points; the friendlier
+``register`` / ``correspondences`` / ``normal_equations`` accept CUDA tensors.
+
+The library is loaded from this package directory.  If it is missing, import
+succeeds but every call raises: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libicp.so")
+
+ICP_SUCCESS = 0
+ICP_E_INVALID_ARG = -1
+ICP_E_NONFINITE = -2
+ICP_E_TOO_LARGE = -3
+ICP_E_OOM = -4
+ICP_E_DEVICE = -5
+ICP_E_CANCELLED = -6
+ICP_E_NOT_FOUND = -7
+ICP_OK, ICP_CONVERGED, ICP_DEGENERATE = 0, 1, 2
+ICP_POINT_TO_POINT, ICP_POINT_TO_PLANE = 0, 1
+ICP_PREC_F32_KAHAN_F64, ICP_PREC_F64 = 0, 1
+
+VARIANTS = {"point_to_point": ICP_POINT_TO_POINT, "point_to_plane": ICP_POINT_TO_PLANE,
+            ICP_POINT_TO_POINT: ICP_POINT_TO_POINT, ICP_POINT_TO_PLANE: ICP_POINT_TO_PLANE}
+PRECISIONS = {"kahan32": ICP_PREC_F32_KAHAN_F64, "f32_kahan_f64": ICP_PREC_F32_KAHAN_F64,
+              "f64": ICP_PREC_F64, ICP_PREC_F32_KAHAN_F64: ICP_PREC_F32_KAHAN_F64,
+              ICP_PREC_F64: ICP_PREC_F64}
+
+
+class IcpError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class icp_result_t(C.Structure):
+    _fields_ = [("T", C.c_double * 16), ("fitness", C.c_double), ("inlier_rmse", C.c_double),
+                ("n_inliers", C.c_int64), ("n_iter", C.c_int32), ("status", C.c_int32)]
+
+
+class icp_profile_t(C.Structure):
+    _fields_ = [("pass_ms", C.c_double), ("pass_launches", C.c_int64), ("pass_points", C.c_int64),
+                ("call_ms", C.c_double), ("calls", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise IcpError(ICP_E_DEVICE, f"HIP library not built: {LIB_PATH} is missing "
+                                         "(run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int32, C.c_double
+        L.icp_version.restype = C.c_char_p
+        L.icp_strerror.restype = C.c_char_p
+        L.icp_strerror.argtypes = [C.c_int]
+        L.icp_last_error.restype = C.c_char_p
+        L.icp_ctx_create.argtypes = [C.c_int, vp, C.POINTER(vp)]
+        L.icp_ctx_destroy.argtypes = [vp]
+        L.icp_register.argtypes = [vp, vp, i64, vp, vp, i64, vp, dbl, i32, dbl, i32, i32,
+                                   C.POINTER(icp_result_t)]
+        L.icp_correspondences.argtypes = [vp, vp, i64, vp, vp, i64, dbl, vp, vp]
+        L.icp_normal_equations.argtypes = [vp, vp, i64, vp, vp, vp, i64, dbl, i32, i32, vp, vp,
+                                           C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.icp_ctx_set_profiling.argtypes = [vp, C.c_int]
+        L.icp_ctx_get_profile.argtypes = [vp, C.POINTER(icp_profile_t)]
+        for name in ("icp_ctx_create", "icp_ctx_destroy", "icp_register", "icp_correspondences",
+                     "icp_normal_equations", "icp_ctx_set_profiling", "icp_ctx_get_profile"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> None:
+    if rc != ICP_SUCCESS:
+        L = lib()
+        raise IcpError(rc, f"{L.icp_strerror(rc).decode()}: {L.icp_last_error().decode()}")
+
+
+def _pose(T) -> np.ndarray:
+    T = np.ascontiguousarray(np.asarray(T, dtype=np.float64).reshape(16))
+    return T
+
+
+# ---------------------------------------------------------------- raw entry points
+def icp_version() -> str:
+    return lib().icp_version().decode()
+
+
+def icp_ctx_create(device: int, hip_stream: int | None) -> int:
+    h = C.c_void_p()
+    _check(lib().icp_ctx_create(int(device), hip_stream or None, C.byref(h)))
+    return h.value
+
+
+def icp_ctx_destroy(ctx: int | None) -> None:
+    _check(lib().icp_ctx_destroy(ctx))
+
+
+def icp_register(ctx, src_ptr, n_src, tgt_ptr, tgt_n_ptr, n_tgt, T_init, max_corr_dist, max_iter,
+                 rel_tol, variant, precision) -> icp_result_t:
+    out = icp_result_t()
+    T = _pose(T_init)
+    _check(lib().icp_register(ctx, src_ptr, int(n_src), tgt_ptr, tgt_n_ptr, int(n_tgt),
+                              T.ctypes.data, float(max_corr_dist), int(max_iter), float(rel_tol),
+                              int(variant), int(precision), C.byref(out)))
+    return out
+
+
+def icp_correspondences(ctx, src_ptr, n_src, T, tgt_ptr, n_tgt, max_corr_dist, idx_ptr, d2_ptr):
+    T = _pose(T)
+    _check(lib().icp_correspondences(ctx, src_ptr, int(n_src), T.ctypes.data, tgt_ptr, int(n_tgt),
+                                     float(max_corr_dist), idx_ptr, d2_ptr))
+
+
+def icp_normal_equations(ctx, src_ptr, n_src, T, tgt_ptr, tgt_n_ptr, n_tgt, max_corr_dist, variant,
+                         precision):
+    T = _pose(T)
+    A = np.zeros(21, np.float64)
+    b = np.zeros(6, np.float64)
+    sd2 = C.c_double()
+    nin = C.c_int64()
+    _check(lib().icp_normal_equations(ctx, src_ptr, int(n_src), T.ctypes.data, tgt_ptr, tgt_n_ptr,
+                                      int(n_tgt), float(max_corr_dist), int(variant),
+                                      int(precision), A.ctypes.data, b.ctypes.data, C.byref(sd2),
+                                      C.byref(nin)))
+    return A, b, sd2.value, nin.value
+
+
+# ---------------------------------------------------------------- tensor-level helpers
+def _dev_pts(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise IcpError(ICP_E_INVALID_ARG, f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float32 or t.dim() != 2 or t.shape[1] != 3 or not t.is_contiguous():
+        raise IcpError(ICP_E_INVALID_ARG, f"{name} must be a contiguous (N, 3) float32 tensor")
+    return t.data_ptr(), t.shape[0]
+
+
+class Context:
+    """Owns an icp_ctx_t bound to a device and a HIP stream (default: torch's
+    current stream of that device)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.device = device
+        self.stream = stream
+        self.handle = icp_ctx_create(device, stream.cuda_stream if stream is not None else None)
+
+    def set_profiling(self, enable: bool) -> None:
+        _check(lib().icp_ctx_set_profiling(self.handle, 1 if enable else 0))
+
+    def profile(self) -> dict:
+        p = icp_profile_t()
+        _check(lib().icp_ctx_get_profile(self.handle, C.byref(p)))
+        return {k: getattr(p, k) for k, _ in icp_profile_t._fields_}
+
+    def close(self):
+        if self.handle:
+            icp_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class IcpResult:
+    T: np.ndarray
+    fitness: float
+    inlier_rmse: float
+    n_inliers: int
+    n_iter: int
+    status: int
+
+
+def register(src, tgt, tgt_normals, T_init, max_corr_dist, max_iter=30, rel_tol=0.0,
+             variant="point_to_plane", precision="kahan32", ctx: Context | None = None) -> IcpResult:
+    sp, ns = _dev_pts(src, "src")
+    tp, nt = _dev_pts(tgt, "tgt")
+    npn = None
+    if tgt_normals is not None:
+        npn, nn = _dev_pts(tgt_normals, "tgt_normals")
+        if nn != nt:
+            raise IcpError(ICP_E_INVALID_ARG, "tgt_normals must have as many rows as tgt")
+    r = icp_register(ctx.handle if ctx else None, sp, ns, tp, npn, nt, T_init, max_corr_dist,
+                     max_iter, rel_tol, VARIANTS[variant], PRECISIONS[precision])
+    return IcpResult(np.array(r.T[:], dtype=np.float64).reshape(4, 4), r.fitness, r.inlier_rmse,
+                     r.n_inliers, r.n_iter, r.status)
+
+
+def correspondences(src, T, tgt, max_corr_dist, ctx: Context | None = None):
+    """(idx int32 tensor, d2 float32 tensor) per source point, on the device."""
+    import torch
+    sp, ns = _dev_pts(src, "src")
+    tp, nt = _dev_pts(tgt, "tgt")
+    idx = torch.empty(ns, dtype=torch.int32, device=src.device)
+    d2 = torch.empty(ns, dtype=torch.float32, device=src.device)
+    icp_correspondences(ctx.handle if ctx else None, sp, ns, T, tp, nt, max_corr_dist,
+                        idx.data_ptr(), d2.data_ptr())
+    return idx, d2
+
+
+def normal_equations(src, T, tgt, tgt_normals, max_corr_dist, variant="point_to_plane",
+                     precision="kahan32", ctx: Context | None = None):
+    """(AtA21, Atb6, sum_d2, n_in) at pose T."""
+    sp, ns = _dev_pts(src, "src")
+    tp, nt = _dev_pts(tgt, "tgt")
+    npn = _dev_pts(tgt_normals, "tgt_normals")[0] if tgt_normals is not None else None
+    return icp_normal_equations(ctx.handle if ctx else None, sp, ns, T, tp, npn, nt, max_corr_dist,
+                                VARIANTS[variant], PRECISIONS[precision])
+
+
+def full_matrix(A21) -> np.ndarray:
+    """Symmetric 6x6 matrix from its 21-entry upper triangle (row-major)."""
+    A = np.zeros((6, 6))
+    k = 0
+    for u in range(6):
+        for v in range(u, 6):
+            A[u, v] = A[v, u] = A21[k]
+            k += 1
+    return A

@@ -1,0 +1,111 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+declared in include/icp.h, and rejects invalid arguments on the host before
+any device work (so these calls are safe without a GPU)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1801_09847_amd import icp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FAKE = 1 << 20          # aligned, never dereferenced: validation fails first
+MISALIGNED = FAKE + 2
+
+
+def declared_functions():
+    names = []
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", h)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names += re.findall(r"^[A-Za-z_][\w \*]*?\b(icp_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    L = icp.lib()
+    names = declared_functions()
+    assert "icp_register" in names and "icp_correspondences" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert icp.icp_version().startswith("icp-mi355x")
+
+
+def test_strerror_covers_codes():
+    L = icp.lib()
+    for code in range(0, -8, -1):
+        assert L.icp_strerror(code).decode() not in ("", "unknown error code")
+    assert L.icp_strerror(-99).decode() == "unknown error code"
+
+
+def _reg(**kw):
+    a = dict(ctx=None, src_ptr=FAKE, n_src=100, tgt_ptr=FAKE, tgt_n_ptr=FAKE, n_tgt=100,
+             T_init=np.eye(4), max_corr_dist=0.05, max_iter=10, rel_tol=0.0,
+             variant=icp.ICP_POINT_TO_PLANE, precision=icp.ICP_PREC_F32_KAHAN_F64)
+    a.update(kw)
+    with pytest.raises(icp.IcpError) as e:
+        icp.icp_register(**a)
+    return e.value.code
+
+
+def test_register_validation_codes():
+    bad_T = np.eye(4); bad_T[3, 0] = 1.0
+    nan_T = np.eye(4); nan_T[0, 3] = np.nan
+    skew_T = np.eye(4); skew_T[0, 1] = 0.01
+    assert _reg(src_ptr=None) == icp.ICP_E_INVALID_ARG
+    assert _reg(tgt_ptr=None) == icp.ICP_E_INVALID_ARG
+    assert _reg(n_src=0) == icp.ICP_E_INVALID_ARG
+    assert _reg(n_tgt=-5) == icp.ICP_E_INVALID_ARG
+    assert _reg(n_src=2**31) == icp.ICP_E_TOO_LARGE
+    assert _reg(max_corr_dist=0.0) == icp.ICP_E_INVALID_ARG
+    assert _reg(max_corr_dist=float("nan")) == icp.ICP_E_INVALID_ARG
+    assert _reg(max_corr_dist=float("inf")) == icp.ICP_E_INVALID_ARG
+    assert _reg(max_iter=-1) == icp.ICP_E_INVALID_ARG
+    assert _reg(rel_tol=-1e-3) == icp.ICP_E_INVALID_ARG
+    assert _reg(rel_tol=float("nan")) == icp.ICP_E_INVALID_ARG
+    assert _reg(T_init=bad_T) == icp.ICP_E_INVALID_ARG
+    assert _reg(T_init=nan_T) == icp.ICP_E_INVALID_ARG
+    assert _reg(T_init=skew_T) == icp.ICP_E_INVALID_ARG
+    # point-to-plane needs normals with the target's record count (Sec. 3.1 field rule)
+    assert _reg(tgt_n_ptr=None) == icp.ICP_E_INVALID_ARG
+    assert _reg(variant=7) == icp.ICP_E_INVALID_ARG
+    assert _reg(precision=3) == icp.ICP_E_INVALID_ARG
+    assert _reg(src_ptr=MISALIGNED) == icp.ICP_E_INVALID_ARG
+    assert "aligned" in icp.lib().icp_last_error().decode()
+
+
+def test_null_out_and_hooks_validation():
+    L = icp.lib()
+    T = np.eye(4)
+    rc = L.icp_register(None, FAKE, 10, FAKE, FAKE, 10, T.ctypes.data, 0.1, 3, 0.0, 1, 0, None)
+    assert rc == icp.ICP_E_INVALID_ARG
+    with pytest.raises(icp.IcpError) as e:
+        icp.icp_correspondences(None, FAKE, 10, T, FAKE, 10, 0.1, None, FAKE)
+    assert e.value.code == icp.ICP_E_INVALID_ARG
+    with pytest.raises(icp.IcpError) as e:
+        icp.icp_correspondences(None, FAKE, 10, T, FAKE, 10, -0.1, FAKE, FAKE)
+    assert e.value.code == icp.ICP_E_INVALID_ARG
+    with pytest.raises(icp.IcpError) as e:
+        icp.icp_normal_equations(None, FAKE, 10, T, FAKE, None, 10, 0.1, 1, 0)
+    assert e.value.code == icp.ICP_E_INVALID_ARG
+    rc = L.icp_ctx_create(0, None, None)
+    assert rc == icp.ICP_E_INVALID_ARG
+    assert L.icp_ctx_destroy(None) == 0
+
+
+def test_product_path_has_no_oracle_or_cpu_fallback():
+    """The package never imports the oracle, and the binding carries no
+    computation of its own."""
+    pkg = os.path.join(ROOT, "paper_1801_09847_amd")
+    for f in os.listdir(pkg):
+        if f.endswith(".py"):
+            src = open(os.path.join(pkg, f)).read()
+            assert "import oracle" not in src and "from oracle" not in src, f
+    for f in os.listdir(os.path.join(pkg, "csrc")):
+        if not f.endswith((".hip", ".h", ".cpp")):
+            continue
+        src = open(os.path.join(pkg, "csrc", f)).read()
+        assert "oracle" not in src.lower(), f

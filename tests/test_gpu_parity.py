@@ -1,0 +1,256 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars:
+  * correspondence indices and inlier counts bit-exact against the oracle's
+    pinned-FP32 selection at the same pose (the pinned distance itself too);
+  * normal equations within 1e-6 (FP32-Kahan) / 1e-12 (FP64) of the sum of the
+    absolute per-correspondence terms, entry by entry;
+  * final pose within 1e-5 rad rotation and 1e-6 m translation of the oracle,
+    equal inlier count; the rmse difference is printed for every result.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1801_09847_amd import synth
+
+sys.path.insert(0, os.path.dirname(__file__))
+from cases import adversarial_sets, pose_error  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def icp():
+    _need_gpu()
+    from paper_1801_09847_amd import icp as m
+    m.lib()
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return synth.c1_heightfield(0)
+
+
+def abs_term_sums(micro, T, src, tgt, nrm, idx, variant):
+    """Per-entry sums of |J_u J_v| and |J_u r| over the oracle's matches (the
+    scale of the normal-equation tolerance)."""
+    q = micro.transform64(T, src)
+    m = idx >= 0
+    p = tgt[idx[m]].astype(np.float64)
+    n = nrm[idx[m]].astype(np.float64) if nrm is not None else np.zeros_like(p)
+    r, J = micro.jacobians(variant, q[m], p, n)
+    SA = np.abs(J).T @ np.abs(J)
+    Sb = np.abs(J).T @ np.abs(r)
+    iu = np.triu_indices(6)
+    return SA[iu], Sb
+
+
+# ------------------------------------------------------------------ library is the HIP one
+def test_native_library_loaded(icp, c1):
+    s, t = dev(c1["src"]), dev(c1["tgt"])
+    icp.correspondences(s, np.eye(4), t, 0.05)
+    maps = open("/proc/self/maps").read()
+    assert icp.LIB_PATH in maps
+
+
+# ------------------------------------------------------------------ correspondences
+def test_correspondences_adversarial_bit_exact(icp, oracle_lib):
+    rng = np.random.default_rng(0)
+    for name, src, tgt, r in adversarial_sets():
+        for T in (np.eye(4), _small_T(rng)):
+            idx, d2 = icp.correspondences(dev(src), T, dev(tgt), r)
+            oi, of, _ = oracle_lib.correspondences(src, T, tgt, r, search=1)
+            np.testing.assert_array_equal(idx.cpu().numpy().astype(np.int64), oi, err_msg=name)
+            np.testing.assert_array_equal(d2.cpu().numpy().view(np.uint32), of.view(np.uint32),
+                                          err_msg=name)
+
+
+def _small_T(rng, deg=2.0, t=0.01):
+    from scipy.spatial.transform import Rotation
+    ax = rng.normal(size=3)
+    T = np.eye(4)
+    T[:3, :3] = Rotation.from_rotvec(ax / np.linalg.norm(ax) * np.radians(rng.uniform(0, deg))).as_matrix()
+    T[:3, 3] = rng.uniform(-t, t, 3)
+    return T
+
+
+@pytest.mark.parametrize("scale", ["1", "1.5", "2", "3.7"])
+def test_correspondences_c1_grid_invariant(icp, oracle_lib, c1, scale, monkeypatch):
+    """Same matches for any cell edge >= r (1 + 2^-10), bit-exact vs the oracle."""
+    monkeypatch.setenv("ICP_GRID_SCALE", scale)
+    rng = np.random.default_rng(1)
+    s, t = dev(c1["src"]), dev(c1["tgt"])
+    for T in (np.eye(4), c1["T_gt"], _small_T(rng) @ c1["T_gt"]):
+        idx, d2 = icp.correspondences(s, T, t, 0.05)
+        oi, of, _ = oracle_lib.correspondences(c1["src"], T, c1["tgt"], 0.05)
+        np.testing.assert_array_equal(idx.cpu().numpy().astype(np.int64), oi)
+        np.testing.assert_array_equal(d2.cpu().numpy().view(np.uint32), of.view(np.uint32))
+
+
+# ------------------------------------------------------------------ normal equations
+@pytest.mark.parametrize("variant", ["point_to_plane", "point_to_point"])
+@pytest.mark.parametrize("precision,tol", [("kahan32", 1e-6), ("f64", 1e-12)])
+def test_normal_equations_c1(icp, oracle_lib, c1, variant, precision, tol):
+    from oracle import micro
+    T = c1["T_gt"]
+    s, t, n = dev(c1["src"]), dev(c1["tgt"]), dev(c1["tgt_normals"])
+    A, b, sd2, nin = icp.normal_equations(s, T, t, n, 0.05, variant, precision)
+    oA, ob, osd2, onin = oracle_lib.normal_equations(c1["src"], T, c1["tgt"], c1["tgt_normals"],
+                                                     0.05, variant)
+    assert nin == onin
+    idx, _, _ = oracle_lib.correspondences(c1["src"], T, c1["tgt"], 0.05)
+    SA, Sb = abs_term_sums(micro, T, c1["src"], c1["tgt"], c1["tgt_normals"], idx, variant)
+    assert np.all(np.abs(A - oA) <= tol * SA + 1e-300), np.max(np.abs(A - oA) / SA)
+    assert np.all(np.abs(b - ob) <= tol * Sb + 1e-300), np.max(np.abs(b - ob) / Sb)
+    assert abs(sd2 - osd2) <= tol * osd2 * 10
+
+
+# ------------------------------------------------------------------ lockstep along the oracle's trajectory
+def test_lockstep_c1(icp, oracle_lib, c1):
+    from oracle import micro
+    orc = oracle_lib.icp_register(c1["src"], c1["tgt"], c1["tgt_normals"], np.eye(4), 0.05, 30,
+                                  trajectory=True)
+    s, t, n = dev(c1["src"]), dev(c1["tgt"]), dev(c1["tgt_normals"])
+    for k, T in enumerate(orc.traj_T):
+        idx, d2 = icp.correspondences(s, T, t, 0.05)
+        oi, of, _ = oracle_lib.correspondences(c1["src"], T, c1["tgt"], 0.05)
+        np.testing.assert_array_equal(idx.cpu().numpy().astype(np.int64), oi, err_msg=f"k={k}")
+        A, b, _, nin = icp.normal_equations(s, T, t, n, 0.05, "point_to_plane", "kahan32")
+        oA, ob, _, onin = oracle_lib.normal_equations(c1["src"], T, c1["tgt"], c1["tgt_normals"], 0.05)
+        assert nin == onin == orc.traj_n[k]
+        SA, Sb = abs_term_sums(micro, T, c1["src"], c1["tgt"], c1["tgt_normals"], oi,
+                               "point_to_plane")
+        assert np.all(np.abs(A - oA) <= 1e-6 * SA)
+        assert np.all(np.abs(b - ob) <= 1e-6 * Sb)
+
+
+# ------------------------------------------------------------------ end to end
+def _compare(name, g, o, rot_tol=1e-5, t_tol=1e-6):
+    ang, dt = pose_error(g.T, o.T)
+    print(f"\n{name}: rot {ang:.3e} rad, trans {dt:.3e} m, n_in {g.n_inliers}/{o.n_inliers}, "
+          f"rmse {g.inlier_rmse:.9e} vs {o.inlier_rmse:.9e} (d {g.inlier_rmse - o.inlier_rmse:.2e}), "
+          f"iters {g.n_iter}/{o.n_iter}, status {g.status}/{o.status}")
+    assert g.n_inliers == o.n_inliers
+    assert ang <= rot_tol and dt <= t_tol
+
+
+@pytest.mark.parametrize("variant", ["point_to_plane", "point_to_point"])
+@pytest.mark.parametrize("precision", ["kahan32", "f64"])
+def test_register_c1(icp, oracle_lib, c1, variant, precision):
+    s, t, n = dev(c1["src"]), dev(c1["tgt"]), dev(c1["tgt_normals"])
+    g = icp.register(s, t, n, np.eye(4), 0.05, 30, 0.0, variant, precision)
+    o = oracle_lib.icp_register(c1["src"], c1["tgt"], c1["tgt_normals"], np.eye(4), 0.05, 30,
+                                variant=variant)
+    _compare(f"C1 {variant} {precision}", g, o)
+    assert abs(g.fitness - o.fitness) == 0.0
+
+
+@pytest.mark.parametrize("precision", ["kahan32", "f64"])
+def test_register_c2(icp, oracle_lib, precision):
+    d = synth.c2_room(0)
+    s, t, n = dev(d["src"]), dev(d["tgt"]), dev(d["tgt_normals"])
+    g = icp.register(s, t, n, np.eye(4), 0.03, 50, 0.0, "point_to_plane", precision)
+    o = oracle_lib.icp_register(d["src"], d["tgt"], d["tgt_normals"], np.eye(4), 0.03, 50)
+    _compare(f"C2 p2plane {precision}", g, o)
+
+
+# ------------------------------------------------------------------ edge cases
+def test_edge_tiny_and_ragged(icp, oracle_lib):
+    rng = np.random.default_rng(5)
+    for ns, nt in [(1, 1), (1, 300), (300, 1), (255, 257), (257, 1000), (1023, 4097), (4096, 64)]:
+        tgt = rng.uniform(0, 0.5, (nt, 3)).astype(np.float32)
+        src = (tgt[rng.integers(0, nt, ns)] + rng.normal(0, 0.01, (ns, 3))).astype(np.float32)
+        nrm = rng.normal(size=(nt, 3))
+        nrm = (nrm / np.linalg.norm(nrm, axis=1, keepdims=True)).astype(np.float32)
+        T = _small_T(rng, 1.0, 0.005)
+        idx, d2 = icp.correspondences(dev(src), T, dev(tgt), 0.05)
+        oi, of, _ = oracle_lib.correspondences(src, T, tgt, 0.05)
+        np.testing.assert_array_equal(idx.cpu().numpy().astype(np.int64), oi, err_msg=str((ns, nt)))
+        for var in ("point_to_plane", "point_to_point"):
+            g = icp.register(dev(src), dev(tgt), dev(nrm), T, 0.05, 5, 0.0, var, "f64")
+            o = oracle_lib.icp_register(src, tgt, nrm, T, 0.05, 5, variant=var)
+            assert g.status == o.status and g.n_inliers == o.n_inliers, (ns, nt, var)
+            if o.status != 2:
+                ang, dt = pose_error(g.T, o.T)
+                assert ang < 1e-8 and dt < 1e-8, (ns, nt, var, ang, dt)
+
+
+def test_edge_max_iter_zero_and_degenerate(icp, oracle_lib, c1):
+    s, t, n = dev(c1["src"]), dev(c1["tgt"]), dev(c1["tgt_normals"])
+    T0 = c1["T_gt"]
+    g = icp.register(s, t, n, T0, 0.05, 0)
+    o = oracle_lib.icp_register(c1["src"], c1["tgt"], c1["tgt_normals"], T0, 0.05, 0)
+    np.testing.assert_array_equal(g.T, T0)
+    assert g.n_iter == 0 and g.status == 0 and g.n_inliers == o.n_inliers
+    assert abs(g.inlier_rmse - o.inlier_rmse) <= 1e-6 * o.inlier_rmse
+    # no inliers at all
+    far = dev(c1["src"] + np.float32(10.0))
+    g = icp.register(far, t, n, np.eye(4), 0.05, 10)
+    assert g.status == 2 and g.fitness == 0.0 and g.n_inliers == 0 and g.inlier_rmse == 0.0
+    np.testing.assert_array_equal(g.T, np.eye(4))
+    # single plane: J^T J has rank 3
+    u = np.linspace(0.0, 1.0, 41)
+    P = np.stack(np.meshgrid(u, u, indexing="ij"), -1).reshape(-1, 2)
+    P = np.column_stack([P, np.zeros(len(P))]).astype(np.float32)
+    N = np.tile(np.array([[0, 0, 1]], np.float32), (len(P), 1))
+    g = icp.register(dev(P + np.float32([0, 0, 0.004])), dev(P), dev(N), np.eye(4), 0.05, 10)
+    assert g.status == 2 and g.n_iter == 0 and g.fitness == 1.0
+
+
+def test_edge_nonfinite_rejected(icp, c1):
+    bad = c1["src"].copy()
+    bad[123, 1] = np.nan
+    with pytest.raises(icp.IcpError) as e:
+        icp.register(dev(bad), dev(c1["tgt"]), dev(c1["tgt_normals"]), np.eye(4), 0.05, 5)
+    assert e.value.code == icp.ICP_E_NONFINITE
+    badn = c1["tgt_normals"].copy()
+    badn[7, 0] = np.inf
+    with pytest.raises(icp.IcpError) as e:
+        icp.register(dev(c1["src"]), dev(c1["tgt"]), dev(badn), np.eye(4), 0.05, 5)
+    assert e.value.code == icp.ICP_E_NONFINITE
+    # point-to-point ignores normals entirely
+    g = icp.register(dev(c1["src"]), dev(c1["tgt"]), dev(badn), np.eye(4), 0.05, 2, 0.0,
+                     "point_to_point")
+    assert g.status in (0, 1)
+
+
+def test_identical_clouds_converge_to_identity(icp, c1):
+    t, n = dev(c1["tgt"]), dev(c1["tgt_normals"])
+    for prec in ("kahan32", "f64"):
+        g = icp.register(t, t, n, np.eye(4), 0.05, 30, 0.0, "point_to_plane", prec)
+        np.testing.assert_array_equal(g.T, np.eye(4))
+        assert g.fitness == 1.0 and g.inlier_rmse == 0.0 and g.n_iter == 1 and g.status == 1
+
+
+def test_deterministic_bitwise(icp, c1):
+    s, t, n = dev(c1["src"]), dev(c1["tgt"]), dev(c1["tgt_normals"])
+    rs = [icp.register(s, t, n, np.eye(4), 0.05, 30) for _ in range(3)]
+    for r in rs[1:]:
+        np.testing.assert_array_equal(r.T, rs[0].T)
+        assert r.inlier_rmse == rs[0].inlier_rmse and r.n_inliers == rs[0].n_inliers
+
+
+def test_permutation_invariance(icp, oracle_lib, c1):
+    rng = np.random.default_rng(9)
+    ps, pt = rng.permutation(5000), rng.permutation(5000)
+    a = icp.register(dev(c1["src"]), dev(c1["tgt"]), dev(c1["tgt_normals"]), np.eye(4), 0.05, 30)
+    b = icp.register(dev(c1["src"][ps]), dev(c1["tgt"][pt]), dev(c1["tgt_normals"][pt]), np.eye(4),
+                     0.05, 30)
+    assert a.n_inliers == b.n_inliers
+    ang, dt = pose_error(a.T, b.T)
+    assert ang < 1e-7 and dt < 1e-7

@@ -162,6 +162,7 @@ def main():
             "workload": desc + f", {args.variant}, precision {args.precision}",
             "n_src": len(data["src"]), "n_tgt": len(data["tgt"]), "max_corr_dist": r,
             "max_iter": K, "passes_per_step": res.n_iter + 1,
+            "grid_sub": os.environ.get("ICP_GRID_SUB", "default"),
         },
         "roofline": {
             "bound": "hbm",

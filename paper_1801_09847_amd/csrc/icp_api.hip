@@ -89,7 +89,7 @@ struct icp_ctx {
   Buf bbox_part, bbox_out;
   Buf t_key, t_rank, t_cs, t_tp, t_tn, scan_tmp;
   Buf s_keys, s_vals, s_keys2, s_vals2, s_hist, s_x, s_y, s_z;
-  Buf part, state;
+  Buf part, state, jprev;
   void* host = nullptr;  // pinned readback area
   size_t host_cap = 0;
   // kernel timing
@@ -101,6 +101,7 @@ struct icp_ctx {
 namespace {
 
 constexpr size_t kHostBytes = 4096;
+constexpr int kDefaultSub = 1;
 
 struct DeviceGuard {
   int prev = -1;
@@ -133,7 +134,7 @@ void ctx_free(icp_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   Buf* bufs[] = {&c->bbox_part, &c->bbox_out, &c->t_key, &c->t_rank, &c->t_cs, &c->t_tp,
                  &c->t_tn, &c->scan_tmp, &c->s_keys, &c->s_vals, &c->s_keys2, &c->s_vals2,
-                 &c->s_hist, &c->s_x, &c->s_y, &c->s_z, &c->part, &c->state};
+                 &c->s_hist, &c->s_x, &c->s_y, &c->s_z, &c->part, &c->state, &c->jprev};
   for (Buf* b : bufs) b->release();
   if (c->host) (void)hipHostFree(c->host);
   c->host = nullptr;
@@ -245,9 +246,19 @@ double grid_scale() {
   return (v >= 1.0 && v <= 64.0) ? v : 1.0;
 }
 
+// Cells per max_corr_dist along an axis (1: 27-cell neighbourhood, 2: 125
+// smaller cells).  ICP_GRID_SUB overrides the default (debugging and tests).
+int grid_sub() {
+  const char* e = getenv("ICP_GRID_SUB");
+  if (e && atoi(e) == 1) return 1;
+  if (e && atoi(e) == 2) return 2;
+  return kDefaultSub;
+}
+
 GridDesc make_grid(const float* mn, const float* mx, double r, int64_t n_tgt) {
   const double cap = std::min<double>(1073741824.0, std::max<double>(16777216.0, 32.0 * (double)n_tgt));
-  double h = r * (1.0 + 1.0 / 1024.0) * grid_scale();
+  const int sub = grid_sub();
+  double h = r * (1.0 + 1.0 / 1024.0) * grid_scale() / sub;
   GridDesc g{};
   for (int it = 0; it < 64; ++it) {
     const double inv_h = 1.0 / h;
@@ -259,6 +270,7 @@ GridDesc make_grid(const float* mn, const float* mx, double r, int64_t n_tgt) {
       g.inv_h = inv_h;
       g.dx = (int32_t)d[0]; g.dy = (int32_t)d[1]; g.dz = (int32_t)d[2];
       g.ncell = (uint32_t)cells;
+      g.sub = sub;
       return g;
     }
     h *= std::cbrt(cells / cap) * 1.001;
@@ -299,10 +311,12 @@ int prepare(icp_ctx* c, const float* src, int64_t n_src, const float* tgt, const
                              with_normals ? c->t_tn.as<float4>() : nullptr,
                              c->scan_tmp.as<uint32_t>(), scan_cap, s),
           "target grid");
-  // source order (Morton curve over 1024^3 cells spanning the source box)
+  // source order: Morton curve over 1024^3 cells spanning the source box.  It
+  // depends on the source cloud only, so the summation order (and hence every
+  // result bit) does not change with the grid's cell size.
   double ext = 0.0;
   for (int a = 0; a < 3; ++a) ext = std::max(ext, (double)smx[a] - (double)smn[a]);
-  const double hs = std::max(1.0 / g.inv_h, ext / 1023.5);
+  const double hs = ext > 0.0 ? ext / 1023.5 : 1.0;
   const int64_t hist_cap = radix_hist_needed(n_src);
   HIP_TRY(c->s_keys.ensure(4 * (size_t)n_src), "alloc");
   HIP_TRY(c->s_vals.ensure(4 * (size_t)n_src), "alloc");
@@ -318,7 +332,7 @@ int prepare(icp_ctx* c, const float* src, int64_t n_src, const float* tgt, const
                               c->s_vals2.as<uint32_t>(), c->s_hist.as<uint32_t>(), hist_cap,
                               c->s_x.as<float>(), c->s_y.as<float>(), c->s_z.as<float>(), &perm, s),
           "source order");
-  const int32_t n_blocks = (int32_t)((n_src + kBlock - 1) / kBlock);
+  const int32_t n_blocks = (int32_t)((n_src + kTile - 1) / kTile);
   HIP_TRY(c->part.ensure(sizeof(double) * kNumSums * (size_t)n_blocks), "alloc");
   HIP_TRY(c->state.ensure(sizeof(IterState)), "alloc");
 
@@ -334,6 +348,9 @@ int prepare(icp_ctx* c, const float* src, int64_t n_src, const float* tgt, const
   a.cs = c->t_cs.as<uint32_t>();
   a.g = g;
   a.r2f = (float)(r * r);
+  a.inv_h2 = (float)(g.inv_h * g.inv_h);
+  a.n_tgt = (int32_t)n_tgt;
+  a.jprev = nullptr;
   a.st = c->state.as<IterState>();
   a.part = c->part.as<double>();
   a.n_blocks = n_blocks;
@@ -451,6 +468,9 @@ int icp_register(icp_ctx_t* ctx, const float* src_xyz, int64_t n_src, const floa
   Prepared P;
   if ((rc = prepare(c, src_xyz, n_src, tgt_xyz, tgt_normals, n_tgt, max_corr_dist, plane, &P)) != 0)
     return rc;
+  HIP_TRY(c->jprev.ensure(4 * (size_t)n_src), "alloc");
+  HIP_TRY(hipMemsetAsync(c->jprev.p, 0xff, 4 * (size_t)n_src, c->stream), "memset");
+  P.pa.jprev = c->jprev.as<uint32_t>();
   const bool prof = c->profiling;
   if (prof && (rc = ensure_events(c, max_iter + 1)) != 0) return rc;
   if (prof) HIP_TRY(hipEventRecord(c->ev[0], c->stream), "hipEventRecord");

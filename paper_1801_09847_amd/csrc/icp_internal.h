@@ -7,17 +7,21 @@
 namespace icp {
 
 constexpr int kBlock = 256;        // threads per block of the pass kernel
+constexpr int kTile = 1024;        // queries per block of the pass kernel (4 per thread)
 constexpr int kNumSums = 29;       // 21 (J^T J upper) + 6 (J^T r) + sum d2 + count
 constexpr int kSumD2 = 27;
 constexpr int kSumCount = 28;
 
 // Uniform voxel grid over the target: cell = floor((p - origin) * inv_h) per
-// axis in float64; dense key = (cz * dy + cy) * dx + cx.
+// axis in float64; dense key = (cz * dy + cy) * dx + cx.  The cell edge is
+// >= r (1 + 2^-10) / sub, so a query's candidates lie in the (2 sub + 1)^3
+// cells around its own.
 struct GridDesc {
   double ox, oy, oz;
   double inv_h;
   int32_t dx, dy, dz;
   uint32_t ncell;  // dx * dy * dz
+  int32_t sub;     // 1 or 2
 };
 
 // Device-resident loop state of one registration.
@@ -46,6 +50,9 @@ struct PassArgs {
   const uint32_t* cs;     // cell start table, ncell + 1 entries
   GridDesc g;
   float r2f;              // (float)(max_corr_dist^2)
+  float inv_h2;           // (float)(inv_h^2)
+  int32_t n_tgt;
+  uint32_t* jprev;        // optional per-query match of the previous pass (warm start), in/out
   const IterState* st;
   double* part;           // [kNumSums][n_blocks] block partials
   int32_t n_blocks;

@@ -28,6 +28,8 @@ namespace icp {
 namespace {
 
 constexpr int kWave = 64;
+constexpr int kRounds = 4;  // queries per thread in one pass launch
+static_assert(kRounds * kBlock == kTile, "tile size");
 
 __device__ inline int lane_id() { return __lane_id(); }
 
@@ -388,161 +390,309 @@ __device__ inline void record_terms(F qx, F qy, F qz, F rx, F ry, F rz, F nx, F 
   }
 }
 
-template <int VAR, int PREC, bool WRITE>
-__global__ __launch_bounds__(kBlock) void pass_kernel(PassArgs a) {
-  if (a.st->done) return;
-  double T[12];
-#pragma unroll
-  for (int k = 0; k < 12; ++k) T[k] = a.st->T[k];
+// Correspondence search of one query on the dense grid (cells of edge
+// h >= r (1 + 2^-10) / R, neighbourhood of (2R+1)^3 cells).  Cells are pruned
+// when their box lies farther from the query than the best distance known so
+// far (the previous pass's match when a warm start is available, else r); the
+// bound is conservative (relative margin 1e-4 on the squared distance, 1e-5
+// cell on each gap) so no candidate that could win under the float32 pinned
+// distance is dropped.  Candidates of one (dy, dz) row are contiguous in the
+// cell-ordered target, so each surviving row is one index range; the ranges of
+// a lane are staged in LDS and scanned as a single flattened loop so that the
+// wavefront runs max(candidates) iterations instead of a sum over rows of the
+// per-row maximum.
+template <int R>
+__device__ inline void find_nearest(const PassArgs& a, float q32x, float q32y, float q32z,
+                                    uint2* lane_ranges, uint64_t& best, uint32_t& bj) {
+  constexpr int W = 2 * R + 1;
+  const GridDesc& g = a.g;
+  const double lo = -(double)R - 1.0;
+  double ux = ((double)q32x - g.ox) * g.inv_h;
+  double uy = ((double)q32y - g.oy) * g.inv_h;
+  double uz = ((double)q32z - g.oz) * g.inv_h;
+  ux = fmin(fmax(ux, lo), (double)g.dx + R);
+  uy = fmin(fmax(uy, lo), (double)g.dy + R);
+  uz = fmin(fmax(uz, lo), (double)g.dz + R);
+  const double flx = floor(ux), fly = floor(uy), flz = floor(uz);
+  const int cx = (int)flx, cy = (int)fly, cz = (int)flz;
+  const float fx = (float)(ux - flx), fy = (float)(uy - fly), fz = (float)(uz - flz);
 
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  bool inl = false;
-  float bd = INFINITY;
-  uint32_t bo = 0xffffffffu;
-  float4 bp = make_float4(0.f, 0.f, 0.f, 0.f);
-  uint32_t bj = 0;
-  double q64x = 0.0, q64y = 0.0, q64z = 0.0;
-  float q32x = 0.f, q32y = 0.f, q32z = 0.f;
-  if (i < a.n_src) {
-    const double sx = a.sx[i], sy = a.sy[i], sz = a.sz[i];
-    double t;
-    t = T[0] * sx; t = t + T[1] * sy; t = t + T[2] * sz; q64x = t + T[3];
-    t = T[4] * sx; t = t + T[5] * sy; t = t + T[6] * sz; q64y = t + T[7];
-    t = T[8] * sx; t = t + T[9] * sy; t = t + T[10] * sz; q64z = t + T[11];
-    q32x = (float)q64x; q32y = (float)q64y; q32z = (float)q64z;
-    const GridDesc g = a.g;
-    const int cx = cell_of(q32x, g.ox, g.inv_h, g.dx);
-    const int cy = cell_of(q32y, g.oy, g.inv_h, g.dy);
-    const int cz = cell_of(q32z, g.oz, g.inv_h, g.dz);
-    const int x0 = max(cx - 1, 0), x1 = min(cx + 1, g.dx - 1);
-    if (x0 <= x1) {
-      for (int ddz = -1; ddz <= 1; ++ddz) {
-        const int z = cz + ddz;
-        if ((unsigned)z >= (unsigned)g.dz) continue;
-        for (int ddy = -1; ddy <= 1; ++ddy) {
-          const int y = cy + ddy;
-          if ((unsigned)y >= (unsigned)g.dy) continue;
+  // squared gaps (in cells) from the query to the slab of offset d, lowered by
+  // a safety margin
+  float g2x[W], g2y[W], g2z[W];
+#pragma unroll
+  for (int d = -R; d <= R; ++d) {
+    float gx = 0.f, gy = 0.f, gz = 0.f;
+    if (d < 0) {
+      gx = fx + (float)(-d - 1); gy = fy + (float)(-d - 1); gz = fz + (float)(-d - 1);
+    } else if (d > 0) {
+      gx = (float)d - fx; gy = (float)d - fy; gz = (float)d - fz;
+    }
+    gx = fmaxf(gx - 1e-5f, 0.f); gy = fmaxf(gy - 1e-5f, 0.f); gz = fmaxf(gz - 1e-5f, 0.f);
+    g2x[d + R] = gx * gx; g2y[d + R] = gy * gy; g2z[d + R] = gz * gz;
+  }
+  float B = a.r2f;
+  if (best != ~0ull) B = fminf(B, __uint_as_float((uint32_t)(best >> 32)));
+  const float thr = B * a.inv_h2 * (1.0f + 1e-4f) + 1e-6f;
+
+  int m = 0;
+  uint32_t total = 0;
+#pragma unroll
+  for (int dz = -R; dz <= R; ++dz) {
+    const int z = cz + dz;
+#pragma unroll
+    for (int dy = -R; dy <= R; ++dy) {
+      const int y = cy + dy;
+      const float gyz = g2z[dz + R] + g2y[dy + R];
+      if ((unsigned)z < (unsigned)g.dz && (unsigned)y < (unsigned)g.dy && gyz <= thr) {
+        int xlo = cx, xhi = cx;
+#pragma unroll
+        for (int d = 1; d <= R; ++d) {
+          if (gyz + g2x[R - d] <= thr) xlo = cx - d;
+          if (gyz + g2x[R + d] <= thr) xhi = cx + d;
+        }
+        xlo = max(xlo, 0);
+        xhi = min(xhi, g.dx - 1);
+        if (xlo <= xhi) {
           const uint32_t row = ((uint32_t)z * (uint32_t)g.dy + (uint32_t)y) * (uint32_t)g.dx;
-          const uint32_t beg = a.cs[row + x0], end = a.cs[row + x1 + 1];
-          for (uint32_t j = beg; j < end; ++j) {
-            const float4 p = a.tp[j];
-            const float dx = q32x - p.x, dy = q32y - p.y, dz = q32z - p.z;
-            float d2 = dx * dx + dy * dy;
-            d2 = d2 + dz * dz;
-            const uint32_t o = __float_as_uint(p.w);
-            if (d2 < bd || (d2 == bd && o < bo)) {
-              bd = d2;
-              bo = o;
-              bp = p;
-              bj = j;
-            }
+          const uint32_t beg = a.cs[row + xlo], end = a.cs[row + xhi + 1];
+          if (beg < end) {
+            lane_ranges[m * kWave] = make_uint2(beg, end);
+            ++m;
+            total += end - beg;
           }
         }
       }
     }
-    inl = bd <= a.r2f;
-    if (WRITE) {
-      const uint32_t oi = a.sperm[i];
-      a.idx_out[oi] = inl ? (int32_t)bo : -1;
-      a.d2_out[oi] = inl ? bd : INFINITY;
-    }
   }
+  if (m == 0) return;
+  uint2 e = lane_ranges[0];
+  uint32_t pos = e.x, end = e.y;
+  int slot = 0;
+  for (uint32_t k = 0; k < total; ++k) {
+    if (pos == end) {
+      ++slot;
+      e = lane_ranges[slot * kWave];
+      pos = e.x;
+      end = e.y;
+    }
+    const float4 p = a.tp[pos];
+    const float dx = q32x - p.x, dy = q32y - p.y, dz = q32z - p.z;
+    float d2 = dx * dx + dy * dy;
+    d2 = d2 + dz * dz;
+    const uint64_t key = ((uint64_t)__float_as_uint(d2) << 32) | (uint64_t)__float_as_uint(p.w);
+    if (key < best) {
+      best = key;
+      bj = pos;
+    }
+    ++pos;
+  }
+}
 
+// Per-wave LDS region: during the search it holds the lanes' candidate ranges
+// ([slot][lane] uint2), during the reduction the transposed terms
+// ([value][lane] float, or [value][lane] double for half of the values).
+template <int R>
+struct WaveScratch {
+  static constexpr int kRangeWords = (2 * R + 1) * (2 * R + 1) * kWave * 2;
+  static constexpr int kTermWords = 28 * kWave;
+  static constexpr int kWords = kRangeWords > kTermWords ? kRangeWords : kTermWords;
+};
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One pass over a tile of kRounds * kBlock queries per block: correspondence,
+// per-correspondence J^T J / J^T r terms, and their sum.  Reduction: each
+// round, every lane writes its 28 terms to the wave's LDS region transposed
+// ([term][lane]); lane L (< 56) then adds the 32 entries (L & 1) * 32.. of term
+// L >> 1 into its own running sum (float32 Kahan, or float64).  After the last
+// round the two halves and the block's waves are merged in a fixed order and
+// one float64 partial per term is written, so results do not depend on timing.
+template <int VAR, int PREC, bool WRITE, int R>
+__global__ __launch_bounds__(kBlock) void pass_kernel(PassArgs a) {
+  if (a.st->done) return;
+  __shared__ __align__(16) uint32_t scratch[kBlock / kWave][WaveScratch<R>::kWords];
   __shared__ float red_s[kBlock / kWave][kNumSums];
   __shared__ float red_c[kBlock / kWave][kNumSums];
   __shared__ double red_d[kBlock / kWave][kNumSums];
-  __shared__ int red_n[kBlock / kWave];
+  __shared__ uint32_t red_n[kBlock / kWave];
+  double T[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) T[k] = a.st->T[k];
   const int w = threadIdx.x / kWave, lane = lane_id();
-  int cnt = inl ? 1 : 0;
-  cnt = wave_sum_xor(cnt);
+  uint32_t* ws = scratch[w];
+  uint2* lane_ranges = reinterpret_cast<uint2*>(ws) + lane;
+  float* xf = reinterpret_cast<float*>(ws);
+  double* xd = reinterpret_cast<double*>(ws);
 
-  if (PREC == 0) {
-    float v[28];
-    if (inl) {
-      const double rx = q64x - (double)bp.x, ry = q64y - (double)bp.y, rz = q64z - (double)bp.z;
-      const float fx = (float)rx, fy = (float)ry, fz = (float)rz;
-      float4 n = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (VAR == 1) n = a.tn[bj];
-      record_terms<VAR, float>(q32x, q32y, q32z, fx, fy, fz, n.x, n.y, n.z, v);
-      float d2 = fx * fx + fy * fy;
-      v[27] = d2 + fz * fz;
+  // running sums owned by this lane
+  float acc_s = 0.f, acc_c = 0.f;   // float32 Kahan: term lane>>1, half lane&1
+  double acc_d0 = 0.0, acc_d1 = 0.0; // float64: terms lane>>2 and 14 + (lane>>2), quarter lane&3
+  uint32_t cnt = 0;
+
+  const int64_t tile = (int64_t)blockIdx.x * (kRounds * kBlock);
+  for (int round = 0; round < kRounds; ++round) {
+    const int64_t i = tile + round * kBlock + threadIdx.x;
+    bool inl = false;
+    float4 bp = make_float4(0.f, 0.f, 0.f, 0.f);
+    uint32_t bj = 0xffffffffu;
+    double q64x = 0.0, q64y = 0.0, q64z = 0.0;
+    float q32x = 0.f, q32y = 0.f, q32z = 0.f;
+    if (i < a.n_src) {
+      const double sx = a.sx[i], sy = a.sy[i], sz = a.sz[i];
+      double t;
+      t = T[0] * sx; t = t + T[1] * sy; t = t + T[2] * sz; q64x = t + T[3];
+      t = T[4] * sx; t = t + T[5] * sy; t = t + T[6] * sz; q64y = t + T[7];
+      t = T[8] * sx; t = t + T[9] * sy; t = t + T[10] * sz; q64z = t + T[11];
+      q32x = (float)q64x; q32y = (float)q64y; q32z = (float)q64z;
+      uint64_t best = ~0ull;
+      if (a.jprev) {
+        // warm start: the previous pass's match bounds this pass's distance
+        const uint32_t jp = a.jprev[i];
+        if (jp < (uint32_t)a.n_tgt) {
+          const float4 p = a.tp[jp];
+          const float dx = q32x - p.x, dy = q32y - p.y, dz = q32z - p.z;
+          float d2 = dx * dx + dy * dy;
+          d2 = d2 + dz * dz;
+          if (d2 <= a.r2f) {
+            best = ((uint64_t)__float_as_uint(d2) << 32) | (uint64_t)__float_as_uint(p.w);
+            bj = jp;
+          }
+        }
+      }
+      find_nearest<R>(a, q32x, q32y, q32z, lane_ranges, best, bj);
+      const float bd = __uint_as_float((uint32_t)(best >> 32));
+      const uint32_t bo = (uint32_t)best;
+      inl = best != ~0ull && bd <= a.r2f;
+      if (inl) bp = a.tp[bj];
+      if (a.jprev) a.jprev[i] = inl ? bj : 0xffffffffu;
+      if (WRITE) {
+        const uint32_t oi = a.sperm[i];
+        a.idx_out[oi] = inl ? (int32_t)bo : -1;
+        a.d2_out[oi] = inl ? bd : INFINITY;
+      }
+    }
+    cnt += (uint32_t)__popcll(__ballot(inl));
+    wave_sync();  // the search's LDS ranges are dead from here on
+
+    if (PREC == 0) {
+      float v[28];
+      if (inl) {
+        const double rx = q64x - (double)bp.x, ry = q64y - (double)bp.y, rz = q64z - (double)bp.z;
+        const float fx = (float)rx, fy = (float)ry, fz = (float)rz;
+        float4 n = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (VAR == 1) n = a.tn[bj];
+        record_terms<VAR, float>(q32x, q32y, q32z, fx, fy, fz, n.x, n.y, n.z, v);
+        const float d2 = fx * fx + fy * fy;
+        v[27] = d2 + fz * fz;
+      } else {
+#pragma unroll
+        for (int k = 0; k < 28; ++k) v[k] = 0.0f;
+      }
+#pragma unroll
+      for (int k = 0; k < 28; ++k) xf[k * kWave + lane] = v[k];
+      wave_sync();
+      if (lane < 56) {
+        const float4* src = reinterpret_cast<const float4*>(xf + (lane >> 1) * kWave + (lane & 1) * 32);
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          const float4 x4 = src[m];
+          const float xs[4] = {x4.x, x4.y, x4.z, x4.w};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float y = xs[e] - acc_c;
+            const float t = acc_s + y;
+            acc_c = (t - acc_s) - y;
+            acc_s = t;
+          }
+        }
+      }
+      wave_sync();
     } else {
 #pragma unroll
-      for (int k = 0; k < 28; ++k) v[k] = 0.0f;
-    }
-    float c[28];
+      for (int half = 0; half < 2; ++half) {
+        double v[28];
+        if (inl) {
+          const double px = bp.x, py = bp.y, pz = bp.z;
+          const double rx = q64x - px, ry = q64y - py, rz = q64z - pz;
+          double nx = 0.0, ny = 0.0, nz = 0.0;
+          if (VAR == 1) {
+            const float4 n = a.tn[bj];
+            nx = n.x; ny = n.y; nz = n.z;
+          }
+          record_terms<VAR, double>(q64x, q64y, q64z, rx, ry, rz, nx, ny, nz, v);
+          v[27] = (rx * rx + ry * ry) + rz * rz;
+        } else {
 #pragma unroll
-    for (int k = 0; k < 28; ++k) c[k] = 0.0f;
+          for (int k = 0; k < 28; ++k) v[k] = 0.0;
+        }
 #pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) {
+        for (int k = 0; k < 14; ++k) xd[k * kWave + lane] = v[14 * half + k];
+        wave_sync();
+        if (lane < 56) {
+          const double2* src = reinterpret_cast<const double2*>(xd + (lane >> 2) * kWave + (lane & 3) * 16);
+          double sacc = 0.0;
 #pragma unroll
-      for (int k = 0; k < 28; ++k) {
-        const float so = __shfl_xor(v[k], off, kWave);
-        const float co = __shfl_xor(c[k], off, kWave);
-        float s, e;
-        two_sum(v[k], so, s, e);
-        v[k] = s;
-        c[k] = (c[k] + co) + e;
+          for (int m = 0; m < 8; ++m) {
+            const double2 x2 = src[m];
+            sacc = sacc + x2.x;
+            sacc = sacc + x2.y;
+          }
+          if (half == 0) acc_d0 = acc_d0 + sacc; else acc_d1 = acc_d1 + sacc;
+        }
+        wave_sync();
       }
     }
-    if (lane == 0) {
-#pragma unroll
-      for (int k = 0; k < 28; ++k) {
-        red_s[w][k] = v[k];
-        red_c[w][k] = c[k];
-      }
-      red_n[w] = cnt;
-    }
-    __syncthreads();
-    if (threadIdx.x < 28) {
-      const int k = threadIdx.x;
-      float s = red_s[0][k], cc = red_c[0][k];
-      for (int ww = 1; ww < kBlock / kWave; ++ww) {
-        float t2, e;
-        two_sum(s, red_s[ww][k], t2, e);
-        s = t2;
-        cc = (cc + red_c[ww][k]) + e;
-      }
-      a.part[(int64_t)k * a.n_blocks + blockIdx.x] = (double)s + (double)cc;
-    } else if (threadIdx.x == 28) {
-      int nn = 0;
-      for (int ww = 0; ww < kBlock / kWave; ++ww) nn += red_n[ww];
-      a.part[(int64_t)28 * a.n_blocks + blockIdx.x] = (double)nn;
+  }
+
+  // merge within the wave, then across the block's waves, in a fixed order
+  if (PREC == 0) {
+    const float so = __shfl_xor(acc_s, 1, kWave);
+    const float co = __shfl_xor(acc_c, 1, kWave);
+    float s2, e;
+    two_sum(acc_s, so, s2, e);
+    const float c2 = (acc_c + co) + e;
+    if (lane < 56 && (lane & 1) == 0) {
+      red_s[w][lane >> 1] = s2;
+      red_c[w][lane >> 1] = c2;
     }
   } else {
-    double v[28];
-    if (inl) {
-      const double px = bp.x, py = bp.y, pz = bp.z;
-      const double rx = q64x - px, ry = q64y - py, rz = q64z - pz;
-      double nx = 0.0, ny = 0.0, nz = 0.0;
-      if (VAR == 1) {
-        const float4 n = a.tn[bj];
-        nx = n.x; ny = n.y; nz = n.z;
+    double d0 = acc_d0 + __shfl_xor(acc_d0, 1, kWave);
+    double d1 = acc_d1 + __shfl_xor(acc_d1, 1, kWave);
+    d0 = d0 + __shfl_xor(d0, 2, kWave);
+    d1 = d1 + __shfl_xor(d1, 2, kWave);
+    if (lane < 56 && (lane & 3) == 0) {
+      red_d[w][lane >> 2] = d0;
+      red_d[w][14 + (lane >> 2)] = d1;
+    }
+  }
+  if (lane == 0) red_n[w] = cnt;
+  __syncthreads();
+  if (threadIdx.x < 28) {
+    const int k = threadIdx.x;
+    double out;
+    if (PREC == 0) {
+      float S = red_s[0][k], C = red_c[0][k];
+      for (int ww = 1; ww < kBlock / kWave; ++ww) {
+        float t2, e;
+        two_sum(S, red_s[ww][k], t2, e);
+        S = t2;
+        C = (C + red_c[ww][k]) + e;
       }
-      record_terms<VAR, double>(q64x, q64y, q64z, rx, ry, rz, nx, ny, nz, v);
-      v[27] = (rx * rx + ry * ry) + rz * rz;
+      out = (double)S + (double)C;
     } else {
-#pragma unroll
-      for (int k = 0; k < 28; ++k) v[k] = 0.0;
+      out = red_d[0][k];
+      for (int ww = 1; ww < kBlock / kWave; ++ww) out = out + red_d[ww][k];
     }
-#pragma unroll
-    for (int k = 0; k < 28; ++k) v[k] = wave_sum_xor(v[k]);
-    if (lane == 0) {
-#pragma unroll
-      for (int k = 0; k < 28; ++k) red_d[w][k] = v[k];
-      red_n[w] = cnt;
-    }
-    __syncthreads();
-    if (threadIdx.x < 28) {
-      const int k = threadIdx.x;
-      double s = red_d[0][k];
-      for (int ww = 1; ww < kBlock / kWave; ++ww) s = s + red_d[ww][k];
-      a.part[(int64_t)k * a.n_blocks + blockIdx.x] = s;
-    } else if (threadIdx.x == 28) {
-      int nn = 0;
-      for (int ww = 0; ww < kBlock / kWave; ++ww) nn += red_n[ww];
-      a.part[(int64_t)28 * a.n_blocks + blockIdx.x] = (double)nn;
-    }
+    a.part[(int64_t)k * a.n_blocks + blockIdx.x] = out;
+  } else if (threadIdx.x == 28) {
+    uint32_t nn = 0;
+    for (int ww = 0; ww < kBlock / kWave; ++ww) nn += red_n[ww];
+    a.part[(int64_t)28 * a.n_blocks + blockIdx.x] = (double)nn;
   }
 }
 
@@ -638,14 +788,26 @@ __global__ __launch_bounds__(1024) void solve_kernel(SolveArgs a) {
   IterState* st = a.st;
   if (st->done) return;
   __shared__ double sums[kNumSums];
-  const int w = threadIdx.x / kWave, lane = lane_id();
-  for (int v = w; v < kNumSums; v += 1024 / kWave) {
+  // term v = t / 32 is summed by 32 threads (half a wave), each over the block
+  // partials g, g + 32, ... in order, then by a fixed shuffle tree
+  const int t = threadIdx.x, v = t >> 5, g = t & 31;
+  double acc = 0.0;
+  if (v < kNumSums) {
     const double* p = a.part + (int64_t)v * a.n_blocks;
-    double acc = 0.0;
-    for (int b = lane; b < a.n_blocks; b += kWave) acc += p[b];
-    acc = wave_sum_xor(acc);
-    if (lane == 0) sums[v] = acc;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int b = g;
+    for (; b + 96 < a.n_blocks; b += 128) {
+      a0 = a0 + p[b];
+      a1 = a1 + p[b + 32];
+      a2 = a2 + p[b + 64];
+      a3 = a3 + p[b + 96];
+    }
+    for (; b < a.n_blocks; b += 32) a0 = a0 + p[b];
+    acc = (a0 + a1) + (a2 + a3);
   }
+#pragma unroll
+  for (int off = 16; off > 0; off >>= 1) acc = acc + __shfl_xor(acc, off, kWave);
+  if (v < kNumSums && g == 0) sums[v] = acc;
   __syncthreads();
   if (threadIdx.x != 0) return;
   const double n = sums[kSumCount];
@@ -785,9 +947,10 @@ hipError_t launch_state_init(IterState* st, const double T[16], hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_pass(const PassArgs& a, int variant, int precision, bool write_corr, hipStream_t s) {
+template <int R>
+void launch_pass_r(const PassArgs& a, int variant, int precision, bool write_corr, hipStream_t s) {
   const dim3 grid((unsigned)a.n_blocks), block(kBlock);
-#define ICP_PASS(V, P, W) hipLaunchKernelGGL((pass_kernel<V, P, W>), grid, block, 0, s, a)
+#define ICP_PASS(V, P, W) hipLaunchKernelGGL((pass_kernel<V, P, W, R>), grid, block, 0, s, a)
   if (write_corr) {
     if (variant == 1) { if (precision == 0) ICP_PASS(1, 0, true); else ICP_PASS(1, 1, true); }
     else { if (precision == 0) ICP_PASS(0, 0, true); else ICP_PASS(0, 1, true); }
@@ -796,6 +959,13 @@ hipError_t launch_pass(const PassArgs& a, int variant, int precision, bool write
     else { if (precision == 0) ICP_PASS(0, 0, false); else ICP_PASS(0, 1, false); }
   }
 #undef ICP_PASS
+}
+
+hipError_t launch_pass(const PassArgs& a, int variant, int precision, bool write_corr, hipStream_t s) {
+  if (a.g.sub == 2)
+    launch_pass_r<2>(a, variant, precision, write_corr, s);
+  else
+    launch_pass_r<1>(a, variant, precision, write_corr, s);
   return hipGetLastError();
 }
 

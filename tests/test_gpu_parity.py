@@ -89,10 +89,12 @@ def _small_T(rng, deg=2.0, t=0.01):
     return T
 
 
+@pytest.mark.parametrize("sub", ["1", "2"])
 @pytest.mark.parametrize("scale", ["1", "1.5", "2", "3.7"])
-def test_correspondences_c1_grid_invariant(icp, oracle_lib, c1, scale, monkeypatch):
-    """Same matches for any cell edge >= r (1 + 2^-10), bit-exact vs the oracle."""
+def test_correspondences_c1_grid_invariant(icp, oracle_lib, c1, scale, sub, monkeypatch):
+    """Same matches for any cell edge >= r (1 + 2^-10) / sub, bit-exact vs the oracle."""
     monkeypatch.setenv("ICP_GRID_SCALE", scale)
+    monkeypatch.setenv("ICP_GRID_SUB", sub)
     rng = np.random.default_rng(1)
     s, t = dev(c1["src"]), dev(c1["tgt"])
     for T in (np.eye(4), c1["T_gt"], _small_T(rng) @ c1["T_gt"]):
@@ -235,6 +237,21 @@ def test_identical_clouds_converge_to_identity(icp, c1):
         g = icp.register(t, t, n, np.eye(4), 0.05, 30, 0.0, "point_to_plane", prec)
         np.testing.assert_array_equal(g.T, np.eye(4))
         assert g.fitness == 1.0 and g.inlier_rmse == 0.0 and g.n_iter == 1 and g.status == 1
+
+
+def test_grid_resolution_does_not_change_results(icp, monkeypatch):
+    """Registration (with warm-started, pruned search) is bitwise the same for
+    both neighbourhood sizes and several cell edges."""
+    d = synth.room_pair(2, 60000, 50000, 4.0, 3.0, 2.5, 8, 4, overlap=0.7)
+    s, t, n = dev(d["src"]), dev(d["tgt"]), dev(d["tgt_normals"])
+    out = []
+    for sub, scale in (("1", "1"), ("2", "1"), ("1", "2.5"), ("2", "1.7")):
+        monkeypatch.setenv("ICP_GRID_SUB", sub)
+        monkeypatch.setenv("ICP_GRID_SCALE", scale)
+        out.append(icp.register(s, t, n, np.eye(4), 0.03, 20))
+    for r in out[1:]:
+        np.testing.assert_array_equal(r.T, out[0].T)
+        assert r.n_inliers == out[0].n_inliers and r.inlier_rmse == out[0].inlier_rmse
 
 
 def test_deterministic_bitwise(icp, c1):

@@ -60,18 +60,91 @@ def load_traffic(workload: str, variant: str, n_src: int):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(data, variant, passes):
+def cpu_baseline(data, variant, passes, min_seconds=10.0):
+    """The oracle (FP64, k-d tree, OpenMP over all host threads) on the same
+    pair: the first `passes` passes of the registration, repeated until at
+    least `min_seconds` of wall time have been spent."""
+    import numpy as np
+
     import oracle
     oracle.build(force=False)
+    executed, runs = 0, 0
     t = time.perf_counter()
-    r = oracle.icp_register(data["src"], data["tgt"], data["tgt_normals"], __import__("numpy").eye(4),
-                            data["max_corr_dist"], passes - 1, 0.0, variant=variant)
-    dt = time.perf_counter() - t
-    executed = r.n_iter + 1
+    while True:
+        r = oracle.icp_register(data["src"], data["tgt"], data["tgt_normals"], np.eye(4),
+                                data["max_corr_dist"], passes - 1, 0.0, variant=variant)
+        executed += r.n_iter + 1
+        runs += 1
+        dt = time.perf_counter() - t
+        if dt >= min_seconds:
+            break
     return {"value": executed * len(data["src"]) / dt, "unit": "corr-evals/s",
             "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"same pair, first {executed} passes (max_iter={passes - 1}), FP64 oracle with "
-                      f"k-d tree, {dt:.1f} s wall incl. tree build"}
+            "sample": f"same pair, first {passes} passes (max_iter={passes - 1}) run {runs}x, FP64 oracle "
+                      f"with k-d tree, {dt:.1f} s wall incl. tree builds"}
+
+
+def batched_section(args, icp, synth, np, torch, oracle_sample=8):
+    """C4: 256 independent pairs, sizes log-uniform in [2k, 200k], one batched
+    call vs the same pairs through the plain per-pair call."""
+    print("bench: generating 256 batched pairs", file=sys.stderr, flush=True)
+    data = [synth.c4_pair(p) for p in range(args.batch_pairs)]
+    dev = torch.device("cuda:0")
+    tens = [(torch.from_numpy(d["src"]).to(dev), torch.from_numpy(d["tgt"]).to(dev),
+             torch.from_numpy(d["tgt_normals"]).to(dev)) for d in data]
+    torch.cuda.synchronize()
+    ctx = icp.Context(0)
+    out = {"workload": f"{len(data)} room pairs (6x4x3 m), sizes log-uniform in [2k, 200k], overlap "
+                       "U(0.5, 0.9), r = max(3 cm, 2 sqrt(A/N)), point-to-plane, 30 iterations, "
+                       "rel_tol 1e-6",
+           "pairs": len(data), "points_src_total": int(sum(len(d["src"]) for d in data))}
+    for prec in ("kahan32", "f64"):
+        descs = [icp.make_pair(*t, np.eye(4), d["max_corr_dist"], d["max_iter"], d["rel_tol"])
+                 for t, d in zip(tens, data)]
+        icp.register_batch(descs, "point_to_plane", prec, ctx=ctx)  # warm-up
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(args.batch_reps):
+            t0 = time.perf_counter()
+            res = icp.register_batch(descs, "point_to_plane", prec, ctx=ctx)
+            times.append(time.perf_counter() - t0)
+        tb = float(np.median(times))
+        evals = sum((r.n_iter + 1) * len(d["src"]) for r, d in zip(res, data))
+        # plain per-pair calls, same pairs, one after another
+        for t, d in list(zip(tens, data))[:4]:
+            icp.register(*t, np.eye(4), d["max_corr_dist"], d["max_iter"], d["rel_tol"],
+                         "point_to_plane", prec, ctx=ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plain = [icp.register(*t, np.eye(4), d["max_corr_dist"], d["max_iter"], d["rel_tol"],
+                              "point_to_plane", prec, ctx=ctx) for t, d in zip(tens, data)]
+        tp = time.perf_counter() - t0
+        same = all(np.array_equal(a.T, b.T) and a.n_iter == b.n_iter for a, b in zip(res, plain))
+        entry = {"batched_ms": tb * 1e3, "batched_pairs_per_s": len(data) / tb,
+                 "batched_corr_evals_per_s": evals / tb, "plain_ms": tp * 1e3,
+                 "plain_pairs_per_s": len(data) / tp, "speedup": tp / tb,
+                 "batched_equals_plain_bitwise": bool(same)}
+        if oracle_sample:
+            import oracle
+            oracle.build(force=False)
+            errs = []
+            idx = sorted(range(len(data)), key=lambda k: len(data[k]["src"]))[::len(data) // oracle_sample][:oracle_sample]
+            for k in idx:
+                d = data[k]
+                o = oracle.icp_register(d["src"], d["tgt"], d["tgt_normals"], np.eye(4), d["max_corr_dist"],
+                                        d["max_iter"], d["rel_tol"])
+                g = res[k]
+                dR = np.linalg.norm(g.T[:3, :3] - o.T[:3, :3])
+                ang = 2 * np.arcsin(min(1.0, dR / (2 * np.sqrt(2))))
+                errs.append({"pair": k, "n": len(d["src"]), "rot_rad": float(ang),
+                             "trans_m": float(np.linalg.norm(g.T[:3, 3] - o.T[:3, 3])),
+                             "rmse_diff": g.inlier_rmse - o.inlier_rmse,
+                             "n_iter": [g.n_iter, o.n_iter], "n_in": [g.n_inliers, o.n_inliers]})
+            entry["pose_error_vs_oracle_sample"] = errs
+        out[prec] = entry
+        print(f"bench: batched {prec}: {tb*1e3:.1f} ms vs plain {tp*1e3:.1f} ms", file=sys.stderr, flush=True)
+    ctx.close()
+    return out
 
 
 def main():
@@ -84,6 +157,9 @@ def main():
     ap.add_argument("--precision", default="kahan32", choices=["kahan32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-passes", type=int, default=6)
+    ap.add_argument("--no-batched", action="store_true", help="skip the 256-pair batched section")
+    ap.add_argument("--batch-pairs", type=int, default=256)
+    ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -182,6 +258,9 @@ def main():
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(data, args.variant, args.cpu_passes)
+    if not args.no_batched:
+        del s, t, n
+        out["batched"] = batched_section(args, icp, synth, np, torch)
     print(json.dumps(out), flush=True)
 
 

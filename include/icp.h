@@ -151,6 +151,34 @@ int icp_normal_equations(icp_ctx_t *ctx, const float *src_xyz, int64_t n_src, co
                          double max_corr_dist, int32_t variant, int32_t precision,
                          double AtA21[21], double Atb6[6], double *sum_d2, int64_t *n_in);
 
+/* ---- batched form -------------------------------------------------------- */
+typedef struct {
+  const float *src_xyz;      /* device (n_src, 3) float32 */
+  const float *tgt_xyz;      /* device (n_tgt, 3) float32 */
+  const float *tgt_normals;  /* device (n_tgt, 3) float32; required for point-to-plane */
+  int64_t n_src;
+  int64_t n_tgt;
+  double T_init[16];         /* row-major initial pose */
+  double max_corr_dist;      /* as icp_register */
+  double rel_tol;            /* as icp_register */
+  int32_t max_iter;          /* as icp_register */
+  int32_t reserved;          /* must be 0 */
+} icp_pair_t;
+
+/* Registers n_pairs independent pairs together (Sec. 3.3 ICP refinement, as
+ * many fragment pairs are registered in the reconstruction pipeline of
+ * Sec. 3.4).  Every pair runs exactly the per-pair computation of
+ * icp_register (same stopping rules, its own max_corr_dist / max_iter /
+ * rel_tol), but one launch per iteration covers the source tiles of all pairs
+ * still running, and one launch solves all pairs' systems.  A pair's result is
+ * independent of the other pairs in the batch (bitwise).
+ *   pairs  host array of n_pairs descriptors (device point pointers)
+ *   out    host array of n_pairs results
+ * All pairs share `variant` and `precision`.  Errors: as icp_register; on any
+ * error no result is written; icp_last_error() names the offending pair. */
+int icp_register_batch(icp_ctx_t *ctx, const icp_pair_t *pairs, int32_t n_pairs, int32_t variant,
+                       int32_t precision, icp_result_t *out);
+
 /* ---- kernel timing (measurement support) --------------------------------
  * With profiling enabled, every registration call on the context records a
  * pair of HIP events around each launch of the fused correspondence /

@@ -90,6 +90,7 @@ struct icp_ctx {
   Buf t_key, t_rank, t_cs, t_tp, t_tn, scan_tmp;
   Buf s_keys, s_vals, s_keys2, s_vals2, s_hist, s_x, s_y, s_z;
   Buf part, state, jprev;
+  Buf batch;  // persistent per-pair data of icp_register_batch
   void* host = nullptr;  // pinned readback area
   size_t host_cap = 0;
   // kernel timing
@@ -134,7 +135,7 @@ void ctx_free(icp_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   Buf* bufs[] = {&c->bbox_part, &c->bbox_out, &c->t_key, &c->t_rank, &c->t_cs, &c->t_tp,
                  &c->t_tn, &c->scan_tmp, &c->s_keys, &c->s_vals, &c->s_keys2, &c->s_vals2,
-                 &c->s_hist, &c->s_x, &c->s_y, &c->s_z, &c->part, &c->state, &c->jprev};
+                 &c->s_hist, &c->s_x, &c->s_y, &c->s_z, &c->part, &c->state, &c->jprev, &c->batch};
   for (Buf* b : bufs) b->release();
   if (c->host) (void)hipHostFree(c->host);
   c->host = nullptr;
@@ -278,82 +279,161 @@ GridDesc make_grid(const float* mn, const float* mx, double r, int64_t n_tgt) {
   return g;  // unreachable for finite inputs
 }
 
-int prepare(icp_ctx* c, const float* src, int64_t n_src, const float* tgt, const float* tgt_n,
-            int64_t n_tgt, double r, bool with_normals, Prepared* P) {
+int ensure_host(icp_ctx* c, size_t bytes) {
+  if (bytes <= c->host_cap) return ICP_SUCCESS;
+  HIP_TRY(hipStreamSynchronize(c->stream), "sync");
+  if (c->host) (void)hipHostFree(c->host);
+  c->host = nullptr;
+  c->host_cap = 0;
+  const size_t want = std::max(bytes + bytes / 4, kHostBytes);
+  HIP_TRY(hipHostMalloc(&c->host, want, hipHostMallocDefault), "hipHostMalloc");
+  c->host_cap = want;
+  return ICP_SUCCESS;
+}
+
+struct CloudBox {
+  float tmn[3], tmx[3], smn[3], smx[3];
+};
+
+// Finiteness check and bounding boxes of n pairs: all reductions are launched,
+// then read back with a single synchronisation.  `which` receives the first
+// pair with a non-finite value.
+int bboxes(icp_ctx* c, int n, const float* const* src, const int64_t* n_src,
+           const float* const* tgt, const float* const* tgt_n, const int64_t* n_tgt, CloudBox* out,
+           int* which) {
   hipStream_t s = c->stream;
-  const int nb_t = bbox_blocks(n_tgt), nb_s = bbox_blocks(n_src);
-  HIP_TRY(c->bbox_part.ensure(sizeof(float) * 8 * (size_t)(nb_t + nb_s)), "alloc");
-  HIP_TRY(c->bbox_out.ensure(sizeof(float) * 16), "alloc");
+  size_t blocks = 0;
+  for (int p = 0; p < n; ++p) blocks += (size_t)bbox_blocks(n_tgt[p]) + (size_t)bbox_blocks(n_src[p]);
+  HIP_TRY(c->bbox_part.ensure(sizeof(float) * 8 * blocks), "alloc");
+  HIP_TRY(c->bbox_out.ensure(sizeof(float) * 16 * (size_t)n), "alloc");
+  int rc;
+  if ((rc = ensure_host(c, sizeof(float) * 16 * (size_t)n)) != 0) return rc;
   float* bp = c->bbox_part.as<float>();
   float* bo = c->bbox_out.as<float>();
-  HIP_TRY(launch_bbox(tgt, with_normals ? tgt_n : nullptr, n_tgt, bp, nb_t, bo, s), "bbox");
-  HIP_TRY(launch_bbox(src, nullptr, n_src, bp + 8 * nb_t, nb_s, bo + 8, s), "bbox");
+  for (int p = 0; p < n; ++p) {
+    const int nb_t = bbox_blocks(n_tgt[p]), nb_s = bbox_blocks(n_src[p]);
+    HIP_TRY(launch_bbox(tgt[p], tgt_n[p], n_tgt[p], bp, nb_t, bo + 16 * p, s), "bbox");
+    bp += 8 * nb_t;
+    HIP_TRY(launch_bbox(src[p], nullptr, n_src[p], bp, nb_s, bo + 16 * p + 8, s), "bbox");
+    bp += 8 * nb_s;
+  }
   float* hb = static_cast<float*>(c->host);
-  HIP_TRY(hipMemcpyAsync(hb, bo, sizeof(float) * 16, hipMemcpyDeviceToHost, s), "readback");
+  HIP_TRY(hipMemcpyAsync(hb, bo, sizeof(float) * 16 * (size_t)n, hipMemcpyDeviceToHost, s), "readback");
   HIP_TRY(hipStreamSynchronize(s), "sync");
-  if (hb[6] != 0.0f || hb[14] != 0.0f)
-    return fail(ICP_E_NONFINITE, hb[6] != 0.0f ? "non-finite target coordinate or normal"
-                                               : "non-finite source coordinate");
-  float tmn[3] = {hb[0], hb[1], hb[2]}, tmx[3] = {hb[3], hb[4], hb[5]};
-  float smn[3] = {hb[8], hb[9], hb[10]}, smx[3] = {hb[11], hb[12], hb[13]};
+  for (int p = 0; p < n; ++p) {
+    const float* h = hb + 16 * p;
+    if (h[6] != 0.0f || h[14] != 0.0f) {
+      *which = p;
+      return fail(ICP_E_NONFINITE, (h[6] != 0.0f ? std::string("non-finite target coordinate or normal")
+                                                 : std::string("non-finite source coordinate")) +
+                                       (n > 1 ? " in pair " + std::to_string(p) : std::string()));
+    }
+    for (int k = 0; k < 3; ++k) {
+      out[p].tmn[k] = h[k];
+      out[p].tmx[k] = h[3 + k];
+      out[p].smn[k] = h[8 + k];
+      out[p].smx[k] = h[11 + k];
+    }
+  }
+  return ICP_SUCCESS;
+}
 
-  const GridDesc g = make_grid(tmn, tmx, r, n_tgt);
-  // target grid
-  const int64_t scan_cap = scan_block_sums_needed((int64_t)g.ncell + 1);
+// Transient build buffers, shared by every pair built on the context's stream
+// (the stream orders their reuse).
+int ensure_scratch(icp_ctx* c, int64_t n_src, int64_t n_tgt, uint64_t ncell) {
   HIP_TRY(c->t_key.ensure(4 * (size_t)n_tgt), "alloc");
   HIP_TRY(c->t_rank.ensure(4 * (size_t)n_tgt), "alloc");
-  HIP_TRY(c->t_cs.ensure(4 * ((size_t)g.ncell + 1)), "alloc");
-  HIP_TRY(c->t_tp.ensure(16 * (size_t)n_tgt), "alloc");
-  if (with_normals) HIP_TRY(c->t_tn.ensure(16 * (size_t)n_tgt), "alloc");
-  HIP_TRY(c->scan_tmp.ensure(4 * (size_t)scan_cap), "alloc");
-  HIP_TRY(launch_target_grid(tgt, with_normals ? tgt_n : nullptr, n_tgt, g, c->t_key.as<uint32_t>(),
-                             c->t_rank.as<uint32_t>(), c->t_cs.as<uint32_t>(), c->t_tp.as<float4>(),
-                             with_normals ? c->t_tn.as<float4>() : nullptr,
-                             c->scan_tmp.as<uint32_t>(), scan_cap, s),
-          "target grid");
-  // source order: Morton curve over 1024^3 cells spanning the source box.  It
-  // depends on the source cloud only, so the summation order (and hence every
-  // result bit) does not change with the grid's cell size.
-  double ext = 0.0;
-  for (int a = 0; a < 3; ++a) ext = std::max(ext, (double)smx[a] - (double)smn[a]);
-  const double hs = ext > 0.0 ? ext / 1023.5 : 1.0;
-  const int64_t hist_cap = radix_hist_needed(n_src);
+  HIP_TRY(c->scan_tmp.ensure(4 * (size_t)scan_block_sums_needed((int64_t)ncell + 1)), "alloc");
   HIP_TRY(c->s_keys.ensure(4 * (size_t)n_src), "alloc");
   HIP_TRY(c->s_vals.ensure(4 * (size_t)n_src), "alloc");
   HIP_TRY(c->s_keys2.ensure(4 * (size_t)n_src), "alloc");
   HIP_TRY(c->s_vals2.ensure(4 * (size_t)n_src), "alloc");
-  HIP_TRY(c->s_hist.ensure(4 * (size_t)hist_cap), "alloc");
-  HIP_TRY(c->s_x.ensure(4 * (size_t)n_src), "alloc");
-  HIP_TRY(c->s_y.ensure(4 * (size_t)n_src), "alloc");
-  HIP_TRY(c->s_z.ensure(4 * (size_t)n_src), "alloc");
-  uint32_t* perm = nullptr;
-  HIP_TRY(launch_source_order(src, n_src, smn[0], smn[1], smn[2], 1.0 / hs, c->s_keys.as<uint32_t>(),
-                              c->s_vals.as<uint32_t>(), c->s_keys2.as<uint32_t>(),
-                              c->s_vals2.as<uint32_t>(), c->s_hist.as<uint32_t>(), hist_cap,
-                              c->s_x.as<float>(), c->s_y.as<float>(), c->s_z.as<float>(), &perm, s),
-          "source order");
-  const int32_t n_blocks = (int32_t)((n_src + kTile - 1) / kTile);
-  HIP_TRY(c->part.ensure(sizeof(double) * kNumSums * (size_t)n_blocks), "alloc");
-  HIP_TRY(c->state.ensure(sizeof(IterState)), "alloc");
+  HIP_TRY(c->s_hist.ensure(4 * (size_t)radix_hist_needed(n_src)), "alloc");
+  return ICP_SUCCESS;
+}
 
-  PassArgs& a = P->pa;
+struct PairDst {
+  uint32_t* cs;
+  float4* tp;
+  float4* tn;  // may be null (point-to-point)
+  float* sx;
+  float* sy;
+  float* sz;
+};
+
+// Builds the target grid (cell table + cell-ordered target) and the
+// Morton-ordered source of one pair into `d`.  *perm_out (transient, valid
+// until the next build) maps ordered source positions to original indices.
+int build_pair(icp_ctx* c, const float* src, int64_t n_src, const float* tgt, const float* tgt_n,
+               int64_t n_tgt, const GridDesc& g, const CloudBox& b, const PairDst& d,
+               uint32_t** perm_out) {
+  hipStream_t s = c->stream;
+  const int64_t scan_cap = scan_block_sums_needed((int64_t)g.ncell + 1);
+  HIP_TRY(launch_target_grid(tgt, d.tn ? tgt_n : nullptr, n_tgt, g, c->t_key.as<uint32_t>(),
+                             c->t_rank.as<uint32_t>(), d.cs, d.tp, d.tn, c->scan_tmp.as<uint32_t>(),
+                             scan_cap, s),
+          "target grid");
+  // Morton curve over 1024^3 cells spanning the source box.  It depends on the
+  // source cloud only, so the summation order (and every result bit) does not
+  // change with the grid's cell size.
+  double ext = 0.0;
+  for (int a = 0; a < 3; ++a) ext = std::max(ext, (double)b.smx[a] - (double)b.smn[a]);
+  const double hs = ext > 0.0 ? ext / 1023.5 : 1.0;
+  HIP_TRY(launch_source_order(src, n_src, b.smn[0], b.smn[1], b.smn[2], 1.0 / hs,
+                              c->s_keys.as<uint32_t>(), c->s_vals.as<uint32_t>(),
+                              c->s_keys2.as<uint32_t>(), c->s_vals2.as<uint32_t>(),
+                              c->s_hist.as<uint32_t>(), radix_hist_needed(n_src), d.sx, d.sy, d.sz,
+                              perm_out, s),
+          "source order");
+  return ICP_SUCCESS;
+}
+
+void fill_pass_args(PassArgs& a, const PairDst& d, const uint32_t* perm, int64_t n_src,
+                    int64_t n_tgt, const GridDesc& g, double r, IterState* st, double* part,
+                    uint32_t* jprev) {
   memset(&a, 0, sizeof a);
-  a.sx = c->s_x.as<float>();
-  a.sy = c->s_y.as<float>();
-  a.sz = c->s_z.as<float>();
+  a.sx = d.sx;
+  a.sy = d.sy;
+  a.sz = d.sz;
   a.sperm = perm;
   a.n_src = (int32_t)n_src;
-  a.tp = c->t_tp.as<float4>();
-  a.tn = with_normals ? c->t_tn.as<float4>() : nullptr;
-  a.cs = c->t_cs.as<uint32_t>();
+  a.tp = d.tp;
+  a.tn = d.tn;
+  a.cs = d.cs;
   a.g = g;
   a.r2f = (float)(r * r);
   a.inv_h2 = (float)(g.inv_h * g.inv_h);
   a.n_tgt = (int32_t)n_tgt;
-  a.jprev = nullptr;
-  a.st = c->state.as<IterState>();
-  a.part = c->part.as<double>();
-  a.n_blocks = n_blocks;
+  a.jprev = jprev;
+  a.st = st;
+  a.part = part;
+  a.n_blocks = (int32_t)((n_src + kTile - 1) / kTile);
+}
+
+int prepare(icp_ctx* c, const float* src, int64_t n_src, const float* tgt, const float* tgt_n,
+            int64_t n_tgt, double r, bool with_normals, Prepared* P) {
+  CloudBox b;
+  int which = -1, rc;
+  const float* tn = with_normals ? tgt_n : nullptr;
+  if ((rc = bboxes(c, 1, &src, &n_src, &tgt, &tn, &n_tgt, &b, &which)) != 0) return rc;
+  const GridDesc g = make_grid(b.tmn, b.tmx, r, n_tgt);
+  if ((rc = ensure_scratch(c, n_src, n_tgt, g.ncell)) != 0) return rc;
+  HIP_TRY(c->t_cs.ensure(4 * ((size_t)g.ncell + 1)), "alloc");
+  HIP_TRY(c->t_tp.ensure(16 * (size_t)n_tgt), "alloc");
+  if (with_normals) HIP_TRY(c->t_tn.ensure(16 * (size_t)n_tgt), "alloc");
+  HIP_TRY(c->s_x.ensure(4 * (size_t)n_src), "alloc");
+  HIP_TRY(c->s_y.ensure(4 * (size_t)n_src), "alloc");
+  HIP_TRY(c->s_z.ensure(4 * (size_t)n_src), "alloc");
+  const PairDst d{c->t_cs.as<uint32_t>(), c->t_tp.as<float4>(),
+                  with_normals ? c->t_tn.as<float4>() : nullptr, c->s_x.as<float>(),
+                  c->s_y.as<float>(), c->s_z.as<float>()};
+  uint32_t* perm = nullptr;
+  if ((rc = build_pair(c, src, n_src, tgt, tgt_n, n_tgt, g, b, d, &perm)) != 0) return rc;
+  const int32_t n_blocks = (int32_t)((n_src + kTile - 1) / kTile);
+  HIP_TRY(c->part.ensure(sizeof(double) * kNumSums * (size_t)n_blocks), "alloc");
+  HIP_TRY(c->state.ensure(sizeof(IterState)), "alloc");
+  fill_pass_args(P->pa, d, perm, n_src, n_tgt, g, r, c->state.as<IterState>(), c->part.as<double>(),
+                 nullptr);
   P->n_src = n_src;
   return ICP_SUCCESS;
 }
@@ -493,6 +573,160 @@ int icp_register(icp_ctx_t* ctx, const float* src_xyz, int64_t n_src, const floa
   out->n_inliers = st.n_in;
   out->n_iter = st.k;
   out->status = st.status;
+  return ICP_SUCCESS;
+}
+
+int icp_register_batch(icp_ctx_t* ctx, const icp_pair_t* pairs, int32_t n_pairs, int32_t variant,
+                       int32_t precision, icp_result_t* out) {
+  if (!pairs || !out) return fail(ICP_E_INVALID_ARG, "pairs / out is NULL");
+  if (n_pairs < 1) return fail(ICP_E_INVALID_ARG, "n_pairs must be >= 1");
+  int rc;
+  int64_t total_src = 0, total_tgt = 0;
+  int32_t iters = 0;
+  for (int p = 0; p < n_pairs; ++p) {
+    const icp_pair_t& q = pairs[p];
+    if ((rc = check_common(q.src_xyz, q.n_src, q.tgt_xyz, q.tgt_normals, q.n_tgt, q.T_init,
+                           q.max_corr_dist, variant, precision, true)) != 0 ||
+        (q.max_iter < 0 && (rc = fail(ICP_E_INVALID_ARG, "max_iter must be >= 0")) != 0) ||
+        ((!(q.rel_tol >= 0.0) || !std::isfinite(q.rel_tol)) &&
+         (rc = fail(ICP_E_INVALID_ARG, "rel_tol must be finite and >= 0")) != 0) ||
+        (q.reserved != 0 && (rc = fail(ICP_E_INVALID_ARG, "reserved must be 0")) != 0)) {
+      g_last_error += " (pair " + std::to_string(p) + ")";
+      return rc;
+    }
+    total_src += q.n_src;
+    total_tgt += q.n_tgt;
+    iters = std::max(iters, q.max_iter);
+  }
+  if (total_src > (int64_t)INT32_MAX || total_tgt > (int64_t)INT32_MAX)
+    return fail(ICP_E_TOO_LARGE, "more than 2^31-1 points in one batch");
+  icp_ctx* c = nullptr;
+  if ((rc = resolve_ctx(ctx, &c)) != 0) return rc;
+  DeviceGuard dg(c->device);
+  const bool plane = variant == ICP_POINT_TO_PLANE;
+  const int n = n_pairs;
+
+  std::vector<const float*> srcs(n), tgts(n), tns(n);
+  std::vector<int64_t> ns(n), nt(n);
+  for (int p = 0; p < n; ++p) {
+    srcs[p] = pairs[p].src_xyz;
+    tgts[p] = pairs[p].tgt_xyz;
+    tns[p] = plane ? pairs[p].tgt_normals : nullptr;
+    ns[p] = pairs[p].n_src;
+    nt[p] = pairs[p].n_tgt;
+  }
+  std::vector<CloudBox> box(n);
+  int which = -1;
+  if ((rc = bboxes(c, n, srcs.data(), ns.data(), tgts.data(), tns.data(), nt.data(), box.data(),
+                   &which)) != 0)
+    return rc;
+
+  // layout of the batch region: header (pass args, solve args, states, work
+  // items) first, then every pair's persistent arrays
+  std::vector<GridDesc> grid(n);
+  int64_t n_items = 0, max_src = 0, max_tgt = 0;
+  uint64_t max_cell = 0;
+  for (int p = 0; p < n; ++p) {
+    grid[p] = make_grid(box[p].tmn, box[p].tmx, pairs[p].max_corr_dist, nt[p]);
+    n_items += (ns[p] + kTile - 1) / kTile;
+    max_src = std::max(max_src, ns[p]);
+    max_tgt = std::max(max_tgt, nt[p]);
+    max_cell = std::max<uint64_t>(max_cell, grid[p].ncell);
+  }
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = (off + 255) & ~(size_t)255;
+    off = o + bytes;
+    return o;
+  };
+  const size_t o_pargs = take(sizeof(PassArgs) * n);
+  const size_t o_sargs = take(sizeof(SolveArgs) * n);
+  const size_t o_states = take(sizeof(IterState) * n);
+  const size_t o_items = take(sizeof(uint2) * (size_t)n_items);
+  const size_t header = off;
+  const size_t o_jprev = take(4 * (size_t)total_src);
+  struct Offs { size_t cs, tp, tn, sx, sy, sz, part; };
+  std::vector<Offs> po(n);
+  for (int p = 0; p < n; ++p) {
+    po[p].cs = take(4 * ((size_t)grid[p].ncell + 1));
+    po[p].tp = take(16 * (size_t)nt[p]);
+    po[p].tn = plane ? take(16 * (size_t)nt[p]) : 0;
+    po[p].sx = take(4 * (size_t)ns[p]);
+    po[p].sy = take(4 * (size_t)ns[p]);
+    po[p].sz = take(4 * (size_t)ns[p]);
+    po[p].part = take(sizeof(double) * kNumSums * (size_t)((ns[p] + kTile - 1) / kTile));
+  }
+  HIP_TRY(c->batch.ensure(off), "alloc");
+  if ((rc = ensure_scratch(c, max_src, max_tgt, max_cell)) != 0) return rc;
+  if ((rc = ensure_host(c, std::max(header, sizeof(IterState) * n))) != 0) return rc;
+  char* base = c->batch.as<char>();
+
+  char* hh = static_cast<char*>(c->host);
+  PassArgs* hp = reinterpret_cast<PassArgs*>(hh + o_pargs);
+  SolveArgs* hs = reinterpret_cast<SolveArgs*>(hh + o_sargs);
+  IterState* hst = reinterpret_cast<IterState*>(hh + o_states);
+  uint2* hit = reinterpret_cast<uint2*>(hh + o_items);
+  IterState* dst_states = reinterpret_cast<IterState*>(base + o_states);
+  uint32_t* jprev = reinterpret_cast<uint32_t*>(base + o_jprev);
+  int64_t item = 0, src_off = 0;
+  for (int p = 0; p < n; ++p) {
+    const PairDst d{reinterpret_cast<uint32_t*>(base + po[p].cs), reinterpret_cast<float4*>(base + po[p].tp),
+                    plane ? reinterpret_cast<float4*>(base + po[p].tn) : nullptr,
+                    reinterpret_cast<float*>(base + po[p].sx), reinterpret_cast<float*>(base + po[p].sy),
+                    reinterpret_cast<float*>(base + po[p].sz)};
+    uint32_t* perm = nullptr;
+    if ((rc = build_pair(c, srcs[p], ns[p], tgts[p], pairs[p].tgt_normals, nt[p], grid[p], box[p], d,
+                         &perm)) != 0)
+      return rc;
+    double* part = reinterpret_cast<double*>(base + po[p].part);
+    fill_pass_args(hp[p], d, nullptr, ns[p], nt[p], grid[p], pairs[p].max_corr_dist, dst_states + p,
+                   part, jprev + src_off);
+    hs[p] = SolveArgs{part, hp[p].n_blocks, dst_states + p, ns[p], pairs[p].max_iter,
+                      pairs[p].rel_tol, 0};
+    IterState& st = hst[p];
+    memset(&st, 0, sizeof st);
+    for (int k = 0; k < 16; ++k) st.T[k] = pairs[p].T_init[k];
+    for (int t = 0; t < hp[p].n_blocks; ++t) hit[item++] = make_uint2((uint32_t)p, (uint32_t)t);
+    src_off += ns[p];
+  }
+  HIP_TRY(hipMemsetAsync(jprev, 0xff, 4 * (size_t)total_src, c->stream), "memset");
+  HIP_TRY(hipMemcpyAsync(base, hh, header, hipMemcpyHostToDevice, c->stream), "upload");
+  const PassArgs* dp = reinterpret_cast<const PassArgs*>(base + o_pargs);
+  const SolveArgs* ds = reinterpret_cast<const SolveArgs*>(base + o_sargs);
+  const uint2* di = reinterpret_cast<const uint2*>(base + o_items);
+  const int sub = grid[0].sub;
+  const bool prof = c->profiling;
+  if (prof && (rc = ensure_events(c, iters + 1)) != 0) return rc;
+  if (prof) HIP_TRY(hipEventRecord(c->ev[0], c->stream), "hipEventRecord");
+  for (int32_t k = 0; k <= iters; ++k) {
+    if (prof) HIP_TRY(hipEventRecord(c->ev[2 + 2 * k], c->stream), "hipEventRecord");
+    HIP_TRY(launch_batch_pass(dp, di, (int)n_items, sub, variant, precision, c->stream), "pass");
+    if (prof) HIP_TRY(hipEventRecord(c->ev[3 + 2 * k], c->stream), "hipEventRecord");
+    HIP_TRY(launch_batch_solve(ds, n, c->stream), "solve");
+  }
+  if (prof) HIP_TRY(hipEventRecord(c->ev[1], c->stream), "hipEventRecord");
+  HIP_TRY(hipMemcpyAsync(hh, dst_states, sizeof(IterState) * n, hipMemcpyDeviceToHost, c->stream),
+          "readback");
+  HIP_TRY(hipStreamSynchronize(c->stream), "sync");
+  const IterState* res = reinterpret_cast<const IterState*>(hh);
+  int32_t max_k = 0;
+  int64_t evals = 0;
+  for (int p = 0; p < n; ++p) {
+    const IterState& st = res[p];
+    for (int k = 0; k < 12; ++k) out[p].T[k] = st.T[k];
+    out[p].T[12] = 0.0; out[p].T[13] = 0.0; out[p].T[14] = 0.0; out[p].T[15] = 1.0;
+    out[p].fitness = st.fitness;
+    out[p].inlier_rmse = st.rmse;
+    out[p].n_inliers = st.n_in;
+    out[p].n_iter = st.k;
+    out[p].status = st.status;
+    max_k = std::max(max_k, st.k);
+    evals += (int64_t)(st.k + 1) * ns[p];
+  }
+  if (prof) {
+    if ((rc = collect_profile(c, max_k + 1, 0)) != 0) return rc;
+    c->prof.pass_points += evals;
+  }
   return ICP_SUCCESS;
 }
 

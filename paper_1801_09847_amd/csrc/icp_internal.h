@@ -98,4 +98,9 @@ hipError_t launch_state_init(IterState* st, const double T[16], hipStream_t s);
 hipError_t launch_pass(const PassArgs& a, int variant, int precision, bool write_corr, hipStream_t s);
 hipError_t launch_solve(const SolveArgs& a, hipStream_t s);
 
+// Batched forms: `pairs` / `items` / `arr` are device arrays.
+hipError_t launch_batch_pass(const PassArgs* pairs, const uint2* items, int n_items, int sub,
+                             int variant, int precision, hipStream_t s);
+hipError_t launch_batch_solve(const SolveArgs* arr, int n_pairs, hipStream_t s);
+
 }  // namespace icp

@@ -513,8 +513,7 @@ __device__ inline void wave_sync() {
 // round the two halves and the block's waves are merged in a fixed order and
 // one float64 partial per term is written, so results do not depend on timing.
 template <int VAR, int PREC, bool WRITE, int R>
-__global__ __launch_bounds__(kBlock) void pass_kernel(PassArgs a) {
-  if (a.st->done) return;
+__device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
   __shared__ __align__(16) uint32_t scratch[kBlock / kWave][WaveScratch<R>::kWords];
   __shared__ float red_s[kBlock / kWave][kNumSums];
   __shared__ float red_c[kBlock / kWave][kNumSums];
@@ -534,7 +533,7 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(PassArgs a) {
   double acc_d0 = 0.0, acc_d1 = 0.0; // float64: terms lane>>2 and 14 + (lane>>2), quarter lane&3
   uint32_t cnt = 0;
 
-  const int64_t tile = (int64_t)blockIdx.x * (kRounds * kBlock);
+  const int64_t tile = (int64_t)tile_index * (kRounds * kBlock);
   for (int round = 0; round < kRounds; ++round) {
     const int64_t i = tile + round * kBlock + threadIdx.x;
     bool inl = false;
@@ -688,12 +687,30 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(PassArgs a) {
       out = red_d[0][k];
       for (int ww = 1; ww < kBlock / kWave; ++ww) out = out + red_d[ww][k];
     }
-    a.part[(int64_t)k * a.n_blocks + blockIdx.x] = out;
+    a.part[(int64_t)k * a.n_blocks + tile_index] = out;
   } else if (threadIdx.x == 28) {
     uint32_t nn = 0;
     for (int ww = 0; ww < kBlock / kWave; ++ww) nn += red_n[ww];
-    a.part[(int64_t)28 * a.n_blocks + blockIdx.x] = (double)nn;
+    a.part[(int64_t)28 * a.n_blocks + tile_index] = (double)nn;
   }
+}
+
+template <int VAR, int PREC, bool WRITE, int R>
+__global__ __launch_bounds__(kBlock) void pass_kernel(PassArgs a) {
+  if (a.st->done) return;
+  pass_tile<VAR, PREC, WRITE, R>(a, blockIdx.x);
+}
+
+// Batched form: block b handles tile items[b].y of pair items[b].x.  Tiles and
+// their partial slots are the same as when the pair is registered alone, so a
+// pair's result does not depend on the rest of the batch.
+template <int VAR, int PREC, int R>
+__global__ __launch_bounds__(kBlock) void batch_pass_kernel(const PassArgs* __restrict__ pairs,
+                                                            const uint2* __restrict__ items) {
+  const uint2 it = items[blockIdx.x];
+  const PassArgs& a = pairs[it.x];
+  if (a.st->done) return;
+  pass_tile<VAR, PREC, false, R>(a, it.y);
 }
 
 // ------------------------------------------------------------------ solve + pose update
@@ -784,7 +801,7 @@ __device__ void apply_exp(const double* xi, double* T) {
   for (int k = 0; k < 12; ++k) T[k] = N[k];
 }
 
-__global__ __launch_bounds__(1024) void solve_kernel(SolveArgs a) {
+__device__ void solve_body(const SolveArgs& a) {
   IterState* st = a.st;
   if (st->done) return;
   __shared__ double sums[kNumSums];
@@ -852,6 +869,13 @@ __global__ __launch_bounds__(1024) void solve_kernel(SolveArgs a) {
     st->e_prev = ek;
     st->k = k + 1;
   }
+}
+
+__global__ __launch_bounds__(1024) void solve_kernel(SolveArgs a) { solve_body(a); }
+
+// Batched form: block p reduces, solves and updates pair p.
+__global__ __launch_bounds__(1024) void batch_solve_kernel(const SolveArgs* __restrict__ arr) {
+  solve_body(arr[blockIdx.x]);
 }
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -971,6 +995,32 @@ hipError_t launch_pass(const PassArgs& a, int variant, int precision, bool write
 
 hipError_t launch_solve(const SolveArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(solve_kernel, dim3(1), dim3(1024), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int R>
+void launch_batch_pass_r(const PassArgs* pairs, const uint2* items, int n_items, int variant,
+                         int precision, hipStream_t s) {
+  const dim3 grid((unsigned)n_items), block(kBlock);
+#define ICP_BPASS(V, P) hipLaunchKernelGGL((batch_pass_kernel<V, P, R>), grid, block, 0, s, pairs, items)
+  if (variant == 1) { if (precision == 0) ICP_BPASS(1, 0); else ICP_BPASS(1, 1); }
+  else { if (precision == 0) ICP_BPASS(0, 0); else ICP_BPASS(0, 1); }
+#undef ICP_BPASS
+}
+
+hipError_t launch_batch_pass(const PassArgs* pairs, const uint2* items, int n_items, int sub,
+                             int variant, int precision, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  if (sub == 2)
+    launch_batch_pass_r<2>(pairs, items, n_items, variant, precision, s);
+  else
+    launch_batch_pass_r<1>(pairs, items, n_items, variant, precision, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_solve(const SolveArgs* arr, int n_pairs, hipStream_t s) {
+  if (n_pairs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_solve_kernel, dim3((unsigned)n_pairs), dim3(1024), 0, s, arr);
   return hipGetLastError();
 }
 

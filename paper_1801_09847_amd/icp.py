@@ -50,6 +50,13 @@ class icp_result_t(C.Structure):
                 ("n_inliers", C.c_int64), ("n_iter", C.c_int32), ("status", C.c_int32)]
 
 
+class icp_pair_t(C.Structure):
+    _fields_ = [("src_xyz", C.c_void_p), ("tgt_xyz", C.c_void_p), ("tgt_normals", C.c_void_p),
+                ("n_src", C.c_int64), ("n_tgt", C.c_int64), ("T_init", C.c_double * 16),
+                ("max_corr_dist", C.c_double), ("rel_tol", C.c_double), ("max_iter", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
 class icp_profile_t(C.Structure):
     _fields_ = [("pass_ms", C.c_double), ("pass_launches", C.c_int64), ("pass_points", C.c_int64),
                 ("call_ms", C.c_double), ("calls", C.c_int64)]
@@ -78,10 +85,13 @@ def lib():
         L.icp_correspondences.argtypes = [vp, vp, i64, vp, vp, i64, dbl, vp, vp]
         L.icp_normal_equations.argtypes = [vp, vp, i64, vp, vp, vp, i64, dbl, i32, i32, vp, vp,
                                            C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.icp_register_batch.argtypes = [vp, C.POINTER(icp_pair_t), i32, i32, i32,
+                                         C.POINTER(icp_result_t)]
         L.icp_ctx_set_profiling.argtypes = [vp, C.c_int]
         L.icp_ctx_get_profile.argtypes = [vp, C.POINTER(icp_profile_t)]
         for name in ("icp_ctx_create", "icp_ctx_destroy", "icp_register", "icp_correspondences",
-                     "icp_normal_equations", "icp_ctx_set_profiling", "icp_ctx_get_profile"):
+                     "icp_normal_equations", "icp_ctx_set_profiling", "icp_ctx_get_profile",
+                     "icp_register_batch"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -121,6 +131,15 @@ def icp_register(ctx, src_ptr, n_src, tgt_ptr, tgt_n_ptr, n_tgt, T_init, max_cor
                               T.ctypes.data, float(max_corr_dist), int(max_iter), float(rel_tol),
                               int(variant), int(precision), C.byref(out)))
     return out
+
+
+def icp_register_batch(ctx, pairs, variant, precision):
+    """pairs: sequence of icp_pair_t; returns a list of icp_result_t."""
+    n = len(pairs)
+    arr = (icp_pair_t * n)(*pairs)
+    out = (icp_result_t * n)()
+    _check(lib().icp_register_batch(ctx, arr, n, int(variant), int(precision), out))
+    return list(out)
 
 
 def icp_correspondences(ctx, src_ptr, n_src, T, tgt_ptr, n_tgt, max_corr_dist, idx_ptr, d2_ptr):
@@ -208,6 +227,32 @@ def register(src, tgt, tgt_normals, T_init, max_corr_dist, max_iter=30, rel_tol=
                      max_iter, rel_tol, VARIANTS[variant], PRECISIONS[precision])
     return IcpResult(np.array(r.T[:], dtype=np.float64).reshape(4, 4), r.fitness, r.inlier_rmse,
                      r.n_inliers, r.n_iter, r.status)
+
+
+def make_pair(src, tgt, tgt_normals, T_init, max_corr_dist, max_iter=30, rel_tol=0.0) -> icp_pair_t:
+    """Descriptor of one pair for register_batch (tensors must stay alive)."""
+    sp, ns = _dev_pts(src, "src")
+    tp, nt = _dev_pts(tgt, "tgt")
+    npn = None
+    if tgt_normals is not None:
+        npn, nn = _dev_pts(tgt_normals, "tgt_normals")
+        if nn != nt:
+            raise IcpError(ICP_E_INVALID_ARG, "tgt_normals must have as many rows as tgt")
+    p = icp_pair_t()
+    p.src_xyz, p.tgt_xyz, p.tgt_normals = sp, tp, npn
+    p.n_src, p.n_tgt = ns, nt
+    p.T_init[:] = [float(x) for x in _pose(T_init)]
+    p.max_corr_dist, p.rel_tol, p.max_iter, p.reserved = float(max_corr_dist), float(rel_tol), int(max_iter), 0
+    return p
+
+
+def register_batch(pairs, variant="point_to_plane", precision="kahan32",
+                   ctx: Context | None = None) -> list[IcpResult]:
+    """pairs: list of icp_pair_t (see make_pair)."""
+    res = icp_register_batch(ctx.handle if ctx else None, pairs, VARIANTS[variant],
+                             PRECISIONS[precision])
+    return [IcpResult(np.array(r.T[:], dtype=np.float64).reshape(4, 4), r.fitness, r.inlier_rmse,
+                      r.n_inliers, r.n_iter, r.status) for r in res]
 
 
 def correspondences(src, T, tgt, max_corr_dist, ctx: Context | None = None):

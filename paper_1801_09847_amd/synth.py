@@ -223,6 +223,100 @@ def room_surface(scene: dict, rng: np.random.Generator, h: float = 0.01):
     return np.concatenate(pts), np.concatenate(nrm)
 
 
+def _rect_random(rng, m, axis, value, lo, hi, sign):
+    a1, a2 = [k for k in range(3) if k != axis]
+    p = np.empty((m, 3))
+    p[:, axis] = value
+    p[:, a1] = rng.uniform(lo[a1], hi[a1], m)
+    p[:, a2] = rng.uniform(lo[a2], hi[a2], m)
+    n = np.zeros_like(p)
+    n[:, axis] = sign
+    return p, n
+
+
+def room_surface_random(scene: dict, rng: np.random.Generator, n: int):
+    """``n`` points drawn uniformly by area on the visible surfaces of the scene
+    (the limit of subsampling a fine lattice), with exact normals.  Returns the
+    points, normals and the visible area (m^2)."""
+    W, D, H = scene["W"], scene["D"], scene["H"]
+    parts = []  # (area, sampler(m) -> (p, n), skip_box, skip_sph)
+    lo0, hi0 = np.zeros(3), np.array([W, D, H])
+    for axis, (a, b) in enumerate(((0.0, W), (0.0, D), (0.0, H))):
+        others = [k for k in range(3) if k != axis]
+        area = (hi0[others[0]] - lo0[others[0]]) * (hi0[others[1]] - lo0[others[1]])
+        for value, sign in ((a, +1.0), (b, -1.0)):
+            parts.append((area, (axis, value, lo0, hi0, sign), -1, -1))
+    for bi, (lo, hi) in enumerate(scene["boxes"]):
+        for axis in range(3):
+            others = [k for k in range(3) if k != axis]
+            area = (hi[others[0]] - lo[others[0]]) * (hi[others[1]] - lo[others[1]])
+            for value, sign in ((lo[axis], -1.0), (hi[axis], +1.0)):
+                if axis == 2 and sign < 0:
+                    continue
+                parts.append((area, (axis, value, lo, hi, sign), bi, -1))
+    for si, (c, r) in enumerate(scene["spheres"]):
+        parts.append((4.0 * math.pi * r * r, (c, r), -1, si))
+    areas = np.array([p[0] for p in parts])
+    total = areas.sum()
+    pts, nrm, kept_area = [], [], 0.0
+    want = int(n * 1.3) + 64
+    counts = rng.multinomial(want, areas / total)
+    for (area, prm, sb, ss), m in zip(parts, counts):
+        if m == 0:
+            continue
+        if ss >= 0:
+            c, r = prm
+            d = rng.normal(size=(m, 3))
+            d /= np.linalg.norm(d, axis=1, keepdims=True)
+            p, q = c + r * d, d
+        else:
+            p, q = _rect_random(rng, m, *prm)
+        keep = ~_inside_any(p, scene, skip_box=sb, skip_sph=ss)
+        kept_area += area * keep.mean()
+        pts.append(p[keep]); nrm.append(q[keep])
+    pts, nrm = np.concatenate(pts), np.concatenate(nrm)
+    if len(pts) < n:  # rare: top up with a second round
+        p2, n2, _ = room_surface_random(scene, rng, n - len(pts))
+        pts, nrm = np.concatenate([pts, p2]), np.concatenate([nrm, n2])
+    sel = rng.permutation(len(pts))[:n]
+    return pts[sel], nrm[sel], kept_area
+
+
+def room_pair_random(seed: int, n_tgt: int, n_src: int, W: float = 6.0, D: float = 4.0,
+                     H: float = 3.0, n_box: int = 20, n_sph: int = 10, overlap: float = 0.7,
+                     noise: float = 0.002, max_deg: float = 10.0, max_trans: float = 0.10) -> dict:
+    """Same scene, crop, noise and motion recipe as ``room_pair``, with the
+    surfaces sampled uniformly at random by area instead of through a 1 cm
+    lattice and a subsample (equivalent in distribution, O(N) cost)."""
+    scene = room_scene(seed, W, D, H, n_box, n_sph)
+    rt, rs, rm = _rng(seed, "tgt"), _rng(seed, "src"), _rng(seed, "motion")
+    tp, tn, area = room_surface_random(scene, rt, n_tgt)
+    tp = tp + rt.normal(0.0, noise, tp.shape)
+    from_low = bool(rm.integers(0, 2))
+    xs = np.sort(tp[:, 0])
+    k = min(len(xs) - 1, max(0, int(round(overlap * len(xs))) - 1))
+    cut = xs[k] if from_low else xs[len(xs) - 1 - k]
+    # draw the source from the slab: sample generously, crop, trim
+    sp, sn = np.empty((0, 3)), np.empty((0, 3))
+    want = n_src
+    while len(sp) < n_src:
+        p, q, _ = room_surface_random(scene, rs, int(want / max(overlap, 0.05) * 1.2) + 64)
+        keep = p[:, 0] <= cut if from_low else p[:, 0] >= cut
+        sp, sn = np.concatenate([sp, p[keep]]), np.concatenate([sn, q[keep]])
+        want = n_src - len(sp) + 64
+    sp, sn = sp[:n_src], sn[:n_src]
+    sp = sp + rs.normal(0.0, noise, sp.shape)
+    G = random_motion(rm, max_deg, max_trans, sp.mean(axis=0))
+    src = apply(G, sp)
+    return {
+        "src": _f32(src), "tgt": _f32(tp), "tgt_normals": _f32(tn),
+        "src_normals": _f32(sn @ G[:3, :3].T), "G": G, "T_gt": np.linalg.inv(G),
+        "area": float(area),
+        "meta": {"kind": "room-random", "seed": seed, "W": W, "D": D, "H": H, "n_box": n_box,
+                 "n_sph": n_sph, "overlap": overlap, "from_low": from_low, "cut": float(cut)},
+    }
+
+
 def room_pair(seed: int = 0, n_tgt: int = 300_000, n_src: int = 300_000,
               W: float = 6.0, D: float = 4.0, H: float = 3.0, n_box: int = 20,
               n_sph: int = 10, overlap: float = 0.7, noise: float = 0.002,
@@ -310,7 +404,7 @@ def c4_pair(p: int, lo: float = 2e3, hi: float = 2e5) -> dict:
     rng = _rng(seed, "c4-size")
     n = loguniform_size(rng, lo, hi)
     o = rng.uniform(0.5, 0.9)
-    d = room_pair(seed, n, n, 6.0, 4.0, 3.0, 20, 10, overlap=o)
+    d = room_pair_random(seed, n, n, 6.0, 4.0, 3.0, 20, 10, overlap=o)
     d.update(max_corr_dist=max(0.03, 2.0 * math.sqrt(d["area"] / len(d["tgt"]))),
              max_iter=30, rel_tol=1e-6, variant="point_to_plane")
     return d
@@ -324,7 +418,7 @@ def c5_request_size(q: int, lo: float = 5e3, hi: float = 5e5):
 
 def c5_request(q: int, lo: float = 5e3, hi: float = 5e5) -> dict:
     n, o = c5_request_size(q, lo, hi)
-    d = room_pair(10_000 + q, n, n, 6.0, 4.0, 3.0, 20, 10, overlap=o)
+    d = room_pair_random(10_000 + q, n, n, 6.0, 4.0, 3.0, 20, 10, overlap=o)
     d.update(rel_tol=1e-6, variant="point_to_plane")
     return d
 

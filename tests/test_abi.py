@@ -109,3 +109,30 @@ def test_product_path_has_no_oracle_or_cpu_fallback():
             continue
         src = open(os.path.join(pkg, "csrc", f)).read()
         assert "oracle" not in src.lower(), f
+
+
+def _pair(**kw):
+    p = icp.icp_pair_t()
+    p.src_xyz, p.tgt_xyz, p.tgt_normals = FAKE, FAKE, FAKE
+    p.n_src, p.n_tgt = 100, 100
+    p.T_init[:] = list(np.eye(4).reshape(16))
+    p.max_corr_dist, p.rel_tol, p.max_iter, p.reserved = 0.05, 0.0, 10, 0
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def test_batch_validation():
+    L = icp.lib()
+    out = (icp.icp_result_t * 4)()
+    arr = (icp.icp_pair_t * 4)(_pair(), _pair(), _pair(), _pair())
+    assert L.icp_register_batch(None, arr, 0, 1, 0, out) == icp.ICP_E_INVALID_ARG
+    assert L.icp_register_batch(None, None, 4, 1, 0, out) == icp.ICP_E_INVALID_ARG
+    assert L.icp_register_batch(None, arr, 4, 1, 0, None) == icp.ICP_E_INVALID_ARG
+    for bad in (dict(reserved=1), dict(max_corr_dist=-1.0), dict(max_iter=-2), dict(n_src=0),
+                dict(tgt_normals=None), dict(rel_tol=float("nan"))):
+        arr = (icp.icp_pair_t * 4)(_pair(), _pair(), _pair(**bad), _pair())
+        assert L.icp_register_batch(None, arr, 4, 1, 0, out) == icp.ICP_E_INVALID_ARG, bad
+        assert "pair 2" in L.icp_last_error().decode()
+    big = (icp.icp_pair_t * 2)(_pair(n_src=2**30 + 10), _pair(n_src=2**30 + 10))
+    assert L.icp_register_batch(None, big, 2, 1, 0, out) == icp.ICP_E_TOO_LARGE

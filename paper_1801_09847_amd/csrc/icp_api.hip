@@ -1,23 +1,24 @@
 // Host runtime of libicp.so: argument validation, contexts and their device
-// workspace, grid construction and the per-iteration launch sequence behind
-// the C ABI declared in include/icp.h.
+// workspace, grid sizing and the per-iteration launch sequence behind the C
+// ABI declared in include/icp.h.
 //
-// One registration is: finiteness check + bounding boxes (one small readback
-// that sizes the grid), target grid build, Morton ordering of the source, then
-// max_iter + 1 passes.  Each pass is two launches on the context's stream: the
-// fused correspondence / residual / block-reduction kernel and a single-block
-// kernel that reduces the block partials in fixed order, solves the 6x6
-// system and updates the pose on the device.  The loop state never leaves the
-// device until the final readback; once a stopping rule fires, the remaining
-// launches return immediately.
+// Every registration call, plain or batched, is:
+//   1. finiteness + bounding boxes of all clouds (one segmented reduction and
+//      one small readback that sizes the grids);
+//   2. segmented build of every pair's target grid and Morton-ordered source
+//      (a fixed number of launches, independent of the number of pairs);
+//   3. max_iter + 1 passes of two launches each: the fused correspondence /
+//      normal-equation kernel over all source tiles, then the kernel that
+//      reduces the tile partials in fixed order, solves the 6x6 system and
+//      updates the pose on the device.  Loop state never leaves the device;
+//      launches after a pair's stopping rule fired return immediately;
+//   4. one readback of the final states.
 
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
-#include <cstdio>
-#include <mutex>
 #include <string>
 #include <vector>
 
@@ -41,10 +42,10 @@ int hip_fail(hipError_t e, const char* what) {
   return fail(code, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define HIP_TRY(expr, what)                    \
-  do {                                         \
-    hipError_t e_ = (expr);                    \
-    if (e_ != hipSuccess) return hip_fail(e_, what); \
+#define HIP_TRY(expr, what)                            \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return hip_fail(e_, what);   \
   } while (0)
 
 // A device buffer that only grows (reused across calls).
@@ -59,7 +60,7 @@ struct Buf {
       cap = 0;
       if (e != hipSuccess) return e;
     }
-    size_t want = std::max<size_t>(bytes + bytes / 8, 256);
+    const size_t want = std::max<size_t>(bytes + bytes / 8, 256);
     hipError_t e = hipMalloc(&p, want);
     if (e != hipSuccess) {
       p = nullptr;
@@ -79,30 +80,31 @@ struct Buf {
   }
 };
 
+constexpr size_t kHostBytes = 4096;
+constexpr int kDefaultSub = 1;
+
 }  // namespace
 
 struct icp_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
-  // workspace
-  Buf bbox_part, bbox_out;
-  Buf t_key, t_rank, t_cs, t_tp, t_tn, scan_tmp;
-  Buf s_keys, s_vals, s_keys2, s_vals2, s_hist, s_x, s_y, s_z;
-  Buf part, state, jprev;
-  Buf batch;  // persistent per-pair data of icp_register_batch
-  void* host = nullptr;  // pinned readback area
+  // per-call descriptors, loop header, warm-start matches, partials, states
+  Buf desc;
+  // preparation scratch
+  Buf bbox_part, t_key, t_rank, scan_tmp, s_hist;
+  Buf sk[6];  // sort buffers: klo[2], khi[2], val[2]
+  // prepared pairs (concatenated)
+  Buf cs, tp, tn, sx, sy, sz, perm;
+  void* host = nullptr;  // pinned staging
   size_t host_cap = 0;
   // kernel timing
   bool profiling = false;
-  std::vector<hipEvent_t> ev;  // 2 per pass + call start/end
+  std::vector<hipEvent_t> ev;  // [0] call start, [1] call end, [2+2k]/[3+2k] around pass k
   icp_profile_t prof{};
 };
 
 namespace {
-
-constexpr size_t kHostBytes = 4096;
-constexpr int kDefaultSub = 1;
 
 struct DeviceGuard {
   int prev = -1;
@@ -133,10 +135,10 @@ int ctx_init(icp_ctx* c, int device, void* stream) {
 void ctx_free(icp_ctx* c) {
   DeviceGuard g(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
-  Buf* bufs[] = {&c->bbox_part, &c->bbox_out, &c->t_key, &c->t_rank, &c->t_cs, &c->t_tp,
-                 &c->t_tn, &c->scan_tmp, &c->s_keys, &c->s_vals, &c->s_keys2, &c->s_vals2,
-                 &c->s_hist, &c->s_x, &c->s_y, &c->s_z, &c->part, &c->state, &c->jprev, &c->batch};
+  Buf* bufs[] = {&c->desc, &c->bbox_part, &c->t_key, &c->t_rank, &c->scan_tmp, &c->s_hist,
+                 &c->cs, &c->tp, &c->tn, &c->sx, &c->sy, &c->sz, &c->perm};
   for (Buf* b : bufs) b->release();
+  for (Buf& b : c->sk) b.release();
   if (c->host) (void)hipHostFree(c->host);
   c->host = nullptr;
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
@@ -181,11 +183,24 @@ int resolve_ctx(icp_ctx* in, icp_ctx** out) {
   return ICP_SUCCESS;
 }
 
+int ensure_host(icp_ctx* c, size_t bytes) {
+  if (bytes <= c->host_cap) return ICP_SUCCESS;
+  HIP_TRY(hipStreamSynchronize(c->stream), "sync");
+  if (c->host) (void)hipHostFree(c->host);
+  c->host = nullptr;
+  c->host_cap = 0;
+  const size_t want = std::max(bytes + bytes / 4, kHostBytes);
+  HIP_TRY(hipHostMalloc(&c->host, want, hipHostMallocDefault), "hipHostMalloc");
+  c->host_cap = want;
+  return ICP_SUCCESS;
+}
+
 // ------------------------------------------------------------------ validation
 int check_cloud(const float* p, int64_t n, const char* name) {
   if (!p) return fail(ICP_E_INVALID_ARG, std::string(name) + " is NULL");
   if (n < 1) return fail(ICP_E_INVALID_ARG, std::string(name) + ": point count must be >= 1");
-  if (n > (int64_t)INT32_MAX) return fail(ICP_E_TOO_LARGE, std::string(name) + ": more than 2^31-1 points");
+  if (n > (int64_t)INT32_MAX)
+    return fail(ICP_E_TOO_LARGE, std::string(name) + ": more than 2^31-1 points");
   if ((reinterpret_cast<uintptr_t>(p) & 3u) != 0)
     return fail(ICP_E_INVALID_ARG, std::string(name) + " is not 4-byte aligned");
   return ICP_SUCCESS;
@@ -228,18 +243,16 @@ int check_common(const float* src, int64_t n_src, const float* tgt, const float*
   return ICP_SUCCESS;
 }
 
-// ------------------------------------------------------------------ pair preparation
-struct Prepared {
-  PassArgs pa;
-  int64_t n_src;
-};
+int check_iteration(int32_t max_iter, double rel_tol) {
+  if (max_iter < 0) return fail(ICP_E_INVALID_ARG, "max_iter must be >= 0");
+  if (!(rel_tol >= 0.0) || !std::isfinite(rel_tol))
+    return fail(ICP_E_INVALID_ARG, "rel_tol must be finite and >= 0");
+  return ICP_SUCCESS;
+}
 
-// Grid over the target: cell edge h >= r (1 + 2^-10) so that every point
-// within r of a query lies in the 27 cells around the query's cell.  The
-// dense table is capped at max(2^24, 32 n_tgt) cells; a larger extent grows h
-// (still exact: any h >= r works, only the candidate count changes).
+// ------------------------------------------------------------------ grids
 // The environment variable ICP_GRID_SCALE (>= 1, debugging and tests only)
-// multiplies h; results must not change with it.
+// multiplies the cell edge; results must not change with it.
 double grid_scale() {
   const char* e = getenv("ICP_GRID_SCALE");
   if (!e) return 1.0;
@@ -256,6 +269,11 @@ int grid_sub() {
   return kDefaultSub;
 }
 
+// Grid over a target box: cell edge h >= r (1 + 2^-10) / sub so that every
+// point within r of a query lies in the (2 sub + 1)^3 cells around the query's
+// cell.  The dense table is capped at max(2^24, 32 n_tgt) cells; a larger
+// extent grows h (still exact: any h above the bound works, only the candidate
+// count changes).
 GridDesc make_grid(const float* mn, const float* mx, double r, int64_t n_tgt) {
   const double cap = std::min<double>(1073741824.0, std::max<double>(16777216.0, 32.0 * (double)n_tgt));
   const int sub = grid_sub();
@@ -279,174 +297,217 @@ GridDesc make_grid(const float* mn, const float* mx, double r, int64_t n_tgt) {
   return g;  // unreachable for finite inputs
 }
 
-int ensure_host(icp_ctx* c, size_t bytes) {
-  if (bytes <= c->host_cap) return ICP_SUCCESS;
-  HIP_TRY(hipStreamSynchronize(c->stream), "sync");
-  if (c->host) (void)hipHostFree(c->host);
-  c->host = nullptr;
-  c->host_cap = 0;
-  const size_t want = std::max(bytes + bytes / 4, kHostBytes);
-  HIP_TRY(hipHostMalloc(&c->host, want, hipHostMallocDefault), "hipHostMalloc");
-  c->host_cap = want;
-  return ICP_SUCCESS;
-}
-
-struct CloudBox {
-  float tmn[3], tmx[3], smn[3], smx[3];
+// ------------------------------------------------------------------ call layout
+struct PairIn {
+  const float* src;
+  int64_t n_src;
+  const float* tgt;
+  const float* tgt_n;  // null: point-to-point (normals neither checked nor gathered)
+  int64_t n_tgt;
+  double r;
 };
 
-// Finiteness check and bounding boxes of n pairs: all reductions are launched,
-// then read back with a single synchronisation.  `which` receives the first
-// pair with a non-finite value.
-int bboxes(icp_ctx* c, int n, const float* const* src, const int64_t* n_src,
-           const float* const* tgt, const float* const* tgt_n, const int64_t* n_tgt, CloudBox* out,
-           int* which) {
+// Byte offsets of one call's descriptors; the same layout is used in pinned
+// host staging and in the context's `desc` device buffer.
+struct Layout {
+  size_t clouds, blk_bbox, pairs, blk_t, blk_s, src_off;  // preparation
+  size_t pargs, sargs, states, items;                       // loop header
+  size_t header_end;                                        // end of uploaded part
+  size_t bbox_out, jprev, part;                             // device only
+  size_t total;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+Layout make_layout(int n, int64_t n_items, int64_t total_src, int64_t total_tiles) {
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = align256(off);
+    off = o + bytes;
+    return o;
+  };
+  L.clouds = take(sizeof(SegCloud) * 2 * n);
+  L.blk_bbox = take(sizeof(int64_t) * (2 * n + 1));
+  L.pairs = take(sizeof(BuildPair) * n);
+  L.blk_t = take(sizeof(int64_t) * (n + 1));
+  L.blk_s = take(sizeof(int64_t) * (n + 1));
+  L.src_off = take(sizeof(int64_t) * (n + 1));
+  L.pargs = take(sizeof(PassArgs) * n);
+  L.sargs = take(sizeof(SolveArgs) * n);
+  L.states = take(sizeof(IterState) * n);
+  L.items = take(sizeof(uint2) * (size_t)std::max<int64_t>(n_items, 1));
+  L.header_end = align256(off);
+  L.bbox_out = take(sizeof(float) * 16 * n);
+  L.jprev = take(sizeof(uint32_t) * (size_t)total_src);
+  L.part = take(sizeof(double) * kNumSums * (size_t)total_tiles);
+  L.total = align256(off);
+  return L;
+}
+
+struct Prep {
+  int n = 0;
+  Layout L;
+  std::vector<GridDesc> g;
+  std::vector<int64_t> src_off, tgt_off, tile_off;
+  std::vector<uint64_t> tab_off;
+  int64_t total_src = 0, total_tgt = 0, total_tiles = 0;
+  uint64_t total_tab = 0;
+  int sub = 1;
+};
+
+int64_t tiles_of(int64_t n) { return (n + kTile - 1) / kTile; }
+
+// Steps 1 and 2 of a call for n pairs: checks, boxes, grids and the
+// segmented build into the context's concatenated arrays.
+int prepare_pairs(icp_ctx* c, int n, const PairIn* in, Prep* P) {
   hipStream_t s = c->stream;
-  size_t blocks = 0;
-  for (int p = 0; p < n; ++p) blocks += (size_t)bbox_blocks(n_tgt[p]) + (size_t)bbox_blocks(n_src[p]);
-  HIP_TRY(c->bbox_part.ensure(sizeof(float) * 8 * blocks), "alloc");
-  HIP_TRY(c->bbox_out.ensure(sizeof(float) * 16 * (size_t)n), "alloc");
-  int rc;
-  if ((rc = ensure_host(c, sizeof(float) * 16 * (size_t)n)) != 0) return rc;
-  float* bp = c->bbox_part.as<float>();
-  float* bo = c->bbox_out.as<float>();
+  P->n = n;
+  P->src_off.assign(n + 1, 0);
+  P->tgt_off.assign(n + 1, 0);
+  P->tile_off.assign(n + 1, 0);
   for (int p = 0; p < n; ++p) {
-    const int nb_t = bbox_blocks(n_tgt[p]), nb_s = bbox_blocks(n_src[p]);
-    HIP_TRY(launch_bbox(tgt[p], tgt_n[p], n_tgt[p], bp, nb_t, bo + 16 * p, s), "bbox");
-    bp += 8 * nb_t;
-    HIP_TRY(launch_bbox(src[p], nullptr, n_src[p], bp, nb_s, bo + 16 * p + 8, s), "bbox");
-    bp += 8 * nb_s;
+    P->src_off[p + 1] = P->src_off[p] + in[p].n_src;
+    P->tgt_off[p + 1] = P->tgt_off[p] + in[p].n_tgt;
+    P->tile_off[p + 1] = P->tile_off[p] + tiles_of(in[p].n_src);
   }
-  float* hb = static_cast<float*>(c->host);
-  HIP_TRY(hipMemcpyAsync(hb, bo, sizeof(float) * 16 * (size_t)n, hipMemcpyDeviceToHost, s), "readback");
+  P->total_src = P->src_off[n];
+  P->total_tgt = P->tgt_off[n];
+  P->total_tiles = P->tile_off[n];
+  if (P->total_src > (int64_t)INT32_MAX || P->total_tgt > (int64_t)INT32_MAX)
+    return fail(ICP_E_TOO_LARGE, "more than 2^31-1 points in one call");
+  P->L = make_layout(n, P->total_tiles, P->total_src, P->total_tiles);
+  const Layout& L = P->L;
+  int rc;
+  if ((rc = ensure_host(c, L.total)) != 0) return rc;
+  HIP_TRY(c->desc.ensure(L.total), "alloc");
+  char* hh = static_cast<char*>(c->host);
+  char* dd = c->desc.as<char>();
+
+  // 1. boxes and finiteness of all clouds (target with its normals, source)
+  SegCloud* cl = reinterpret_cast<SegCloud*>(hh + L.clouds);
+  int64_t* bo = reinterpret_cast<int64_t*>(hh + L.blk_bbox);
+  bo[0] = 0;
+  for (int p = 0; p < n; ++p) {
+    cl[2 * p] = SegCloud{in[p].tgt, in[p].tgt_n, in[p].n_tgt};
+    cl[2 * p + 1] = SegCloud{in[p].src, nullptr, in[p].n_src};
+    bo[2 * p + 1] = bo[2 * p] + bbox_blocks(in[p].n_tgt);
+    bo[2 * p + 2] = bo[2 * p + 1] + bbox_blocks(in[p].n_src);
+  }
+  const int64_t bbox_total = bo[2 * n];
+  HIP_TRY(c->bbox_part.ensure(sizeof(float) * 8 * (size_t)bbox_total), "alloc");
+  HIP_TRY(hipMemcpyAsync(dd, hh, L.pairs, hipMemcpyHostToDevice, s), "upload");
+  float* dbox = reinterpret_cast<float*>(dd + L.bbox_out);
+  HIP_TRY(launch_seg_bbox(reinterpret_cast<SegCloud*>(dd + L.clouds), 2 * n,
+                          reinterpret_cast<int64_t*>(dd + L.blk_bbox), bbox_total,
+                          c->bbox_part.as<float>(), dbox, s),
+          "bbox");
+  float* hbox = reinterpret_cast<float*>(hh + L.bbox_out);
+  HIP_TRY(hipMemcpyAsync(hbox, dbox, sizeof(float) * 16 * n, hipMemcpyDeviceToHost, s), "readback");
   HIP_TRY(hipStreamSynchronize(s), "sync");
   for (int p = 0; p < n; ++p) {
-    const float* h = hb + 16 * p;
-    if (h[6] != 0.0f || h[14] != 0.0f) {
-      *which = p;
-      return fail(ICP_E_NONFINITE, (h[6] != 0.0f ? std::string("non-finite target coordinate or normal")
+    const float* t = hbox + 16 * p;
+    const float* q = t + 8;
+    if (t[6] != 0.0f || q[6] != 0.0f)
+      return fail(ICP_E_NONFINITE, (t[6] != 0.0f ? std::string("non-finite target coordinate or normal")
                                                  : std::string("non-finite source coordinate")) +
                                        (n > 1 ? " in pair " + std::to_string(p) : std::string()));
-    }
-    for (int k = 0; k < 3; ++k) {
-      out[p].tmn[k] = h[k];
-      out[p].tmx[k] = h[3 + k];
-      out[p].smn[k] = h[8 + k];
-      out[p].smx[k] = h[11 + k];
-    }
   }
-  return ICP_SUCCESS;
-}
 
-// Transient build buffers, shared by every pair built on the context's stream
-// (the stream orders their reuse).
-int ensure_scratch(icp_ctx* c, int64_t n_src, int64_t n_tgt, uint64_t ncell) {
-  HIP_TRY(c->t_key.ensure(4 * (size_t)n_tgt), "alloc");
-  HIP_TRY(c->t_rank.ensure(4 * (size_t)n_tgt), "alloc");
-  HIP_TRY(c->scan_tmp.ensure(4 * (size_t)scan_block_sums_needed((int64_t)ncell + 1)), "alloc");
-  HIP_TRY(c->s_keys.ensure(4 * (size_t)n_src), "alloc");
-  HIP_TRY(c->s_vals.ensure(4 * (size_t)n_src), "alloc");
-  HIP_TRY(c->s_keys2.ensure(4 * (size_t)n_src), "alloc");
-  HIP_TRY(c->s_vals2.ensure(4 * (size_t)n_src), "alloc");
-  HIP_TRY(c->s_hist.ensure(4 * (size_t)radix_hist_needed(n_src)), "alloc");
-  return ICP_SUCCESS;
-}
-
-struct PairDst {
-  uint32_t* cs;
-  float4* tp;
-  float4* tn;  // may be null (point-to-point)
-  float* sx;
-  float* sy;
-  float* sz;
-};
-
-// Builds the target grid (cell table + cell-ordered target) and the
-// Morton-ordered source of one pair into `d`.  *perm_out (transient, valid
-// until the next build) maps ordered source positions to original indices.
-int build_pair(icp_ctx* c, const float* src, int64_t n_src, const float* tgt, const float* tgt_n,
-               int64_t n_tgt, const GridDesc& g, const CloudBox& b, const PairDst& d,
-               uint32_t** perm_out) {
-  hipStream_t s = c->stream;
-  const int64_t scan_cap = scan_block_sums_needed((int64_t)g.ncell + 1);
-  HIP_TRY(launch_target_grid(tgt, d.tn ? tgt_n : nullptr, n_tgt, g, c->t_key.as<uint32_t>(),
-                             c->t_rank.as<uint32_t>(), d.cs, d.tp, d.tn, c->scan_tmp.as<uint32_t>(),
-                             scan_cap, s),
+  // 2. grids, offsets and the segmented build
+  P->g.resize(n);
+  P->tab_off.assign(n + 1, 0);
+  BuildPair* bp = reinterpret_cast<BuildPair*>(hh + L.pairs);
+  int64_t* bt = reinterpret_cast<int64_t*>(hh + L.blk_t);
+  int64_t* bs = reinterpret_cast<int64_t*>(hh + L.blk_s);
+  int64_t* so = reinterpret_cast<int64_t*>(hh + L.src_off);
+  bt[0] = 0;
+  bs[0] = 0;
+  for (int p = 0; p < n; ++p) {
+    const float* t = hbox + 16 * p;
+    const float* q = t + 8;
+    P->g[p] = make_grid(t, t + 3, in[p].r, in[p].n_tgt);
+    P->tab_off[p + 1] = P->tab_off[p] + (uint64_t)P->g[p].ncell + 1;
+    double ext = 0.0;
+    for (int a = 0; a < 3; ++a) ext = std::max(ext, (double)q[3 + a] - (double)q[a]);
+    // Morton grid of the source: 1024 cells per axis over the source's own box,
+    // so the order (and the summation order) depends on the source only
+    const double hs = ext > 0.0 ? ext / 1023.5 : 1.0;
+    bp[p] = BuildPair{in[p].src, in[p].tgt, in[p].tgt_n, in[p].n_src, in[p].n_tgt,
+                      P->src_off[p], P->tgt_off[p], P->tab_off[p], P->g[p],
+                      (double)q[0], (double)q[1], (double)q[2], 1.0 / hs};
+    bt[p + 1] = bt[p] + (in[p].n_tgt + 255) / 256;
+    bs[p + 1] = bs[p] + (in[p].n_src + 255) / 256;
+    so[p] = P->src_off[p];
+  }
+  so[n] = P->src_off[n];
+  P->total_tab = P->tab_off[n];
+  if (P->total_tab >= (uint64_t)UINT32_MAX)
+    return fail(ICP_E_TOO_LARGE, "grid tables of one call exceed 2^32 cells");
+  P->sub = P->g[0].sub;
+  const bool normals = in[0].tgt_n != nullptr;
+  const int64_t scan_cap = scan_block_sums_needed((int64_t)P->total_tab);
+  const int64_t hist_cap = radix_hist_needed(P->total_src);
+  HIP_TRY(c->cs.ensure(4 * (size_t)P->total_tab), "alloc");
+  HIP_TRY(c->tp.ensure(16 * (size_t)P->total_tgt), "alloc");
+  if (normals) HIP_TRY(c->tn.ensure(16 * (size_t)P->total_tgt), "alloc");
+  HIP_TRY(c->sx.ensure(4 * (size_t)P->total_src), "alloc");
+  HIP_TRY(c->sy.ensure(4 * (size_t)P->total_src), "alloc");
+  HIP_TRY(c->sz.ensure(4 * (size_t)P->total_src), "alloc");
+  HIP_TRY(c->perm.ensure(4 * (size_t)P->total_src), "alloc");
+  HIP_TRY(c->t_key.ensure(4 * (size_t)P->total_tgt), "alloc");
+  HIP_TRY(c->t_rank.ensure(4 * (size_t)P->total_tgt), "alloc");
+  HIP_TRY(c->scan_tmp.ensure(4 * (size_t)scan_cap), "alloc");
+  HIP_TRY(c->s_hist.ensure(4 * (size_t)hist_cap), "alloc");
+  for (Buf& b : c->sk) HIP_TRY(b.ensure(4 * (size_t)P->total_src), "alloc");
+  HIP_TRY(hipMemcpyAsync(dd + L.pairs, hh + L.pairs, L.pargs - L.pairs, hipMemcpyHostToDevice, s),
+          "upload");
+  const BuildPair* dbp = reinterpret_cast<const BuildPair*>(dd + L.pairs);
+  HIP_TRY(launch_seg_targets(dbp, n, reinterpret_cast<const int64_t*>(dd + L.blk_t), bt[n],
+                             P->total_tab, c->cs.as<uint32_t>(), c->t_key.as<uint32_t>(),
+                             c->t_rank.as<uint32_t>(), c->scan_tmp.as<uint32_t>(), scan_cap,
+                             c->tp.as<float4>(), normals ? c->tn.as<float4>() : nullptr, s),
           "target grid");
-  // Morton curve over 1024^3 cells spanning the source box.  It depends on the
-  // source cloud only, so the summation order (and every result bit) does not
-  // change with the grid's cell size.
-  double ext = 0.0;
-  for (int a = 0; a < 3; ++a) ext = std::max(ext, (double)b.smx[a] - (double)b.smn[a]);
-  const double hs = ext > 0.0 ? ext / 1023.5 : 1.0;
-  HIP_TRY(launch_source_order(src, n_src, b.smn[0], b.smn[1], b.smn[2], 1.0 / hs,
-                              c->s_keys.as<uint32_t>(), c->s_vals.as<uint32_t>(),
-                              c->s_keys2.as<uint32_t>(), c->s_vals2.as<uint32_t>(),
-                              c->s_hist.as<uint32_t>(), radix_hist_needed(n_src), d.sx, d.sy, d.sz,
-                              perm_out, s),
+  SortBufs sb;
+  for (int k = 0; k < 2; ++k) {
+    sb.klo[k] = c->sk[k].as<uint32_t>();
+    sb.khi[k] = c->sk[2 + k].as<uint32_t>();
+    sb.val[k] = c->sk[4 + k].as<uint32_t>();
+  }
+  HIP_TRY(launch_seg_sources(dbp, n, reinterpret_cast<const int64_t*>(dd + L.blk_s), bs[n],
+                             reinterpret_cast<const int64_t*>(dd + L.src_off), P->total_src, sb,
+                             c->s_hist.as<uint32_t>(), hist_cap, c->sx.as<float>(),
+                             c->sy.as<float>(), c->sz.as<float>(), c->perm.as<uint32_t>(), s),
           "source order");
   return ICP_SUCCESS;
 }
 
-void fill_pass_args(PassArgs& a, const PairDst& d, const uint32_t* perm, int64_t n_src,
-                    int64_t n_tgt, const GridDesc& g, double r, IterState* st, double* part,
-                    uint32_t* jprev) {
+// Pass arguments of pair p of a prepared call (pointers into the device
+// buffers; `st`, `part`, `jprev` inside the call's desc region).
+PassArgs pass_args(icp_ctx* c, const Prep& P, int p, double r, bool with_jprev, bool normals) {
+  const Layout& L = P.L;
+  char* dd = c->desc.as<char>();
+  PassArgs a;
   memset(&a, 0, sizeof a);
-  a.sx = d.sx;
-  a.sy = d.sy;
-  a.sz = d.sz;
-  a.sperm = perm;
-  a.n_src = (int32_t)n_src;
-  a.tp = d.tp;
-  a.tn = d.tn;
-  a.cs = d.cs;
-  a.g = g;
+  a.sx = c->sx.as<float>() + P.src_off[p];
+  a.sy = c->sy.as<float>() + P.src_off[p];
+  a.sz = c->sz.as<float>() + P.src_off[p];
+  a.sperm = c->perm.as<uint32_t>() + P.src_off[p];
+  a.n_src = (int32_t)(P.src_off[p + 1] - P.src_off[p]);
+  a.tp = c->tp.as<float4>();
+  a.tn = normals ? c->tn.as<float4>() : nullptr;
+  a.cs = c->cs.as<uint32_t>() + P.tab_off[p];
+  a.g = P.g[p];
   a.r2f = (float)(r * r);
-  a.inv_h2 = (float)(g.inv_h * g.inv_h);
-  a.n_tgt = (int32_t)n_tgt;
-  a.jprev = jprev;
-  a.st = st;
-  a.part = part;
-  a.n_blocks = (int32_t)((n_src + kTile - 1) / kTile);
+  a.inv_h2 = (float)(P.g[p].inv_h * P.g[p].inv_h);
+  a.n_tgt = (int32_t)(P.tgt_off[p + 1] - P.tgt_off[p]);
+  a.jprev = with_jprev ? reinterpret_cast<uint32_t*>(dd + L.jprev) + P.src_off[p] : nullptr;
+  a.st = reinterpret_cast<IterState*>(dd + L.states) + p;
+  a.part = reinterpret_cast<double*>(dd + L.part) + (size_t)kNumSums * P.tile_off[p];
+  a.n_blocks = (int32_t)(P.tile_off[p + 1] - P.tile_off[p]);
+  return a;
 }
 
-int prepare(icp_ctx* c, const float* src, int64_t n_src, const float* tgt, const float* tgt_n,
-            int64_t n_tgt, double r, bool with_normals, Prepared* P) {
-  CloudBox b;
-  int which = -1, rc;
-  const float* tn = with_normals ? tgt_n : nullptr;
-  if ((rc = bboxes(c, 1, &src, &n_src, &tgt, &tn, &n_tgt, &b, &which)) != 0) return rc;
-  const GridDesc g = make_grid(b.tmn, b.tmx, r, n_tgt);
-  if ((rc = ensure_scratch(c, n_src, n_tgt, g.ncell)) != 0) return rc;
-  HIP_TRY(c->t_cs.ensure(4 * ((size_t)g.ncell + 1)), "alloc");
-  HIP_TRY(c->t_tp.ensure(16 * (size_t)n_tgt), "alloc");
-  if (with_normals) HIP_TRY(c->t_tn.ensure(16 * (size_t)n_tgt), "alloc");
-  HIP_TRY(c->s_x.ensure(4 * (size_t)n_src), "alloc");
-  HIP_TRY(c->s_y.ensure(4 * (size_t)n_src), "alloc");
-  HIP_TRY(c->s_z.ensure(4 * (size_t)n_src), "alloc");
-  const PairDst d{c->t_cs.as<uint32_t>(), c->t_tp.as<float4>(),
-                  with_normals ? c->t_tn.as<float4>() : nullptr, c->s_x.as<float>(),
-                  c->s_y.as<float>(), c->s_z.as<float>()};
-  uint32_t* perm = nullptr;
-  if ((rc = build_pair(c, src, n_src, tgt, tgt_n, n_tgt, g, b, d, &perm)) != 0) return rc;
-  const int32_t n_blocks = (int32_t)((n_src + kTile - 1) / kTile);
-  HIP_TRY(c->part.ensure(sizeof(double) * kNumSums * (size_t)n_blocks), "alloc");
-  HIP_TRY(c->state.ensure(sizeof(IterState)), "alloc");
-  fill_pass_args(P->pa, d, perm, n_src, n_tgt, g, r, c->state.as<IterState>(), c->part.as<double>(),
-                 nullptr);
-  P->n_src = n_src;
-  return ICP_SUCCESS;
-}
-
-int read_state(icp_ctx* c, IterState* out) {
-  HIP_TRY(hipMemcpyAsync(c->host, c->state.p, sizeof(IterState), hipMemcpyDeviceToHost, c->stream),
-          "readback");
-  HIP_TRY(hipStreamSynchronize(c->stream), "sync");
-  memcpy(out, c->host, sizeof(IterState));
-  return ICP_SUCCESS;
-}
-
-// Event slots: [0] call start, [1] call end, [2 + 2k] / [3 + 2k] around pass k.
 int ensure_events(icp_ctx* c, int passes) {
   const size_t need = 2 + 2 * (size_t)passes;
   while (c->ev.size() < need) {
@@ -457,17 +518,123 @@ int ensure_events(icp_ctx* c, int passes) {
   return ICP_SUCCESS;
 }
 
-int collect_profile(icp_ctx* c, int counted_passes, int64_t n_src) {
+int collect_profile(icp_ctx* c, int counted_passes, int64_t evals) {
   float ms = 0.0f;
   for (int k = 0; k < counted_passes; ++k) {
     HIP_TRY(hipEventElapsedTime(&ms, c->ev[2 + 2 * k], c->ev[3 + 2 * k]), "hipEventElapsedTime");
     c->prof.pass_ms += ms;
     c->prof.pass_launches += 1;
-    c->prof.pass_points += n_src;
   }
+  c->prof.pass_points += evals;
   HIP_TRY(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]), "hipEventElapsedTime");
   c->prof.call_ms += ms;
   c->prof.calls += 1;
+  return ICP_SUCCESS;
+}
+
+void to_result(const IterState& st, icp_result_t* out) {
+  for (int k = 0; k < 12; ++k) out->T[k] = st.T[k];
+  out->T[12] = 0.0; out->T[13] = 0.0; out->T[14] = 0.0; out->T[15] = 1.0;
+  out->fitness = st.fitness;
+  out->inlier_rmse = st.rmse;
+  out->n_inliers = st.n_in;
+  out->n_iter = st.k;
+  out->status = st.status;
+}
+
+struct LoopIn {
+  const double* T_init;  // 16 doubles
+  double r;
+  int32_t max_iter;
+  double rel_tol;
+};
+
+// Steps 3 and 4 for n prepared pairs: initial states, loop, readback.  A
+// single pair runs the per-pair kernels with arguments by value; several pairs
+// run the batched kernels over the (pair, tile) item list.
+int run_loop(icp_ctx* c, const Prep& P, const LoopIn* in, bool normals, int variant,
+             int precision, icp_result_t* out) {
+  hipStream_t s = c->stream;
+  const Layout& L = P.L;
+  const int n = P.n;
+  int rc;
+  // results are read back behind the staged header
+  if ((rc = ensure_host(c, L.total + sizeof(IterState) * n)) != 0) return rc;
+  char* hh = static_cast<char*>(c->host);
+  char* dd = c->desc.as<char>();
+  PassArgs* hp = reinterpret_cast<PassArgs*>(hh + L.pargs);
+  SolveArgs* hs = reinterpret_cast<SolveArgs*>(hh + L.sargs);
+  IterState* hst = reinterpret_cast<IterState*>(hh + L.states);
+  uint2* hit = reinterpret_cast<uint2*>(hh + L.items);
+  int32_t iters = 0;
+  int64_t item = 0;
+  for (int p = 0; p < n; ++p) {
+    hp[p] = pass_args(c, P, p, in[p].r, true, normals);
+    hs[p] = SolveArgs{hp[p].part, hp[p].n_blocks, const_cast<IterState*>(hp[p].st),
+                      P.src_off[p + 1] - P.src_off[p], in[p].max_iter, in[p].rel_tol, 0};
+    memset(&hst[p], 0, sizeof(IterState));
+    for (int k = 0; k < 16; ++k) hst[p].T[k] = in[p].T_init[k];
+    for (int t = 0; t < hp[p].n_blocks; ++t) hit[item++] = make_uint2((uint32_t)p, (uint32_t)t);
+    iters = std::max(iters, in[p].max_iter);
+  }
+  HIP_TRY(hipMemsetAsync(dd + L.jprev, 0xff, 4 * (size_t)P.total_src, s), "memset");
+  HIP_TRY(hipMemcpyAsync(dd + L.pargs, hh + L.pargs, L.header_end - L.pargs, hipMemcpyHostToDevice, s),
+          "upload");
+  const bool prof = c->profiling;
+  if (prof && (rc = ensure_events(c, iters + 1)) != 0) return rc;
+  if (prof) HIP_TRY(hipEventRecord(c->ev[0], s), "hipEventRecord");
+  const PassArgs* dp = reinterpret_cast<const PassArgs*>(dd + L.pargs);
+  const SolveArgs* ds = reinterpret_cast<const SolveArgs*>(dd + L.sargs);
+  const uint2* di = reinterpret_cast<const uint2*>(dd + L.items);
+  for (int32_t k = 0; k <= iters; ++k) {
+    if (prof) HIP_TRY(hipEventRecord(c->ev[2 + 2 * k], s), "hipEventRecord");
+    if (n == 1)
+      HIP_TRY(launch_pass(hp[0], variant, precision, false, s), "pass");
+    else
+      HIP_TRY(launch_batch_pass(dp, di, (int)P.total_tiles, P.sub, variant, precision, s), "pass");
+    if (prof) HIP_TRY(hipEventRecord(c->ev[3 + 2 * k], s), "hipEventRecord");
+    if (n == 1)
+      HIP_TRY(launch_solve(hs[0], s), "solve");
+    else
+      HIP_TRY(launch_batch_solve(ds, n, s), "solve");
+  }
+  if (prof) HIP_TRY(hipEventRecord(c->ev[1], s), "hipEventRecord");
+  IterState* res = reinterpret_cast<IterState*>(hh + L.total);
+  HIP_TRY(hipMemcpyAsync(res, dd + L.states, sizeof(IterState) * n, hipMemcpyDeviceToHost, s),
+          "readback");
+  HIP_TRY(hipStreamSynchronize(s), "sync");
+  int32_t max_k = 0;
+  int64_t evals = 0;
+  for (int p = 0; p < n; ++p) {
+    to_result(res[p], out + p);
+    max_k = std::max(max_k, res[p].k);
+    evals += (int64_t)(res[p].k + 1) * (P.src_off[p + 1] - P.src_off[p]);
+  }
+  if (prof && (rc = collect_profile(c, max_k + 1, evals)) != 0) return rc;
+  return ICP_SUCCESS;
+}
+
+// One pass at a given pose for a single prepared pair (test hooks).
+int single_pass(icp_ctx* c, const Prep& P, double r, const double T[16], bool normals, int variant,
+                int precision, int32_t* idx_out, float* d2_out, bool reduce, IterState* st_out) {
+  hipStream_t s = c->stream;
+  PassArgs a = pass_args(c, P, 0, r, false, normals);
+  a.idx_out = idx_out;
+  a.d2_out = d2_out;
+  HIP_TRY(launch_state_init(const_cast<IterState*>(a.st), T, s), "state init");
+  HIP_TRY(launch_pass(a, variant, precision, idx_out != nullptr, s), "pass");
+  if (reduce) {
+    SolveArgs sa{a.part, a.n_blocks, const_cast<IterState*>(a.st), P.src_off[1], 0, 0.0, 1};
+    HIP_TRY(launch_solve(sa, s), "reduce");
+    int rc;
+    if ((rc = ensure_host(c, P.L.total + sizeof(IterState))) != 0) return rc;
+    IterState* res = reinterpret_cast<IterState*>(static_cast<char*>(c->host) + P.L.total);
+    HIP_TRY(hipMemcpyAsync(res, a.st, sizeof(IterState), hipMemcpyDeviceToHost, s), "readback");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    *st_out = *res;
+  } else {
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+  }
   return ICP_SUCCESS;
 }
 
@@ -476,7 +643,7 @@ int collect_profile(icp_ctx* c, int counted_passes, int64_t n_src) {
 // ====================================================================== C ABI
 extern "C" {
 
-const char* icp_version(void) { return "icp-mi355x 0.1 (gfx950)"; }
+const char* icp_version(void) { return "icp-mi355x 0.2 (gfx950)"; }
 
 const char* icp_strerror(int code) {
   switch (code) {
@@ -510,6 +677,13 @@ int icp_ctx_create(int device, void* hip_stream, icp_ctx_t** out) {
   return ICP_SUCCESS;
 }
 
+int icp_ctx_destroy(icp_ctx_t* ctx) {
+  if (!ctx) return ICP_SUCCESS;
+  ctx_free(ctx);
+  delete ctx;
+  return ICP_SUCCESS;
+}
+
 int icp_ctx_set_profiling(icp_ctx_t* ctx, int enable) {
   if (!ctx) return fail(ICP_E_INVALID_ARG, "ctx is NULL");
   ctx->profiling = enable != 0;
@@ -523,13 +697,6 @@ int icp_ctx_get_profile(icp_ctx_t* ctx, icp_profile_t* out) {
   return ICP_SUCCESS;
 }
 
-int icp_ctx_destroy(icp_ctx_t* ctx) {
-  if (!ctx) return ICP_SUCCESS;
-  ctx_free(ctx);
-  delete ctx;
-  return ICP_SUCCESS;
-}
-
 int icp_register(icp_ctx_t* ctx, const float* src_xyz, int64_t n_src, const float* tgt_xyz,
                  const float* tgt_normals, int64_t n_tgt, const double T_init[16],
                  double max_corr_dist, int32_t max_iter, double rel_tol, int32_t variant,
@@ -537,43 +704,17 @@ int icp_register(icp_ctx_t* ctx, const float* src_xyz, int64_t n_src, const floa
   int rc = check_common(src_xyz, n_src, tgt_xyz, tgt_normals, n_tgt, T_init, max_corr_dist, variant,
                         precision, true);
   if (rc) return rc;
-  if (max_iter < 0) return fail(ICP_E_INVALID_ARG, "max_iter must be >= 0");
-  if (!(rel_tol >= 0.0) || !std::isfinite(rel_tol))
-    return fail(ICP_E_INVALID_ARG, "rel_tol must be finite and >= 0");
+  if ((rc = check_iteration(max_iter, rel_tol)) != 0) return rc;
   if (!out) return fail(ICP_E_INVALID_ARG, "out is NULL");
   icp_ctx* c = nullptr;
   if ((rc = resolve_ctx(ctx, &c)) != 0) return rc;
   DeviceGuard dg(c->device);
   const bool plane = variant == ICP_POINT_TO_PLANE;
-  Prepared P;
-  if ((rc = prepare(c, src_xyz, n_src, tgt_xyz, tgt_normals, n_tgt, max_corr_dist, plane, &P)) != 0)
-    return rc;
-  HIP_TRY(c->jprev.ensure(4 * (size_t)n_src), "alloc");
-  HIP_TRY(hipMemsetAsync(c->jprev.p, 0xff, 4 * (size_t)n_src, c->stream), "memset");
-  P.pa.jprev = c->jprev.as<uint32_t>();
-  const bool prof = c->profiling;
-  if (prof && (rc = ensure_events(c, max_iter + 1)) != 0) return rc;
-  if (prof) HIP_TRY(hipEventRecord(c->ev[0], c->stream), "hipEventRecord");
-  HIP_TRY(launch_state_init(c->state.as<IterState>(), T_init, c->stream), "state init");
-  SolveArgs sa{P.pa.part, P.pa.n_blocks, c->state.as<IterState>(), n_src, max_iter, rel_tol, 0};
-  for (int32_t k = 0; k <= max_iter; ++k) {
-    if (prof) HIP_TRY(hipEventRecord(c->ev[2 + 2 * k], c->stream), "hipEventRecord");
-    HIP_TRY(launch_pass(P.pa, variant, precision, false, c->stream), "pass");
-    if (prof) HIP_TRY(hipEventRecord(c->ev[3 + 2 * k], c->stream), "hipEventRecord");
-    HIP_TRY(launch_solve(sa, c->stream), "solve");
-  }
-  if (prof) HIP_TRY(hipEventRecord(c->ev[1], c->stream), "hipEventRecord");
-  IterState st;
-  if ((rc = read_state(c, &st)) != 0) return rc;
-  if (prof && (rc = collect_profile(c, st.k + 1, n_src)) != 0) return rc;
-  for (int k = 0; k < 12; ++k) out->T[k] = st.T[k];
-  out->T[12] = 0.0; out->T[13] = 0.0; out->T[14] = 0.0; out->T[15] = 1.0;
-  out->fitness = st.fitness;
-  out->inlier_rmse = st.rmse;
-  out->n_inliers = st.n_in;
-  out->n_iter = st.k;
-  out->status = st.status;
-  return ICP_SUCCESS;
+  const PairIn in{src_xyz, n_src, tgt_xyz, plane ? tgt_normals : nullptr, n_tgt, max_corr_dist};
+  Prep P;
+  if ((rc = prepare_pairs(c, 1, &in, &P)) != 0) return rc;
+  const LoopIn li{T_init, max_corr_dist, max_iter, rel_tol};
+  return run_loop(c, P, &li, plane, variant, precision, out);
 }
 
 int icp_register_batch(icp_ctx_t* ctx, const icp_pair_t* pairs, int32_t n_pairs, int32_t variant,
@@ -582,21 +723,18 @@ int icp_register_batch(icp_ctx_t* ctx, const icp_pair_t* pairs, int32_t n_pairs,
   if (n_pairs < 1) return fail(ICP_E_INVALID_ARG, "n_pairs must be >= 1");
   int rc;
   int64_t total_src = 0, total_tgt = 0;
-  int32_t iters = 0;
   for (int p = 0; p < n_pairs; ++p) {
     const icp_pair_t& q = pairs[p];
-    if ((rc = check_common(q.src_xyz, q.n_src, q.tgt_xyz, q.tgt_normals, q.n_tgt, q.T_init,
-                           q.max_corr_dist, variant, precision, true)) != 0 ||
-        (q.max_iter < 0 && (rc = fail(ICP_E_INVALID_ARG, "max_iter must be >= 0")) != 0) ||
-        ((!(q.rel_tol >= 0.0) || !std::isfinite(q.rel_tol)) &&
-         (rc = fail(ICP_E_INVALID_ARG, "rel_tol must be finite and >= 0")) != 0) ||
-        (q.reserved != 0 && (rc = fail(ICP_E_INVALID_ARG, "reserved must be 0")) != 0)) {
+    rc = check_common(q.src_xyz, q.n_src, q.tgt_xyz, q.tgt_normals, q.n_tgt, q.T_init,
+                      q.max_corr_dist, variant, precision, true);
+    if (!rc) rc = check_iteration(q.max_iter, q.rel_tol);
+    if (!rc && q.reserved != 0) rc = fail(ICP_E_INVALID_ARG, "reserved must be 0");
+    if (rc) {
       g_last_error += " (pair " + std::to_string(p) + ")";
       return rc;
     }
     total_src += q.n_src;
     total_tgt += q.n_tgt;
-    iters = std::max(iters, q.max_iter);
   }
   if (total_src > (int64_t)INT32_MAX || total_tgt > (int64_t)INT32_MAX)
     return fail(ICP_E_TOO_LARGE, "more than 2^31-1 points in one batch");
@@ -604,130 +742,17 @@ int icp_register_batch(icp_ctx_t* ctx, const icp_pair_t* pairs, int32_t n_pairs,
   if ((rc = resolve_ctx(ctx, &c)) != 0) return rc;
   DeviceGuard dg(c->device);
   const bool plane = variant == ICP_POINT_TO_PLANE;
-  const int n = n_pairs;
-
-  std::vector<const float*> srcs(n), tgts(n), tns(n);
-  std::vector<int64_t> ns(n), nt(n);
-  for (int p = 0; p < n; ++p) {
-    srcs[p] = pairs[p].src_xyz;
-    tgts[p] = pairs[p].tgt_xyz;
-    tns[p] = plane ? pairs[p].tgt_normals : nullptr;
-    ns[p] = pairs[p].n_src;
-    nt[p] = pairs[p].n_tgt;
+  std::vector<PairIn> in(n_pairs);
+  std::vector<LoopIn> li(n_pairs);
+  for (int p = 0; p < n_pairs; ++p) {
+    const icp_pair_t& q = pairs[p];
+    in[p] = PairIn{q.src_xyz, q.n_src, q.tgt_xyz, plane ? q.tgt_normals : nullptr, q.n_tgt,
+                   q.max_corr_dist};
+    li[p] = LoopIn{q.T_init, q.max_corr_dist, q.max_iter, q.rel_tol};
   }
-  std::vector<CloudBox> box(n);
-  int which = -1;
-  if ((rc = bboxes(c, n, srcs.data(), ns.data(), tgts.data(), tns.data(), nt.data(), box.data(),
-                   &which)) != 0)
-    return rc;
-
-  // layout of the batch region: header (pass args, solve args, states, work
-  // items) first, then every pair's persistent arrays
-  std::vector<GridDesc> grid(n);
-  int64_t n_items = 0, max_src = 0, max_tgt = 0;
-  uint64_t max_cell = 0;
-  for (int p = 0; p < n; ++p) {
-    grid[p] = make_grid(box[p].tmn, box[p].tmx, pairs[p].max_corr_dist, nt[p]);
-    n_items += (ns[p] + kTile - 1) / kTile;
-    max_src = std::max(max_src, ns[p]);
-    max_tgt = std::max(max_tgt, nt[p]);
-    max_cell = std::max<uint64_t>(max_cell, grid[p].ncell);
-  }
-  size_t off = 0;
-  auto take = [&](size_t bytes) {
-    const size_t o = (off + 255) & ~(size_t)255;
-    off = o + bytes;
-    return o;
-  };
-  const size_t o_pargs = take(sizeof(PassArgs) * n);
-  const size_t o_sargs = take(sizeof(SolveArgs) * n);
-  const size_t o_states = take(sizeof(IterState) * n);
-  const size_t o_items = take(sizeof(uint2) * (size_t)n_items);
-  const size_t header = off;
-  const size_t o_jprev = take(4 * (size_t)total_src);
-  struct Offs { size_t cs, tp, tn, sx, sy, sz, part; };
-  std::vector<Offs> po(n);
-  for (int p = 0; p < n; ++p) {
-    po[p].cs = take(4 * ((size_t)grid[p].ncell + 1));
-    po[p].tp = take(16 * (size_t)nt[p]);
-    po[p].tn = plane ? take(16 * (size_t)nt[p]) : 0;
-    po[p].sx = take(4 * (size_t)ns[p]);
-    po[p].sy = take(4 * (size_t)ns[p]);
-    po[p].sz = take(4 * (size_t)ns[p]);
-    po[p].part = take(sizeof(double) * kNumSums * (size_t)((ns[p] + kTile - 1) / kTile));
-  }
-  HIP_TRY(c->batch.ensure(off), "alloc");
-  if ((rc = ensure_scratch(c, max_src, max_tgt, max_cell)) != 0) return rc;
-  if ((rc = ensure_host(c, std::max(header, sizeof(IterState) * n))) != 0) return rc;
-  char* base = c->batch.as<char>();
-
-  char* hh = static_cast<char*>(c->host);
-  PassArgs* hp = reinterpret_cast<PassArgs*>(hh + o_pargs);
-  SolveArgs* hs = reinterpret_cast<SolveArgs*>(hh + o_sargs);
-  IterState* hst = reinterpret_cast<IterState*>(hh + o_states);
-  uint2* hit = reinterpret_cast<uint2*>(hh + o_items);
-  IterState* dst_states = reinterpret_cast<IterState*>(base + o_states);
-  uint32_t* jprev = reinterpret_cast<uint32_t*>(base + o_jprev);
-  int64_t item = 0, src_off = 0;
-  for (int p = 0; p < n; ++p) {
-    const PairDst d{reinterpret_cast<uint32_t*>(base + po[p].cs), reinterpret_cast<float4*>(base + po[p].tp),
-                    plane ? reinterpret_cast<float4*>(base + po[p].tn) : nullptr,
-                    reinterpret_cast<float*>(base + po[p].sx), reinterpret_cast<float*>(base + po[p].sy),
-                    reinterpret_cast<float*>(base + po[p].sz)};
-    uint32_t* perm = nullptr;
-    if ((rc = build_pair(c, srcs[p], ns[p], tgts[p], pairs[p].tgt_normals, nt[p], grid[p], box[p], d,
-                         &perm)) != 0)
-      return rc;
-    double* part = reinterpret_cast<double*>(base + po[p].part);
-    fill_pass_args(hp[p], d, nullptr, ns[p], nt[p], grid[p], pairs[p].max_corr_dist, dst_states + p,
-                   part, jprev + src_off);
-    hs[p] = SolveArgs{part, hp[p].n_blocks, dst_states + p, ns[p], pairs[p].max_iter,
-                      pairs[p].rel_tol, 0};
-    IterState& st = hst[p];
-    memset(&st, 0, sizeof st);
-    for (int k = 0; k < 16; ++k) st.T[k] = pairs[p].T_init[k];
-    for (int t = 0; t < hp[p].n_blocks; ++t) hit[item++] = make_uint2((uint32_t)p, (uint32_t)t);
-    src_off += ns[p];
-  }
-  HIP_TRY(hipMemsetAsync(jprev, 0xff, 4 * (size_t)total_src, c->stream), "memset");
-  HIP_TRY(hipMemcpyAsync(base, hh, header, hipMemcpyHostToDevice, c->stream), "upload");
-  const PassArgs* dp = reinterpret_cast<const PassArgs*>(base + o_pargs);
-  const SolveArgs* ds = reinterpret_cast<const SolveArgs*>(base + o_sargs);
-  const uint2* di = reinterpret_cast<const uint2*>(base + o_items);
-  const int sub = grid[0].sub;
-  const bool prof = c->profiling;
-  if (prof && (rc = ensure_events(c, iters + 1)) != 0) return rc;
-  if (prof) HIP_TRY(hipEventRecord(c->ev[0], c->stream), "hipEventRecord");
-  for (int32_t k = 0; k <= iters; ++k) {
-    if (prof) HIP_TRY(hipEventRecord(c->ev[2 + 2 * k], c->stream), "hipEventRecord");
-    HIP_TRY(launch_batch_pass(dp, di, (int)n_items, sub, variant, precision, c->stream), "pass");
-    if (prof) HIP_TRY(hipEventRecord(c->ev[3 + 2 * k], c->stream), "hipEventRecord");
-    HIP_TRY(launch_batch_solve(ds, n, c->stream), "solve");
-  }
-  if (prof) HIP_TRY(hipEventRecord(c->ev[1], c->stream), "hipEventRecord");
-  HIP_TRY(hipMemcpyAsync(hh, dst_states, sizeof(IterState) * n, hipMemcpyDeviceToHost, c->stream),
-          "readback");
-  HIP_TRY(hipStreamSynchronize(c->stream), "sync");
-  const IterState* res = reinterpret_cast<const IterState*>(hh);
-  int32_t max_k = 0;
-  int64_t evals = 0;
-  for (int p = 0; p < n; ++p) {
-    const IterState& st = res[p];
-    for (int k = 0; k < 12; ++k) out[p].T[k] = st.T[k];
-    out[p].T[12] = 0.0; out[p].T[13] = 0.0; out[p].T[14] = 0.0; out[p].T[15] = 1.0;
-    out[p].fitness = st.fitness;
-    out[p].inlier_rmse = st.rmse;
-    out[p].n_inliers = st.n_in;
-    out[p].n_iter = st.k;
-    out[p].status = st.status;
-    max_k = std::max(max_k, st.k);
-    evals += (int64_t)(st.k + 1) * ns[p];
-  }
-  if (prof) {
-    if ((rc = collect_profile(c, max_k + 1, 0)) != 0) return rc;
-    c->prof.pass_points += evals;
-  }
-  return ICP_SUCCESS;
+  Prep P;
+  if ((rc = prepare_pairs(c, n_pairs, in.data(), &P)) != 0) return rc;
+  return run_loop(c, P, li.data(), plane, variant, precision, out);
 }
 
 int icp_correspondences(icp_ctx_t* ctx, const float* src_xyz, int64_t n_src, const double T[16],
@@ -740,15 +765,11 @@ int icp_correspondences(icp_ctx_t* ctx, const float* src_xyz, int64_t n_src, con
   icp_ctx* c = nullptr;
   if ((rc = resolve_ctx(ctx, &c)) != 0) return rc;
   DeviceGuard dg(c->device);
-  Prepared P;
-  if ((rc = prepare(c, src_xyz, n_src, tgt_xyz, nullptr, n_tgt, max_corr_dist, false, &P)) != 0)
-    return rc;
-  P.pa.idx_out = idx_out;
-  P.pa.d2_out = d2_out;
-  HIP_TRY(launch_state_init(c->state.as<IterState>(), T, c->stream), "state init");
-  HIP_TRY(launch_pass(P.pa, ICP_POINT_TO_POINT, ICP_PREC_F32_KAHAN_F64, true, c->stream), "pass");
-  HIP_TRY(hipStreamSynchronize(c->stream), "sync");
-  return ICP_SUCCESS;
+  const PairIn in{src_xyz, n_src, tgt_xyz, nullptr, n_tgt, max_corr_dist};
+  Prep P;
+  if ((rc = prepare_pairs(c, 1, &in, &P)) != 0) return rc;
+  return single_pass(c, P, max_corr_dist, T, false, ICP_POINT_TO_POINT, ICP_PREC_F32_KAHAN_F64,
+                     idx_out, d2_out, false, nullptr);
 }
 
 int icp_normal_equations(icp_ctx_t* ctx, const float* src_xyz, int64_t n_src, const double T[16],
@@ -763,15 +784,13 @@ int icp_normal_equations(icp_ctx_t* ctx, const float* src_xyz, int64_t n_src, co
   if ((rc = resolve_ctx(ctx, &c)) != 0) return rc;
   DeviceGuard dg(c->device);
   const bool plane = variant == ICP_POINT_TO_PLANE;
-  Prepared P;
-  if ((rc = prepare(c, src_xyz, n_src, tgt_xyz, tgt_normals, n_tgt, max_corr_dist, plane, &P)) != 0)
-    return rc;
-  HIP_TRY(launch_state_init(c->state.as<IterState>(), T, c->stream), "state init");
-  HIP_TRY(launch_pass(P.pa, variant, precision, false, c->stream), "pass");
-  SolveArgs sa{P.pa.part, P.pa.n_blocks, c->state.as<IterState>(), n_src, 0, 0.0, 1};
-  HIP_TRY(launch_solve(sa, c->stream), "reduce");
+  const PairIn in{src_xyz, n_src, tgt_xyz, plane ? tgt_normals : nullptr, n_tgt, max_corr_dist};
+  Prep P;
+  if ((rc = prepare_pairs(c, 1, &in, &P)) != 0) return rc;
   IterState st;
-  if ((rc = read_state(c, &st)) != 0) return rc;
+  if ((rc = single_pass(c, P, max_corr_dist, T, plane, variant, precision, nullptr, nullptr, true,
+                        &st)) != 0)
+    return rc;
   for (int k = 0; k < 21; ++k) AtA21[k] = st.sums[k];
   for (int k = 0; k < 6; ++k) Atb6[k] = st.sums[21 + k];
   *sum_d2 = st.sums[kSumD2];

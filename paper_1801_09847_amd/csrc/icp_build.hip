@@ -1,0 +1,447 @@
+// Per-call preparation kernels for gfx950: finiteness checks and bounding
+// boxes, the dense target grid (cell table + cell-ordered target), and the
+// Morton ordering of the source -- for any number of pairs at once.
+//
+// All pairs of a call are processed by the same launches ("segmented"
+// kernels): a block finds its pair from a table of per-pair block offsets, the
+// cell tables of all pairs are concatenated and prefix-summed by one scan, and
+// the sources of all pairs are ordered by one stable LSD radix sort on the key
+// (pair, Morton code), which yields, inside each pair, exactly the order that
+// pair gets when it is prepared alone.
+
+#include <math.h>
+
+#include <algorithm>
+#include <utility>
+
+#include "icp_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace icp {
+
+namespace {
+
+constexpr int kWave = 64;
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+__device__ inline int lane_id() { return __lane_id(); }
+
+// Largest p with off[p] <= x, for a non-decreasing off[0..n].
+__device__ inline int find_segment(const int64_t* __restrict__ off, int n, int64_t x) {
+  int lo = 0, hi = n;  // invariant: off[lo] <= x < off[hi] (off[n] > x)
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= x) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// ------------------------------------------------------------------ bbox + finiteness
+__global__ __launch_bounds__(256) void seg_bbox_kernel(const SegCloud* __restrict__ clouds, int n_clouds,
+                                                       const int64_t* __restrict__ blk_off,
+                                                       float* __restrict__ block_out) {
+  const int c = find_segment(blk_off, n_clouds, blockIdx.x);
+  const SegCloud cl = clouds[c];
+  const int64_t nb = blk_off[c + 1] - blk_off[c];
+  const int64_t lb = blockIdx.x - blk_off[c];
+  float mn[3] = {INFINITY, INFINITY, INFINITY};
+  float mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+  float bad = 0.0f;
+  for (int64_t i = lb * 256 + threadIdx.x; i < cl.n; i += nb * 256) {
+    const float x = cl.pts[3 * i + 0], y = cl.pts[3 * i + 1], z = cl.pts[3 * i + 2];
+    if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
+      bad = 1.0f;
+    } else {
+      mn[0] = fminf(mn[0], x); mn[1] = fminf(mn[1], y); mn[2] = fminf(mn[2], z);
+      mx[0] = fmaxf(mx[0], x); mx[1] = fmaxf(mx[1], y); mx[2] = fmaxf(mx[2], z);
+    }
+    if (cl.nrm) {
+      const float a = cl.nrm[3 * i + 0], b = cl.nrm[3 * i + 1], d = cl.nrm[3 * i + 2];
+      if (!(isfinite(a) && isfinite(b) && isfinite(d))) bad = 1.0f;
+    }
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    for (int a = 0; a < 3; ++a) {
+      mn[a] = fminf(mn[a], __shfl_xor(mn[a], off, kWave));
+      mx[a] = fmaxf(mx[a], __shfl_xor(mx[a], off, kWave));
+    }
+    bad = fmaxf(bad, __shfl_xor(bad, off, kWave));
+  }
+  __shared__ float red[4][8];
+  const int w = threadIdx.x / kWave;
+  if (lane_id() == 0) {
+    for (int a = 0; a < 3; ++a) { red[w][a] = mn[a]; red[w][3 + a] = mx[a]; }
+    red[w][6] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x < 7) {
+    const int a = threadIdx.x;
+    float v = red[0][a];
+    for (int k = 1; k < 4; ++k) v = (a < 3) ? fminf(v, red[k][a]) : fmaxf(v, red[k][a]);
+    block_out[(int64_t)blockIdx.x * 8 + a] = v;
+  }
+}
+
+// One block per cloud: min / max / non-finite flag over the cloud's blocks.
+__global__ __launch_bounds__(256) void seg_bbox_final_kernel(const int64_t* __restrict__ blk_off,
+                                                             const float* __restrict__ block_out,
+                                                             float* __restrict__ out) {
+  const int c = blockIdx.x;
+  const int64_t b0 = blk_off[c], b1 = blk_off[c + 1];
+  __shared__ float red[7][256];
+  for (int a = 0; a < 7; ++a) {
+    float v = (a < 3) ? INFINITY : -INFINITY;
+    if (a == 6) v = 0.0f;
+    for (int64_t b = b0 + threadIdx.x; b < b1; b += 256) {
+      const float x = block_out[b * 8 + a];
+      v = (a < 3) ? fminf(v, x) : fmaxf(v, x);
+    }
+    red[a][threadIdx.x] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 7) {
+    const int a = threadIdx.x;
+    float v = red[a][0];
+    for (int t = 1; t < 256; ++t) v = (a < 3) ? fminf(v, red[a][t]) : fmaxf(v, red[a][t]);
+    out[(int64_t)c * 8 + a] = v;
+  }
+}
+
+// ------------------------------------------------------------------ exclusive scan (uint32)
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+template <int kThreads>
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* total) {
+  __shared__ uint32_t wsum[kThreads / kWave];
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  uint32_t x = v;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off, kWave);
+    if (lane >= off) x += y;
+  }
+  if (lane == kWave - 1) wsum[w] = x;
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+  for (int k = 0; k < kThreads / kWave; ++k) {
+    if (k < w) before += wsum[k];
+    all += wsum[k];
+  }
+  __syncthreads();
+  *total = all;
+  return before + x - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_tile_sums_kernel(const uint32_t* __restrict__ d,
+                                                                      int64_t n,
+                                                                      uint32_t* __restrict__ sums) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k)
+    if (base + k < n) s += d[base + k];
+  uint32_t total;
+  block_exclusive_scan<kScanThreads>(s, &total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// Single block: exclusive scan of nb tile sums in place (each thread owns a
+// contiguous chunk; chunk totals are scanned across the block).
+__global__ __launch_bounds__(1024) void scan_top_kernel(uint32_t* __restrict__ sums, int64_t nb) {
+  const int64_t per = (nb + 1023) / 1024;
+  const int64_t b0 = (int64_t)threadIdx.x * per;
+  uint32_t s = 0;
+  for (int64_t k = 0; k < per; ++k)
+    if (b0 + k < nb) s += sums[b0 + k];
+  uint32_t total;
+  uint32_t run = block_exclusive_scan<1024>(s, &total);
+  for (int64_t k = 0; k < per; ++k)
+    if (b0 + k < nb) {
+      const uint32_t v = sums[b0 + k];
+      sums[b0 + k] = run;
+      run += v;
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(uint32_t* __restrict__ d, int64_t n,
+                                                                  const uint32_t* __restrict__ sums) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = (base + k < n) ? d[base + k] : 0u;
+    s += v[k];
+  }
+  uint32_t total;
+  uint32_t run = block_exclusive_scan<kScanThreads>(s, &total) + sums[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) d[base + k] = run;
+    run += v[k];
+  }
+}
+
+// ------------------------------------------------------------------ target grid
+__device__ inline int cell_of(float p, double o, double inv_h, int dim) {
+  double u = ((double)p - o) * inv_h;
+  u = fmin(fmax(u, -2.0), (double)dim + 1.0);
+  return (int)floor(u);
+}
+
+// Cell key of every target point (global: offset by the pair's table) and its
+// rank among the points of its cell (order of arrival; the search breaks ties
+// by original index, so the order inside a cell never matters).
+__global__ __launch_bounds__(256) void seg_target_key_kernel(const BuildPair* __restrict__ pairs, int n,
+                                                             const int64_t* __restrict__ blk_off,
+                                                             uint32_t* __restrict__ counts,
+                                                             uint32_t* __restrict__ key,
+                                                             uint32_t* __restrict__ rank) {
+  const int p = find_segment(blk_off, n, blockIdx.x);
+  const BuildPair& bp = pairs[p];
+  const int64_t i = (int64_t)(blockIdx.x - blk_off[p]) * 256 + threadIdx.x;
+  if (i >= bp.n_tgt) return;
+  const GridDesc g = bp.g;
+  const float* t = bp.tgt + 3 * i;
+  const int cx = min(max(cell_of(t[0], g.ox, g.inv_h, g.dx), 0), g.dx - 1);
+  const int cy = min(max(cell_of(t[1], g.oy, g.inv_h, g.dy), 0), g.dy - 1);
+  const int cz = min(max(cell_of(t[2], g.oz, g.inv_h, g.dz), 0), g.dz - 1);
+  const uint32_t k = ((uint32_t)cz * (uint32_t)g.dy + (uint32_t)cy) * (uint32_t)g.dx + (uint32_t)cx;
+  const uint32_t gk = (uint32_t)bp.tab_off + k;
+  key[bp.tgt_off + i] = gk;
+  rank[bp.tgt_off + i] = atomicAdd(&counts[gk], 1u);
+}
+
+__global__ __launch_bounds__(256) void seg_target_scatter_kernel(
+    const BuildPair* __restrict__ pairs, int n, const int64_t* __restrict__ blk_off,
+    const uint32_t* __restrict__ key, const uint32_t* __restrict__ rank,
+    const uint32_t* __restrict__ cs, float4* __restrict__ tp, float4* __restrict__ tn) {
+  const int p = find_segment(blk_off, n, blockIdx.x);
+  const BuildPair& bp = pairs[p];
+  const int64_t i = (int64_t)(blockIdx.x - blk_off[p]) * 256 + threadIdx.x;
+  if (i >= bp.n_tgt) return;
+  const int64_t gi = bp.tgt_off + i;
+  const uint32_t pos = cs[key[gi]] + rank[gi];
+  const float* t = bp.tgt + 3 * i;
+  tp[pos] = make_float4(t[0], t[1], t[2], __uint_as_float((uint32_t)i));
+  if (bp.tgt_n && tn) {
+    const float* m = bp.tgt_n + 3 * i;
+    tn[pos] = make_float4(m[0], m[1], m[2], 0.0f);
+  }
+}
+
+// ------------------------------------------------------------------ stable LSD radix sort
+// Keys are one or two 32-bit words (lo, hi); the sort orders by hi, then lo,
+// then by input position (stability).  Values ride along.
+constexpr int kSortThreads = 256;
+constexpr int kSortRounds = 8;
+constexpr int kSortTile = kSortThreads * kSortRounds;
+
+__global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const uint32_t* __restrict__ keys,
+                                                                  int64_t n, int shift,
+                                                                  uint32_t* __restrict__ hist,
+                                                                  int nblk) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t tile = (int64_t)blockIdx.x * kSortTile;
+  for (int k = 0; k < kSortRounds; ++k) {
+    const int64_t i = tile + k * kSortThreads + threadIdx.x;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter of one 8-bit digit of `dig` (one of the key words).  Inside a
+// tile, items are ranked in input order: per round, lanes with equal digits
+// are found by ballots on the digit bits, and earlier waves' counts are added.
+__global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
+    const uint32_t* __restrict__ dig, const uint32_t* __restrict__ klo,
+    const uint32_t* __restrict__ khi, const uint32_t* __restrict__ vals, int64_t n, int shift,
+    const uint32_t* __restrict__ offs, int nblk, uint32_t* __restrict__ klo_out,
+    uint32_t* __restrict__ khi_out, uint32_t* __restrict__ vals_out) {
+  __shared__ uint32_t base[256];
+  __shared__ uint32_t wcnt[kSortThreads / kWave][256];
+  const int t = threadIdx.x, w = t / kWave, lane = lane_id();
+  base[t] = offs[(int64_t)t * nblk + blockIdx.x];
+  for (int k = 0; k < kSortThreads / kWave; ++k) wcnt[k][t] = 0;
+  __syncthreads();
+  const int64_t tile = (int64_t)blockIdx.x * kSortTile;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int r = 0; r < kSortRounds; ++r) {
+    const int64_t i = tile + r * kSortThreads + t;
+    const bool valid = i < n;
+    const uint32_t d = valid ? ((dig[i] >> shift) & 255u) : 0u;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bb = __ballot(bit);
+      peers &= bit ? bb : ~bb;
+    }
+    const uint32_t rank_w = __popcll(peers & lt_mask);
+    if (valid && rank_w == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t dst = base[d] + rank_w;
+      for (int k = 0; k < w; ++k) dst += wcnt[k][d];
+      klo_out[dst] = klo[i];
+      if (khi) khi_out[dst] = khi[i];
+      vals_out[dst] = vals[i];
+    }
+    __syncthreads();
+    uint32_t add = 0;
+    for (int k = 0; k < kSortThreads / kWave; ++k) {
+      add += wcnt[k][t];
+      wcnt[k][t] = 0;
+    }
+    base[t] += add;
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ source ordering
+__device__ inline uint32_t spread10(uint32_t v) {
+  v &= 0x3ffu;
+  v = (v | (v << 16)) & 0x030000ffu;
+  v = (v | (v << 8)) & 0x0300f00fu;
+  v = (v | (v << 4)) & 0x030c30c3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+// Morton code of every source point over 1024^3 cells spanning its own cloud's
+// box (lo word), pair index (hi word), global index (value).
+__global__ __launch_bounds__(256) void seg_source_key_kernel(const BuildPair* __restrict__ pairs, int n,
+                                                             const int64_t* __restrict__ blk_off,
+                                                             uint32_t* __restrict__ klo,
+                                                             uint32_t* __restrict__ khi,
+                                                             uint32_t* __restrict__ vals) {
+  const int p = find_segment(blk_off, n, blockIdx.x);
+  const BuildPair& bp = pairs[p];
+  const int64_t i = (int64_t)(blockIdx.x - blk_off[p]) * 256 + threadIdx.x;
+  if (i >= bp.n_src) return;
+  const float* s = bp.src + 3 * i;
+  const int cx = min(max(cell_of(s[0], bp.sox, bp.sinv_h, 1024), 0), 1023);
+  const int cy = min(max(cell_of(s[1], bp.soy, bp.sinv_h, 1024), 0), 1023);
+  const int cz = min(max(cell_of(s[2], bp.soz, bp.sinv_h, 1024), 0), 1023);
+  const int64_t gi = bp.src_off + i;
+  klo[gi] = spread10(cx) | (spread10(cy) << 1) | (spread10(cz) << 2);
+  if (khi) khi[gi] = (uint32_t)p;
+  vals[gi] = (uint32_t)gi;
+}
+
+// Ordered position -> pair (positions are grouped by pair after the sort),
+// copy the point into the structure-of-arrays source and record its index
+// inside its own cloud.
+__global__ __launch_bounds__(256) void source_gather_kernel(const BuildPair* __restrict__ pairs, int n,
+                                                            const int64_t* __restrict__ src_off,
+                                                            int64_t total,
+                                                            const uint32_t* __restrict__ sorted_vals,
+                                                            float* __restrict__ sx,
+                                                            float* __restrict__ sy,
+                                                            float* __restrict__ sz,
+                                                            uint32_t* __restrict__ perm_local) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int p = find_segment(src_off, n, i);
+  const BuildPair& bp = pairs[p];
+  const int64_t local = (int64_t)sorted_vals[i] - bp.src_off;
+  const float* s = bp.src + 3 * local;
+  sx[i] = s[0];
+  sy[i] = s[1];
+  sz[i] = s[2];
+  perm_local[i] = (uint32_t)local;
+}
+
+}  // namespace
+
+// ====================================================================== launchers
+int64_t scan_block_sums_needed(int64_t n) { return ceil_div(std::max<int64_t>(n, 1), kScanTile); }
+
+hipError_t launch_scan_exclusive(uint32_t* data, int64_t n, uint32_t* block_sums, int64_t cap_blocks,
+                                 hipStream_t s) {
+  const int64_t nb = ceil_div(n, kScanTile);
+  if (nb > cap_blocks) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(scan_tile_sums_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n,
+                     block_sums);
+  hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(1024), 0, s, block_sums, nb);
+  hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n,
+                     block_sums);
+  return hipGetLastError();
+}
+
+int64_t bbox_blocks(int64_t n) { return std::min<int64_t>(1024, std::max<int64_t>(1, ceil_div(n, 256))); }
+
+hipError_t launch_seg_bbox(const SegCloud* clouds, int n_clouds, const int64_t* blk_off,
+                           int64_t total_blocks, float* block_out, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(seg_bbox_kernel, dim3((unsigned)total_blocks), dim3(256), 0, s, clouds, n_clouds,
+                     blk_off, block_out);
+  hipLaunchKernelGGL(seg_bbox_final_kernel, dim3((unsigned)n_clouds), dim3(256), 0, s, blk_off,
+                     block_out, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_seg_targets(const BuildPair* pairs, int n, const int64_t* blk_off,
+                              int64_t total_blocks, uint64_t total_tab, uint32_t* cs,
+                              uint32_t* key, uint32_t* rank, uint32_t* scan_tmp, int64_t scan_cap,
+                              float4* tp, float4* tn, hipStream_t s) {
+  hipError_t e = hipMemsetAsync(cs, 0, sizeof(uint32_t) * (size_t)total_tab, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(seg_target_key_kernel, dim3((unsigned)total_blocks), dim3(256), 0, s, pairs, n,
+                     blk_off, cs, key, rank);
+  e = launch_scan_exclusive(cs, (int64_t)total_tab, scan_tmp, scan_cap, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(seg_target_scatter_kernel, dim3((unsigned)total_blocks), dim3(256), 0, s, pairs,
+                     n, blk_off, key, rank, cs, tp, tn);
+  return hipGetLastError();
+}
+
+int64_t radix_hist_needed(int64_t n) {
+  const int64_t h = 256 * ceil_div(std::max<int64_t>(n, 1), kSortTile);
+  return h + scan_block_sums_needed(h);
+}
+
+hipError_t launch_seg_sources(const BuildPair* pairs, int n, const int64_t* blk_off,
+                              int64_t total_blocks, const int64_t* src_off, int64_t total,
+                              SortBufs sb, uint32_t* hist, int64_t hist_cap, float* sx, float* sy,
+                              float* sz, uint32_t* perm_local, hipStream_t s) {
+  const bool two = n > 1;
+  hipLaunchKernelGGL(seg_source_key_kernel, dim3((unsigned)total_blocks), dim3(256), 0, s, pairs, n,
+                     blk_off, sb.klo[0], two ? sb.khi[0] : nullptr, sb.val[0]);
+  int hi_bits = 0;
+  while ((1 << hi_bits) < n) ++hi_bits;
+  const int nblk = (int)ceil_div(std::max<int64_t>(total, 1), kSortTile);
+  if ((int64_t)256 * nblk > hist_cap) return hipErrorInvalidValue;
+  uint32_t* scan_tmp = hist + (int64_t)256 * nblk;
+  const int64_t scan_cap = hist_cap - (int64_t)256 * nblk;
+  int cur = 0;
+  auto pass = [&](bool on_hi, int shift) -> hipError_t {
+    const uint32_t* dig = on_hi ? sb.khi[cur] : sb.klo[cur];
+    hipLaunchKernelGGL(radix_hist_kernel, dim3(nblk), dim3(kSortThreads), 0, s, dig, total, shift,
+                       hist, nblk);
+    hipError_t e = launch_scan_exclusive(hist, (int64_t)256 * nblk, scan_tmp, scan_cap, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(radix_scatter_kernel, dim3(nblk), dim3(kSortThreads), 0, s, dig, sb.klo[cur],
+                       two ? sb.khi[cur] : nullptr, sb.val[cur], total, shift, hist, nblk,
+                       sb.klo[cur ^ 1], two ? sb.khi[cur ^ 1] : nullptr, sb.val[cur ^ 1]);
+    cur ^= 1;
+    return hipGetLastError();
+  };
+  hipError_t e;
+  for (int shift = 0; shift < 30; shift += 8)
+    if ((e = pass(false, shift)) != hipSuccess) return e;
+  for (int shift = 0; shift < hi_bits; shift += 8)
+    if ((e = pass(true, shift)) != hipSuccess) return e;
+  hipLaunchKernelGGL(source_gather_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, pairs,
+                     n, src_off, total, sb.val[cur], sx, sy, sz, perm_local);
+  return hipGetLastError();
+}
+
+}  // namespace icp

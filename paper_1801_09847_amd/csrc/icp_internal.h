@@ -47,7 +47,7 @@ struct PassArgs {
   int32_t n_src;
   const float4* tp;       // cell-ordered target (x, y, z, bit pattern of original index)
   const float4* tn;       // cell-ordered target normals (nx, ny, nz, 0)
-  const uint32_t* cs;     // cell start table, ncell + 1 entries
+  const uint32_t* cs;     // cell start table, ncell + 1 entries (positions into tp)
   GridDesc g;
   float r2f;              // (float)(max_corr_dist^2)
   float inv_h2;           // (float)(inv_h^2)
@@ -70,29 +70,52 @@ struct SolveArgs {
   int32_t reduce_only;
 };
 
-// ---- launchers (icp_kernels.hip) ---------------------------------------
-hipError_t launch_bbox(const float* pts, const float* nrm, int64_t n, float* block_out, int nblk,
-                       float* final_out, hipStream_t s);
-int bbox_blocks(int64_t n);
+// ---- preparation (icp_build.hip) -----------------------------------------
+struct SegCloud {
+  const float* pts;  // (n, 3)
+  const float* nrm;  // optional (n, 3), checked for finiteness only
+  int64_t n;
+};
 
+// One pair of a segmented preparation call.  The cell tables of all pairs are
+// concatenated (pair p's table starts at tab_off and has g.ncell + 1 entries)
+// and hold positions into the concatenated cell-ordered target; sources are
+// concatenated at src_off, targets at tgt_off.
+struct BuildPair {
+  const float* src;
+  const float* tgt;
+  const float* tgt_n;  // null: no normals to gather
+  int64_t n_src, n_tgt;
+  int64_t src_off, tgt_off;
+  uint64_t tab_off;
+  GridDesc g;
+  double sox, soy, soz, sinv_h;  // Morton grid of the source (1024 cells per axis)
+};
+
+struct SortBufs {
+  uint32_t* klo[2];
+  uint32_t* khi[2];
+  uint32_t* val[2];
+};
+
+int64_t bbox_blocks(int64_t n);
+int64_t scan_block_sums_needed(int64_t n);
+int64_t radix_hist_needed(int64_t n);
 hipError_t launch_scan_exclusive(uint32_t* data, int64_t n, uint32_t* block_sums, int64_t cap_blocks,
                                  hipStream_t s);
-int64_t scan_block_sums_needed(int64_t n);
+// out: 8 floats per cloud (min xyz, max xyz, non-finite flag)
+hipError_t launch_seg_bbox(const SegCloud* clouds, int n_clouds, const int64_t* blk_off,
+                           int64_t total_blocks, float* block_out, float* out, hipStream_t s);
+hipError_t launch_seg_targets(const BuildPair* pairs, int n, const int64_t* blk_off,
+                              int64_t total_blocks, uint64_t total_tab, uint32_t* cs,
+                              uint32_t* key, uint32_t* rank, uint32_t* scan_tmp, int64_t scan_cap,
+                              float4* tp, float4* tn, hipStream_t s);
+hipError_t launch_seg_sources(const BuildPair* pairs, int n, const int64_t* blk_off,
+                              int64_t total_blocks, const int64_t* src_off, int64_t total,
+                              SortBufs sb, uint32_t* hist, int64_t hist_cap, float* sx, float* sy,
+                              float* sz, uint32_t* perm_local, hipStream_t s);
 
-hipError_t launch_target_grid(const float* tgt, const float* tgt_n, int64_t n, const GridDesc& g,
-                              uint32_t* key, uint32_t* rank, uint32_t* cs, float4* tp, float4* tn,
-                              uint32_t* scan_tmp, int64_t scan_cap, hipStream_t s);
-
-hipError_t launch_source_order(const float* src, int64_t n, double ox, double oy, double oz,
-                               double inv_h, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
-                               uint32_t* vals_alt, uint32_t* hist, int64_t hist_cap, float* sx,
-                               float* sy, float* sz, uint32_t** perm_out, hipStream_t s);
-int64_t radix_hist_needed(int64_t n);
-
-hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
-                             int64_t n, int key_bits, uint32_t* hist, int64_t hist_cap,
-                             uint32_t** keys_out, uint32_t** vals_out, hipStream_t s);
-
+// ---- loop (icp_kernels.hip) ---------------------------------------------
 hipError_t launch_state_init(IterState* st, const double T[16], hipStream_t s);
 
 hipError_t launch_pass(const PassArgs& a, int variant, int precision, bool write_corr, hipStream_t s);

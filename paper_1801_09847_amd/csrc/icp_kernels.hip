@@ -1,4 +1,7 @@
-// HIP kernels of the ICP registration loop for CDNA4 (gfx950, wave64).
+// HIP kernels of the ICP registration loop for CDNA4 (gfx950, wave64): the
+// per-iteration pass (correspondence + normal equations) and the solve /
+// pose update.  The grid and source ordering they consume are built by the
+// kernels in icp_build.hip.
 //
 // Method: Open3D paper Sec. 3.3 (ICP refinement with a maximum
 // correspondence distance, point-to-plane / point-to-point) and Sec. 4
@@ -52,291 +55,6 @@ __device__ inline void two_sum(float a, float b, float& s, float& e) {
 struct Mat16 {
   double v[16];
 };
-
-// ------------------------------------------------------------------ bbox + finiteness
-__global__ __launch_bounds__(256) void bbox_kernel(const float* __restrict__ pts,
-                                                   const float* __restrict__ nrm, int64_t n,
-                                                   float* __restrict__ block_out) {
-  float mn[3] = {INFINITY, INFINITY, INFINITY};
-  float mx[3] = {-INFINITY, -INFINITY, -INFINITY};
-  float bad = 0.0f;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const float x = pts[3 * i + 0], y = pts[3 * i + 1], z = pts[3 * i + 2];
-    if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
-      bad = 1.0f;
-    } else {
-      mn[0] = fminf(mn[0], x); mn[1] = fminf(mn[1], y); mn[2] = fminf(mn[2], z);
-      mx[0] = fmaxf(mx[0], x); mx[1] = fmaxf(mx[1], y); mx[2] = fmaxf(mx[2], z);
-    }
-    if (nrm) {
-      const float a = nrm[3 * i + 0], b = nrm[3 * i + 1], c = nrm[3 * i + 2];
-      if (!(isfinite(a) && isfinite(b) && isfinite(c))) bad = 1.0f;
-    }
-  }
-#pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) {
-    for (int a = 0; a < 3; ++a) {
-      mn[a] = fminf(mn[a], __shfl_xor(mn[a], off, kWave));
-      mx[a] = fmaxf(mx[a], __shfl_xor(mx[a], off, kWave));
-    }
-    bad = fmaxf(bad, __shfl_xor(bad, off, kWave));
-  }
-  __shared__ float red[4][8];
-  const int w = threadIdx.x / kWave;
-  if (lane_id() == 0) {
-    for (int a = 0; a < 3; ++a) { red[w][a] = mn[a]; red[w][3 + a] = mx[a]; }
-    red[w][6] = bad;
-  }
-  __syncthreads();
-  if (threadIdx.x < 7) {
-    const int a = threadIdx.x;
-    float v = red[0][a];
-    for (int k = 1; k < 4; ++k) v = (a < 3) ? fminf(v, red[k][a]) : fmaxf(v, red[k][a]);
-    block_out[blockIdx.x * 8 + a] = v;
-  }
-}
-
-__global__ __launch_bounds__(256) void bbox_final_kernel(const float* __restrict__ block_out, int nblk,
-                                                         float* __restrict__ out) {
-  __shared__ float red[7][256];
-  for (int a = 0; a < 7; ++a) {
-    float v = (a < 3) ? INFINITY : -INFINITY;
-    if (a == 6) v = 0.0f;
-    for (int b = threadIdx.x; b < nblk; b += 256) {
-      const float x = block_out[b * 8 + a];
-      v = (a < 3) ? fminf(v, x) : fmaxf(v, x);
-    }
-    red[a][threadIdx.x] = v;
-  }
-  __syncthreads();
-  if (threadIdx.x < 7) {
-    const int a = threadIdx.x;
-    float v = red[a][0];
-    for (int t = 1; t < 256; ++t) v = (a < 3) ? fminf(v, red[a][t]) : fmaxf(v, red[a][t]);
-    out[a] = v;
-  }
-}
-
-// ------------------------------------------------------------------ exclusive scan (uint32)
-constexpr int kScanThreads = 256;
-constexpr int kScanItems = 16;
-constexpr int kScanTile = kScanThreads * kScanItems;
-
-__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* total) {
-  __shared__ uint32_t wsum[kScanThreads / kWave];
-  const int lane = lane_id(), w = threadIdx.x / kWave;
-  uint32_t x = v;
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    const uint32_t y = __shfl_up(x, off, kWave);
-    if (lane >= off) x += y;
-  }
-  if (lane == kWave - 1) wsum[w] = x;
-  __syncthreads();
-  uint32_t before = 0, all = 0;
-  for (int k = 0; k < kScanThreads / kWave; ++k) {
-    if (k < w) before += wsum[k];
-    all += wsum[k];
-  }
-  __syncthreads();
-  *total = all;
-  return before + x - v;
-}
-
-__global__ __launch_bounds__(kScanThreads) void scan_tile_sums_kernel(const uint32_t* __restrict__ d,
-                                                                      int64_t n,
-                                                                      uint32_t* __restrict__ sums) {
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-  uint32_t s = 0;
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k)
-    if (base + k < n) s += d[base + k];
-  uint32_t total;
-  block_exclusive_scan(s, &total);
-  if (threadIdx.x == 0) sums[blockIdx.x] = total;
-}
-
-// Single block: exclusive scan of nb tile sums in place.
-__global__ __launch_bounds__(1024) void scan_top_kernel(uint32_t* __restrict__ sums, int64_t nb) {
-  __shared__ uint32_t tsum[1024];
-  const int64_t per = (nb + 1023) / 1024;
-  const int64_t b0 = (int64_t)threadIdx.x * per;
-  uint32_t s = 0;
-  for (int64_t k = 0; k < per; ++k)
-    if (b0 + k < nb) s += sums[b0 + k];
-  tsum[threadIdx.x] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t run = 0;
-    for (int t = 0; t < 1024; ++t) {
-      const uint32_t v = tsum[t];
-      tsum[t] = run;
-      run += v;
-    }
-  }
-  __syncthreads();
-  uint32_t run = tsum[threadIdx.x];
-  for (int64_t k = 0; k < per; ++k)
-    if (b0 + k < nb) {
-      const uint32_t v = sums[b0 + k];
-      sums[b0 + k] = run;
-      run += v;
-    }
-}
-
-__global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(uint32_t* __restrict__ d, int64_t n,
-                                                                  const uint32_t* __restrict__ sums) {
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-  uint32_t v[kScanItems];
-  uint32_t s = 0;
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    v[k] = (base + k < n) ? d[base + k] : 0u;
-    s += v[k];
-  }
-  uint32_t total;
-  uint32_t run = block_exclusive_scan(s, &total) + sums[blockIdx.x];
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    if (base + k < n) d[base + k] = run;
-    run += v[k];
-  }
-}
-
-// ------------------------------------------------------------------ target grid
-__device__ inline int cell_of(float p, double o, double inv_h, int dim) {
-  double u = ((double)p - o) * inv_h;
-  u = fmin(fmax(u, -2.0), (double)dim + 1.0);
-  return (int)floor(u);
-}
-
-__global__ __launch_bounds__(256) void target_key_kernel(const float* __restrict__ tgt, int64_t n,
-                                                         GridDesc g, uint32_t* __restrict__ counts,
-                                                         uint32_t* __restrict__ key,
-                                                         uint32_t* __restrict__ rank) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int cx = min(max(cell_of(tgt[3 * i + 0], g.ox, g.inv_h, g.dx), 0), g.dx - 1);
-  const int cy = min(max(cell_of(tgt[3 * i + 1], g.oy, g.inv_h, g.dy), 0), g.dy - 1);
-  const int cz = min(max(cell_of(tgt[3 * i + 2], g.oz, g.inv_h, g.dz), 0), g.dz - 1);
-  const uint32_t k = ((uint32_t)cz * (uint32_t)g.dy + (uint32_t)cy) * (uint32_t)g.dx + (uint32_t)cx;
-  key[i] = k;
-  rank[i] = atomicAdd(&counts[k], 1u);
-}
-
-__global__ __launch_bounds__(256) void target_scatter_kernel(
-    const float* __restrict__ tgt, const float* __restrict__ tgt_n, int64_t n,
-    const uint32_t* __restrict__ key, const uint32_t* __restrict__ rank,
-    const uint32_t* __restrict__ cs, float4* __restrict__ tp, float4* __restrict__ tn) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t pos = cs[key[i]] + rank[i];
-  tp[pos] = make_float4(tgt[3 * i + 0], tgt[3 * i + 1], tgt[3 * i + 2], __uint_as_float((uint32_t)i));
-  if (tgt_n) tn[pos] = make_float4(tgt_n[3 * i + 0], tgt_n[3 * i + 1], tgt_n[3 * i + 2], 0.0f);
-}
-
-// ------------------------------------------------------------------ LSD radix sort (stable)
-constexpr int kSortThreads = 256;
-constexpr int kSortRounds = 8;
-constexpr int kSortTile = kSortThreads * kSortRounds;
-
-__global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const uint32_t* __restrict__ keys,
-                                                                  int64_t n, int shift,
-                                                                  uint32_t* __restrict__ hist,
-                                                                  int nblk) {
-  __shared__ uint32_t h[256];
-  h[threadIdx.x] = 0;
-  __syncthreads();
-  const int64_t tile = (int64_t)blockIdx.x * kSortTile;
-  for (int k = 0; k < kSortRounds; ++k) {
-    const int64_t i = tile + k * kSortThreads + threadIdx.x;
-    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
-  }
-  __syncthreads();
-  hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
-}
-
-__global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
-    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals, int64_t n, int shift,
-    const uint32_t* __restrict__ offs, int nblk, uint32_t* __restrict__ keys_out,
-    uint32_t* __restrict__ vals_out) {
-  __shared__ uint32_t base[256];
-  __shared__ uint32_t wcnt[kSortThreads / kWave][256];
-  const int t = threadIdx.x, w = t / kWave, lane = lane_id();
-  base[t] = offs[(int64_t)t * nblk + blockIdx.x];
-  for (int k = 0; k < kSortThreads / kWave; ++k) wcnt[k][t] = 0;
-  __syncthreads();
-  const int64_t tile = (int64_t)blockIdx.x * kSortTile;
-  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int r = 0; r < kSortRounds; ++r) {
-    const int64_t i = tile + r * kSortThreads + t;
-    const bool valid = i < n;
-    const uint32_t key = valid ? keys[i] : 0u;
-    const uint32_t val = valid ? vals[i] : 0u;
-    const uint32_t d = (key >> shift) & 255u;
-    uint64_t peers = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t bb = __ballot(bit);
-      peers &= bit ? bb : ~bb;
-    }
-    const uint32_t rank_w = __popcll(peers & lt_mask);
-    if (valid && rank_w == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
-    __syncthreads();
-    if (valid) {
-      uint32_t dst = base[d] + rank_w;
-      for (int k = 0; k < w; ++k) dst += wcnt[k][d];
-      keys_out[dst] = key;
-      vals_out[dst] = val;
-    }
-    __syncthreads();
-    uint32_t add = 0;
-    for (int k = 0; k < kSortThreads / kWave; ++k) {
-      add += wcnt[k][t];
-      wcnt[k][t] = 0;
-    }
-    base[t] += add;
-    __syncthreads();
-  }
-}
-
-// ------------------------------------------------------------------ source ordering
-__device__ inline uint32_t spread10(uint32_t v) {
-  v &= 0x3ffu;
-  v = (v | (v << 16)) & 0x030000ffu;
-  v = (v | (v << 8)) & 0x0300f00fu;
-  v = (v | (v << 4)) & 0x030c30c3u;
-  v = (v | (v << 2)) & 0x09249249u;
-  return v;
-}
-
-__global__ __launch_bounds__(256) void source_key_kernel(const float* __restrict__ src, int64_t n,
-                                                         double ox, double oy, double oz,
-                                                         double inv_h, uint32_t* __restrict__ keys,
-                                                         uint32_t* __restrict__ vals) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int cx = min(max(cell_of(src[3 * i + 0], ox, inv_h, 1024), 0), 1023);
-  const int cy = min(max(cell_of(src[3 * i + 1], oy, inv_h, 1024), 0), 1023);
-  const int cz = min(max(cell_of(src[3 * i + 2], oz, inv_h, 1024), 0), 1023);
-  keys[i] = spread10(cx) | (spread10(cy) << 1) | (spread10(cz) << 2);
-  vals[i] = (uint32_t)i;
-}
-
-__global__ __launch_bounds__(256) void source_gather_kernel(const float* __restrict__ src, int64_t n,
-                                                            const uint32_t* __restrict__ perm,
-                                                            float* __restrict__ sx,
-                                                            float* __restrict__ sy,
-                                                            float* __restrict__ sz) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int64_t o = perm[i];
-  sx[i] = src[3 * o + 0];
-  sy[i] = src[3 * o + 1];
-  sz[i] = src[3 * o + 2];
-}
 
 // ------------------------------------------------------------------ loop state
 __global__ void state_init_kernel(IterState* st, Mat16 T) {
@@ -552,7 +270,7 @@ __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
       if (a.jprev) {
         // warm start: the previous pass's match bounds this pass's distance
         const uint32_t jp = a.jprev[i];
-        if (jp < (uint32_t)a.n_tgt) {
+        if (jp != 0xffffffffu) {
           const float4 p = a.tp[jp];
           const float dx = q32x - p.x, dy = q32y - p.y, dz = q32z - p.z;
           float d2 = dx * dx + dy * dy;
@@ -883,87 +601,6 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 }  // namespace
 
 // ====================================================================== launchers
-int bbox_blocks(int64_t n) { return (int)std::min<int64_t>(1024, std::max<int64_t>(1, ceil_div(n, 256))); }
-
-hipError_t launch_bbox(const float* pts, const float* nrm, int64_t n, float* block_out, int nblk,
-                       float* final_out, hipStream_t s) {
-  hipLaunchKernelGGL(bbox_kernel, dim3(nblk), dim3(256), 0, s, pts, nrm, n, block_out);
-  hipLaunchKernelGGL(bbox_final_kernel, dim3(1), dim3(256), 0, s, block_out, nblk, final_out);
-  return hipGetLastError();
-}
-
-int64_t scan_block_sums_needed(int64_t n) { return ceil_div(n, kScanTile); }
-
-hipError_t launch_scan_exclusive(uint32_t* data, int64_t n, uint32_t* block_sums, int64_t cap_blocks,
-                                 hipStream_t s) {
-  const int64_t nb = ceil_div(n, kScanTile);
-  if (nb > cap_blocks) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(scan_tile_sums_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n,
-                     block_sums);
-  hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(1024), 0, s, block_sums, nb);
-  hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n,
-                     block_sums);
-  return hipGetLastError();
-}
-
-hipError_t launch_target_grid(const float* tgt, const float* tgt_n, int64_t n, const GridDesc& g,
-                              uint32_t* key, uint32_t* rank, uint32_t* cs, float4* tp, float4* tn,
-                              uint32_t* scan_tmp, int64_t scan_cap, hipStream_t s) {
-  hipError_t e = hipMemsetAsync(cs, 0, ((size_t)g.ncell + 1) * sizeof(uint32_t), s);
-  if (e != hipSuccess) return e;
-  const unsigned nb = (unsigned)ceil_div(n, 256);
-  hipLaunchKernelGGL(target_key_kernel, dim3(nb), dim3(256), 0, s, tgt, n, g, cs, key, rank);
-  e = launch_scan_exclusive(cs, (int64_t)g.ncell + 1, scan_tmp, scan_cap, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(target_scatter_kernel, dim3(nb), dim3(256), 0, s, tgt, tgt_n, n, key, rank, cs,
-                     tp, tn);
-  return hipGetLastError();
-}
-
-int64_t radix_hist_needed(int64_t n) {
-  const int64_t h = 256 * ceil_div(std::max<int64_t>(n, 1), kSortTile);
-  return h + ceil_div(h, kScanTile);
-}
-
-hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
-                             int64_t n, int key_bits, uint32_t* hist, int64_t hist_cap,
-                             uint32_t** keys_out, uint32_t** vals_out, hipStream_t s) {
-  const int nblk = (int)ceil_div(std::max<int64_t>(n, 1), kSortTile);
-  if ((int64_t)256 * nblk > hist_cap) return hipErrorInvalidValue;
-  // the histogram scan needs its own tile sums after the histogram itself
-  uint32_t* scan_tmp = hist + (int64_t)256 * nblk;
-  const int64_t scan_cap = hist_cap - (int64_t)256 * nblk;
-  uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
-  for (int shift = 0; shift < key_bits; shift += 8) {
-    hipLaunchKernelGGL(radix_hist_kernel, dim3(nblk), dim3(kSortThreads), 0, s, ki, n, shift, hist,
-                       nblk);
-    hipError_t e = launch_scan_exclusive(hist, (int64_t)256 * nblk, scan_tmp, scan_cap, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(radix_scatter_kernel, dim3(nblk), dim3(kSortThreads), 0, s, ki, vi, n, shift,
-                       hist, nblk, ko, vo);
-    std::swap(ki, ko);
-    std::swap(vi, vo);
-  }
-  *keys_out = ki;
-  *vals_out = vi;
-  return hipGetLastError();
-}
-
-hipError_t launch_source_order(const float* src, int64_t n, double ox, double oy, double oz,
-                               double inv_h, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
-                               uint32_t* vals_alt, uint32_t* hist, int64_t hist_cap, float* sx,
-                               float* sy, float* sz, uint32_t** perm_out, hipStream_t s) {
-  const unsigned nb = (unsigned)ceil_div(n, 256);
-  hipLaunchKernelGGL(source_key_kernel, dim3(nb), dim3(256), 0, s, src, n, ox, oy, oz, inv_h, keys,
-                     vals);
-  uint32_t *ko = nullptr, *vo = nullptr;
-  hipError_t e = launch_radix_sort(keys, vals, keys_alt, vals_alt, n, 30, hist, hist_cap, &ko, &vo, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(source_gather_kernel, dim3(nb), dim3(256), 0, s, src, n, vo, sx, sy, sz);
-  *perm_out = vo;
-  return hipGetLastError();
-}
-
 hipError_t launch_state_init(IterState* st, const double T[16], hipStream_t s) {
   Mat16 m;
   for (int k = 0; k < 16; ++k) m.v[k] = T[k];

@@ -179,6 +179,126 @@ typedef struct {
 int icp_register_batch(icp_ctx_t *ctx, const icp_pair_t *pairs, int32_t n_pairs, int32_t variant,
                        int32_t precision, icp_result_t *out);
 
+/* ---- voxel downsampling and multi-scale registration --------------------
+ * Voxel downsampling (Sec. 3.3, voxel_down_sample before registration): the
+ * cloud's box minimum o and the voxel edge v define voxel indices
+ * floor((p - o) / v) per axis (float64); each occupied voxel yields the mean
+ * of its points (float64 sum in original-index order, rounded to float32)
+ * and, with normals, the normalised float64 sum of its points' normals (the
+ * first point's normal if that sum is shorter than 1e-12).  Outputs are in
+ * voxel-key order (x fastest, then y, then z). */
+
+/* Downsamples one device cloud.
+ *   pts, normals  device (n, 3) float32; normals may be NULL
+ *   voxel         finite, > 0 (metres)
+ *   out_pts, out_normals  device (cap, 3) float32 (out_normals required iff
+ *                 normals given); cap = n always suffices
+ *   n_out         host: number of occupied voxels
+ * Errors: INVALID_ARG, NONFINITE, TOO_LARGE (more than 2^48 voxels in the box,
+ * or cap < *n_out: then *n_out is set and no output beyond cap is written),
+ * OOM, DEVICE. */
+int icp_voxel_downsample(icp_ctx_t *ctx, const float *pts, const float *normals, int64_t n,
+                         double voxel, float *out_pts, float *out_normals, int64_t cap,
+                         int64_t *n_out);
+
+/* Coarse-to-fine registration (as in the fragment registration stage of the
+ * reconstruction pipeline, Sec. 3.4): for each level l, both clouds are
+ * downsampled with voxel[l] (0: the original clouds), then registered with
+ * max_corr_dist[l] and max_iter[l] starting from the previous level's pose.
+ * A DEGENERATE level ends the call.  `out` is the last level's result with
+ * n_iter = the total number of pose updates.  n_levels in [1, 16]; arrays are
+ * host memory.  Errors as icp_register / icp_voxel_downsample. */
+int icp_register_multiscale(icp_ctx_t *ctx, const float *src_xyz, int64_t n_src, const float *tgt_xyz,
+                            const float *tgt_normals, int64_t n_tgt, const double T_init[16],
+                            int32_t n_levels, const double *voxel, const int32_t *max_iter,
+                            const double *max_corr_dist, double rel_tol, int32_t variant,
+                            int32_t precision, icp_result_t *out);
+
+/* ---- served form: continuous batching of registration requests ----------
+ * Requests (pairs of clouds, as produced one by one by a reconstruction
+ * pipeline's fragment registration stage, Sec. 3.4) are submitted at any
+ * time.  The server copies each request's inputs into its own device memory,
+ * admits requests FIFO while registration slots are free and its device
+ * memory budget allows, and advances every admitted request through a
+ * coarse-to-fine schedule (voxel downsampling then ICP per level, as
+ * icp_register_multiscale).  One server step runs `iters_per_step`
+ * iterations of all running requests together (one captured HIP graph), then
+ * retires finished levels and requests.  A request's result is bitwise the
+ * one icp_register_multiscale gives for it alone.
+ * Level l of a request uses max_corr_dist = corr_dist[l] if > 0, else
+ * corr_factor * max(voxel[l], spacing) with the request's target spacing. */
+typedef struct icp_server icp_server_t;
+
+typedef struct {
+  int32_t device;
+  int32_t max_slots;          /* requests registered concurrently, >= 1 */
+  uint64_t hbm_budget_bytes;  /* device memory for inputs and working data of all requests */
+  int32_t n_levels;           /* 1..4 */
+  int32_t iters[4];           /* max_iter per level */
+  double voxel[4];            /* voxel edge per level (0: original clouds) */
+  double corr_dist[4];        /* > 0: fixed max_corr_dist per level */
+  double corr_factor;         /* rule factor for levels without corr_dist (e.g. 2) */
+  int32_t variant;            /* ICP_POINT_TO_PLANE / ICP_POINT_TO_POINT */
+  int32_t precision;          /* ICP_PREC_* */
+  int32_t iters_per_step;     /* iterations per server step, 1..64 */
+  int32_t background_thread;  /* 1: a server thread runs steps; 0: caller drives icp_server_step */
+} icp_server_cfg_t;
+
+typedef struct {
+  const float *src_xyz;       /* (n_src, 3) float32, device or host (host_memory) */
+  const float *tgt_xyz;       /* (n_tgt, 3) */
+  const float *tgt_normals;   /* (n_tgt, 3); required for point-to-plane */
+  int64_t n_src;
+  int64_t n_tgt;
+  double T_init[16];          /* host, row-major */
+  double rel_tol;             /* >= 0, per level */
+  double spacing;             /* mean target point spacing (m), 0 if unknown */
+  int32_t host_memory;        /* 1: the three arrays are host memory */
+  int32_t reserved;           /* must be 0 */
+  uint64_t user_tag;
+} icp_request_t;
+
+typedef struct {
+  uint64_t ticket;
+  uint64_t user_tag;
+  icp_result_t result;        /* valid when error == 0; n_iter = total pose updates */
+  int32_t error;              /* 0 or a negative ICP_E_* code */
+  int32_t reserved;
+  int64_t t_submit_ns;        /* CLOCK_MONOTONIC, at icp_server_submit entry */
+  int64_t t_admit_ns;         /* when a slot was assigned */
+  int64_t t_done_ns;          /* when the result was posted */
+} icp_completion_t;
+
+/* Creates a server (its own context, stream, device memory pool of
+ * hbm_budget_bytes and captured step graph).  Errors: INVALID_ARG, OOM, DEVICE. */
+int icp_server_create(const icp_server_cfg_t *cfg, icp_server_t **out);
+
+/* Copies the request's inputs (device-to-device or host-to-device) into
+ * server memory before returning -- the caller may free its buffers at once
+ * -- and queues it.  *ticket identifies the completion.  Thread-safe.
+ * Errors: INVALID_ARG, TOO_LARGE (inputs alone exceed the budget), DEVICE. */
+int icp_server_submit(icp_server_t *srv, const icp_request_t *req, uint64_t *ticket);
+
+/* Caller-driven mode: one server step (admission, level preparation,
+ * iters_per_step iterations, retirement).  *n_busy (optional) receives the
+ * number of queued + running requests after the step.  With a background
+ * thread this is a no-op.  Errors: DEVICE (the server is then unusable). */
+int icp_server_step(icp_server_t *srv, int32_t *n_busy);
+
+/* Moves up to cap finished requests' completions to out (host), in
+ * completion order; *n_out receives the count.  Non-blocking.  Thread-safe. */
+int icp_server_poll(icp_server_t *srv, icp_completion_t *out, int32_t cap, int32_t *n_out);
+
+/* Blocks until `ticket` has completed and moves its completion to *out (in
+ * caller-driven mode it runs steps itself).  Errors: NOT_FOUND (unknown or
+ * already delivered ticket), DEVICE. */
+int icp_server_wait(icp_server_t *srv, uint64_t ticket, icp_completion_t *out);
+
+/* Stops the server: requests not yet completed are completed with
+ * ICP_E_CANCELLED (and dropped), all device memory is released.  NULL is a
+ * no-op. */
+int icp_server_destroy(icp_server_t *srv);
+
 /* ---- kernel timing (measurement support) --------------------------------
  * With profiling enabled, every registration call on the context records a
  * pair of HIP events around each launch of the fused correspondence /

@@ -72,6 +72,9 @@ def lib():
             C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
             C.POINTER(C.c_int32), C.c_void_p, C.c_void_p, C.c_void_p]
         L.oracle_icp_register.restype = C.c_int
+        L.oracle_voxel_downsample.argtypes = [_f32p, C.c_void_p, C.c_int64, C.c_double, _f32p,
+                                              C.c_void_p]
+        L.oracle_voxel_downsample.restype = C.c_int64
         _lib = L
     return _lib
 
@@ -159,6 +162,41 @@ def normal_equations(src, T, tgt, tgt_normals, max_corr_dist, variant="point_to_
     if rc != 0:
         raise ValueError("oracle_normal_equations: invalid arguments")
     return A21, b6, sd2.value, nin.value
+
+
+def voxel_downsample(pts, voxel, normals=None):
+    """(points, normals or None) of the voxel means, in voxel-key order."""
+    pts = _pts(pts)
+    nrm = _pts(normals) if normals is not None else None
+    out = np.empty_like(pts)
+    outn = np.empty_like(pts) if nrm is not None else None
+    m = lib().oracle_voxel_downsample(pts, nrm.ctypes.data if nrm is not None else None, len(pts),
+                                      float(voxel), out, outn.ctypes.data if outn is not None else None)
+    if m < 0:
+        raise ValueError("oracle_voxel_downsample: invalid arguments")
+    return out[:m].copy(), (outn[:m].copy() if outn is not None else None)
+
+
+def register_multiscale(src, tgt, tgt_normals, T_init, voxels, iters, dists, rel_tol=0.0,
+                        variant="point_to_plane", selection=SEL_PINNED_F32):
+    """Coarse-to-fine: per level, downsample both clouds (voxel 0: keep) and
+    register from the previous level's pose; stops at a degenerate level."""
+    T = np.asarray(T_init, np.float64).reshape(4, 4)
+    total = 0
+    res = None
+    for v, k, r in zip(voxels, iters, dists):
+        if v > 0:
+            s, _ = voxel_downsample(src, v)
+            t, tn = voxel_downsample(tgt, v, tgt_normals if variant in ("point_to_plane", 1) else None)
+        else:
+            s, t, tn = src, tgt, tgt_normals
+        res = icp_register(s, t, tn, T, r, k, rel_tol, variant, selection)
+        total += res.n_iter
+        T = res.T
+        if res.status == STATUS_DEGENERATE:
+            break
+    res.n_iter = total
+    return res
 
 
 @dataclass

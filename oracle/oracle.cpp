@@ -556,4 +556,61 @@ int oracle_icp_register(const float* src, int64_t n_src, const float* tgt, const
   }
 }
 
+// Voxel downsampling (Sec. 3.3, voxel_down_sample): voxel indices
+// floor(((double)p - o) * (1 / voxel)) per axis with o the box minimum and
+// dims = floor((max - o) / voxel) + 1, key = (cz * dy + cy) * dx + cx; output
+// one point per occupied voxel in increasing key order: the float64 mean of
+// its points summed in original-index order (rounded to float32) and, with
+// normals, the normalised float64 sum of its normals (the first point's
+// normal when that sum is shorter than 1e-12).  Returns the voxel count.
+int64_t oracle_voxel_downsample(const float* pts, const float* nrm, int64_t n, double voxel,
+                                float* out_pts, float* out_nrm) {
+  if (!pts || n < 1 || !(voxel > 0.0)) return -1;
+  double mn[3], mx[3];
+  for (int a = 0; a < 3; ++a) mn[a] = mx[a] = pts[a];
+  for (int64_t i = 1; i < n; ++i)
+    for (int a = 0; a < 3; ++a) {
+      mn[a] = std::min(mn[a], (double)pts[3 * i + a]);
+      mx[a] = std::max(mx[a], (double)pts[3 * i + a]);
+    }
+  const double inv = 1.0 / voxel;
+  int64_t dims[3];
+  for (int a = 0; a < 3; ++a) dims[a] = (int64_t)std::floor((mx[a] - mn[a]) * inv) + 1;
+  std::vector<uint64_t> key((size_t)n);
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t c[3];
+    for (int a = 0; a < 3; ++a) {
+      c[a] = (int64_t)std::floor(((double)pts[3 * i + a] - mn[a]) * inv);
+      c[a] = std::min(std::max(c[a], (int64_t)0), dims[a] - 1);
+    }
+    key[(size_t)i] = (uint64_t)((c[2] * dims[1] + c[1]) * dims[0] + c[0]);
+  }
+  std::vector<int64_t> order((size_t)n);
+  for (int64_t i = 0; i < n; ++i) order[(size_t)i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int64_t a, int64_t b) { return key[(size_t)a] < key[(size_t)b]; });
+  int64_t v = 0;
+  for (int64_t s = 0; s < n;) {
+    int64_t e = s;
+    while (e < n && key[(size_t)order[(size_t)e]] == key[(size_t)order[(size_t)s]]) ++e;
+    double sum[3] = {0.0, 0.0, 0.0}, ns[3] = {0.0, 0.0, 0.0};
+    for (int64_t k = s; k < e; ++k) {
+      const int64_t i = order[(size_t)k];
+      for (int a = 0; a < 3; ++a) {
+        sum[a] += (double)pts[3 * i + a];
+        if (nrm) ns[a] += (double)nrm[3 * i + a];
+      }
+    }
+    for (int a = 0; a < 3; ++a) out_pts[3 * v + a] = (float)(sum[a] / (double)(e - s));
+    if (nrm && out_nrm) {
+      const double len = std::sqrt((ns[0] * ns[0] + ns[1] * ns[1]) + ns[2] * ns[2]);
+      for (int a = 0; a < 3; ++a)
+        out_nrm[3 * v + a] = len < 1e-12 ? nrm[3 * order[(size_t)s] + a] : (float)(ns[a] / len);
+    }
+    ++v;
+    s = e;
+  }
+  return v;
+}
+
 }  // extern "C"

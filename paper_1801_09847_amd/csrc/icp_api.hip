@@ -22,12 +22,11 @@
 #include <string>
 #include <vector>
 
-#include "../../include/icp.h"
-#include "icp_internal.h"
+#include "icp_runtime.h"
 
 using namespace icp;
 
-namespace {
+namespace icp_rt {
 
 thread_local std::string g_last_error;
 
@@ -41,81 +40,6 @@ int hip_fail(hipError_t e, const char* what) {
                                                                                 : ICP_E_DEVICE;
   return fail(code, std::string(what) + ": " + hipGetErrorString(e));
 }
-
-#define HIP_TRY(expr, what)                            \
-  do {                                                 \
-    hipError_t e_ = (expr);                            \
-    if (e_ != hipSuccess) return hip_fail(e_, what);   \
-  } while (0)
-
-// A device buffer that only grows (reused across calls).
-struct Buf {
-  void* p = nullptr;
-  size_t cap = 0;
-  hipError_t ensure(size_t bytes) {
-    if (bytes <= cap && p) return hipSuccess;
-    if (p) {
-      hipError_t e = hipFree(p);
-      p = nullptr;
-      cap = 0;
-      if (e != hipSuccess) return e;
-    }
-    const size_t want = std::max<size_t>(bytes + bytes / 8, 256);
-    hipError_t e = hipMalloc(&p, want);
-    if (e != hipSuccess) {
-      p = nullptr;
-      return e;
-    }
-    cap = want;
-    return hipSuccess;
-  }
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    cap = 0;
-  }
-  template <class T>
-  T* as() const {
-    return static_cast<T*>(p);
-  }
-};
-
-constexpr size_t kHostBytes = 4096;
-constexpr int kDefaultSub = 1;
-
-}  // namespace
-
-struct icp_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  // per-call descriptors, loop header, warm-start matches, partials, states
-  Buf desc;
-  // preparation scratch
-  Buf bbox_part, t_key, t_rank, scan_tmp, s_hist;
-  Buf sk[6];  // sort buffers: klo[2], khi[2], val[2]
-  // prepared pairs (concatenated)
-  Buf cs, tp, tn, sx, sy, sz, perm;
-  void* host = nullptr;  // pinned staging
-  size_t host_cap = 0;
-  // kernel timing
-  bool profiling = false;
-  std::vector<hipEvent_t> ev;  // [0] call start, [1] call end, [2+2k]/[3+2k] around pass k
-  icp_profile_t prof{};
-};
-
-namespace {
-
-struct DeviceGuard {
-  int prev = -1;
-  bool ok = false;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(dev) == hipSuccess) ok = true;
-  }
-  ~DeviceGuard() {
-    if (prev >= 0) (void)hipSetDevice(prev);
-  }
-};
 
 int ctx_init(icp_ctx* c, int device, void* stream) {
   c->device = device;
@@ -136,7 +60,8 @@ void ctx_free(icp_ctx* c) {
   DeviceGuard g(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   Buf* bufs[] = {&c->desc, &c->bbox_part, &c->t_key, &c->t_rank, &c->scan_tmp, &c->s_hist,
-                 &c->cs, &c->tp, &c->tn, &c->sx, &c->sy, &c->sz, &c->perm};
+                 &c->cs, &c->tp, &c->tn, &c->sx, &c->sy, &c->sz, &c->perm, &c->vdesc,
+                 &c->vflags, &c->vstarts, &c->lvl_src, &c->lvl_tgt, &c->lvl_tn};
   for (Buf* b : bufs) b->release();
   for (Buf& b : c->sk) b.release();
   if (c->host) (void)hipHostFree(c->host);
@@ -298,25 +223,6 @@ GridDesc make_grid(const float* mn, const float* mx, double r, int64_t n_tgt) {
 }
 
 // ------------------------------------------------------------------ call layout
-struct PairIn {
-  const float* src;
-  int64_t n_src;
-  const float* tgt;
-  const float* tgt_n;  // null: point-to-point (normals neither checked nor gathered)
-  int64_t n_tgt;
-  double r;
-};
-
-// Byte offsets of one call's descriptors; the same layout is used in pinned
-// host staging and in the context's `desc` device buffer.
-struct Layout {
-  size_t clouds, blk_bbox, pairs, blk_t, blk_s, src_off;  // preparation
-  size_t pargs, sargs, states, items;                       // loop header
-  size_t header_end;                                        // end of uploaded part
-  size_t bbox_out, jprev, part;                             // device only
-  size_t total;
-};
-
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 Layout make_layout(int n, int64_t n_items, int64_t total_src, int64_t total_tiles) {
@@ -333,6 +239,7 @@ Layout make_layout(int n, int64_t n_items, int64_t total_src, int64_t total_tile
   L.blk_t = take(sizeof(int64_t) * (n + 1));
   L.blk_s = take(sizeof(int64_t) * (n + 1));
   L.src_off = take(sizeof(int64_t) * (n + 1));
+  L.blk_tab = take(sizeof(int64_t) * (n + 1));
   L.pargs = take(sizeof(PassArgs) * n);
   L.sargs = take(sizeof(SolveArgs) * n);
   L.states = take(sizeof(IterState) * n);
@@ -345,24 +252,15 @@ Layout make_layout(int n, int64_t n_items, int64_t total_src, int64_t total_tile
   return L;
 }
 
-struct Prep {
-  int n = 0;
-  Layout L;
-  std::vector<GridDesc> g;
-  std::vector<int64_t> src_off, tgt_off, tile_off;
-  std::vector<uint64_t> tab_off;
-  int64_t total_src = 0, total_tgt = 0, total_tiles = 0;
-  uint64_t total_tab = 0;
-  int sub = 1;
-};
-
 int64_t tiles_of(int64_t n) { return (n + kTile - 1) / kTile; }
 
-// Steps 1 and 2 of a call for n pairs: checks, boxes, grids and the
-// segmented build into the context's concatenated arrays.
-int prepare_pairs(icp_ctx* c, int n, const PairIn* in, Prep* P) {
+// Step 1 of a call for n pairs: checks, boxes and grid sizes.  The staged
+// build descriptors stay in pinned host memory for build_pairs.
+int plan_pairs(icp_ctx* c, int n, const PairIn* in, Prep* P, int* bad) {
   hipStream_t s = c->stream;
+  *bad = -1;
   P->n = n;
+  P->normals = in[0].tgt_n != nullptr;
   P->src_off.assign(n + 1, 0);
   P->tgt_off.assign(n + 1, 0);
   P->tile_off.assign(n + 1, 0);
@@ -384,7 +282,7 @@ int prepare_pairs(icp_ctx* c, int n, const PairIn* in, Prep* P) {
   char* hh = static_cast<char*>(c->host);
   char* dd = c->desc.as<char>();
 
-  // 1. boxes and finiteness of all clouds (target with its normals, source)
+  // boxes and finiteness of all clouds (target with its normals, source)
   SegCloud* cl = reinterpret_cast<SegCloud*>(hh + L.clouds);
   int64_t* bo = reinterpret_cast<int64_t*>(hh + L.blk_bbox);
   bo[0] = 0;
@@ -408,21 +306,25 @@ int prepare_pairs(icp_ctx* c, int n, const PairIn* in, Prep* P) {
   for (int p = 0; p < n; ++p) {
     const float* t = hbox + 16 * p;
     const float* q = t + 8;
-    if (t[6] != 0.0f || q[6] != 0.0f)
+    if (t[6] != 0.0f || q[6] != 0.0f) {
+      *bad = p;
       return fail(ICP_E_NONFINITE, (t[6] != 0.0f ? std::string("non-finite target coordinate or normal")
                                                  : std::string("non-finite source coordinate")) +
                                        (n > 1 ? " in pair " + std::to_string(p) : std::string()));
+    }
   }
 
-  // 2. grids, offsets and the segmented build
+  // grids and offsets
   P->g.resize(n);
   P->tab_off.assign(n + 1, 0);
   BuildPair* bp = reinterpret_cast<BuildPair*>(hh + L.pairs);
   int64_t* bt = reinterpret_cast<int64_t*>(hh + L.blk_t);
   int64_t* bs = reinterpret_cast<int64_t*>(hh + L.blk_s);
   int64_t* so = reinterpret_cast<int64_t*>(hh + L.src_off);
+  int64_t* bk = reinterpret_cast<int64_t*>(hh + L.blk_tab);
   bt[0] = 0;
   bs[0] = 0;
+  bk[0] = 0;
   for (int p = 0; p < n; ++p) {
     const float* t = hbox + 16 * p;
     const float* q = t + 8;
@@ -435,9 +337,11 @@ int prepare_pairs(icp_ctx* c, int n, const PairIn* in, Prep* P) {
     const double hs = ext > 0.0 ? ext / 1023.5 : 1.0;
     bp[p] = BuildPair{in[p].src, in[p].tgt, in[p].tgt_n, in[p].n_src, in[p].n_tgt,
                       P->src_off[p], P->tgt_off[p], P->tab_off[p], P->g[p],
-                      (double)q[0], (double)q[1], (double)q[2], 1.0 / hs};
+                      (double)q[0], (double)q[1], (double)q[2], 1.0 / hs,
+                      nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     bt[p + 1] = bt[p] + (in[p].n_tgt + 255) / 256;
     bs[p + 1] = bs[p] + (in[p].n_src + 255) / 256;
+    bk[p + 1] = bk[p] + ((int64_t)P->g[p].ncell + 1 + 255) / 256;
     so[p] = P->src_off[p];
   }
   so[n] = P->src_off[n];
@@ -445,28 +349,64 @@ int prepare_pairs(icp_ctx* c, int n, const PairIn* in, Prep* P) {
   if (P->total_tab >= (uint64_t)UINT32_MAX)
     return fail(ICP_E_TOO_LARGE, "grid tables of one call exceed 2^32 cells");
   P->sub = P->g[0].sub;
-  const bool normals = in[0].tgt_n != nullptr;
+  return ICP_SUCCESS;
+}
+
+// Step 2: segmented build of a planned call into dst[] (null: slices of the
+// context's concatenated arrays; the cell tables are then localised in place).
+int build_pairs(icp_ctx* c, Prep* P, const PairDst* dst) {
+  hipStream_t s = c->stream;
+  const Layout& L = P->L;
+  const int n = P->n;
+  const bool normals = P->normals;
+  char* hh = static_cast<char*>(c->host);
+  char* dd = c->desc.as<char>();
+  BuildPair* bp = reinterpret_cast<BuildPair*>(hh + L.pairs);
+  const int64_t* bt = reinterpret_cast<const int64_t*>(hh + L.blk_t);
+  const int64_t* bs = reinterpret_cast<const int64_t*>(hh + L.blk_s);
+  const int64_t* bk = reinterpret_cast<const int64_t*>(hh + L.blk_tab);
   const int64_t scan_cap = scan_block_sums_needed((int64_t)P->total_tab);
   const int64_t hist_cap = radix_hist_needed(P->total_src);
   HIP_TRY(c->cs.ensure(4 * (size_t)P->total_tab), "alloc");
-  HIP_TRY(c->tp.ensure(16 * (size_t)P->total_tgt), "alloc");
-  if (normals) HIP_TRY(c->tn.ensure(16 * (size_t)P->total_tgt), "alloc");
-  HIP_TRY(c->sx.ensure(4 * (size_t)P->total_src), "alloc");
-  HIP_TRY(c->sy.ensure(4 * (size_t)P->total_src), "alloc");
-  HIP_TRY(c->sz.ensure(4 * (size_t)P->total_src), "alloc");
   HIP_TRY(c->perm.ensure(4 * (size_t)P->total_src), "alloc");
+  if (!dst) {
+    HIP_TRY(c->tp.ensure(16 * (size_t)P->total_tgt), "alloc");
+    if (normals) HIP_TRY(c->tn.ensure(16 * (size_t)P->total_tgt), "alloc");
+    HIP_TRY(c->sx.ensure(4 * (size_t)P->total_src), "alloc");
+    HIP_TRY(c->sy.ensure(4 * (size_t)P->total_src), "alloc");
+    HIP_TRY(c->sz.ensure(4 * (size_t)P->total_src), "alloc");
+  }
   HIP_TRY(c->t_key.ensure(4 * (size_t)P->total_tgt), "alloc");
   HIP_TRY(c->t_rank.ensure(4 * (size_t)P->total_tgt), "alloc");
   HIP_TRY(c->scan_tmp.ensure(4 * (size_t)scan_cap), "alloc");
   HIP_TRY(c->s_hist.ensure(4 * (size_t)hist_cap), "alloc");
-  for (Buf& b : c->sk) HIP_TRY(b.ensure(4 * (size_t)P->total_src), "alloc");
+  for (Buf& b : c->sk) HIP_TRY(b.ensure(4 * ((size_t)P->total_src + 1)), "alloc");
+  for (int p = 0; p < n; ++p) {
+    if (dst) {
+      bp[p].cs_dst = dst[p].cs;
+      bp[p].tp_dst = dst[p].tp;
+      bp[p].tn_dst = normals ? dst[p].tn : nullptr;
+      bp[p].sx_dst = dst[p].sx;
+      bp[p].sy_dst = dst[p].sy;
+      bp[p].sz_dst = dst[p].sz;
+      bp[p].perm_dst = dst[p].perm ? dst[p].perm : c->perm.as<uint32_t>() + P->src_off[p];
+    } else {
+      bp[p].cs_dst = c->cs.as<uint32_t>() + P->tab_off[p];
+      bp[p].tp_dst = c->tp.as<float4>() + P->tgt_off[p];
+      bp[p].tn_dst = normals ? c->tn.as<float4>() + P->tgt_off[p] : nullptr;
+      bp[p].sx_dst = c->sx.as<float>() + P->src_off[p];
+      bp[p].sy_dst = c->sy.as<float>() + P->src_off[p];
+      bp[p].sz_dst = c->sz.as<float>() + P->src_off[p];
+      bp[p].perm_dst = c->perm.as<uint32_t>() + P->src_off[p];
+    }
+  }
   HIP_TRY(hipMemcpyAsync(dd + L.pairs, hh + L.pairs, L.pargs - L.pairs, hipMemcpyHostToDevice, s),
           "upload");
   const BuildPair* dbp = reinterpret_cast<const BuildPair*>(dd + L.pairs);
   HIP_TRY(launch_seg_targets(dbp, n, reinterpret_cast<const int64_t*>(dd + L.blk_t), bt[n],
+                             reinterpret_cast<const int64_t*>(dd + L.blk_tab), bk[n],
                              P->total_tab, c->cs.as<uint32_t>(), c->t_key.as<uint32_t>(),
-                             c->t_rank.as<uint32_t>(), c->scan_tmp.as<uint32_t>(), scan_cap,
-                             c->tp.as<float4>(), normals ? c->tn.as<float4>() : nullptr, s),
+                             c->t_rank.as<uint32_t>(), c->scan_tmp.as<uint32_t>(), scan_cap, s),
           "target grid");
   SortBufs sb;
   for (int k = 0; k < 2; ++k) {
@@ -476,10 +416,15 @@ int prepare_pairs(icp_ctx* c, int n, const PairIn* in, Prep* P) {
   }
   HIP_TRY(launch_seg_sources(dbp, n, reinterpret_cast<const int64_t*>(dd + L.blk_s), bs[n],
                              reinterpret_cast<const int64_t*>(dd + L.src_off), P->total_src, sb,
-                             c->s_hist.as<uint32_t>(), hist_cap, c->sx.as<float>(),
-                             c->sy.as<float>(), c->sz.as<float>(), c->perm.as<uint32_t>(), s),
+                             c->s_hist.as<uint32_t>(), hist_cap, s),
           "source order");
   return ICP_SUCCESS;
+}
+
+int prepare_pairs(icp_ctx* c, int n, const PairIn* in, Prep* P) {
+  int bad = -1, rc;
+  if ((rc = plan_pairs(c, n, in, P, &bad)) != 0) return rc;
+  return build_pairs(c, P, nullptr);
 }
 
 // Pass arguments of pair p of a prepared call (pointers into the device
@@ -494,8 +439,8 @@ PassArgs pass_args(icp_ctx* c, const Prep& P, int p, double r, bool with_jprev, 
   a.sz = c->sz.as<float>() + P.src_off[p];
   a.sperm = c->perm.as<uint32_t>() + P.src_off[p];
   a.n_src = (int32_t)(P.src_off[p + 1] - P.src_off[p]);
-  a.tp = c->tp.as<float4>();
-  a.tn = normals ? c->tn.as<float4>() : nullptr;
+  a.tp = c->tp.as<float4>() + P.tgt_off[p];
+  a.tn = normals ? c->tn.as<float4>() + P.tgt_off[p] : nullptr;
   a.cs = c->cs.as<uint32_t>() + P.tab_off[p];
   a.g = P.g[p];
   a.r2f = (float)(r * r);
@@ -638,7 +583,108 @@ int single_pass(icp_ctx* c, const Prep& P, double r, const double T[16], bool no
   return ICP_SUCCESS;
 }
 
-}  // namespace
+// ------------------------------------------------------------------ voxel downsampling
+// Downsamples m clouds in one segmented call; counts[c] receives the number of
+// occupied voxels of cloud c (outputs beyond cap are not written).  `bad`
+// receives the first cloud with a non-finite value, or -1.
+int downsample_clouds(icp_ctx* c, int m, const VoxIn* in, int64_t* counts, int* bad) {
+  hipStream_t s = c->stream;
+  *bad = -1;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = align256(off);
+    off = o + bytes;
+    return o;
+  };
+  const size_t o_clouds = take(sizeof(SegCloud) * m);
+  const size_t o_bblk = take(sizeof(int64_t) * (m + 1));
+  const size_t o_vox = take(sizeof(VoxCloud) * m);
+  const size_t o_vblk = take(sizeof(int64_t) * (m + 1));
+  const size_t o_ptoff = take(sizeof(int64_t) * (m + 1));
+  const size_t o_upload = align256(off);
+  const size_t o_box = take(sizeof(float) * 8 * m);
+  const size_t o_counts = take(sizeof(int64_t) * m);
+  const size_t total_bytes = align256(off);
+  int rc;
+  if ((rc = ensure_host(c, total_bytes)) != 0) return rc;
+  HIP_TRY(c->vdesc.ensure(total_bytes), "alloc");
+  char* hh = static_cast<char*>(c->host);
+  char* dd = c->vdesc.as<char>();
+  SegCloud* cl = reinterpret_cast<SegCloud*>(hh + o_clouds);
+  int64_t* bb = reinterpret_cast<int64_t*>(hh + o_bblk);
+  bb[0] = 0;
+  int64_t total = 0;
+  for (int k = 0; k < m; ++k) {
+    cl[k] = SegCloud{in[k].pts, in[k].nrm, in[k].n};
+    bb[k + 1] = bb[k] + bbox_blocks(in[k].n);
+    total += in[k].n;
+  }
+  if (total > (int64_t)INT32_MAX) return fail(ICP_E_TOO_LARGE, "more than 2^31-1 points in one call");
+  HIP_TRY(c->bbox_part.ensure(sizeof(float) * 8 * (size_t)bb[m]), "alloc");
+  HIP_TRY(hipMemcpyAsync(dd, hh, o_vox, hipMemcpyHostToDevice, s), "upload");
+  HIP_TRY(launch_seg_bbox(reinterpret_cast<SegCloud*>(dd + o_clouds), m,
+                          reinterpret_cast<int64_t*>(dd + o_bblk), bb[m], c->bbox_part.as<float>(),
+                          reinterpret_cast<float*>(dd + o_box), s),
+          "bbox");
+  float* hbox = reinterpret_cast<float*>(hh + o_box);
+  HIP_TRY(hipMemcpyAsync(hbox, dd + o_box, sizeof(float) * 8 * m, hipMemcpyDeviceToHost, s), "readback");
+  HIP_TRY(hipStreamSynchronize(s), "sync");
+  VoxCloud* vc = reinterpret_cast<VoxCloud*>(hh + o_vox);
+  int64_t* vb = reinterpret_cast<int64_t*>(hh + o_vblk);
+  int64_t* po = reinterpret_cast<int64_t*>(hh + o_ptoff);
+  vb[0] = 0;
+  po[0] = 0;
+  bool wide = false;
+  if (m > 65535) return fail(ICP_E_TOO_LARGE, "more than 65535 clouds in one downsampling call");
+  for (int k = 0; k < m; ++k) {
+    const float* b = hbox + 8 * k;
+    if (b[6] != 0.0f) {
+      *bad = k;
+      return fail(ICP_E_NONFINITE, "non-finite coordinate or normal in a cloud to downsample");
+    }
+    const double inv_v = 1.0 / in[k].voxel;
+    double d[3];
+    for (int a = 0; a < 3; ++a) d[a] = floor(((double)b[3 + a] - (double)b[a]) * inv_v) + 1.0;
+    if (d[0] * d[1] * d[2] >= 281474976710656.0)
+      return fail(ICP_E_TOO_LARGE, "voxel grid of a cloud exceeds 2^48 voxels");
+    if (d[0] * d[1] * d[2] >= 4294967296.0) wide = true;
+    vc[k] = VoxCloud{in[k].pts, in[k].nrm, in[k].n, po[k], (double)b[0], (double)b[1], (double)b[2],
+                     inv_v, (int32_t)d[0], (int32_t)d[1], (int32_t)d[2], 0, in[k].out_pts,
+                     in[k].out_nrm, in[k].cap};
+    vb[k + 1] = vb[k] + (in[k].n + 255) / 256;
+    po[k + 1] = po[k] + in[k].n;
+  }
+  const int64_t hist_cap = radix_hist_needed(total);
+  const int64_t scan_cap = std::max(scan_block_sums_needed(total), (int64_t)1);
+  for (Buf& b : c->sk) HIP_TRY(b.ensure(4 * ((size_t)total + 1)), "alloc");
+  HIP_TRY(c->s_hist.ensure(4 * (size_t)hist_cap), "alloc");
+  HIP_TRY(c->scan_tmp.ensure(4 * (size_t)scan_cap), "alloc");
+  HIP_TRY(c->vflags.ensure(4 * (size_t)voxel_scratch_words(total)), "alloc");
+  HIP_TRY(c->vstarts.ensure(4 * (size_t)voxel_scratch_words(total)), "alloc");
+  HIP_TRY(hipMemcpyAsync(dd + o_vox, hh + o_vox, o_upload - o_vox, hipMemcpyHostToDevice, s), "upload");
+  SortBufs sb;
+  for (int k = 0; k < 2; ++k) {
+    sb.klo[k] = c->sk[k].as<uint32_t>();
+    sb.khi[k] = c->sk[2 + k].as<uint32_t>();
+    sb.val[k] = c->sk[4 + k].as<uint32_t>();
+  }
+  HIP_TRY(launch_seg_voxel(reinterpret_cast<VoxCloud*>(dd + o_vox), m, wide,
+                           reinterpret_cast<int64_t*>(dd + o_vblk), vb[m],
+                           reinterpret_cast<int64_t*>(dd + o_ptoff), total, sb,
+                           c->s_hist.as<uint32_t>(), hist_cap, c->vflags.as<uint32_t>(),
+                           c->vstarts.as<uint32_t>(), c->scan_tmp.as<uint32_t>(), scan_cap,
+                           reinterpret_cast<int64_t*>(dd + o_counts), s),
+          "voxel downsample");
+  int64_t* hc = reinterpret_cast<int64_t*>(hh + o_counts);
+  HIP_TRY(hipMemcpyAsync(hc, dd + o_counts, sizeof(int64_t) * m, hipMemcpyDeviceToHost, s), "readback");
+  HIP_TRY(hipStreamSynchronize(s), "sync");
+  for (int k = 0; k < m; ++k) counts[k] = hc[k];
+  return ICP_SUCCESS;
+}
+
+}  // namespace icp_rt
+
+using namespace icp_rt;
 
 // ====================================================================== C ABI
 extern "C" {
@@ -753,6 +799,92 @@ int icp_register_batch(icp_ctx_t* ctx, const icp_pair_t* pairs, int32_t n_pairs,
   Prep P;
   if ((rc = prepare_pairs(c, n_pairs, in.data(), &P)) != 0) return rc;
   return run_loop(c, P, li.data(), plane, variant, precision, out);
+}
+
+int icp_voxel_downsample(icp_ctx_t* ctx, const float* pts, const float* normals, int64_t n,
+                         double voxel, float* out_pts, float* out_normals, int64_t cap,
+                         int64_t* n_out) {
+  int rc;
+  if ((rc = check_cloud(pts, n, "pts")) != 0) return rc;
+  if (!(voxel > 0.0) || !std::isfinite(voxel)) return fail(ICP_E_INVALID_ARG, "voxel must be finite and > 0");
+  if (!out_pts || !n_out || cap < 1) return fail(ICP_E_INVALID_ARG, "out_pts / n_out is NULL or cap < 1");
+  if (normals && !out_normals) return fail(ICP_E_INVALID_ARG, "out_normals is NULL while normals are given");
+  if ((reinterpret_cast<uintptr_t>(out_pts) & 3u) || (normals && (reinterpret_cast<uintptr_t>(normals) & 3u)) ||
+      (out_normals && (reinterpret_cast<uintptr_t>(out_normals) & 3u)))
+    return fail(ICP_E_INVALID_ARG, "pointer is not 4-byte aligned");
+  icp_ctx* c = nullptr;
+  if ((rc = resolve_ctx(ctx, &c)) != 0) return rc;
+  DeviceGuard dg(c->device);
+  const VoxIn in{pts, normals, n, voxel, out_pts, normals ? out_normals : nullptr, cap};
+  int64_t cnt = 0;
+  int bad = -1;
+  if ((rc = downsample_clouds(c, 1, &in, &cnt, &bad)) != 0) return rc;
+  *n_out = cnt;
+  if (cnt > cap) return fail(ICP_E_TOO_LARGE, "output capacity too small: " + std::to_string(cnt) + " voxels");
+  return ICP_SUCCESS;
+}
+
+int icp_register_multiscale(icp_ctx_t* ctx, const float* src_xyz, int64_t n_src, const float* tgt_xyz,
+                            const float* tgt_normals, int64_t n_tgt, const double T_init[16],
+                            int32_t n_levels, const double* voxel, const int32_t* max_iter,
+                            const double* max_corr_dist, double rel_tol, int32_t variant,
+                            int32_t precision, icp_result_t* out) {
+  if (n_levels < 1 || n_levels > 16 || !voxel || !max_iter || !max_corr_dist)
+    return fail(ICP_E_INVALID_ARG, "n_levels must be in [1, 16] with voxel / max_iter / max_corr_dist given");
+  int rc;
+  for (int l = 0; l < n_levels; ++l) {
+    rc = check_common(src_xyz, n_src, tgt_xyz, tgt_normals, n_tgt, T_init, max_corr_dist[l], variant,
+                      precision, true);
+    if (!rc) rc = check_iteration(max_iter[l], rel_tol);
+    if (!rc && !(voxel[l] >= 0.0 && std::isfinite(voxel[l])))
+      rc = fail(ICP_E_INVALID_ARG, "voxel must be finite and >= 0 (0: no downsampling)");
+    if (rc) {
+      g_last_error += " (level " + std::to_string(l) + ")";
+      return rc;
+    }
+  }
+  if (!out) return fail(ICP_E_INVALID_ARG, "out is NULL");
+  icp_ctx* c = nullptr;
+  if ((rc = resolve_ctx(ctx, &c)) != 0) return rc;
+  DeviceGuard dg(c->device);
+  const bool plane = variant == ICP_POINT_TO_PLANE;
+  double T[16];
+  memcpy(T, T_init, sizeof T);
+  icp_result_t res{};
+  int32_t iters_total = 0;
+  for (int l = 0; l < n_levels; ++l) {
+    const float* s = src_xyz;
+    const float* t = tgt_xyz;
+    const float* tn = plane ? tgt_normals : nullptr;
+    int64_t ns = n_src, nt = n_tgt;
+    if (voxel[l] > 0.0) {
+      HIP_TRY(c->lvl_src.ensure(12 * (size_t)n_src), "alloc");
+      HIP_TRY(c->lvl_tgt.ensure(12 * (size_t)n_tgt), "alloc");
+      if (plane) HIP_TRY(c->lvl_tn.ensure(12 * (size_t)n_tgt), "alloc");
+      const VoxIn vin[2] = {{src_xyz, nullptr, n_src, voxel[l], c->lvl_src.as<float>(), nullptr, n_src},
+                            {tgt_xyz, tn, n_tgt, voxel[l], c->lvl_tgt.as<float>(),
+                             plane ? c->lvl_tn.as<float>() : nullptr, n_tgt}};
+      int64_t cnt[2];
+      int bad = -1;
+      if ((rc = downsample_clouds(c, 2, vin, cnt, &bad)) != 0) return rc;
+      s = c->lvl_src.as<float>();
+      t = c->lvl_tgt.as<float>();
+      tn = plane ? c->lvl_tn.as<float>() : nullptr;
+      ns = cnt[0];
+      nt = cnt[1];
+    }
+    const PairIn in{s, ns, t, tn, nt, max_corr_dist[l]};
+    Prep P;
+    if ((rc = prepare_pairs(c, 1, &in, &P)) != 0) return rc;
+    const LoopIn li{T, max_corr_dist[l], max_iter[l], rel_tol};
+    if ((rc = run_loop(c, P, &li, plane, variant, precision, &res)) != 0) return rc;
+    iters_total += res.n_iter;
+    memcpy(T, res.T, sizeof T);
+    if (res.status == ICP_DEGENERATE) break;
+  }
+  res.n_iter = iters_total;
+  *out = res;
+  return ICP_SUCCESS;
 }
 
 int icp_correspondences(icp_ctx_t* ctx, const float* src_xyz, int64_t n_src, const double T[16],

@@ -217,22 +217,36 @@ __global__ __launch_bounds__(256) void seg_target_key_kernel(const BuildPair* __
   rank[bp.tgt_off + i] = atomicAdd(&counts[gk], 1u);
 }
 
+// After the scan, counts[] holds positions in the concatenation of all pairs'
+// targets; subtracting the pair's offset gives its local position.
 __global__ __launch_bounds__(256) void seg_target_scatter_kernel(
     const BuildPair* __restrict__ pairs, int n, const int64_t* __restrict__ blk_off,
     const uint32_t* __restrict__ key, const uint32_t* __restrict__ rank,
-    const uint32_t* __restrict__ cs, float4* __restrict__ tp, float4* __restrict__ tn) {
+    const uint32_t* __restrict__ cs_global) {
   const int p = find_segment(blk_off, n, blockIdx.x);
   const BuildPair& bp = pairs[p];
   const int64_t i = (int64_t)(blockIdx.x - blk_off[p]) * 256 + threadIdx.x;
   if (i >= bp.n_tgt) return;
   const int64_t gi = bp.tgt_off + i;
-  const uint32_t pos = cs[key[gi]] + rank[gi];
+  const uint32_t pos = cs_global[key[gi]] + rank[gi] - (uint32_t)bp.tgt_off;
   const float* t = bp.tgt + 3 * i;
-  tp[pos] = make_float4(t[0], t[1], t[2], __uint_as_float((uint32_t)i));
-  if (bp.tgt_n && tn) {
+  bp.tp_dst[pos] = make_float4(t[0], t[1], t[2], __uint_as_float((uint32_t)i));
+  if (bp.tgt_n && bp.tn_dst) {
     const float* m = bp.tgt_n + 3 * i;
-    tn[pos] = make_float4(m[0], m[1], m[2], 0.0f);
+    bp.tn_dst[pos] = make_float4(m[0], m[1], m[2], 0.0f);
   }
+}
+
+// Pair-local cell table: cs_dst[k] = counts[tab_off + k] - tgt_off (in place
+// when cs_dst aliases the scratch).
+__global__ __launch_bounds__(256) void seg_table_local_kernel(const BuildPair* __restrict__ pairs, int n,
+                                                              const int64_t* __restrict__ blk_off,
+                                                              const uint32_t* cs_global) {
+  const int p = find_segment(blk_off, n, blockIdx.x);
+  const BuildPair& bp = pairs[p];
+  const int64_t k = (int64_t)(blockIdx.x - blk_off[p]) * 256 + threadIdx.x;
+  if (k > (int64_t)bp.g.ncell) return;
+  bp.cs_dst[k] = cs_global[bp.tab_off + k] - (uint32_t)bp.tgt_off;
 }
 
 // ------------------------------------------------------------------ stable LSD radix sort
@@ -343,21 +357,128 @@ __global__ __launch_bounds__(256) void seg_source_key_kernel(const BuildPair* __
 __global__ __launch_bounds__(256) void source_gather_kernel(const BuildPair* __restrict__ pairs, int n,
                                                             const int64_t* __restrict__ src_off,
                                                             int64_t total,
-                                                            const uint32_t* __restrict__ sorted_vals,
-                                                            float* __restrict__ sx,
-                                                            float* __restrict__ sy,
-                                                            float* __restrict__ sz,
-                                                            uint32_t* __restrict__ perm_local) {
+                                                            const uint32_t* __restrict__ sorted_vals) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= total) return;
   const int p = find_segment(src_off, n, i);
   const BuildPair& bp = pairs[p];
   const int64_t local = (int64_t)sorted_vals[i] - bp.src_off;
+  const int64_t pos = i - bp.src_off;
   const float* s = bp.src + 3 * local;
-  sx[i] = s[0];
-  sy[i] = s[1];
-  sz[i] = s[2];
-  perm_local[i] = (uint32_t)local;
+  bp.sx_dst[pos] = s[0];
+  bp.sy_dst[pos] = s[1];
+  bp.sz_dst[pos] = s[2];
+  bp.perm_dst[pos] = (uint32_t)local;
+}
+
+// ------------------------------------------------------------------ voxel downsampling
+// Voxel key (< 2^48) split into words: lo = bits 0..31, hi = (cloud << 16) |
+// bits 32..47, so one sort orders by cloud, then key, then original index.
+__global__ __launch_bounds__(256) void seg_voxel_key_kernel(const VoxCloud* __restrict__ clouds, int n,
+                                                            const int64_t* __restrict__ blk_off,
+                                                            uint32_t* __restrict__ klo,
+                                                            uint32_t* __restrict__ khi,
+                                                            uint32_t* __restrict__ vals) {
+  const int c = find_segment(blk_off, n, blockIdx.x);
+  const VoxCloud& vc = clouds[c];
+  const int64_t i = (int64_t)(blockIdx.x - blk_off[c]) * 256 + threadIdx.x;
+  if (i >= vc.n) return;
+  const float* p = vc.pts + 3 * i;
+  const int cx = min(max(cell_of(p[0], vc.ox, vc.inv_v, vc.dx), 0), vc.dx - 1);
+  const int cy = min(max(cell_of(p[1], vc.oy, vc.inv_v, vc.dy), 0), vc.dy - 1);
+  const int cz = min(max(cell_of(p[2], vc.oz, vc.inv_v, vc.dz), 0), vc.dz - 1);
+  const uint64_t key = ((uint64_t)cz * (uint64_t)vc.dy + (uint64_t)cy) * (uint64_t)vc.dx + (uint64_t)cx;
+  const int64_t gi = vc.off + i;
+  klo[gi] = (uint32_t)key;
+  if (khi) khi[gi] = ((uint32_t)c << 16) | (uint32_t)(key >> 32);
+  vals[gi] = (uint32_t)gi;
+}
+
+// flags[i] = 1 where a new voxel starts in the sorted order.
+__global__ __launch_bounds__(256) void voxel_flag_kernel(const uint32_t* __restrict__ klo,
+                                                         const uint32_t* __restrict__ khi,
+                                                         int64_t total, uint32_t* __restrict__ flags) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  bool f = i == 0 || klo[i] != klo[i - 1];
+  if (khi && i > 0) f = f || khi[i] != khi[i - 1];
+  flags[i] = f ? 1u : 0u;
+}
+
+// After the exclusive scan of the flags (vid = voxel index of each start):
+// starts[vid] = sorted position where the voxel begins.
+__global__ __launch_bounds__(256) void voxel_start_kernel(const uint32_t* __restrict__ klo,
+                                                          const uint32_t* __restrict__ khi,
+                                                          const uint32_t* __restrict__ vid,
+                                                          int64_t total, uint32_t* __restrict__ starts) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  bool f = i == 0 || klo[i] != klo[i - 1];
+  if (khi && i > 0) f = f || khi[i] != khi[i - 1];
+  if (f) starts[vid[i]] = (uint32_t)i;
+  if (i == total - 1) starts[vid[i] + (f ? 1u : 0u)] = (uint32_t)total;
+}
+
+// One thread per voxel: float64 sums over its members in sorted order (the
+// stable sort keeps original-index order inside a voxel).
+__global__ __launch_bounds__(256) void voxel_reduce_kernel(const VoxCloud* __restrict__ clouds, int n,
+                                                           const int64_t* __restrict__ pt_off,
+                                                           const uint32_t* __restrict__ vid,
+                                                           const uint32_t* __restrict__ flags,
+                                                           const uint32_t* __restrict__ starts,
+                                                           const uint32_t* __restrict__ sorted_vals,
+                                                           int64_t total) {
+  const int64_t nvox = (int64_t)vid[total - 1] + (int64_t)flags[total - 1];
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nvox) return;
+  const uint32_t b = starts[v], e = starts[v + 1];
+  const int c = find_segment(pt_off, n, (int64_t)b);
+  const VoxCloud& vc = clouds[c];
+  const int64_t local_v = v - (int64_t)vid[vc.off];
+  if (local_v >= vc.out_cap) return;
+  double sx = 0.0, sy = 0.0, sz = 0.0, nx = 0.0, ny = 0.0, nz = 0.0;
+  for (uint32_t k = b; k < e; ++k) {
+    const int64_t li = (int64_t)sorted_vals[k] - vc.off;
+    const float* p = vc.pts + 3 * li;
+    sx = sx + (double)p[0];
+    sy = sy + (double)p[1];
+    sz = sz + (double)p[2];
+    if (vc.nrm) {
+      const float* q = vc.nrm + 3 * li;
+      nx = nx + (double)q[0];
+      ny = ny + (double)q[1];
+      nz = nz + (double)q[2];
+    }
+  }
+  const double cnt = (double)(e - b);
+  vc.out_pts[3 * local_v + 0] = (float)(sx / cnt);
+  vc.out_pts[3 * local_v + 1] = (float)(sy / cnt);
+  vc.out_pts[3 * local_v + 2] = (float)(sz / cnt);
+  if (vc.nrm && vc.out_nrm) {
+    const double len = sqrt((nx * nx + ny * ny) + nz * nz);
+    float o0, o1, o2;
+    if (len < 1e-12) {
+      const float* q = vc.nrm + 3 * ((int64_t)sorted_vals[b] - vc.off);
+      o0 = q[0]; o1 = q[1]; o2 = q[2];
+    } else {
+      o0 = (float)(nx / len); o1 = (float)(ny / len); o2 = (float)(nz / len);
+    }
+    vc.out_nrm[3 * local_v + 0] = o0;
+    vc.out_nrm[3 * local_v + 1] = o1;
+    vc.out_nrm[3 * local_v + 2] = o2;
+  }
+}
+
+// Voxel count of every cloud: first voxel index of the next cloud minus its own.
+__global__ void voxel_count_kernel(const VoxCloud* __restrict__ clouds, int n,
+                                   const uint32_t* __restrict__ vid, const uint32_t* __restrict__ flags,
+                                   int64_t total, int64_t* __restrict__ counts) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int64_t first = vid[clouds[c].off];
+  const int64_t last_plus = (c + 1 < n) ? (int64_t)vid[clouds[c + 1].off]
+                                        : (int64_t)vid[total - 1] + (int64_t)flags[total - 1];
+  counts[c] = last_plus - first;
 }
 
 }  // namespace
@@ -389,29 +510,100 @@ hipError_t launch_seg_bbox(const SegCloud* clouds, int n_clouds, const int64_t* 
 }
 
 hipError_t launch_seg_targets(const BuildPair* pairs, int n, const int64_t* blk_off,
-                              int64_t total_blocks, uint64_t total_tab, uint32_t* cs,
+                              int64_t total_blocks, const int64_t* tab_blk_off,
+                              int64_t tab_blocks, uint64_t total_tab, uint32_t* counts,
                               uint32_t* key, uint32_t* rank, uint32_t* scan_tmp, int64_t scan_cap,
-                              float4* tp, float4* tn, hipStream_t s) {
-  hipError_t e = hipMemsetAsync(cs, 0, sizeof(uint32_t) * (size_t)total_tab, s);
+                              hipStream_t s) {
+  hipError_t e = hipMemsetAsync(counts, 0, sizeof(uint32_t) * (size_t)total_tab, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(seg_target_key_kernel, dim3((unsigned)total_blocks), dim3(256), 0, s, pairs, n,
-                     blk_off, cs, key, rank);
-  e = launch_scan_exclusive(cs, (int64_t)total_tab, scan_tmp, scan_cap, s);
+                     blk_off, counts, key, rank);
+  e = launch_scan_exclusive(counts, (int64_t)total_tab, scan_tmp, scan_cap, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(seg_target_scatter_kernel, dim3((unsigned)total_blocks), dim3(256), 0, s, pairs,
-                     n, blk_off, key, rank, cs, tp, tn);
+                     n, blk_off, key, rank, counts);
+  hipLaunchKernelGGL(seg_table_local_kernel, dim3((unsigned)tab_blocks), dim3(256), 0, s, pairs, n,
+                     tab_blk_off, counts);
   return hipGetLastError();
 }
+
+int64_t voxel_scratch_words(int64_t total) { return total + 1; }
 
 int64_t radix_hist_needed(int64_t n) {
   const int64_t h = 256 * ceil_div(std::max<int64_t>(n, 1), kSortTile);
   return h + scan_block_sums_needed(h);
 }
 
+// Stable LSD sort of (lo, hi, val) triples by (hi, lo); returns the buffer
+// index (0 or 1) holding the result.
+static hipError_t radix_sort_2w(SortBufs sb, bool two, int64_t total, int lo_bits, int hi_from,
+                                int hi_bits, uint32_t* hist, int64_t hist_cap, hipStream_t s,
+                                int* out_cur) {
+  const int nblk = (int)ceil_div(std::max<int64_t>(total, 1), kSortTile);
+  if ((int64_t)256 * nblk > hist_cap) return hipErrorInvalidValue;
+  uint32_t* scan_tmp = hist + (int64_t)256 * nblk;
+  const int64_t scan_cap = hist_cap - (int64_t)256 * nblk;
+  int cur = 0;
+  auto pass = [&](bool on_hi, int shift) -> hipError_t {
+    const uint32_t* dig = on_hi ? sb.khi[cur] : sb.klo[cur];
+    hipLaunchKernelGGL(radix_hist_kernel, dim3(nblk), dim3(kSortThreads), 0, s, dig, total, shift,
+                       hist, nblk);
+    hipError_t e = launch_scan_exclusive(hist, (int64_t)256 * nblk, scan_tmp, scan_cap, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(radix_scatter_kernel, dim3(nblk), dim3(kSortThreads), 0, s, dig, sb.klo[cur],
+                       two ? sb.khi[cur] : nullptr, sb.val[cur], total, shift, hist, nblk,
+                       sb.klo[cur ^ 1], two ? sb.khi[cur ^ 1] : nullptr, sb.val[cur ^ 1]);
+    cur ^= 1;
+    return hipGetLastError();
+  };
+  hipError_t e;
+  for (int shift = 0; shift < lo_bits; shift += 8)
+    if ((e = pass(false, shift)) != hipSuccess) return e;
+  for (int shift = hi_from; two && shift < hi_bits; shift += 8)
+    if ((e = pass(true, shift)) != hipSuccess) return e;
+  *out_cur = cur;
+  return hipSuccess;
+}
+
+hipError_t launch_seg_voxel(const VoxCloud* clouds, int n, bool wide_keys, const int64_t* blk_off,
+                            int64_t total_blocks, const int64_t* pt_off, int64_t total, SortBufs sb,
+                            uint32_t* hist, int64_t hist_cap, uint32_t* flags, uint32_t* starts,
+                            uint32_t* scan_tmp, int64_t scan_cap, int64_t* counts_out,
+                            hipStream_t s) {
+  const bool two = n > 1 || wide_keys;
+  hipLaunchKernelGGL(seg_voxel_key_kernel, dim3((unsigned)total_blocks), dim3(256), 0, s, clouds, n,
+                     blk_off, sb.klo[0], two ? sb.khi[0] : nullptr, sb.val[0]);
+  int cloud_bits = 0;
+  while ((1 << cloud_bits) < n) ++cloud_bits;
+  int cur = 0;
+  hipError_t e = radix_sort_2w(sb, two, total, 32, wide_keys ? 0 : 16, 16 + cloud_bits, hist, hist_cap,
+                               s, &cur);
+  if (e != hipSuccess) return e;
+  const uint32_t* klo = sb.klo[cur];
+  const uint32_t* khi = two ? sb.khi[cur] : nullptr;
+  const unsigned nb = (unsigned)ceil_div(total, 256);
+  hipLaunchKernelGGL(voxel_flag_kernel, dim3(nb), dim3(256), 0, s, klo, khi, total, flags);
+  // vid = exclusive scan of a copy of the flags (kept for the counts)
+  e = hipMemcpyAsync(starts, flags, sizeof(uint32_t) * (size_t)total, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return e;
+  e = launch_scan_exclusive(starts, total, scan_tmp, scan_cap, s);
+  if (e != hipSuccess) return e;
+  // `starts` now holds vid; the voxel starts (nvox + 1 <= total + 1 entries)
+  // go into the key buffer that the sort no longer needs, which the caller
+  // sizes to total + 1 words
+  uint32_t* vid = starts;
+  uint32_t* vstart = sb.klo[cur ^ 1];
+  hipLaunchKernelGGL(voxel_start_kernel, dim3(nb), dim3(256), 0, s, klo, khi, vid, total, vstart);
+  hipLaunchKernelGGL(voxel_reduce_kernel, dim3(nb), dim3(256), 0, s, clouds, n, pt_off, vid, flags,
+                     vstart, sb.val[cur], total);
+  hipLaunchKernelGGL(voxel_count_kernel, dim3((unsigned)ceil_div(n, 64)), dim3(64), 0, s, clouds, n,
+                     vid, flags, total, counts_out);
+  return hipGetLastError();
+}
+
 hipError_t launch_seg_sources(const BuildPair* pairs, int n, const int64_t* blk_off,
                               int64_t total_blocks, const int64_t* src_off, int64_t total,
-                              SortBufs sb, uint32_t* hist, int64_t hist_cap, float* sx, float* sy,
-                              float* sz, uint32_t* perm_local, hipStream_t s) {
+                              SortBufs sb, uint32_t* hist, int64_t hist_cap, hipStream_t s) {
   const bool two = n > 1;
   hipLaunchKernelGGL(seg_source_key_kernel, dim3((unsigned)total_blocks), dim3(256), 0, s, pairs, n,
                      blk_off, sb.klo[0], two ? sb.khi[0] : nullptr, sb.val[0]);
@@ -439,8 +631,9 @@ hipError_t launch_seg_sources(const BuildPair* pairs, int n, const int64_t* blk_
     if ((e = pass(false, shift)) != hipSuccess) return e;
   for (int shift = 0; shift < hi_bits; shift += 8)
     if ((e = pass(true, shift)) != hipSuccess) return e;
+
   hipLaunchKernelGGL(source_gather_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, pairs,
-                     n, src_off, total, sb.val[cur], sx, sy, sz, perm_local);
+                     n, src_off, total, sb.val[cur]);
   return hipGetLastError();
 }
 

@@ -77,10 +77,11 @@ struct SegCloud {
   int64_t n;
 };
 
-// One pair of a segmented preparation call.  The cell tables of all pairs are
-// concatenated (pair p's table starts at tab_off and has g.ncell + 1 entries)
-// and hold positions into the concatenated cell-ordered target; sources are
-// concatenated at src_off, targets at tgt_off.
+// One pair of a segmented preparation call.  Counting and scanning use
+// concatenated scratch (pair p's counts start at tab_off and have g.ncell + 1
+// entries; its targets are counted from tgt_off, its sources from src_off);
+// the results are written to the pair's own destinations with pair-local
+// positions: cs_dst[k] = first position of cell k in tp_dst.
 struct BuildPair {
   const float* src;
   const float* tgt;
@@ -90,6 +91,13 @@ struct BuildPair {
   uint64_t tab_off;
   GridDesc g;
   double sox, soy, soz, sinv_h;  // Morton grid of the source (1024 cells per axis)
+  uint32_t* cs_dst;              // g.ncell + 1 entries
+  float4* tp_dst;                // n_tgt
+  float4* tn_dst;                // n_tgt, or null
+  float* sx_dst;                 // n_src each
+  float* sy_dst;
+  float* sz_dst;
+  uint32_t* perm_dst;            // n_src: ordered position -> original source index
 };
 
 struct SortBufs {
@@ -106,14 +114,47 @@ hipError_t launch_scan_exclusive(uint32_t* data, int64_t n, uint32_t* block_sums
 // out: 8 floats per cloud (min xyz, max xyz, non-finite flag)
 hipError_t launch_seg_bbox(const SegCloud* clouds, int n_clouds, const int64_t* blk_off,
                            int64_t total_blocks, float* block_out, float* out, hipStream_t s);
+// counts: scratch of total_tab entries; tab_blk_off: per-pair block offsets
+// over the tables (256 entries per block) for the localising copy.
 hipError_t launch_seg_targets(const BuildPair* pairs, int n, const int64_t* blk_off,
-                              int64_t total_blocks, uint64_t total_tab, uint32_t* cs,
+                              int64_t total_blocks, const int64_t* tab_blk_off,
+                              int64_t tab_blocks, uint64_t total_tab, uint32_t* counts,
                               uint32_t* key, uint32_t* rank, uint32_t* scan_tmp, int64_t scan_cap,
-                              float4* tp, float4* tn, hipStream_t s);
+                              hipStream_t s);
 hipError_t launch_seg_sources(const BuildPair* pairs, int n, const int64_t* blk_off,
                               int64_t total_blocks, const int64_t* src_off, int64_t total,
-                              SortBufs sb, uint32_t* hist, int64_t hist_cap, float* sx, float* sy,
-                              float* sz, uint32_t* perm_local, hipStream_t s);
+                              SortBufs sb, uint32_t* hist, int64_t hist_cap, hipStream_t s);
+
+// ---- voxel downsampling (icp_build.hip) ----------------------------------
+// One cloud of a segmented downsampling call.  Voxel of p: floor((p - o) /
+// voxel) per axis in float64 (o = the cloud's box minimum), key = (cz * dy +
+// cy) * dx + cx < 2^48.  Output (key order): mean position of each occupied
+// voxel (float64 sum in original-index order, then rounded), and with normals
+// the normalised float64 sum of the members' normals (the first member's
+// normal if that sum is shorter than 1e-12).
+struct VoxCloud {
+  const float* pts;
+  const float* nrm;  // optional
+  int64_t n;
+  int64_t off;       // offset in the concatenation of all clouds' points
+  double ox, oy, oz, inv_v;
+  int32_t dx, dy, dz;
+  int32_t pad;
+  float* out_pts;    // capacity out_cap voxels
+  float* out_nrm;    // optional
+  int64_t out_cap;
+};
+
+// counts_out: per cloud, the number of occupied voxels (written even if it
+// exceeds out_cap; points beyond the capacity are not written).  Sort buffers,
+// `flags` and `starts` hold at least total + 1 words.
+// wide_keys: some cloud's key space exceeds 2^32; n <= 65535 clouds.
+hipError_t launch_seg_voxel(const VoxCloud* clouds, int n, bool wide_keys, const int64_t* blk_off,
+                            int64_t total_blocks, const int64_t* pt_off, int64_t total, SortBufs sb,
+                            uint32_t* hist, int64_t hist_cap, uint32_t* flags, uint32_t* starts,
+                            uint32_t* scan_tmp, int64_t scan_cap, int64_t* counts_out,
+                            hipStream_t s);
+int64_t voxel_scratch_words(int64_t total);  // words needed for `flags` and `starts` each
 
 // ---- loop (icp_kernels.hip) ---------------------------------------------
 hipError_t launch_state_init(IterState* st, const double T[16], hipStream_t s);
@@ -125,5 +166,12 @@ hipError_t launch_solve(const SolveArgs& a, hipStream_t s);
 hipError_t launch_batch_pass(const PassArgs* pairs, const uint2* items, int n_items, int sub,
                              int variant, int precision, hipStream_t s);
 hipError_t launch_batch_solve(const SolveArgs* arr, int n_pairs, hipStream_t s);
+
+// Served form (graph-capturable: fixed launch shapes, counts read on device).
+// ctrl[0] = items, ctrl[1] = item counter, ctrl[2] = active slots.
+hipError_t launch_persistent_pass(const PassArgs* pairs, const uint2* items, int* ctrl, int blocks,
+                                  int sub, int variant, int precision, hipStream_t s);
+hipError_t launch_slot_solve(const SolveArgs* arr, int* ctrl, int slots, hipStream_t s);
+hipError_t launch_gather_states(const SolveArgs* arr, int n, IterState* out, hipStream_t s);
 
 }  // namespace icp

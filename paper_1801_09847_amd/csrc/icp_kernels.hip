@@ -431,6 +431,29 @@ __global__ __launch_bounds__(kBlock) void batch_pass_kernel(const PassArgs* __re
   pass_tile<VAR, PREC, false, R>(a, it.y);
 }
 
+// Served form: a fixed grid of blocks takes (pair, tile) items from a device
+// counter until the item list is exhausted, so the launch shape does not
+// depend on the active set and the launch can be captured once in a graph.
+// ctrl[0] = number of items (written before the launch), ctrl[1] = item
+// counter (0 at launch; reset by the solve kernel that follows).
+template <int VAR, int PREC, int R>
+__global__ __launch_bounds__(kBlock) void persistent_pass_kernel(const PassArgs* __restrict__ pairs,
+                                                                 const uint2* __restrict__ items,
+                                                                 int* ctrl) {
+  __shared__ int s_item;
+  const int n_items = ctrl[0];
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(&ctrl[1], 1);
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();
+    if (it >= n_items) break;
+    const uint2 w = items[it];
+    const PassArgs& a = pairs[w.x];
+    if (!a.st->done) pass_tile<VAR, PREC, false, R>(a, w.y);
+  }
+}
+
 // ------------------------------------------------------------------ solve + pose update
 // 6x6 Cholesky of A (given by its upper triangle), x = -A^{-1} b.  Fails when
 // a pivot is <= 1e-12 * max(diag A).
@@ -596,6 +619,22 @@ __global__ __launch_bounds__(1024) void batch_solve_kernel(const SolveArgs* __re
   solve_body(arr[blockIdx.x]);
 }
 
+// Served form: a fixed grid of max_slots blocks; block b serves slot b when
+// b < ctrl[2] (active slots).  Block 0 resets the pass kernel's item counter.
+__global__ __launch_bounds__(1024) void slot_solve_kernel(const SolveArgs* __restrict__ arr, int* ctrl) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctrl[1] = 0;
+  if ((int)blockIdx.x < ctrl[2]) solve_body(arr[blockIdx.x]);
+}
+
+// Copies the states of the served slots into one array (one readback).
+__global__ void gather_states_kernel(const SolveArgs* __restrict__ arr, int n, IterState* __restrict__ out) {
+  const int b = blockIdx.x;
+  if (b >= n) return;
+  const double* src = reinterpret_cast<const double*>(arr[b].st);
+  double* dst = reinterpret_cast<double*>(out + b);
+  for (int k = threadIdx.x; k < (int)(sizeof(IterState) / sizeof(double)); k += blockDim.x) dst[k] = src[k];
+}
+
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 }  // namespace
@@ -652,6 +691,37 @@ hipError_t launch_batch_pass(const PassArgs* pairs, const uint2* items, int n_it
     launch_batch_pass_r<2>(pairs, items, n_items, variant, precision, s);
   else
     launch_batch_pass_r<1>(pairs, items, n_items, variant, precision, s);
+  return hipGetLastError();
+}
+
+template <int R>
+void launch_persistent_pass_r(const PassArgs* pairs, const uint2* items, int* ctrl, int blocks,
+                              int variant, int precision, hipStream_t s) {
+  const dim3 grid((unsigned)blocks), block(kBlock);
+#define ICP_PPASS(V, P) \
+  hipLaunchKernelGGL((persistent_pass_kernel<V, P, R>), grid, block, 0, s, pairs, items, ctrl)
+  if (variant == 1) { if (precision == 0) ICP_PPASS(1, 0); else ICP_PPASS(1, 1); }
+  else { if (precision == 0) ICP_PPASS(0, 0); else ICP_PPASS(0, 1); }
+#undef ICP_PPASS
+}
+
+hipError_t launch_persistent_pass(const PassArgs* pairs, const uint2* items, int* ctrl, int blocks,
+                                  int sub, int variant, int precision, hipStream_t s) {
+  if (sub == 2)
+    launch_persistent_pass_r<2>(pairs, items, ctrl, blocks, variant, precision, s);
+  else
+    launch_persistent_pass_r<1>(pairs, items, ctrl, blocks, variant, precision, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_slot_solve(const SolveArgs* arr, int* ctrl, int slots, hipStream_t s) {
+  hipLaunchKernelGGL(slot_solve_kernel, dim3((unsigned)slots), dim3(1024), 0, s, arr, ctrl);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_states(const SolveArgs* arr, int n, IterState* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_states_kernel, dim3((unsigned)n), dim3(64), 0, s, arr, n, out);
   return hipGetLastError();
 }
 

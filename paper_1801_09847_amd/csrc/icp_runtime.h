@@ -1,0 +1,175 @@
+// Host-side runtime shared by the C-ABI translation units (plain / batched
+// registration, voxel downsampling, the request server).
+#pragma once
+
+#include <stdint.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/icp.h"
+#include "icp_internal.h"
+
+namespace icp_rt {
+
+using namespace icp;
+
+extern thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define HIP_TRY(expr, what)                            \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return ::icp_rt::hip_fail(e_, what); \
+  } while (0)
+
+// A device buffer that only grows (reused across calls).
+struct Buf {
+  void* p = nullptr;
+  size_t cap = 0;
+  hipError_t ensure(size_t bytes) {
+    if (bytes <= cap && p) return hipSuccess;
+    if (p) {
+      hipError_t e = hipFree(p);
+      p = nullptr;
+      cap = 0;
+      if (e != hipSuccess) return e;
+    }
+    const size_t want = std::max<size_t>(bytes + bytes / 8, 256);
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
+    cap = want;
+    return hipSuccess;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+constexpr size_t kHostBytes = 4096;
+constexpr int kDefaultSub = 1;
+
+}  // namespace icp_rt
+
+struct icp_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  // per-call descriptors, loop header, warm-start matches, partials, states
+  icp_rt::Buf desc;
+  // preparation scratch
+  icp_rt::Buf bbox_part, t_key, t_rank, scan_tmp, s_hist;
+  icp_rt::Buf sk[6];  // sort buffers: klo[2], khi[2], val[2]
+  // prepared pairs (concatenated)
+  icp_rt::Buf cs, tp, tn, sx, sy, sz, perm;
+  // voxel downsampling: descriptors, scratch, multi-scale level clouds
+  icp_rt::Buf vdesc, vflags, vstarts, lvl_src, lvl_tgt, lvl_tn;
+  void* host = nullptr;  // pinned staging
+  size_t host_cap = 0;
+  // kernel timing
+  bool profiling = false;
+  std::vector<hipEvent_t> ev;  // [0] call start, [1] call end, [2+2k]/[3+2k] around pass k
+  icp_profile_t prof{};
+};
+
+namespace icp_rt {
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(dev) == hipSuccess) ok = true;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+int ctx_init(icp_ctx* c, int device, void* stream);
+void ctx_free(icp_ctx* c);
+int ensure_host(icp_ctx* c, size_t bytes);
+int check_cloud(const float* p, int64_t n, const char* name);
+int check_pose(const double* T, const char* name);
+int check_common(const float* src, int64_t n_src, const float* tgt, const float* tgt_n,
+                 int64_t n_tgt, const double* T, double r, int32_t variant, int32_t precision,
+                 bool need_normals_for_plane);
+int check_iteration(int32_t max_iter, double rel_tol);
+size_t align256(size_t x);
+int64_t tiles_of(int64_t n);
+
+struct PairIn {
+  const float* src;
+  int64_t n_src;
+  const float* tgt;
+  const float* tgt_n;  // null: point-to-point (normals neither checked nor gathered)
+  int64_t n_tgt;
+  double r;
+};
+
+// Byte offsets of one call's descriptors; the same layout is used in pinned
+// host staging and in the context's `desc` device buffer.
+struct Layout {
+  size_t clouds, blk_bbox, pairs, blk_t, blk_s, src_off, blk_tab;  // preparation
+  size_t pargs, sargs, states, items;                                // loop header
+  size_t header_end;                                                 // end of uploaded part
+  size_t bbox_out, jprev, part;                                      // device only
+  size_t total;
+};
+
+struct Prep {
+  int n = 0;
+  Layout L;
+  std::vector<GridDesc> g;
+  std::vector<int64_t> src_off, tgt_off, tile_off;
+  std::vector<uint64_t> tab_off;
+  int64_t total_src = 0, total_tgt = 0, total_tiles = 0;
+  uint64_t total_tab = 0;
+  int sub = 1;
+  bool normals = false;
+};
+
+// Destinations of one pair's prepared data (device); perm may alias scratch.
+struct PairDst {
+  uint32_t* cs;  // g.ncell + 1
+  float4* tp;    // n_tgt
+  float4* tn;    // n_tgt or null
+  float* sx;     // n_src each
+  float* sy;
+  float* sz;
+  uint32_t* perm;
+};
+
+// Boxes, finiteness and grid sizes of n pairs (one synchronisation).  On a
+// non-finite input, *bad receives the pair index and ICP_E_NONFINITE is
+// returned.
+int plan_pairs(icp_ctx* c, int n, const PairIn* in, Prep* P, int* bad);
+// Segmented build of a planned call into dst[] (null: the context's arrays).
+int build_pairs(icp_ctx* c, Prep* P, const PairDst* dst);
+int prepare_pairs(icp_ctx* c, int n, const PairIn* in, Prep* P);
+
+struct VoxIn {
+  const float* pts;
+  const float* nrm;  // optional
+  int64_t n;
+  double voxel;
+  float* out_pts;
+  float* out_nrm;    // optional
+  int64_t cap;
+};
+int downsample_clouds(icp_ctx* c, int m, const VoxIn* in, int64_t* counts, int* bad);
+
+void to_result(const IterState& st, icp_result_t* out);
+
+}  // namespace icp_rt

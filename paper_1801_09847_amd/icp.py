@@ -57,6 +57,27 @@ class icp_pair_t(C.Structure):
                 ("reserved", C.c_int32)]
 
 
+class icp_server_cfg_t(C.Structure):
+    _fields_ = [("device", C.c_int32), ("max_slots", C.c_int32), ("hbm_budget_bytes", C.c_uint64),
+                ("n_levels", C.c_int32), ("iters", C.c_int32 * 4), ("voxel", C.c_double * 4),
+                ("corr_dist", C.c_double * 4), ("corr_factor", C.c_double), ("variant", C.c_int32),
+                ("precision", C.c_int32), ("iters_per_step", C.c_int32),
+                ("background_thread", C.c_int32)]
+
+
+class icp_request_t(C.Structure):
+    _fields_ = [("src_xyz", C.c_void_p), ("tgt_xyz", C.c_void_p), ("tgt_normals", C.c_void_p),
+                ("n_src", C.c_int64), ("n_tgt", C.c_int64), ("T_init", C.c_double * 16),
+                ("rel_tol", C.c_double), ("spacing", C.c_double), ("host_memory", C.c_int32),
+                ("reserved", C.c_int32), ("user_tag", C.c_uint64)]
+
+
+class icp_completion_t(C.Structure):
+    _fields_ = [("ticket", C.c_uint64), ("user_tag", C.c_uint64), ("result", icp_result_t),
+                ("error", C.c_int32), ("reserved", C.c_int32), ("t_submit_ns", C.c_int64),
+                ("t_admit_ns", C.c_int64), ("t_done_ns", C.c_int64)]
+
+
 class icp_profile_t(C.Structure):
     _fields_ = [("pass_ms", C.c_double), ("pass_launches", C.c_int64), ("pass_points", C.c_int64),
                 ("call_ms", C.c_double), ("calls", C.c_int64)]
@@ -87,11 +108,22 @@ def lib():
                                            C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.icp_register_batch.argtypes = [vp, C.POINTER(icp_pair_t), i32, i32, i32,
                                          C.POINTER(icp_result_t)]
+        L.icp_voxel_downsample.argtypes = [vp, vp, vp, i64, dbl, vp, vp, i64, C.POINTER(C.c_int64)]
+        L.icp_register_multiscale.argtypes = [vp, vp, i64, vp, vp, i64, vp, i32, vp, vp, vp, dbl, i32,
+                                              i32, C.POINTER(icp_result_t)]
+        L.icp_server_create.argtypes = [C.POINTER(icp_server_cfg_t), C.POINTER(vp)]
+        L.icp_server_submit.argtypes = [vp, C.POINTER(icp_request_t), C.POINTER(C.c_uint64)]
+        L.icp_server_step.argtypes = [vp, C.POINTER(C.c_int32)]
+        L.icp_server_poll.argtypes = [vp, C.POINTER(icp_completion_t), i32, C.POINTER(C.c_int32)]
+        L.icp_server_wait.argtypes = [vp, C.c_uint64, C.POINTER(icp_completion_t)]
+        L.icp_server_destroy.argtypes = [vp]
         L.icp_ctx_set_profiling.argtypes = [vp, C.c_int]
         L.icp_ctx_get_profile.argtypes = [vp, C.POINTER(icp_profile_t)]
         for name in ("icp_ctx_create", "icp_ctx_destroy", "icp_register", "icp_correspondences",
                      "icp_normal_equations", "icp_ctx_set_profiling", "icp_ctx_get_profile",
-                     "icp_register_batch"):
+                     "icp_register_batch", "icp_voxel_downsample", "icp_register_multiscale",
+                     "icp_server_create", "icp_server_submit", "icp_server_step", "icp_server_poll",
+                     "icp_server_wait", "icp_server_destroy"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -255,6 +287,45 @@ def register_batch(pairs, variant="point_to_plane", precision="kahan32",
                       r.n_inliers, r.n_iter, r.status) for r in res]
 
 
+def icp_voxel_downsample(ctx, pts_ptr, nrm_ptr, n, voxel, out_ptr, out_nrm_ptr, cap) -> int:
+    n_out = C.c_int64()
+    _check(lib().icp_voxel_downsample(ctx, pts_ptr, nrm_ptr, int(n), float(voxel), out_ptr,
+                                      out_nrm_ptr, int(cap), C.byref(n_out)))
+    return n_out.value
+
+
+def voxel_downsample(pts, voxel, normals=None, ctx: Context | None = None):
+    """(points, normals or None) as new device tensors."""
+    import torch
+    pp, n = _dev_pts(pts, "pts")
+    npn = _dev_pts(normals, "normals")[0] if normals is not None else None
+    out = torch.empty((n, 3), dtype=torch.float32, device=pts.device)
+    outn = torch.empty((n, 3), dtype=torch.float32, device=pts.device) if normals is not None else None
+    m = icp_voxel_downsample(ctx.handle if ctx else None, pp, npn, n, voxel, out.data_ptr(),
+                             outn.data_ptr() if outn is not None else None, n)
+    return out[:m], (outn[:m] if outn is not None else None)
+
+
+def register_multiscale(src, tgt, tgt_normals, T_init, voxels, iters, dists, rel_tol=0.0,
+                        variant="point_to_plane", precision="kahan32",
+                        ctx: Context | None = None) -> IcpResult:
+    sp, ns = _dev_pts(src, "src")
+    tp, nt = _dev_pts(tgt, "tgt")
+    npn = _dev_pts(tgt_normals, "tgt_normals")[0] if tgt_normals is not None else None
+    L = len(voxels)
+    v = np.ascontiguousarray(voxels, dtype=np.float64)
+    k = np.ascontiguousarray(iters, dtype=np.int32)
+    r = np.ascontiguousarray(dists, dtype=np.float64)
+    out = icp_result_t()
+    T = _pose(T_init)
+    _check(lib().icp_register_multiscale(ctx.handle if ctx else None, sp, ns, tp, npn, nt, T.ctypes.data,
+                                         L, v.ctypes.data, k.ctypes.data, r.ctypes.data,
+                                         float(rel_tol), VARIANTS[variant], PRECISIONS[precision],
+                                         C.byref(out)))
+    return IcpResult(np.array(out.T[:], dtype=np.float64).reshape(4, 4), out.fitness, out.inlier_rmse,
+                     out.n_inliers, out.n_iter, out.status)
+
+
 def correspondences(src, T, tgt, max_corr_dist, ctx: Context | None = None):
     """(idx int32 tensor, d2 float32 tensor) per source point, on the device."""
     import torch
@@ -286,3 +357,90 @@ def full_matrix(A21) -> np.ndarray:
             A[u, v] = A[v, u] = A21[k]
             k += 1
     return A
+
+
+# ---------------------------------------------------------------- served form
+@dataclass
+class Completion:
+    ticket: int
+    user_tag: int
+    error: int
+    result: IcpResult | None
+    t_submit_ns: int
+    t_admit_ns: int
+    t_done_ns: int
+
+
+def _completion(c: icp_completion_t) -> Completion:
+    r = c.result
+    res = IcpResult(np.array(r.T[:], dtype=np.float64).reshape(4, 4), r.fitness, r.inlier_rmse,
+                    r.n_inliers, r.n_iter, r.status) if c.error == 0 else None
+    return Completion(c.ticket, c.user_tag, c.error, res, c.t_submit_ns, c.t_admit_ns, c.t_done_ns)
+
+
+class Server:
+    """Continuous-batching registration server (icp_server_*)."""
+
+    def __init__(self, voxels=(0.04, 0.02, 0.01), iters=(30, 20, 10), corr_dist=None,
+                 corr_factor=2.0, max_slots=64, budget_bytes=8 << 30, variant="point_to_plane",
+                 precision="kahan32", iters_per_step=5, background_thread=False, device=0):
+        cfg = icp_server_cfg_t()
+        cfg.device, cfg.max_slots, cfg.hbm_budget_bytes = device, max_slots, int(budget_bytes)
+        cfg.n_levels = len(voxels)
+        for k, (v, it) in enumerate(zip(voxels, iters)):
+            cfg.voxel[k], cfg.iters[k] = float(v), int(it)
+            cfg.corr_dist[k] = float(corr_dist[k]) if corr_dist else 0.0
+        cfg.corr_factor = float(corr_factor)
+        cfg.variant, cfg.precision = VARIANTS[variant], PRECISIONS[precision]
+        cfg.iters_per_step, cfg.background_thread = int(iters_per_step), int(background_thread)
+        h = C.c_void_p()
+        _check(lib().icp_server_create(C.byref(cfg), C.byref(h)))
+        self.handle = h.value
+        self.background = bool(background_thread)
+
+    def submit(self, src, tgt, tgt_normals, T_init=None, rel_tol=0.0, spacing=0.0, tag=0) -> int:
+        """src/tgt/tgt_normals: CUDA tensors or numpy arrays (host memory)."""
+        q = icp_request_t()
+        host = isinstance(src, np.ndarray)
+        if host:
+            arrs = [np.ascontiguousarray(a, dtype=np.float32) if a is not None else None
+                    for a in (src, tgt, tgt_normals)]
+            q.src_xyz, q.tgt_xyz = arrs[0].ctypes.data, arrs[1].ctypes.data
+            q.tgt_normals = arrs[2].ctypes.data if arrs[2] is not None else None
+            q.n_src, q.n_tgt = len(arrs[0]), len(arrs[1])
+        else:
+            q.src_xyz, q.n_src = _dev_pts(src, "src")
+            q.tgt_xyz, q.n_tgt = _dev_pts(tgt, "tgt")
+            q.tgt_normals = _dev_pts(tgt_normals, "tgt_normals")[0] if tgt_normals is not None else None
+        q.T_init[:] = [float(x) for x in _pose(np.eye(4) if T_init is None else T_init)]
+        q.rel_tol, q.spacing, q.host_memory, q.reserved, q.user_tag = float(rel_tol), float(spacing), int(host), 0, int(tag)
+        t = C.c_uint64()
+        _check(lib().icp_server_submit(self.handle, C.byref(q), C.byref(t)))
+        return t.value
+
+    def step(self) -> int:
+        n = C.c_int32()
+        _check(lib().icp_server_step(self.handle, C.byref(n)))
+        return n.value
+
+    def poll(self, cap=256) -> list[Completion]:
+        buf = (icp_completion_t * cap)()
+        n = C.c_int32()
+        _check(lib().icp_server_poll(self.handle, buf, cap, C.byref(n)))
+        return [_completion(buf[k]) for k in range(n.value)]
+
+    def wait(self, ticket) -> Completion:
+        c = icp_completion_t()
+        _check(lib().icp_server_wait(self.handle, int(ticket), C.byref(c)))
+        return _completion(c)
+
+    def close(self):
+        if self.handle:
+            _check(lib().icp_server_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -136,3 +136,22 @@ def test_batch_validation():
         assert "pair 2" in L.icp_last_error().decode()
     big = (icp.icp_pair_t * 2)(_pair(n_src=2**30 + 10), _pair(n_src=2**30 + 10))
     assert L.icp_register_batch(None, big, 2, 1, 0, out) == icp.ICP_E_TOO_LARGE
+
+
+def test_server_create_validation():
+    L = icp.lib()
+    h = C.c_void_p()
+    good = icp.icp_server_cfg_t()
+    good.max_slots, good.hbm_budget_bytes, good.n_levels = 4, 1 << 28, 1
+    good.iters[0], good.voxel[0], good.corr_factor = 10, 0.02, 2.0
+    good.variant, good.precision, good.iters_per_step = 1, 0, 4
+    assert L.icp_server_create(None, C.byref(h)) == icp.ICP_E_INVALID_ARG
+    for field, val in (("max_slots", 0), ("n_levels", 5), ("iters_per_step", 0),
+                       ("hbm_budget_bytes", 1000), ("variant", 3), ("precision", 9),
+                       ("corr_factor", 0.0)):
+        cfg = icp.icp_server_cfg_t.from_buffer_copy(good)
+        setattr(cfg, field, val)
+        if field == "corr_factor":
+            cfg.voxel[0] = 0.0
+        assert L.icp_server_create(C.byref(cfg), C.byref(h)) == icp.ICP_E_INVALID_ARG, field
+    assert L.icp_server_destroy(None) == 0

@@ -1,0 +1,163 @@
+"""Served form (icp_server_*) on the GPU.
+
+Every completed request must equal, bitwise, icp_register_multiscale run on
+that request alone (same levels, same max_corr_dist rule): the server's
+batching, admission order and graph replays must not change any result.
+Failure isolation: a request with non-finite input, an injected step failure
+or an oversized input fails alone; the others complete unchanged."""
+import math
+import os
+import sys
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_1801_09847_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+VOX = (0.04, 0.02, 0.01)
+ITS = (12, 8, 4)
+
+
+@pytest.fixture(scope="module")
+def icp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1801_09847_amd import icp as m
+    m.lib()
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+@pytest.fixture(scope="module")
+def requests():
+    out = []
+    for q, n in enumerate([3000, 20000, 800, 45000, 9000, 15000]):
+        d = synth.room_pair_random(20_000 + q, n, n, 4.0, 3.0, 2.5, 6, 3,
+                                   overlap=0.6 + 0.05 * q)
+        d["spacing"] = math.sqrt(d["area"] / n)
+        out.append(d)
+    return out
+
+
+def _plain(icp, d):
+    dists = [2.0 * max(v, d["spacing"]) for v in VOX]
+    return icp.register_multiscale(dev(d["src"]), dev(d["tgt"]), dev(d["tgt_normals"]), np.eye(4),
+                                   VOX, ITS, dists)
+
+
+def _same(c, p):
+    assert c.error == 0, c.error
+    r = c.result
+    np.testing.assert_array_equal(r.T, p.T)
+    assert (r.fitness, r.inlier_rmse, r.n_inliers, r.n_iter, r.status) == \
+        (p.fitness, p.inlier_rmse, p.n_inliers, p.n_iter, p.status)
+
+
+def test_server_results_equal_plain_multiscale(icp, requests):
+    plain = [_plain(icp, d) for d in requests]
+    srv = icp.Server(VOX, ITS, max_slots=4, budget_bytes=1 << 30, iters_per_step=3)
+    keep = [(dev(d["src"]), dev(d["tgt"]), dev(d["tgt_normals"])) for d in requests]
+    tickets = {}
+    # arrivals interleaved with steps: requests join while others run
+    for k, (d, t) in enumerate(zip(requests, keep)):
+        tickets[srv.submit(*t, spacing=d["spacing"], tag=k)] = k
+        srv.step()
+    del keep  # inputs were copied at submit
+    done = []
+    for _ in range(500):
+        done += srv.poll()
+        if len(done) == len(requests):
+            break
+        srv.step()
+    assert len(done) == len(requests)
+    for c in done:
+        k = tickets[c.ticket]
+        assert c.user_tag == k
+        _same(c, plain[k])
+        assert c.t_submit_ns <= c.t_admit_ns <= c.t_done_ns
+    srv.close()
+    # alone: a server with a single request gives the same bits
+    srv = icp.Server(VOX, ITS, max_slots=1, budget_bytes=1 << 30, iters_per_step=7)
+    d = requests[3]
+    t = srv.submit(dev(d["src"]), dev(d["tgt"]), dev(d["tgt_normals"]), spacing=d["spacing"])
+    _same(srv.wait(t), plain[3])
+    srv.close()
+
+
+def test_server_background_thread_and_host_inputs(icp, requests):
+    plain = [_plain(icp, d) for d in requests[:4]]
+    srv = icp.Server(VOX, ITS, max_slots=8, budget_bytes=1 << 30, background_thread=True)
+    tickets = []
+
+    def client():
+        for k, d in enumerate(requests[:4]):
+            src = d["src"] if k % 2 else dev(d["src"])
+            tgt = d["tgt"] if k % 2 else dev(d["tgt"])
+            tn = d["tgt_normals"] if k % 2 else dev(d["tgt_normals"])
+            tickets.append(srv.submit(src, tgt, tn, spacing=d["spacing"], tag=k))
+            time.sleep(0.01)
+
+    th = threading.Thread(target=client)
+    th.start()
+    th.join()
+    for k, t in enumerate(tickets):
+        _same(srv.wait(t), plain[k])
+    with pytest.raises(icp.IcpError) as e:
+        srv.wait(tickets[0])
+    assert e.value.code == icp.ICP_E_NOT_FOUND
+    srv.close()
+
+
+def test_server_small_budget_queues(icp, requests):
+    """A budget far below the total forces host-held inputs and waiting; all
+    requests still complete with the same results."""
+    plain = [_plain(icp, d) for d in requests]
+    srv = icp.Server(VOX, ITS, max_slots=6, budget_bytes=12 << 20, iters_per_step=4)
+    tickets = [srv.submit(dev(d["src"]), dev(d["tgt"]), dev(d["tgt_normals"]), spacing=d["spacing"], tag=k)
+               for k, d in enumerate(requests)]
+    for k, t in enumerate(tickets):
+        _same(srv.wait(t), plain[k])
+    srv.close()
+
+
+def test_server_failure_isolation(icp, requests, monkeypatch):
+    plain = [_plain(icp, d) for d in requests[:4]]
+    monkeypatch.setenv("ICP_FAULT_INJECT", "77")
+    srv = icp.Server(VOX, ITS, max_slots=4, budget_bytes=1 << 30)
+    monkeypatch.delenv("ICP_FAULT_INJECT")
+    bad = requests[1]["src"].copy()
+    bad[17, 1] = np.nan
+    t_ok = [srv.submit(dev(d["src"]), dev(d["tgt"]), dev(d["tgt_normals"]), spacing=d["spacing"], tag=k)
+            for k, d in enumerate(requests[:4])]
+    t_nan = srv.submit(dev(bad), dev(requests[1]["tgt"]), dev(requests[1]["tgt_normals"]),
+                       spacing=requests[1]["spacing"], tag=50)
+    t_inj = srv.submit(dev(requests[0]["src"]), dev(requests[0]["tgt"]), dev(requests[0]["tgt_normals"]),
+                       spacing=requests[0]["spacing"], tag=77)
+    assert srv.wait(t_nan).error == icp.ICP_E_NONFINITE
+    assert srv.wait(t_inj).error == icp.ICP_E_DEVICE
+    for k, t in enumerate(t_ok):
+        _same(srv.wait(t), plain[k])
+    srv.close()
+
+
+def test_server_rejects_and_cancels(icp, requests):
+    srv = icp.Server(VOX, ITS, max_slots=2, budget_bytes=1 << 20)
+    d = requests[3]  # 45k points: 1.6 MB of inputs, above a 1 MiB budget
+    with pytest.raises(icp.IcpError) as e:
+        srv.submit(dev(d["src"]), dev(d["tgt"]), dev(d["tgt_normals"]), spacing=d["spacing"])
+    assert e.value.code == icp.ICP_E_TOO_LARGE
+    small = requests[2]
+    t = srv.submit(dev(small["src"]), dev(small["tgt"]), dev(small["tgt_normals"]), spacing=small["spacing"])
+    srv.close()  # destroys with the request pending: cancelled, no leak or crash
+    srv = icp.Server(VOX, ITS, max_slots=2, budget_bytes=64 << 20)
+    t = srv.submit(dev(small["src"]), dev(small["tgt"]), dev(small["tgt_normals"]), spacing=small["spacing"])
+    assert srv.wait(t).error == 0
+    srv.close()

@@ -415,3 +415,49 @@ def test_heightfield_c1_recovers_ground_truth(oracle_lib):
     ang = math.acos(min(1.0, (np.trace(E[:3, :3]) - 1) / 2))
     assert ang < 2e-3 and np.linalg.norm(E[:3, 3]) < 2e-3
     assert a.fitness > 0.99
+
+
+# ------------------------------------------------------------------ voxel downsampling
+def test_voxel_downsample_definition(oracle_lib):
+    """Each output is the mean of the points of one occupied voxel (brute force
+    over voxel membership), outputs are ordered by voxel key, normals are the
+    normalised sums."""
+    rng = np.random.default_rng(21)
+    pts = rng.uniform(0, 0.3, (700, 3)).astype(np.float32)
+    nrm = rng.normal(size=(700, 3))
+    nrm = (nrm / np.linalg.norm(nrm, axis=1, keepdims=True)).astype(np.float32)
+    v = 0.05
+    out, outn = oracle_lib.voxel_downsample(pts, v, nrm)
+    o = pts.astype(np.float64).min(0)
+    dims = np.floor((pts.astype(np.float64).max(0) - o) / v).astype(np.int64) + 1
+    cell = np.minimum(np.floor((pts.astype(np.float64) - o) * (1.0 / v)).astype(np.int64), dims - 1)
+    key = (cell[:, 2] * dims[1] + cell[:, 1]) * dims[0] + cell[:, 0]
+    keys = np.unique(key)
+    assert len(out) == len(keys)
+    for j, k in enumerate(keys):
+        m = key == k
+        mean = pts[m].astype(np.float64).mean(0)
+        assert np.abs(out[j] - mean).max() <= 1e-7
+        s = nrm[m].astype(np.float64).sum(0)
+        assert np.abs(outn[j] - s / np.linalg.norm(s)).max() <= 1e-6
+        # the mean lies inside its voxel
+        assert np.all(np.floor((out[j].astype(np.float64) - o) / v + 1e-9) <= np.unravel_index(k, dims[::-1])[::-1])
+
+
+def test_voxel_downsample_special_cases(oracle_lib):
+    rng = np.random.default_rng(22)
+    pts = rng.uniform(-1, 1, (300, 3)).astype(np.float32)
+    # one voxel covering everything: the global mean (sequential float64 sum)
+    out, _ = oracle_lib.voxel_downsample(pts, 10.0)
+    assert len(out) == 1
+    ref = np.float32(np.add.accumulate(pts.astype(np.float64), axis=0)[-1] / len(pts))
+    np.testing.assert_array_equal(out[0], ref)
+    # tiny voxels: every point alone, so the output is the input in key order
+    out, _ = oracle_lib.voxel_downsample(pts, 1e-6)
+    assert len(out) == len(pts)
+    assert set(map(tuple, out)) == set(map(tuple, pts))
+    # opposite normals cancel: the first member's normal is kept
+    p2 = np.array([[0.01, 0.01, 0.01], [0.02, 0.02, 0.02]], np.float32)
+    n2 = np.array([[0, 0, 1], [0, 0, -1]], np.float32)
+    out, outn = oracle_lib.voxel_downsample(p2, 1.0, n2)
+    np.testing.assert_array_equal(outn[0], n2[0])

@@ -88,7 +88,7 @@ def batched_section(args, icp, synth, np, torch, oracle_sample=8):
     """C4: 256 independent pairs, sizes log-uniform in [2k, 200k], one batched
     call vs the same pairs through the plain per-pair call."""
     print("bench: generating 256 batched pairs", file=sys.stderr, flush=True)
-    data = [synth.c4_pair(p) for p in range(args.batch_pairs)]
+    data = parallel_generate(_gen_c4, range(args.batch_pairs))
     dev = torch.device("cuda:0")
     tens = [(torch.from_numpy(d["src"]).to(dev), torch.from_numpy(d["tgt"]).to(dev),
              torch.from_numpy(d["tgt_normals"]).to(dev)) for d in data]
@@ -147,6 +147,135 @@ def batched_section(args, icp, synth, np, torch, oracle_sample=8):
     return out
 
 
+def _gen_c5(q):
+    from paper_1801_09847_amd import synth
+    import math
+    d = synth.c5_request(q)
+    return {"src": d["src"], "tgt": d["tgt"], "tgt_normals": d["tgt_normals"],
+            "spacing": math.sqrt(d["area"] / len(d["tgt"]))}
+
+
+def _gen_c4(p):
+    from paper_1801_09847_amd import synth
+    return synth.c4_pair(p)
+
+
+def parallel_generate(fn, items, workers=8):
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(fn, items))
+
+
+def served_section(args, icp, np, torch):
+    """C5: requests (sizes log-uniform in [5k, 500k], room pairs, overlap
+    U(0.5, 0.9)) arriving as a Poisson process; multi-scale ICP (voxel 4/2/1 cm,
+    30/20/10 iterations, max_corr_dist 2 max(voxel, spacing)), point-to-plane.
+    Served: icp_server with a background thread.  Plain: the same requests
+    back to back through icp_register_multiscale."""
+    import threading
+    from paper_1801_09847_amd import synth
+    vox, its = (0.04, 0.02, 0.01), (30, 20, 10)
+    print(f"bench: generating {args.served_pool} served requests", file=sys.stderr, flush=True)
+    pool = parallel_generate(_gen_c5, range(args.served_pool))
+    dev = torch.device("cuda:0")
+    tens = [(torch.from_numpy(d["src"]).to(dev), torch.from_numpy(d["tgt"]).to(dev),
+             torch.from_numpy(d["tgt_normals"]).to(dev)) for d in pool]
+    torch.cuda.synchronize()
+    n_req = args.served_requests
+    order = [q % len(pool) for q in range(n_req)]
+    ctx = icp.Context(0)
+
+    def plain_one(k):
+        d = pool[k]
+        dists = [2.0 * max(v, d["spacing"]) for v in vox]
+        return icp.register_multiscale(*tens[k], np.eye(4), vox, its, dists, 0.0, ctx=ctx)
+
+    for k in range(min(4, len(pool))):
+        plain_one(k)
+    torch.cuda.synchronize()
+    service = []
+    plain_res = {}
+    t0 = time.perf_counter()
+    for k in order:
+        a = time.perf_counter()
+        r = plain_one(k)
+        service.append(time.perf_counter() - a)
+        plain_res.setdefault(k, r)
+    plain_total = time.perf_counter() - t0
+    plain_rate = n_req / plain_total
+    out = {"workload": f"{n_req} requests cycled over {len(pool)} distinct room pairs, sizes "
+                       "log-uniform in [5k, 500k], multi-scale 4/2/1 cm x 30/20/10 iterations, "
+                       "point-to-plane, Poisson arrivals",
+           "plain_pairs_per_s": plain_rate, "plain_ms_total": plain_total * 1e3,
+           "server": {"max_slots": args.served_slots, "iters_per_step": args.served_iters_per_step,
+                      "budget_bytes": args.served_budget}, "rates": []}
+    print(f"bench: plain {plain_rate:.1f} pairs/s", file=sys.stderr, flush=True)
+    rng = np.random.Generator(np.random.PCG64(12345))
+    for mult in args.served_rates:
+        rate = mult * plain_rate
+        gaps = rng.exponential(1.0 / rate, n_req)
+        arrivals = np.cumsum(gaps) - gaps[0]
+        srv = icp.Server(vox, its, corr_factor=2.0, max_slots=args.served_slots,
+                         budget_bytes=args.served_budget, iters_per_step=args.served_iters_per_step,
+                         background_thread=True)
+        warm = srv.submit(*tens[0], spacing=pool[0]["spacing"])
+        srv.wait(warm)
+        tickets = {}
+        base_ns = [0]
+
+        def client():
+            t_start = time.monotonic_ns()
+            base_ns[0] = t_start
+            for q in range(n_req):
+                target = t_start + int(arrivals[q] * 1e9)
+                now = time.monotonic_ns()
+                if target > now:
+                    time.sleep((target - now) / 1e9)
+                k = order[q]
+                tickets[srv.submit(*tens[k], spacing=pool[k]["spacing"], tag=q)] = q
+
+        th = threading.Thread(target=client)
+        th.start()
+        done = []
+        while len(done) < n_req:
+            got = srv.poll()
+            if not got:
+                time.sleep(0.0005)
+            done += got
+        th.join()
+        srv.close()
+        lat = []
+        mismatch = 0
+        last_done = 0
+        for c in done:
+            q = c.user_tag
+            arr_ns = base_ns[0] + int(arrivals[q] * 1e9)
+            lat.append((c.t_done_ns - arr_ns) / 1e6)
+            last_done = max(last_done, c.t_done_ns)
+            p = plain_res[order[q]]
+            if c.error or not np.array_equal(c.result.T, p.T) or c.result.n_iter != p.n_iter:
+                mismatch += 1
+        served_rate = n_req / ((last_done - base_ns[0]) / 1e9)
+        # plain latency under the same arrivals: FIFO single server with the measured service times
+        t_free, plat = 0.0, []
+        for q in range(n_req):
+            start = max(arrivals[q], t_free)
+            t_free = start + service[q]
+            plat.append((t_free - arrivals[q]) * 1e3)
+        entry = {"rate_x_plain": mult, "offered_per_s": rate, "served_pairs_per_s": served_rate,
+                 "speedup_vs_plain": served_rate / plain_rate,
+                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                 "plain_p50_ms": float(np.percentile(plat, 50)),
+                 "plain_p99_ms": float(np.percentile(plat, 99)),
+                 "results_differing_from_plain": mismatch}
+        out["rates"].append(entry)
+        print(f"bench: served x{mult}: {served_rate:.1f} pairs/s p50 {entry['p50_ms']:.1f} ms "
+              f"p99 {entry['p99_ms']:.1f} ms (plain p50 {entry['plain_p50_ms']:.1f} p99 "
+              f"{entry['plain_p99_ms']:.1f})", file=sys.stderr, flush=True)
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,6 +289,13 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 256-pair batched section")
     ap.add_argument("--batch-pairs", type=int, default=256)
     ap.add_argument("--batch-reps", type=int, default=3)
+    ap.add_argument("--no-served", action="store_true", help="skip the served (request server) section")
+    ap.add_argument("--served-requests", type=int, default=400)
+    ap.add_argument("--served-pool", type=int, default=64)
+    ap.add_argument("--served-rates", type=float, nargs="+", default=[1.0, 8.0])
+    ap.add_argument("--served-slots", type=int, default=128)
+    ap.add_argument("--served-iters-per-step", type=int, default=5)
+    ap.add_argument("--served-budget", type=int, default=64 << 30)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -258,9 +394,11 @@ def main():
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(data, args.variant, args.cpu_passes)
+    del s, t, n
     if not args.no_batched:
-        del s, t, n
         out["batched"] = batched_section(args, icp, synth, np, torch)
+    if not args.no_served:
+        out["served"] = served_section(args, icp, np, torch)
     print(json.dumps(out), flush=True)
 
 

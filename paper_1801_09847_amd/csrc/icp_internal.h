@@ -167,11 +167,7 @@ hipError_t launch_batch_pass(const PassArgs* pairs, const uint2* items, int n_it
                              int variant, int precision, hipStream_t s);
 hipError_t launch_batch_solve(const SolveArgs* arr, int n_pairs, hipStream_t s);
 
-// Served form (graph-capturable: fixed launch shapes, counts read on device).
-// ctrl[0] = items, ctrl[1] = item counter, ctrl[2] = active slots.
-hipError_t launch_persistent_pass(const PassArgs* pairs, const uint2* items, int* ctrl, int blocks,
-                                  int sub, int variant, int precision, hipStream_t s);
-hipError_t launch_slot_solve(const SolveArgs* arr, int* ctrl, int slots, hipStream_t s);
+// Copies the loop states of `n` batched pairs into one array (one readback).
 hipError_t launch_gather_states(const SolveArgs* arr, int n, IterState* out, hipStream_t s);
 
 }  // namespace icp

@@ -36,6 +36,23 @@ static_assert(kRounds * kBlock == kTile, "tile size");
 
 __device__ inline int lane_id() { return __lane_id(); }
 
+// Global-address-space view of a pointer.  Arguments that arrive through a
+// struct in memory (batched and served launches) are otherwise generic
+// pointers, which compile to FLAT accesses; FLAT loads share the LDS wait
+// counter and serialise this kernel's LDS and memory waits.
+#define ICP_G __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ ICP_G T* glb(T* p) {
+  return (ICP_G T*)(p);
+}
+// float4 has a user-declared copy constructor on a generic reference, so a
+// global-space element is read as a clang vector and repacked.
+typedef float icp_f4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ld4(const float4* p, int64_t i) {
+  const icp_f4v v = ((const ICP_G icp_f4v*)p)[i];
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+
 // ------------------------------------------------------------------ small helpers
 template <class T>
 __device__ inline T wave_sum_xor(T v) {
@@ -173,7 +190,7 @@ __device__ inline void find_nearest(const PassArgs& a, float q32x, float q32y, f
         xhi = min(xhi, g.dx - 1);
         if (xlo <= xhi) {
           const uint32_t row = ((uint32_t)z * (uint32_t)g.dy + (uint32_t)y) * (uint32_t)g.dx;
-          const uint32_t beg = a.cs[row + xlo], end = a.cs[row + xhi + 1];
+          const uint32_t beg = glb(a.cs)[row + xlo], end = glb(a.cs)[row + xhi + 1];
           if (beg < end) {
             lane_ranges[m * kWave] = make_uint2(beg, end);
             ++m;
@@ -194,7 +211,7 @@ __device__ inline void find_nearest(const PassArgs& a, float q32x, float q32y, f
       pos = e.x;
       end = e.y;
     }
-    const float4 p = a.tp[pos];
+    const float4 p = ld4(a.tp, pos);
     const float dx = q32x - p.x, dy = q32y - p.y, dz = q32z - p.z;
     float d2 = dx * dx + dy * dy;
     d2 = d2 + dz * dz;
@@ -239,7 +256,7 @@ __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
   __shared__ uint32_t red_n[kBlock / kWave];
   double T[12];
 #pragma unroll
-  for (int k = 0; k < 12; ++k) T[k] = a.st->T[k];
+  for (int k = 0; k < 12; ++k) T[k] = glb(a.st)->T[k];
   const int w = threadIdx.x / kWave, lane = lane_id();
   uint32_t* ws = scratch[w];
   uint2* lane_ranges = reinterpret_cast<uint2*>(ws) + lane;
@@ -260,7 +277,7 @@ __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
     double q64x = 0.0, q64y = 0.0, q64z = 0.0;
     float q32x = 0.f, q32y = 0.f, q32z = 0.f;
     if (i < a.n_src) {
-      const double sx = a.sx[i], sy = a.sy[i], sz = a.sz[i];
+      const double sx = glb(a.sx)[i], sy = glb(a.sy)[i], sz = glb(a.sz)[i];
       double t;
       t = T[0] * sx; t = t + T[1] * sy; t = t + T[2] * sz; q64x = t + T[3];
       t = T[4] * sx; t = t + T[5] * sy; t = t + T[6] * sz; q64y = t + T[7];
@@ -269,9 +286,9 @@ __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
       uint64_t best = ~0ull;
       if (a.jprev) {
         // warm start: the previous pass's match bounds this pass's distance
-        const uint32_t jp = a.jprev[i];
+        const uint32_t jp = glb(a.jprev)[i];
         if (jp != 0xffffffffu) {
-          const float4 p = a.tp[jp];
+          const float4 p = ld4(a.tp, jp);
           const float dx = q32x - p.x, dy = q32y - p.y, dz = q32z - p.z;
           float d2 = dx * dx + dy * dy;
           d2 = d2 + dz * dz;
@@ -285,12 +302,12 @@ __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
       const float bd = __uint_as_float((uint32_t)(best >> 32));
       const uint32_t bo = (uint32_t)best;
       inl = best != ~0ull && bd <= a.r2f;
-      if (inl) bp = a.tp[bj];
-      if (a.jprev) a.jprev[i] = inl ? bj : 0xffffffffu;
+      if (inl) bp = ld4(a.tp, bj);
+      if (a.jprev) glb(a.jprev)[i] = inl ? bj : 0xffffffffu;
       if (WRITE) {
-        const uint32_t oi = a.sperm[i];
-        a.idx_out[oi] = inl ? (int32_t)bo : -1;
-        a.d2_out[oi] = inl ? bd : INFINITY;
+        const uint32_t oi = glb(a.sperm)[i];
+        glb(a.idx_out)[oi] = inl ? (int32_t)bo : -1;
+        glb(a.d2_out)[oi] = inl ? bd : INFINITY;
       }
     }
     cnt += (uint32_t)__popcll(__ballot(inl));
@@ -302,7 +319,7 @@ __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
         const double rx = q64x - (double)bp.x, ry = q64y - (double)bp.y, rz = q64z - (double)bp.z;
         const float fx = (float)rx, fy = (float)ry, fz = (float)rz;
         float4 n = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (VAR == 1) n = a.tn[bj];
+        if (VAR == 1) n = ld4(a.tn, bj);
         record_terms<VAR, float>(q32x, q32y, q32z, fx, fy, fz, n.x, n.y, n.z, v);
         const float d2 = fx * fx + fy * fy;
         v[27] = d2 + fz * fz;
@@ -338,7 +355,7 @@ __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
           const double rx = q64x - px, ry = q64y - py, rz = q64z - pz;
           double nx = 0.0, ny = 0.0, nz = 0.0;
           if (VAR == 1) {
-            const float4 n = a.tn[bj];
+            const float4 n = ld4(a.tn, bj);
             nx = n.x; ny = n.y; nz = n.z;
           }
           record_terms<VAR, double>(q64x, q64y, q64z, rx, ry, rz, nx, ny, nz, v);
@@ -405,17 +422,17 @@ __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
       out = red_d[0][k];
       for (int ww = 1; ww < kBlock / kWave; ++ww) out = out + red_d[ww][k];
     }
-    a.part[(int64_t)k * a.n_blocks + tile_index] = out;
+    glb(a.part)[(int64_t)k * a.n_blocks + tile_index] = out;
   } else if (threadIdx.x == 28) {
     uint32_t nn = 0;
     for (int ww = 0; ww < kBlock / kWave; ++ww) nn += red_n[ww];
-    a.part[(int64_t)28 * a.n_blocks + tile_index] = (double)nn;
+    glb(a.part)[(int64_t)28 * a.n_blocks + tile_index] = (double)nn;
   }
 }
 
 template <int VAR, int PREC, bool WRITE, int R>
 __global__ __launch_bounds__(kBlock) void pass_kernel(PassArgs a) {
-  if (a.st->done) return;
+  if (glb(a.st)->done) return;
   pass_tile<VAR, PREC, WRITE, R>(a, blockIdx.x);
 }
 
@@ -426,32 +443,9 @@ template <int VAR, int PREC, int R>
 __global__ __launch_bounds__(kBlock) void batch_pass_kernel(const PassArgs* __restrict__ pairs,
                                                             const uint2* __restrict__ items) {
   const uint2 it = items[blockIdx.x];
-  const PassArgs& a = pairs[it.x];
-  if (a.st->done) return;
+  const PassArgs a = pairs[it.x];  // by value: uniform, kept in scalar registers
+  if (glb(a.st)->done) return;
   pass_tile<VAR, PREC, false, R>(a, it.y);
-}
-
-// Served form: a fixed grid of blocks takes (pair, tile) items from a device
-// counter until the item list is exhausted, so the launch shape does not
-// depend on the active set and the launch can be captured once in a graph.
-// ctrl[0] = number of items (written before the launch), ctrl[1] = item
-// counter (0 at launch; reset by the solve kernel that follows).
-template <int VAR, int PREC, int R>
-__global__ __launch_bounds__(kBlock) void persistent_pass_kernel(const PassArgs* __restrict__ pairs,
-                                                                 const uint2* __restrict__ items,
-                                                                 int* ctrl) {
-  __shared__ int s_item;
-  const int n_items = ctrl[0];
-  for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(&ctrl[1], 1);
-    __syncthreads();
-    const int it = s_item;
-    __syncthreads();
-    if (it >= n_items) break;
-    const uint2 w = items[it];
-    const PassArgs& a = pairs[w.x];
-    if (!a.st->done) pass_tile<VAR, PREC, false, R>(a, w.y);
-  }
 }
 
 // ------------------------------------------------------------------ solve + pose update
@@ -543,7 +537,7 @@ __device__ void apply_exp(const double* xi, double* T) {
 }
 
 __device__ void solve_body(const SolveArgs& a) {
-  IterState* st = a.st;
+  ICP_G IterState* st = glb(a.st);
   if (st->done) return;
   __shared__ double sums[kNumSums];
   // term v = t / 32 is summed by 32 threads (half a wave), each over the block
@@ -551,7 +545,7 @@ __device__ void solve_body(const SolveArgs& a) {
   const int t = threadIdx.x, v = t >> 5, g = t & 31;
   double acc = 0.0;
   if (v < kNumSums) {
-    const double* p = a.part + (int64_t)v * a.n_blocks;
+    const ICP_G double* p = glb(a.part) + (int64_t)v * a.n_blocks;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     int b = g;
     for (; b + 96 < a.n_blocks; b += 128) {
@@ -616,17 +610,11 @@ __global__ __launch_bounds__(1024) void solve_kernel(SolveArgs a) { solve_body(a
 
 // Batched form: block p reduces, solves and updates pair p.
 __global__ __launch_bounds__(1024) void batch_solve_kernel(const SolveArgs* __restrict__ arr) {
-  solve_body(arr[blockIdx.x]);
+  const SolveArgs a = arr[blockIdx.x];
+  solve_body(a);
 }
 
-// Served form: a fixed grid of max_slots blocks; block b serves slot b when
-// b < ctrl[2] (active slots).  Block 0 resets the pass kernel's item counter.
-__global__ __launch_bounds__(1024) void slot_solve_kernel(const SolveArgs* __restrict__ arr, int* ctrl) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) ctrl[1] = 0;
-  if ((int)blockIdx.x < ctrl[2]) solve_body(arr[blockIdx.x]);
-}
-
-// Copies the states of the served slots into one array (one readback).
+// Copies the loop states of a batch's pairs into one array (one readback).
 __global__ void gather_states_kernel(const SolveArgs* __restrict__ arr, int n, IterState* __restrict__ out) {
   const int b = blockIdx.x;
   if (b >= n) return;
@@ -691,31 +679,6 @@ hipError_t launch_batch_pass(const PassArgs* pairs, const uint2* items, int n_it
     launch_batch_pass_r<2>(pairs, items, n_items, variant, precision, s);
   else
     launch_batch_pass_r<1>(pairs, items, n_items, variant, precision, s);
-  return hipGetLastError();
-}
-
-template <int R>
-void launch_persistent_pass_r(const PassArgs* pairs, const uint2* items, int* ctrl, int blocks,
-                              int variant, int precision, hipStream_t s) {
-  const dim3 grid((unsigned)blocks), block(kBlock);
-#define ICP_PPASS(V, P) \
-  hipLaunchKernelGGL((persistent_pass_kernel<V, P, R>), grid, block, 0, s, pairs, items, ctrl)
-  if (variant == 1) { if (precision == 0) ICP_PPASS(1, 0); else ICP_PPASS(1, 1); }
-  else { if (precision == 0) ICP_PPASS(0, 0); else ICP_PPASS(0, 1); }
-#undef ICP_PPASS
-}
-
-hipError_t launch_persistent_pass(const PassArgs* pairs, const uint2* items, int* ctrl, int blocks,
-                                  int sub, int variant, int precision, hipStream_t s) {
-  if (sub == 2)
-    launch_persistent_pass_r<2>(pairs, items, ctrl, blocks, variant, precision, s);
-  else
-    launch_persistent_pass_r<1>(pairs, items, ctrl, blocks, variant, precision, s);
-  return hipGetLastError();
-}
-
-hipError_t launch_slot_solve(const SolveArgs* arr, int* ctrl, int slots, hipStream_t s) {
-  hipLaunchKernelGGL(slot_solve_kernel, dim3((unsigned)slots), dim3(1024), 0, s, arr, ctrl);
   return hipGetLastError();
 }
 

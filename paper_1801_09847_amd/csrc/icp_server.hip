@@ -7,10 +7,10 @@
 // same step), then ICP iterations run together with all other running
 // requests -> completion.  All device memory of a request comes from one
 // first-fit pool of the configured budget, so the step loop never calls
-// hipMalloc.  Each step replays one captured graph of `iters_per_step`
-// (persistent pass, slot solve) launch pairs; the graph reads the slot table
-// (pass arguments, solve arguments, work items, counts) from device memory,
-// so admissions and retirements only rewrite that table.
+// hipMalloc.  Each step uploads one slot table (pass arguments, solve
+// arguments, (slot, tile) work items) and runs `iters_per_step` iterations of
+// the batched pass and solve kernels over it; a slot whose level has finished
+// is skipped on device by its state's done flag.
 
 #include <string.h>
 #include <time.h>
@@ -116,13 +116,10 @@ struct icp_server {
   hipStream_t copy_stream = nullptr;
   Buf pool_mem;
   Pool pool;
-  Buf table;  // PassArgs[slots] | SolveArgs[slots] | uint2 items[items_cap] | int ctrl[4] | IterState[slots]
-  size_t o_pargs = 0, o_sargs = 0, o_items = 0, o_ctrl = 0, o_states = 0, table_bytes = 0;
+  Buf table;  // PassArgs[slots] | SolveArgs[slots] | uint2 items[items_cap] | IterState[slots]
+  size_t o_pargs = 0, o_sargs = 0, o_items = 0, o_states = 0, table_bytes = 0;
   int64_t items_cap = 0;
   void* host_table = nullptr;  // pinned mirror
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  int pass_blocks = 0;
   uint64_t fault_tag = 0;
   bool fault_on = false;
   // bookkeeping (mu)
@@ -443,12 +440,13 @@ int server_step(icp_server* s, int32_t* n_busy) {
     for (Req* r : s->active)
       if (r->state == kRun) run.push_back(r);
   }
+  // (the first running request always fits the item table: its tiles are
+  // bounded by its memory, which the pool budget bounds)
   if (!run.empty()) {
     char* hh = static_cast<char*>(s->host_table);
     PassArgs* hp = reinterpret_cast<PassArgs*>(hh + s->o_pargs);
     SolveArgs* hs = reinterpret_cast<SolveArgs*>(hh + s->o_sargs);
     uint2* hi = reinterpret_cast<uint2*>(hh + s->o_items);
-    int* hc = reinterpret_cast<int*>(hh + s->o_ctrl);
     int64_t items = 0;
     std::vector<Req*> slot;
     for (Req* r : run) {
@@ -459,17 +457,19 @@ int server_step(icp_server* s, int32_t* n_busy) {
       for (int t = 0; t < r->pa.n_blocks; ++t) hi[items++] = make_uint2((uint32_t)b, (uint32_t)t);
       slot.push_back(r);
     }
-    hc[0] = (int)items;
-    hc[1] = 0;
-    hc[2] = (int)slot.size();
-    hc[3] = 0;
+    if (slot.empty()) return fail(ICP_E_DEVICE, "slot table: no running request fits the item table");
     char* dd = s->table.as<char>();
     hipStream_t st = c->stream;
     HIP_TRY(hipMemcpyAsync(dd, hh, s->o_items + sizeof(uint2) * (size_t)items, hipMemcpyHostToDevice, st),
             "upload");
-    HIP_TRY(hipMemcpyAsync(dd + s->o_ctrl, hh + s->o_ctrl, 4 * sizeof(int), hipMemcpyHostToDevice, st),
-            "upload");
-    HIP_TRY(hipGraphLaunch(s->exec, st), "hipGraphLaunch");
+    const PassArgs* dp = reinterpret_cast<const PassArgs*>(dd + s->o_pargs);
+    const SolveArgs* ds = reinterpret_cast<const SolveArgs*>(dd + s->o_sargs);
+    const uint2* di = reinterpret_cast<const uint2*>(dd + s->o_items);
+    const int sub = slot[0]->pa.g.sub;  // one grid rule per process: equal for all slots
+    for (int k = 0; k < s->cfg.iters_per_step; ++k) {
+      HIP_TRY(launch_batch_pass(dp, di, (int)items, sub, s->cfg.variant, s->cfg.precision, st), "pass");
+      HIP_TRY(launch_batch_solve(ds, (int)slot.size(), st), "solve");
+    }
     IterState* dstates = reinterpret_cast<IterState*>(dd + s->o_states);
     HIP_TRY(launch_gather_states(reinterpret_cast<const SolveArgs*>(dd + s->o_sargs), (int)slot.size(),
                                  dstates, st),
@@ -523,35 +523,10 @@ void worker_loop(icp_server* s) {
   }
 }
 
-int capture_graph(icp_server* s) {
-  icp_ctx* c = s->ctx;
-  char* dd = s->table.as<char>();
-  const PassArgs* dp = reinterpret_cast<const PassArgs*>(dd + s->o_pargs);
-  const SolveArgs* ds = reinterpret_cast<const SolveArgs*>(dd + s->o_sargs);
-  const uint2* di = reinterpret_cast<const uint2*>(dd + s->o_items);
-  int* dc = reinterpret_cast<int*>(dd + s->o_ctrl);
-  HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal), "capture");
-  hipError_t e = hipSuccess;
-  for (int k = 0; k < s->cfg.iters_per_step && e == hipSuccess; ++k) {
-    e = launch_persistent_pass(dp, di, dc, s->pass_blocks, kDefaultSub, s->cfg.variant, s->cfg.precision,
-                               c->stream);
-    if (e == hipSuccess) e = launch_slot_solve(ds, dc, s->cfg.max_slots, c->stream);
-  }
-  hipGraph_t g = nullptr;
-  hipError_t e2 = hipStreamEndCapture(c->stream, &g);
-  if (e != hipSuccess) return hip_fail(e, "capture launch");
-  if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
-  s->graph = g;
-  HIP_TRY(hipGraphInstantiate(&s->exec, g, nullptr, nullptr, 0), "hipGraphInstantiate");
-  return ICP_SUCCESS;
-}
-
 void server_free(icp_server* s) {
   if (s->ctx) {
     DeviceGuard dg(s->ctx->device);
     if (s->ctx->stream) (void)hipStreamSynchronize(s->ctx->stream);
-    if (s->exec) (void)hipGraphExecDestroy(s->exec);
-    if (s->graph) (void)hipGraphDestroy(s->graph);
     s->pool_mem.release();
     s->table.release();
     if (s->host_table) (void)hipHostFree(s->host_table);
@@ -615,21 +590,16 @@ int icp_server_create(const icp_server_cfg_t* cfg, icp_server_t** out) {
   s->o_pargs = take(sizeof(PassArgs) * k.max_slots);
   s->o_sargs = take(sizeof(SolveArgs) * k.max_slots);
   s->o_items = take(sizeof(uint2) * (size_t)s->items_cap);
-  s->o_ctrl = take(4 * sizeof(int));
   s->o_states = take(sizeof(IterState) * k.max_slots);
   s->table_bytes = align256(off);
   if ((e = s->table.ensure(s->table_bytes)) != hipSuccess) return bail(hip_fail(e, "table"));
   if ((e = hipMemset(s->table.p, 0, s->table_bytes)) != hipSuccess) return bail(hip_fail(e, "memset"));
   if ((e = hipHostMalloc(&s->host_table, s->table_bytes, hipHostMallocDefault)) != hipSuccess)
     return bail(hip_fail(e, "hipHostMalloc"));
-  hipDeviceProp_t prop;
-  if ((e = hipGetDeviceProperties(&prop, k.device)) != hipSuccess) return bail(hip_fail(e, "props"));
-  s->pass_blocks = std::max(1, prop.multiProcessorCount) * 4;
   if (const char* f = getenv("ICP_FAULT_INJECT")) {
     s->fault_on = true;
     s->fault_tag = strtoull(f, nullptr, 10);
   }
-  if ((rc = capture_graph(s)) != 0) return bail(rc);
   if (k.background_thread) s->worker = std::thread(worker_loop, s);
   *out = s;
   return ICP_SUCCESS;

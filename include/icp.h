@@ -222,9 +222,9 @@ int icp_register_multiscale(icp_ctx_t *ctx, const float *src_xyz, int64_t n_src,
  * memory budget allows, and advances every admitted request through a
  * coarse-to-fine schedule (voxel downsampling then ICP per level, as
  * icp_register_multiscale).  One server step runs `iters_per_step`
- * iterations of all running requests together (one batched pass launch and
- * one batched solve launch per iteration over every running request's tiles),
- * then retires finished levels and requests.  A request's result is bitwise the
+ * iterations of all running requests together (one HIP graph replay: per
+ * iteration one batched pass launch over every running request's tiles and
+ * one batched solve launch), then retires finished levels and requests.  A request's result is bitwise the
  * one icp_register_multiscale gives for it alone.
  * Level l of a request uses max_corr_dist = corr_dist[l] if > 0, else
  * corr_factor * max(voxel[l], spacing) with the request's target spacing. */
@@ -271,7 +271,8 @@ typedef struct {
 } icp_completion_t;
 
 /* Creates a server (its own context, stream, device memory pool of
- * hbm_budget_bytes and slot table).  Errors: INVALID_ARG, OOM, DEVICE. */
+ * hbm_budget_bytes, slot table and step graph).  Errors: INVALID_ARG, OOM,
+ * DEVICE. */
 int icp_server_create(const icp_server_cfg_t *cfg, icp_server_t **out);
 
 /* Copies the request's inputs (device-to-device or host-to-device) into

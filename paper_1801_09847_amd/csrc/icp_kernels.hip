@@ -694,4 +694,30 @@ hipError_t launch_batch_solve(const SolveArgs* arr, int n_pairs, hipStream_t s) 
   return hipGetLastError();
 }
 
+void batch_pass_node(int sub, int variant, int precision, hipKernelNodeParams* p) {
+  void* f;
+#define ICP_F(R, V, P) f = reinterpret_cast<void*>(&batch_pass_kernel<V, P, R>)
+  if (sub == 2) {
+    if (variant == 1) { if (precision == 0) ICP_F(2, 1, 0); else ICP_F(2, 1, 1); }
+    else { if (precision == 0) ICP_F(2, 0, 0); else ICP_F(2, 0, 1); }
+  } else {
+    if (variant == 1) { if (precision == 0) ICP_F(1, 1, 0); else ICP_F(1, 1, 1); }
+    else { if (precision == 0) ICP_F(1, 0, 0); else ICP_F(1, 0, 1); }
+  }
+#undef ICP_F
+  p->func = f;
+  p->blockDim = dim3(kBlock);
+  p->gridDim = dim3(1);
+  p->sharedMemBytes = 0;
+  p->extra = nullptr;
+}
+
+void batch_solve_node(hipKernelNodeParams* p) {
+  p->func = reinterpret_cast<void*>(&batch_solve_kernel);
+  p->blockDim = dim3(1024);
+  p->gridDim = dim3(1);
+  p->sharedMemBytes = 0;
+  p->extra = nullptr;
+}
+
 }  // namespace icp

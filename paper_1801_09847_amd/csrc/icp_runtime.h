@@ -98,6 +98,8 @@ struct DeviceGuard {
 };
 
 int ctx_init(icp_ctx* c, int device, void* stream);
+// Cells per max_corr_dist along an axis for every grid this process builds.
+int grid_sub();
 void ctx_free(icp_ctx* c);
 int ensure_host(icp_ctx* c, size_t bytes);
 int check_cloud(const float* p, int64_t n, const char* name);

@@ -7,10 +7,11 @@
 // same step), then ICP iterations run together with all other running
 // requests -> completion.  All device memory of a request comes from one
 // first-fit pool of the configured budget, so the step loop never calls
-// hipMalloc.  Each step uploads one slot table (pass arguments, solve
-// arguments, (slot, tile) work items) and runs `iters_per_step` iterations of
-// the batched pass and solve kernels over it; a slot whose level has finished
-// is skipped on device by its state's done flag.
+// hipMalloc.  Each step uploads the slot table (pass arguments, solve
+// arguments, (slot, tile) work items) and replays one instantiated graph: a
+// chain of `iters_per_step` (batched pass, batched solve) kernel nodes whose
+// grids are set to the step's item and slot counts before the replay.  A slot
+// whose level finished mid-step is skipped on device by its done flag.
 
 #include <string.h>
 #include <time.h>
@@ -120,6 +121,16 @@ struct icp_server {
   size_t o_pargs = 0, o_sargs = 0, o_items = 0, o_states = 0, table_bytes = 0;
   int64_t items_cap = 0;
   void* host_table = nullptr;  // pinned mirror
+  // step graph: nodes[2k] = pass of iteration k, nodes[2k+1] = its solve
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<hipGraphNode_t> nodes;
+  std::vector<hipKernelNodeParams> node_params;
+  const PassArgs* d_pargs = nullptr;  // kernel argument values the nodes point at
+  const uint2* d_items = nullptr;
+  const SolveArgs* d_sargs = nullptr;
+  void* pass_args[2] = {nullptr, nullptr};
+  void* solve_args[1] = {nullptr};
   uint64_t fault_tag = 0;
   bool fault_on = false;
   // bookkeeping (mu)
@@ -462,14 +473,12 @@ int server_step(icp_server* s, int32_t* n_busy) {
     hipStream_t st = c->stream;
     HIP_TRY(hipMemcpyAsync(dd, hh, s->o_items + sizeof(uint2) * (size_t)items, hipMemcpyHostToDevice, st),
             "upload");
-    const PassArgs* dp = reinterpret_cast<const PassArgs*>(dd + s->o_pargs);
-    const SolveArgs* ds = reinterpret_cast<const SolveArgs*>(dd + s->o_sargs);
-    const uint2* di = reinterpret_cast<const uint2*>(dd + s->o_items);
-    const int sub = slot[0]->pa.g.sub;  // one grid rule per process: equal for all slots
-    for (int k = 0; k < s->cfg.iters_per_step; ++k) {
-      HIP_TRY(launch_batch_pass(dp, di, (int)items, sub, s->cfg.variant, s->cfg.precision, st), "pass");
-      HIP_TRY(launch_batch_solve(ds, (int)slot.size(), st), "solve");
+    for (size_t k = 0; k < s->nodes.size(); ++k) {
+      hipKernelNodeParams& p = s->node_params[k];
+      p.gridDim = dim3((unsigned)((k & 1) ? slot.size() : (size_t)items));
+      HIP_TRY(hipGraphExecKernelNodeSetParams(s->exec, s->nodes[k], &p), "graph node update");
     }
+    HIP_TRY(hipGraphLaunch(s->exec, st), "hipGraphLaunch");
     IterState* dstates = reinterpret_cast<IterState*>(dd + s->o_states);
     HIP_TRY(launch_gather_states(reinterpret_cast<const SolveArgs*>(dd + s->o_sargs), (int)slot.size(),
                                  dstates, st),
@@ -523,10 +532,42 @@ void worker_loop(icp_server* s) {
   }
 }
 
+// Builds the step graph: a chain of iters_per_step (pass, solve) kernel nodes
+// over the device slot table.
+int build_graph(icp_server* s) {
+  char* dd = s->table.as<char>();
+  s->d_pargs = reinterpret_cast<const PassArgs*>(dd + s->o_pargs);
+  s->d_items = reinterpret_cast<const uint2*>(dd + s->o_items);
+  s->d_sargs = reinterpret_cast<const SolveArgs*>(dd + s->o_sargs);
+  s->pass_args[0] = &s->d_pargs;
+  s->pass_args[1] = &s->d_items;
+  s->solve_args[0] = &s->d_sargs;
+  HIP_TRY(hipGraphCreate(&s->graph, 0), "hipGraphCreate");
+  const int n = 2 * s->cfg.iters_per_step;
+  s->nodes.assign(n, nullptr);
+  s->node_params.assign(n, hipKernelNodeParams{});
+  for (int k = 0; k < n; ++k) {
+    hipKernelNodeParams& p = s->node_params[k];
+    if (k & 1) {
+      batch_solve_node(&p);
+      p.kernelParams = s->solve_args;
+    } else {
+      batch_pass_node(grid_sub(), s->cfg.variant, s->cfg.precision, &p);
+      p.kernelParams = s->pass_args;
+    }
+    const hipGraphNode_t* dep = k ? &s->nodes[k - 1] : nullptr;
+    HIP_TRY(hipGraphAddKernelNode(&s->nodes[k], s->graph, dep, k ? 1 : 0, &p), "hipGraphAddKernelNode");
+  }
+  HIP_TRY(hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+  return ICP_SUCCESS;
+}
+
 void server_free(icp_server* s) {
   if (s->ctx) {
     DeviceGuard dg(s->ctx->device);
     if (s->ctx->stream) (void)hipStreamSynchronize(s->ctx->stream);
+    if (s->exec) (void)hipGraphExecDestroy(s->exec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
     s->pool_mem.release();
     s->table.release();
     if (s->host_table) (void)hipHostFree(s->host_table);
@@ -600,6 +641,7 @@ int icp_server_create(const icp_server_cfg_t* cfg, icp_server_t** out) {
     s->fault_on = true;
     s->fault_tag = strtoull(f, nullptr, 10);
   }
+  if ((rc = build_graph(s)) != 0) return bail(rc);
   if (k.background_thread) s->worker = std::thread(worker_loop, s);
   *out = s;
   return ICP_SUCCESS;

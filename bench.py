@@ -49,15 +49,20 @@ def kernel_source_hash() -> str:
 
 
 def load_traffic(workload: str, variant: str, n_src: int):
-    """HBM bytes per pass launch from the committed rocprofv3 PMC summary, or
-    None if there is none for this workload or the kernel source changed."""
-    path = os.path.join(ROOT, "profiles", f"pass_kernel_{workload}_{variant}_pmc.json")
+    """HBM bytes per pass launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration), or None if
+    there is none for this workload or the kernel source changed since."""
+    path = os.path.join(ROOT, "profiles", f"pass_kernel_{WORKLOADS[workload][1]}_{variant}.md")
     if not os.path.exists(path):
         return None
-    d = json.load(open(path))
-    if d.get("kernel_source_hash") != kernel_source_hash():
+    kv = {}
+    for line in open(path):
+        k, sep, v = line.strip().partition(": ")
+        if sep and k in ("kernel_source_hash", "hbm_bytes_per_launch"):
+            kv[k] = v.strip()
+    if kv.get("kernel_source_hash") != kernel_source_hash() or "hbm_bytes_per_launch" not in kv:
         return None
-    return d.get("hbm_bytes_per_launch")
+    return float(kv["hbm_bytes_per_launch"])
 
 
 def cpu_baseline(data, variant, passes, min_seconds=10.0):

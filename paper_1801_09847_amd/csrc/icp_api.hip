@@ -200,7 +200,8 @@ int grid_sub() {
 // extent grows h (still exact: any h above the bound works, only the candidate
 // count changes).
 GridDesc make_grid(const float* mn, const float* mx, double r, int64_t n_tgt) {
-  const double cap = std::min<double>(1073741824.0, std::max<double>(16777216.0, 32.0 * (double)n_tgt));
+  // below 2^30 entries: the pass addresses the table with 32-bit byte offsets
+  const double cap = std::min<double>(1073741824.0 - 1024.0, std::max<double>(16777216.0, 32.0 * (double)n_tgt));
   const int sub = grid_sub();
   double h = r * (1.0 + 1.0 / 1024.0) * grid_scale() / sub;
   GridDesc g{};

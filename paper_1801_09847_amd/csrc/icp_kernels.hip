@@ -53,6 +53,14 @@ __device__ __forceinline__ float4 ld4(const float4* p, int64_t i) {
   return make_float4(v.x, v.y, v.z, v.w);
 }
 
+// Cell-start table entry: the table holds fewer than 2^30 entries, so the
+// byte offset fits 32 bits and the load takes the scalar-base + 32-bit
+// vector-offset form.
+__device__ __forceinline__ uint32_t ld_cell(const uint32_t* cs, uint32_t idx) {
+  const ICP_G char* b = (const ICP_G char*)(cs);
+  return *(const ICP_G uint32_t*)(b + (uint32_t)(idx << 2));
+}
+
 // ------------------------------------------------------------------ small helpers
 template <class T>
 __device__ inline T wave_sum_xor(T v) {
@@ -137,8 +145,8 @@ __device__ inline void record_terms(F qx, F qy, F qz, F rx, F ry, F rz, F nx, F 
 // wavefront runs max(candidates) iterations instead of a sum over rows of the
 // per-row maximum.
 template <int R>
-__device__ inline void find_nearest(const PassArgs& a, float q32x, float q32y, float q32z,
-                                    uint2* lane_ranges, uint64_t& best, uint32_t& bj) {
+__device__ inline uint32_t stage_rows(const PassArgs& a, float q32x, float q32y, float q32z,
+                                      uint2* lane_ranges, uint64_t best) {
   constexpr int W = 2 * R + 1;
   const GridDesc& g = a.g;
   const double lo = -(double)R - 1.0;
@@ -153,7 +161,7 @@ __device__ inline void find_nearest(const PassArgs& a, float q32x, float q32y, f
   const float fx = (float)(ux - flx), fy = (float)(uy - fly), fz = (float)(uz - flz);
 
   // squared gaps (in cells) from the query to the slab of offset d, lowered by
-  // a safety margin
+  // a safety margin; slabs outside the grid get an infinite gap
   float g2x[W], g2y[W], g2z[W];
 #pragma unroll
   for (int d = -R; d <= R; ++d) {
@@ -164,43 +172,75 @@ __device__ inline void find_nearest(const PassArgs& a, float q32x, float q32y, f
       gx = (float)d - fx; gy = (float)d - fy; gz = (float)d - fz;
     }
     gx = fmaxf(gx - 1e-5f, 0.f); gy = fmaxf(gy - 1e-5f, 0.f); gz = fmaxf(gz - 1e-5f, 0.f);
-    g2x[d + R] = gx * gx; g2y[d + R] = gy * gy; g2z[d + R] = gz * gz;
+    g2x[d + R] = gx * gx;
+    g2y[d + R] = (unsigned)(cy + d) < (unsigned)g.dy ? gy * gy : INFINITY;
+    g2z[d + R] = (unsigned)(cz + d) < (unsigned)g.dz ? gz * gz : INFINITY;
   }
   float B = a.r2f;
   if (best != ~0ull) B = fminf(B, __uint_as_float((uint32_t)(best >> 32)));
   const float thr = B * a.inv_h2 * (1.0f + 1e-4f) + 1e-6f;
+  // a row of (y, z) gap gyz spans x offsets -d..d' where gyz + g2x <= thr;
+  // the thresholds and the clamped x bounds are shared by all rows
+  float tlo[R + 1], thi[R + 1];
+  int xlo_c[R + 1], xhi_c[R + 1];
+#pragma unroll
+  for (int d = 0; d <= R; ++d) {
+    tlo[d] = thr - g2x[R - d];
+    thi[d] = thr - g2x[R + d];
+    xlo_c[d] = max(cx - d, 0);
+    xhi_c[d] = min(cx + d, g.dx - 1);
+  }
+  const uint32_t sdx = (uint32_t)g.dx, sdxdy = (uint32_t)g.dx * (uint32_t)g.dy;
+  // row index of (cy, cz); rows of out-of-grid slabs wrap but are never loaded
+  uint32_t base = ((uint32_t)cz * (uint32_t)g.dy + (uint32_t)cy) * sdx;
+  // keep the rows as base + constant: without this the compiler refactors each
+  // row index into its own (quarter-rate) integer multiply
+  asm volatile("" : "+v"(base));
 
-  int m = 0;
-  uint32_t total = 0;
+  // every surviving row's two table entries are loaded before any is used,
+  // so the rows cost one memory round trip instead of one each
+  constexpr int NR = W * W;
+  uint32_t beg[NR], end_[NR];
+  bool ok[NR];
 #pragma unroll
   for (int dz = -R; dz <= R; ++dz) {
-    const int z = cz + dz;
 #pragma unroll
     for (int dy = -R; dy <= R; ++dy) {
-      const int y = cy + dy;
+      const int k = (dz + R) * W + (dy + R);
       const float gyz = g2z[dz + R] + g2y[dy + R];
-      if ((unsigned)z < (unsigned)g.dz && (unsigned)y < (unsigned)g.dy && gyz <= thr) {
-        int xlo = cx, xhi = cx;
+      int xlo = xlo_c[0], xhi = xhi_c[0];
 #pragma unroll
-        for (int d = 1; d <= R; ++d) {
-          if (gyz + g2x[R - d] <= thr) xlo = cx - d;
-          if (gyz + g2x[R + d] <= thr) xhi = cx + d;
-        }
-        xlo = max(xlo, 0);
-        xhi = min(xhi, g.dx - 1);
-        if (xlo <= xhi) {
-          const uint32_t row = ((uint32_t)z * (uint32_t)g.dy + (uint32_t)y) * (uint32_t)g.dx;
-          const uint32_t beg = glb(a.cs)[row + xlo], end = glb(a.cs)[row + xhi + 1];
-          if (beg < end) {
-            lane_ranges[m * kWave] = make_uint2(beg, end);
-            ++m;
-            total += end - beg;
-          }
-        }
+      for (int d = 1; d <= R; ++d) {
+        if (gyz <= tlo[d]) xlo = xlo_c[d];
+        if (gyz <= thi[d]) xhi = xhi_c[d];
+      }
+      ok[k] = gyz <= thr && xlo <= xhi;
+      if (ok[k]) {
+        const uint32_t row = base + (uint32_t)dz * sdxdy + (uint32_t)dy * sdx;
+        beg[k] = ld_cell(a.cs, row + (uint32_t)xlo);
+        end_[k] = ld_cell(a.cs, row + (uint32_t)xhi + 1u);
       }
     }
   }
-  if (m == 0) return;
+  int m = 0;
+  uint32_t total = 0;
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    if (ok[k] && beg[k] < end_[k]) {
+      lane_ranges[m * kWave] = make_uint2(beg[k], end_[k]);
+      ++m;
+      total += end_[k] - beg[k];
+    }
+  }
+  return total;
+}
+
+// Scans the `total` candidates of the lane's staged ranges in order, keeping
+// the smallest (d^2, original index) key.
+__device__ inline void scan_ranges(const PassArgs& a, float q32x, float q32y, float q32z,
+                                   const uint2* lane_ranges, uint32_t total, uint64_t& best,
+                                   uint32_t& bj) {
+  if (total == 0) return;
   uint2 e = lane_ranges[0];
   uint32_t pos = e.x, end = e.y;
   int slot = 0;
@@ -241,12 +281,19 @@ __device__ inline void wave_sync() {
 }
 
 // One pass over a tile of kRounds * kBlock queries per block: correspondence,
-// per-correspondence J^T J / J^T r terms, and their sum.  Reduction: each
-// round, every lane writes its 28 terms to the wave's LDS region transposed
-// ([term][lane]); lane L (< 56) then adds the 32 entries (L & 1) * 32.. of term
-// L >> 1 into its own running sum (float32 Kahan, or float64).  After the last
-// round the two halves and the block's waves are merged in a fixed order and
-// one float64 partial per term is written, so results do not depend on timing.
+// per-correspondence J^T J / J^T r terms, and their sum.
+//
+// Latency: each round's source point, warm-start index and warm-start target
+// point are loaded one round ahead, so a round waits on memory only for its
+// candidate rows, its candidates and (for an inlier) the matched normal.
+//
+// Reduction (float32 Kahan mode): each lane adds its own queries' 28 terms
+// over the rounds in float32; after the last round the lanes write them to
+// the wave's LDS region transposed ([term][lane]) and lane L (< 56) adds the
+// 32 entries (L & 1) * 32.. of term L >> 1 with Kahan compensation.  Float64
+// mode does the transposed sum every round, in float64.  The two halves and
+// the block's waves are then merged in a fixed order and one float64 partial
+// per term is written, so results do not depend on timing.
 template <int VAR, int PREC, bool WRITE, int R>
 __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
   __shared__ __align__(16) uint32_t scratch[kBlock / kWave][WaveScratch<R>::kWords];
@@ -263,46 +310,76 @@ __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
   float* xf = reinterpret_cast<float*>(ws);
   double* xd = reinterpret_cast<double*>(ws);
 
-  // running sums owned by this lane
-  float acc_s = 0.f, acc_c = 0.f;   // float32 Kahan: term lane>>1, half lane&1
-  double acc_d0 = 0.0, acc_d1 = 0.0; // float64: terms lane>>2 and 14 + (lane>>2), quarter lane&3
+  float lacc[28];                    // float32 mode: this lane's terms summed over its rounds
+#pragma unroll
+  for (int k = 0; k < 28; ++k) lacc[k] = 0.0f;
+  double acc_d0 = 0.0, acc_d1 = 0.0; // float64 mode: terms lane>>2 and 14 + (lane>>2), quarter lane&3
   uint32_t cnt = 0;
 
   const int64_t tile = (int64_t)tile_index * (kRounds * kBlock);
+  // Prefetches are unconditional so that no branch forces an early wait on
+  // them: a lane past the end of the source reads the last point, and an
+  // absent warm-start index reads target entry 0; such values are never used.
+  const int64_t last = (int64_t)a.n_src - 1;
+  float nsx, nsy, nsz;
+  uint32_t njp;
+  {
+    const int64_t i0 = min(tile + (int64_t)threadIdx.x, last);
+    nsx = glb(a.sx)[i0]; nsy = glb(a.sy)[i0]; nsz = glb(a.sz)[i0];
+    njp = a.jprev ? glb(a.jprev)[i0] : 0xffffffffu;
+  }
+  float4 npw = ld4(a.tp, njp != 0xffffffffu ? njp : 0u);
+
   for (int round = 0; round < kRounds; ++round) {
     const int64_t i = tile + round * kBlock + threadIdx.x;
+    const float ssx = nsx, ssy = nsy, ssz = nsz;
+    const uint32_t jp = njp;
+    const float4 pw = npw;
+    // the next round's source point and warm-start index (in the last round
+    // the lane rereads its own point, which is then ignored)
+    {
+      const int64_t in = min(round + 1 < kRounds ? i + kBlock : i, last);
+      nsx = glb(a.sx)[in]; nsy = glb(a.sy)[in]; nsz = glb(a.sz)[in];
+      njp = a.jprev ? glb(a.jprev)[in] : 0xffffffffu;
+    }
+
     bool inl = false;
-    float4 bp = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 bp = make_float4(0.f, 0.f, 0.f, 0.f), bn = make_float4(0.f, 0.f, 0.f, 0.f);
     uint32_t bj = 0xffffffffu;
     double q64x = 0.0, q64y = 0.0, q64z = 0.0;
     float q32x = 0.f, q32y = 0.f, q32z = 0.f;
+    uint64_t best = ~0ull;
+    uint32_t total = 0;
     if (i < a.n_src) {
-      const double sx = glb(a.sx)[i], sy = glb(a.sy)[i], sz = glb(a.sz)[i];
+      const double sx = ssx, sy = ssy, sz = ssz;
       double t;
       t = T[0] * sx; t = t + T[1] * sy; t = t + T[2] * sz; q64x = t + T[3];
       t = T[4] * sx; t = t + T[5] * sy; t = t + T[6] * sz; q64y = t + T[7];
       t = T[8] * sx; t = t + T[9] * sy; t = t + T[10] * sz; q64z = t + T[11];
       q32x = (float)q64x; q32y = (float)q64y; q32z = (float)q64z;
-      uint64_t best = ~0ull;
-      if (a.jprev) {
+      if (jp != 0xffffffffu) {
         // warm start: the previous pass's match bounds this pass's distance
-        const uint32_t jp = glb(a.jprev)[i];
-        if (jp != 0xffffffffu) {
-          const float4 p = ld4(a.tp, jp);
-          const float dx = q32x - p.x, dy = q32y - p.y, dz = q32z - p.z;
-          float d2 = dx * dx + dy * dy;
-          d2 = d2 + dz * dz;
-          if (d2 <= a.r2f) {
-            best = ((uint64_t)__float_as_uint(d2) << 32) | (uint64_t)__float_as_uint(p.w);
-            bj = jp;
-          }
+        const float dx = q32x - pw.x, dy = q32y - pw.y, dz = q32z - pw.z;
+        float d2 = dx * dx + dy * dy;
+        d2 = d2 + dz * dz;
+        if (d2 <= a.r2f) {
+          best = ((uint64_t)__float_as_uint(d2) << 32) | (uint64_t)__float_as_uint(pw.w);
+          bj = jp;
         }
       }
-      find_nearest<R>(a, q32x, q32y, q32z, lane_ranges, best, bj);
+      total = stage_rows<R>(a, q32x, q32y, q32z, lane_ranges, best);
+    }
+    // the next round's warm-start point: its index arrived with this round's
+    // candidate rows, and the load overlaps the candidate scan
+    npw = ld4(a.tp, njp != 0xffffffffu ? njp : 0u);
+    if (i < a.n_src) {
+      scan_ranges(a, q32x, q32y, q32z, lane_ranges, total, best, bj);
       const float bd = __uint_as_float((uint32_t)(best >> 32));
       const uint32_t bo = (uint32_t)best;
       inl = best != ~0ull && bd <= a.r2f;
-      if (inl) bp = ld4(a.tp, bj);
+      const uint32_t bjc = inl ? bj : 0u;
+      bp = ld4(a.tp, bjc);
+      if (VAR == 1) bn = ld4(a.tn, bjc);
       if (a.jprev) glb(a.jprev)[i] = inl ? bj : 0xffffffffu;
       if (WRITE) {
         const uint32_t oi = glb(a.sperm)[i];
@@ -311,42 +388,26 @@ __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
       }
     }
     cnt += (uint32_t)__popcll(__ballot(inl));
-    wave_sync();  // the search's LDS ranges are dead from here on
 
     if (PREC == 0) {
+      // a query without a correspondence adds exact zeros: point-to-plane
+      // terms vanish with a zero residual and normal, point-to-point terms
+      // (which hold constants) are selected away
       float v[28];
-      if (inl) {
-        const double rx = q64x - (double)bp.x, ry = q64y - (double)bp.y, rz = q64z - (double)bp.z;
-        const float fx = (float)rx, fy = (float)ry, fz = (float)rz;
-        float4 n = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (VAR == 1) n = ld4(a.tn, bj);
-        record_terms<VAR, float>(q32x, q32y, q32z, fx, fy, fz, n.x, n.y, n.z, v);
-        const float d2 = fx * fx + fy * fy;
-        v[27] = d2 + fz * fz;
-      } else {
+      const double rx = q64x - (double)bp.x, ry = q64y - (double)bp.y, rz = q64z - (double)bp.z;
+      const float fx = inl ? (float)rx : 0.f, fy = inl ? (float)ry : 0.f, fz = inl ? (float)rz : 0.f;
+      const float nx = inl ? bn.x : 0.f, ny = inl ? bn.y : 0.f, nz = inl ? bn.z : 0.f;
+      record_terms<VAR, float>(q32x, q32y, q32z, fx, fy, fz, nx, ny, nz, v);
+      const float d2 = fx * fx + fy * fy;
+      v[27] = d2 + fz * fz;
+      if (VAR != 1) {
 #pragma unroll
-        for (int k = 0; k < 28; ++k) v[k] = 0.0f;
+        for (int k = 0; k < 27; ++k) v[k] = inl ? v[k] : 0.f;
       }
 #pragma unroll
-      for (int k = 0; k < 28; ++k) xf[k * kWave + lane] = v[k];
-      wave_sync();
-      if (lane < 56) {
-        const float4* src = reinterpret_cast<const float4*>(xf + (lane >> 1) * kWave + (lane & 1) * 32);
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-          const float4 x4 = src[m];
-          const float xs[4] = {x4.x, x4.y, x4.z, x4.w};
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const float y = xs[e] - acc_c;
-            const float t = acc_s + y;
-            acc_c = (t - acc_s) - y;
-            acc_s = t;
-          }
-        }
-      }
-      wave_sync();
+      for (int k = 0; k < 28; ++k) lacc[k] = lacc[k] + v[k];
     } else {
+      wave_sync();  // the search's LDS ranges are dead from here on
 #pragma unroll
       for (int half = 0; half < 2; ++half) {
         double v[28];
@@ -355,8 +416,7 @@ __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
           const double rx = q64x - px, ry = q64y - py, rz = q64z - pz;
           double nx = 0.0, ny = 0.0, nz = 0.0;
           if (VAR == 1) {
-            const float4 n = ld4(a.tn, bj);
-            nx = n.x; ny = n.y; nz = n.z;
+            nx = bn.x; ny = bn.y; nz = bn.z;
           }
           record_terms<VAR, double>(q64x, q64y, q64z, rx, ry, rz, nx, ny, nz, v);
           v[27] = (rx * rx + ry * ry) + rz * rz;
@@ -385,6 +445,26 @@ __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
 
   // merge within the wave, then across the block's waves, in a fixed order
   if (PREC == 0) {
+    wave_sync();  // the last search's LDS ranges are dead from here on
+#pragma unroll
+    for (int k = 0; k < 28; ++k) xf[k * kWave + lane] = lacc[k];
+    wave_sync();
+    float acc_s = 0.f, acc_c = 0.f;  // Kahan: term lane>>1, half lane&1
+    if (lane < 56) {
+      const float4* src = reinterpret_cast<const float4*>(xf + (lane >> 1) * kWave + (lane & 1) * 32);
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const float4 x4 = src[m];
+        const float xs[4] = {x4.x, x4.y, x4.z, x4.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float y = xs[e] - acc_c;
+          const float t = acc_s + y;
+          acc_c = (t - acc_s) - y;
+          acc_s = t;
+        }
+      }
+    }
     const float so = __shfl_xor(acc_s, 1, kWave);
     const float co = __shfl_xor(acc_c, 1, kWave);
     float s2, e;

@@ -249,6 +249,7 @@ Layout make_layout(int n, int64_t n_items, int64_t total_src, int64_t total_tile
   L.bbox_out = take(sizeof(float) * 16 * n);
   L.jprev = take(sizeof(uint32_t) * (size_t)total_src);
   L.part = take(sizeof(double) * kNumSums * (size_t)total_tiles);
+  L.red = take(sizeof(double) * kNumSums * 64);  // segment sums of a single pair's solve
   L.total = align256(off);
   return L;
 }
@@ -540,7 +541,7 @@ int run_loop(icp_ctx* c, const Prep& P, const LoopIn* in, bool normals, int vari
       HIP_TRY(launch_batch_pass(dp, di, (int)P.total_tiles, P.sub, variant, precision, s), "pass");
     if (prof) HIP_TRY(hipEventRecord(c->ev[3 + 2 * k], s), "hipEventRecord");
     if (n == 1)
-      HIP_TRY(launch_solve(hs[0], s), "solve");
+      HIP_TRY(launch_solve(hs[0], reinterpret_cast<double*>(dd + L.red), s), "solve");
     else
       HIP_TRY(launch_batch_solve(ds, n, s), "solve");
   }
@@ -571,7 +572,7 @@ int single_pass(icp_ctx* c, const Prep& P, double r, const double T[16], bool no
   HIP_TRY(launch_pass(a, variant, precision, idx_out != nullptr, s), "pass");
   if (reduce) {
     SolveArgs sa{a.part, a.n_blocks, const_cast<IterState*>(a.st), P.src_off[1], 0, 0.0, 1};
-    HIP_TRY(launch_solve(sa, s), "reduce");
+    HIP_TRY(launch_solve(sa, nullptr, s), "reduce");
     int rc;
     if ((rc = ensure_host(c, P.L.total + sizeof(IterState))) != 0) return rc;
     IterState* res = reinterpret_cast<IterState*>(static_cast<char*>(c->host) + P.L.total);

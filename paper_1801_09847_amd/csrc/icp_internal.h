@@ -7,7 +7,7 @@
 namespace icp {
 
 constexpr int kBlock = 256;        // threads per block of the pass kernel
-constexpr int kTile = 1024;        // queries per block of the pass kernel (4 per thread)
+constexpr int kTile = 512;         // queries per block of the pass kernel (2 per thread)
 constexpr int kNumSums = 29;       // 21 (J^T J upper) + 6 (J^T r) + sum d2 + count
 constexpr int kSumD2 = 27;
 constexpr int kSumCount = 28;
@@ -160,7 +160,10 @@ int64_t voxel_scratch_words(int64_t total);  // words needed for `flags` and `st
 hipError_t launch_state_init(IterState* st, const double T[16], hipStream_t s);
 
 hipError_t launch_pass(const PassArgs& a, int variant, int precision, bool write_corr, hipStream_t s);
-hipError_t launch_solve(const SolveArgs& a, hipStream_t s);
+// Solve of one pair.  `red` (kNumSums * 64 doubles of scratch, or null) lets
+// a pair of many pass blocks reduce its partials with many blocks first; the
+// result is the same bits either way.
+hipError_t launch_solve(const SolveArgs& a, double* red, hipStream_t s);
 
 // Batched forms: `pairs` / `items` / `arr` are device arrays.
 hipError_t launch_batch_pass(const PassArgs* pairs, const uint2* items, int n_items, int sub,

@@ -31,7 +31,7 @@ namespace icp {
 namespace {
 
 constexpr int kWave = 64;
-constexpr int kRounds = 4;  // queries per thread in one pass launch
+constexpr int kRounds = kTile / kBlock;  // queries per thread in one pass launch
 static_assert(kRounds * kBlock == kTile, "tile size");
 
 __device__ inline int lane_id() { return __lane_id(); }
@@ -616,26 +616,69 @@ __device__ void apply_exp(const double* xi, double* T) {
   for (int k = 0; k < 12; ++k) T[k] = N[k];
 }
 
-__device__ void solve_body(const SolveArgs& a) {
+// Two-level partial sum, for pairs of more than kTwoLevel pass blocks: the
+// blocks are cut into kSegs segments of ceil(n / kSegs) consecutive blocks; a
+// segment's sum is taken by 8 lanes (lane j adds blocks j, j + 8, ... of the
+// segment in order, then a fixed xor-shuffle tree), and the solve then adds
+// the kSegs segment sums.  A single pair's segment sums come from a separate
+// many-block kernel (one block's bandwidth would bound the solve); the batched
+// solve computes them in-block with the same function, so a pair gets the
+// same bits in both forms.
+constexpr int kSegs = 64;
+constexpr int kTwoLevel = 512;
+
+__device__ double segment_sum(const ICP_G double* row, int n_blocks, int s, int j) {
+  const int len = (n_blocks + kSegs - 1) / kSegs;
+  const int b1 = min(n_blocks, (s + 1) * len);
+  double acc = 0.0;
+  for (int b = s * len + j; b < b1; b += 8) acc = acc + row[b];
+  acc = acc + __shfl_xor(acc, 1, 8);
+  acc = acc + __shfl_xor(acc, 2, 8);
+  acc = acc + __shfl_xor(acc, 4, 8);
+  return acc;
+}
+
+// One thread's share of term v: entries g, g + 32, ... of a row of n values,
+// 32 loads in flight per step, added into 8 accumulators in a fixed order.
+template <class Ptr>
+__device__ double row_share(Ptr p, int n, int g) {
+  double s8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int b0 = g; b0 < n; b0 += 32 * 32) {
+    double x[32];
+#pragma unroll
+    for (int u = 0; u < 32; ++u) {
+      const int b = b0 + 32 * u;
+      x[u] = b < n ? p[b] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 32; ++u) s8[u & 7] = s8[u & 7] + x[u];
+  }
+  return ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
+}
+
+// Reduces a pair's block partials (or, two-level, its segment sums: from
+// `red` when given, else computed here) and updates its loop state.
+__device__ void solve_body(const SolveArgs& a, const double* red) {
   ICP_G IterState* st = glb(a.st);
   if (st->done) return;
   __shared__ double sums[kNumSums];
-  // term v = t / 32 is summed by 32 threads (half a wave), each over the block
-  // partials g, g + 32, ... in order, then by a fixed shuffle tree
+  __shared__ double sred[kNumSums * kSegs];
+  // term v = t / 32 is summed by 32 threads (half a wave), each over its
+  // share of the row, then by a fixed shuffle tree
   const int t = threadIdx.x, v = t >> 5, g = t & 31;
   double acc = 0.0;
-  if (v < kNumSums) {
-    const ICP_G double* p = glb(a.part) + (int64_t)v * a.n_blocks;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int b = g;
-    for (; b + 96 < a.n_blocks; b += 128) {
-      a0 = a0 + p[b];
-      a1 = a1 + p[b + 32];
-      a2 = a2 + p[b + 64];
-      a3 = a3 + p[b + 96];
+  if (a.n_blocks <= kTwoLevel) {
+    if (v < kNumSums) acc = row_share(glb(a.part) + (int64_t)v * a.n_blocks, a.n_blocks, g);
+  } else if (red) {
+    if (v < kNumSums) acc = row_share(glb(red) + v * kSegs, kSegs, g);
+  } else {
+    for (int idx = t >> 3; idx < kNumSums * kSegs; idx += (int)(blockDim.x >> 3)) {
+      const int vv = idx / kSegs;
+      const double x = segment_sum(glb(a.part) + (int64_t)vv * a.n_blocks, a.n_blocks, idx % kSegs, t & 7);
+      if ((t & 7) == 0) sred[idx] = x;
     }
-    for (; b < a.n_blocks; b += 32) a0 = a0 + p[b];
-    acc = (a0 + a1) + (a2 + a3);
+    __syncthreads();
+    if (v < kNumSums) acc = row_share(static_cast<const double*>(sred) + v * kSegs, kSegs, g);
   }
 #pragma unroll
   for (int off = 16; off > 0; off >>= 1) acc = acc + __shfl_xor(acc, off, kWave);
@@ -686,12 +729,23 @@ __device__ void solve_body(const SolveArgs& a) {
   }
 }
 
-__global__ __launch_bounds__(1024) void solve_kernel(SolveArgs a) { solve_body(a); }
+__global__ __launch_bounds__(1024) void solve_kernel(SolveArgs a, const double* red) { solve_body(a, red); }
+
+// Segment sums of a single pair's block partials (two-level form): block s
+// computes segment s of every term.
+__global__ __launch_bounds__(256) void reduce_partials_kernel(SolveArgs a, double* red) {
+  if (glb(a.st)->done) return;
+  const int t = threadIdx.x, v = t >> 3;
+  if (v < kNumSums) {
+    const double x = segment_sum(glb(a.part) + (int64_t)v * a.n_blocks, a.n_blocks, blockIdx.x, t & 7);
+    if ((t & 7) == 0) glb(red)[v * kSegs + blockIdx.x] = x;
+  }
+}
 
 // Batched form: block p reduces, solves and updates pair p.
 __global__ __launch_bounds__(1024) void batch_solve_kernel(const SolveArgs* __restrict__ arr) {
   const SolveArgs a = arr[blockIdx.x];
-  solve_body(a);
+  solve_body(a, nullptr);
 }
 
 // Copies the loop states of a batch's pairs into one array (one readback).
@@ -737,8 +791,13 @@ hipError_t launch_pass(const PassArgs& a, int variant, int precision, bool write
   return hipGetLastError();
 }
 
-hipError_t launch_solve(const SolveArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(solve_kernel, dim3(1), dim3(1024), 0, s, a);
+hipError_t launch_solve(const SolveArgs& a, double* red, hipStream_t s) {
+  if (red && a.n_blocks > kTwoLevel) {
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(kSegs), dim3(256), 0, s, a, red);
+  } else {
+    red = nullptr;
+  }
+  hipLaunchKernelGGL(solve_kernel, dim3(1), dim3(1024), 0, s, a, (const double*)red);
   return hipGetLastError();
 }
 

@@ -126,7 +126,7 @@ struct Layout {
   size_t clouds, blk_bbox, pairs, blk_t, blk_s, src_off, blk_tab;  // preparation
   size_t pargs, sargs, states, items;                                // loop header
   size_t header_end;                                                 // end of uploaded part
-  size_t bbox_out, jprev, part;                                      // device only
+  size_t bbox_out, jprev, part, red;                                 // device only
   size_t total;
 };
 

@@ -114,3 +114,19 @@ def test_batch_nonfinite_names_pair(icp, pairs_data):
     with pytest.raises(icp.IcpError) as e:
         icp.register_batch(descs)
     assert e.value.code == icp.ICP_E_NONFINITE and "pair 2" in str(e.value)
+
+
+@pytest.mark.parametrize("precision", ["kahan32", "f64"])
+def test_large_pair_two_level_sum_same_bits(icp, precision):
+    """A pair of more than 512 pass blocks (300k source points) sums its block
+    partials in two levels: alone, through a separate many-block segment
+    kernel; in a batch, inside the batched solve.  Both must give the same
+    bits."""
+    big = synth.c2_room(0)
+    small = synth.heightfield_pair(7, 3000, 3000)
+    tb = _tensors(big)
+    ts = _tensors(small)
+    alone = icp.register(*tb, np.eye(4), 0.03, 12, 0.0, "point_to_plane", precision)
+    descs = [icp.make_pair(*ts, np.eye(4), 0.05, 12, 0.0), icp.make_pair(*tb, np.eye(4), 0.03, 12, 0.0)]
+    mix = icp.register_batch(descs, "point_to_plane", precision)
+    _same(mix[1], alone)

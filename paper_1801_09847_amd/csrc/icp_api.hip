@@ -408,7 +408,8 @@ int build_pairs(icp_ctx* c, Prep* P, const PairDst* dst) {
   HIP_TRY(launch_seg_targets(dbp, n, reinterpret_cast<const int64_t*>(dd + L.blk_t), bt[n],
                              reinterpret_cast<const int64_t*>(dd + L.blk_tab), bk[n],
                              P->total_tab, c->cs.as<uint32_t>(), c->t_key.as<uint32_t>(),
-                             c->t_rank.as<uint32_t>(), c->scan_tmp.as<uint32_t>(), scan_cap, s),
+                             c->t_rank.as<uint32_t>(), c->scan_tmp.as<uint32_t>(), scan_cap,
+                             dst != nullptr, s),
           "target grid");
   SortBufs sb;
   for (int k = 0; k < 2; ++k) {

@@ -111,20 +111,61 @@ __global__ __launch_bounds__(256) void seg_bbox_final_kernel(const int64_t* __re
 }
 
 // ------------------------------------------------------------------ exclusive scan (uint32)
+// A tile of kScanTile words is handled by one block: thread t owns the
+// 16-byte chunks t, t + 256, t + 512, t + 768 of the tile, so that every wave
+// load or store covers 1 KiB of consecutive memory.  Chunks are scanned in
+// memory order (chunk index j * 256 + t).  Scanned arrays start 16-byte
+// aligned (the launcher checks).
 constexpr int kScanThreads = 256;
-constexpr int kScanItems = 16;
-constexpr int kScanTile = kScanThreads * kScanItems;
+constexpr int kScanVecs = 4;
+constexpr int kScanTile = kScanThreads * kScanVecs * 4;
+constexpr int kScanWaves = kScanThreads / kWave;
 
-template <int kThreads>
-__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* total) {
-  __shared__ uint32_t wsum[kThreads / kWave];
-  const int lane = lane_id(), w = threadIdx.x / kWave;
-  uint32_t x = v;
+typedef uint32_t scan_u4 __attribute__((ext_vector_type(4)));
+#define ICP_GLB __attribute__((address_space(1)))
+
+__device__ inline scan_u4 scan_load(const uint32_t* d, int64_t i, int64_t n) {
+  if (i + 4 <= n) return *(const ICP_GLB scan_u4*)(d + i);
+  scan_u4 v = {0u, 0u, 0u, 0u};
+  if (i < n) v.x = d[i];
+  if (i + 1 < n) v.y = d[i + 1];
+  if (i + 2 < n) v.z = d[i + 2];
+  return v;
+}
+
+__device__ inline void scan_store(uint32_t* d, int64_t i, int64_t n, scan_u4 v) {
+  if (i + 4 <= n) {
+    *(ICP_GLB scan_u4*)(d + i) = v;
+    return;
+  }
+  if (i < n) d[i] = v.x;
+  if (i + 1 < n) d[i + 1] = v.y;
+  if (i + 2 < n) d[i + 2] = v.z;
+}
+
+__device__ inline uint32_t wave_inclusive_sum(uint32_t x) {
+  const int lane = lane_id();
 #pragma unroll
   for (int off = 1; off < kWave; off <<= 1) {
     const uint32_t y = __shfl_up(x, off, kWave);
     if (lane >= off) x += y;
   }
+  return x;
+}
+
+__device__ inline uint32_t wave_sum(uint32_t x) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
+  return x;
+}
+
+// Exclusive scan of a value per thread over the block (thread order); the
+// block total in *total.  Used where the order is the thread order.
+template <int kThreads>
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* total) {
+  __shared__ uint32_t wsum[kThreads / kWave];
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  const uint32_t x = wave_inclusive_sum(v);
   if (lane == kWave - 1) wsum[w] = x;
   __syncthreads();
   uint32_t before = 0, all = 0;
@@ -140,14 +181,22 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* total) {
 __global__ __launch_bounds__(kScanThreads) void scan_tile_sums_kernel(const uint32_t* __restrict__ d,
                                                                       int64_t n,
                                                                       uint32_t* __restrict__ sums) {
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  __shared__ uint32_t wsum[kScanWaves];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + 4 * threadIdx.x;
+  scan_u4 v[kScanVecs];
+#pragma unroll
+  for (int j = 0; j < kScanVecs; ++j) v[j] = scan_load(d, base + (int64_t)j * 4 * kScanThreads, n);
   uint32_t s = 0;
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k)
-    if (base + k < n) s += d[base + k];
-  uint32_t total;
-  block_exclusive_scan<kScanThreads>(s, &total);
-  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+  for (int j = 0; j < kScanVecs; ++j) s += (v[j].x + v[j].y) + (v[j].z + v[j].w);
+  s = wave_sum(s);
+  if (lane_id() == 0) wsum[threadIdx.x / kWave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int k = 0; k < kScanWaves; ++k) t += wsum[k];
+    sums[blockIdx.x] = t;
+  }
 }
 
 // Single block: exclusive scan of nb tile sums in place (each thread owns a
@@ -168,22 +217,67 @@ __global__ __launch_bounds__(1024) void scan_top_kernel(uint32_t* __restrict__ s
     }
 }
 
-__global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(uint32_t* __restrict__ d, int64_t n,
-                                                                  const uint32_t* __restrict__ sums) {
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-  uint32_t v[kScanItems];
-  uint32_t s = 0;
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    v[k] = (base + k < n) ? d[base + k] : 0u;
-    s += v[k];
+// Pair owning entry k of the concatenated cell tables.
+__device__ inline int table_pair(const BuildPair* __restrict__ pairs, int n, uint64_t k) {
+  int lo = 0, hi = n;  // pairs[lo].tab_off <= k < pairs[hi].tab_off (hi == n: end)
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pairs[mid].tab_off <= k) lo = mid; else hi = mid;
   }
-  uint32_t total;
-  uint32_t run = block_exclusive_scan<kScanThreads>(s, &total) + sums[blockIdx.x];
+  return lo;
+}
+
+// Second pass: the tile's chunks are scanned in memory order on top of the
+// tile's offset and written back in place.  With `pairs`, the data are the
+// concatenated cell-count tables of n pairs, and each entry is written as
+// its pair-local target position (global position minus the pair's target
+// offset).
+template <bool kLocal>
+__global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(uint32_t* __restrict__ d, int64_t n,
+                                                                  const uint32_t* __restrict__ sums,
+                                                                  const BuildPair* __restrict__ pairs,
+                                                                  int n_pairs) {
+  __shared__ uint32_t wsum[kScanVecs][kScanWaves];
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + 4 * threadIdx.x;
+  scan_u4 v[kScanVecs];
+  uint32_t s[kScanVecs], x[kScanVecs];
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    if (base + k < n) d[base + k] = run;
-    run += v[k];
+  for (int j = 0; j < kScanVecs; ++j) v[j] = scan_load(d, base + (int64_t)j * 4 * kScanThreads, n);
+#pragma unroll
+  for (int j = 0; j < kScanVecs; ++j) {
+    s[j] = (v[j].x + v[j].y) + (v[j].z + v[j].w);
+    x[j] = wave_inclusive_sum(s[j]);
+    if (lane == kWave - 1) wsum[j][w] = x[j];
+  }
+  __syncthreads();
+  uint32_t run = sums[blockIdx.x];
+#pragma unroll
+  for (int j = 0; j < kScanVecs; ++j) {
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int k = 0; k < kScanWaves; ++k) {
+      if (k < w) before += wsum[j][k];
+      all += wsum[j][k];
+    }
+    uint32_t e = run + before + x[j] - s[j];
+    run += all;
+    scan_u4 o;
+    o.x = e; e += v[j].x;
+    o.y = e; e += v[j].y;
+    o.z = e; e += v[j].z;
+    o.w = e;
+    const int64_t i = base + (int64_t)j * 4 * kScanThreads;
+    if (kLocal && i < n) {
+      int p = table_pair(pairs, n_pairs, (uint64_t)i);
+      uint32_t* oe = reinterpret_cast<uint32_t*>(&o);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        while (p + 1 < n_pairs && (uint64_t)(i + c) >= pairs[p + 1].tab_off) ++p;
+        oe[c] -= (uint32_t)pairs[p].tgt_off;
+      }
+    }
+    scan_store(d, i, n, o);
   }
 }
 
@@ -217,18 +311,18 @@ __global__ __launch_bounds__(256) void seg_target_key_kernel(const BuildPair* __
   rank[bp.tgt_off + i] = atomicAdd(&counts[gk], 1u);
 }
 
-// After the scan, counts[] holds positions in the concatenation of all pairs'
-// targets; subtracting the pair's offset gives its local position.
+// After the scan, the concatenated tables hold each cell's first position
+// among its own pair's targets.
 __global__ __launch_bounds__(256) void seg_target_scatter_kernel(
     const BuildPair* __restrict__ pairs, int n, const int64_t* __restrict__ blk_off,
     const uint32_t* __restrict__ key, const uint32_t* __restrict__ rank,
-    const uint32_t* __restrict__ cs_global) {
+    const uint32_t* __restrict__ cs_all) {
   const int p = find_segment(blk_off, n, blockIdx.x);
   const BuildPair& bp = pairs[p];
   const int64_t i = (int64_t)(blockIdx.x - blk_off[p]) * 256 + threadIdx.x;
   if (i >= bp.n_tgt) return;
   const int64_t gi = bp.tgt_off + i;
-  const uint32_t pos = cs_global[key[gi]] + rank[gi] - (uint32_t)bp.tgt_off;
+  const uint32_t pos = cs_all[key[gi]] + rank[gi];
   const float* t = bp.tgt + 3 * i;
   bp.tp_dst[pos] = make_float4(t[0], t[1], t[2], __uint_as_float((uint32_t)i));
   if (bp.tgt_n && bp.tn_dst) {
@@ -237,61 +331,113 @@ __global__ __launch_bounds__(256) void seg_target_scatter_kernel(
   }
 }
 
-// Pair-local cell table: cs_dst[k] = counts[tab_off + k] - tgt_off (in place
-// when cs_dst aliases the scratch).
-__global__ __launch_bounds__(256) void seg_table_local_kernel(const BuildPair* __restrict__ pairs, int n,
-                                                              const int64_t* __restrict__ blk_off,
-                                                              const uint32_t* cs_global) {
+// Copy of each pair's table out of the concatenation into its own buffer
+// (only launched when some pair's buffer is not its slice of the
+// concatenation).
+__global__ __launch_bounds__(256) void seg_table_copy_kernel(const BuildPair* __restrict__ pairs, int n,
+                                                             const int64_t* __restrict__ blk_off,
+                                                             const uint32_t* __restrict__ cs_all) {
   const int p = find_segment(blk_off, n, blockIdx.x);
   const BuildPair& bp = pairs[p];
   const int64_t k = (int64_t)(blockIdx.x - blk_off[p]) * 256 + threadIdx.x;
-  if (k > (int64_t)bp.g.ncell) return;
-  bp.cs_dst[k] = cs_global[bp.tab_off + k] - (uint32_t)bp.tgt_off;
+  if (k > (int64_t)bp.g.ncell || bp.cs_dst == cs_all + bp.tab_off) return;
+  bp.cs_dst[k] = cs_all[bp.tab_off + k];
 }
 
 // ------------------------------------------------------------------ stable LSD radix sort
 // Keys are one or two 32-bit words (lo, hi); the sort orders by hi, then lo,
-// then by input position (stability).  Values ride along.
+// then by input position (stability).  Values ride along.  One pass per 8-bit
+// digit: per-tile digit counts, a scan of each digit's column of counts, and
+// a scatter that orders its tile in LDS before writing it out.
 constexpr int kSortThreads = 256;
 constexpr int kSortRounds = 8;
 constexpr int kSortTile = kSortThreads * kSortRounds;
+constexpr int kSortWaves = kSortThreads / kWave;
+constexpr int kWaveSpan = kWave * kSortRounds;  // consecutive items per wave
+constexpr int kDigits = 256;
 
 __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const uint32_t* __restrict__ keys,
                                                                   int64_t n, int shift,
                                                                   uint32_t* __restrict__ hist,
                                                                   int nblk) {
-  __shared__ uint32_t h[256];
+  __shared__ uint32_t h[kDigits];
   h[threadIdx.x] = 0;
   __syncthreads();
   const int64_t tile = (int64_t)blockIdx.x * kSortTile;
+  uint32_t d[kSortRounds];
+#pragma unroll
   for (int k = 0; k < kSortRounds; ++k) {
     const int64_t i = tile + k * kSortThreads + threadIdx.x;
-    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    d[k] = i < n ? (keys[i] >> shift) & 255u : kDigits;
   }
+#pragma unroll
+  for (int k = 0; k < kSortRounds; ++k)
+    if (d[k] < kDigits) atomicAdd(&h[d[k]], 1u);
   __syncthreads();
   hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
-// Stable scatter of one 8-bit digit of `dig` (one of the key words).  Inside a
-// tile, items are ranked in input order: per round, lanes with equal digits
-// are found by ballots on the digit bits, and earlier waves' counts are added.
+// Block d: exclusive scan in place of digit d's per-tile counts
+// hist[d * nblk + b] over b; dtot[d] = the digit's count over all tiles.
+__global__ __launch_bounds__(256) void radix_colscan_kernel(uint32_t* __restrict__ hist, int nblk,
+                                                            uint32_t* __restrict__ dtot) {
+  uint32_t* col = hist + (int64_t)blockIdx.x * nblk;
+  uint32_t carry = 0;
+  for (int c0 = 0; c0 < nblk; c0 += 4 * 256) {
+    const int i = c0 + 4 * (int)threadIdx.x;
+    uint32_t v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = (i + k < nblk) ? col[i + k] : 0u;
+    uint32_t total;
+    uint32_t e = carry + block_exclusive_scan<256>((v[0] + v[1]) + (v[2] + v[3]), &total);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (i + k < nblk) col[i + k] = e;
+      e += v[k];
+    }
+    carry += total;
+  }
+  if (threadIdx.x == 0) dtot[blockIdx.x] = carry;
+}
+
+// Stable scatter by one 8-bit digit of the lo (on_hi false) or hi key word.
+// Wave w takes items [w * kWaveSpan, (w + 1) * kWaveSpan) of the tile; ranks
+// inside a wave come from ballots on the digit bits and the wave's running
+// per-digit counts, so the tile is ordered by (digit, input position) in LDS
+// and written out in that order, each digit's run at its global offset.
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
-    const uint32_t* __restrict__ dig, const uint32_t* __restrict__ klo,
-    const uint32_t* __restrict__ khi, const uint32_t* __restrict__ vals, int64_t n, int shift,
-    const uint32_t* __restrict__ offs, int nblk, uint32_t* __restrict__ klo_out,
-    uint32_t* __restrict__ khi_out, uint32_t* __restrict__ vals_out) {
-  __shared__ uint32_t base[256];
-  __shared__ uint32_t wcnt[kSortThreads / kWave][256];
+    const uint32_t* __restrict__ klo, const uint32_t* __restrict__ khi,
+    const uint32_t* __restrict__ vals, int64_t n, bool on_hi, int shift,
+    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ dtot, int nblk,
+    uint32_t* __restrict__ klo_out, uint32_t* __restrict__ khi_out, uint32_t* __restrict__ vals_out) {
+  __shared__ uint32_t cnt[kSortWaves][kDigits];
+  __shared__ uint32_t gstart[kDigits];
+  __shared__ uint32_t s_lo[kSortTile], s_hi[kSortTile], s_val[kSortTile];
   const int t = threadIdx.x, w = t / kWave, lane = lane_id();
-  base[t] = offs[(int64_t)t * nblk + blockIdx.x];
-  for (int k = 0; k < kSortThreads / kWave; ++k) wcnt[k][t] = 0;
-  __syncthreads();
   const int64_t tile = (int64_t)blockIdx.x * kSortTile;
-  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int64_t wbase = tile + (int64_t)w * kWaveSpan;
+  uint32_t lo[kSortRounds], hi[kSortRounds], va[kSortRounds];
+#pragma unroll
   for (int r = 0; r < kSortRounds; ++r) {
-    const int64_t i = tile + r * kSortThreads + t;
+    const int64_t i = wbase + r * kWave + lane;
     const bool valid = i < n;
-    const uint32_t d = valid ? ((dig[i] >> shift) & 255u) : 0u;
+    lo[r] = valid ? klo[i] : 0u;
+    hi[r] = (valid && khi) ? khi[i] : 0u;
+    va[r] = valid ? vals[i] : 0u;
+  }
+  const uint32_t my_tot = dtot[t];
+  const uint32_t my_before = hist[(int64_t)t * nblk + blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kSortWaves; ++k) cnt[k][t] = 0;
+  __syncthreads();
+
+  // ranks inside the wave (the wave's own counters only: no block barrier)
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint32_t rk[kSortRounds];
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    const bool valid = wbase + r * kWave + lane < n;
+    const uint32_t d = ((on_hi ? hi[r] : lo[r]) >> shift) & 255u;
     uint64_t peers = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -299,24 +445,50 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
       const uint64_t bb = __ballot(bit);
       peers &= bit ? bb : ~bb;
     }
-    const uint32_t rank_w = __popcll(peers & lt_mask);
-    if (valid && rank_w == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
-    __syncthreads();
-    if (valid) {
-      uint32_t dst = base[d] + rank_w;
-      for (int k = 0; k < w; ++k) dst += wcnt[k][d];
-      klo_out[dst] = klo[i];
-      if (khi) khi_out[dst] = khi[i];
-      vals_out[dst] = vals[i];
+    const uint32_t below = (uint32_t)__popcll(peers & lt_mask);
+    const uint32_t before = cnt[w][d];
+    rk[r] = before + below;
+    if (valid && below == 0) cnt[w][d] = before + (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+
+  // thread t = digit t: tile-local start of the digit and of each wave's part
+  const uint32_t c0 = cnt[0][t], c1 = cnt[1][t], c2 = cnt[2][t], c3 = cnt[3][t];
+  uint32_t tile_total, all;
+  const uint32_t loc = block_exclusive_scan<kSortThreads>((c0 + c1) + (c2 + c3), &tile_total);
+  const uint32_t dbase = block_exclusive_scan<kSortThreads>(my_tot, &all);
+  static_assert(kSortWaves == 4, "wave parts below assume 4 waves");
+  cnt[0][t] = loc;
+  cnt[1][t] = loc + c0;
+  cnt[2][t] = loc + c0 + c1;
+  cnt[3][t] = loc + c0 + c1 + c2;
+  gstart[t] = dbase + my_before - loc;
+  __syncthreads();
+
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    if (wbase + r * kWave + lane < n) {
+      const uint32_t d = ((on_hi ? hi[r] : lo[r]) >> shift) & 255u;
+      const uint32_t lp = cnt[w][d] + rk[r];
+      s_lo[lp] = lo[r];
+      s_hi[lp] = hi[r];
+      s_val[lp] = va[r];
     }
-    __syncthreads();
-    uint32_t add = 0;
-    for (int k = 0; k < kSortThreads / kWave; ++k) {
-      add += wcnt[k][t];
-      wcnt[k][t] = 0;
+  }
+  __syncthreads();
+
+  const int64_t valid_n = min((int64_t)kSortTile, n - tile);
+#pragma unroll
+  for (int k = 0; k < kSortRounds; ++k) {
+    const int lp = k * kSortThreads + t;
+    if (lp < valid_n) {
+      const uint32_t xl = s_lo[lp], xh = s_hi[lp];
+      const uint32_t d = ((on_hi ? xh : xl) >> shift) & 255u;
+      const uint32_t dst = gstart[d] + (uint32_t)lp;
+      klo_out[dst] = xl;
+      if (khi_out) khi_out[dst] = xh;
+      vals_out[dst] = s_val[lp];
     }
-    base[t] += add;
-    __syncthreads();
   }
 }
 
@@ -486,16 +658,28 @@ __global__ void voxel_count_kernel(const VoxCloud* __restrict__ clouds, int n,
 // ====================================================================== launchers
 int64_t scan_block_sums_needed(int64_t n) { return ceil_div(std::max<int64_t>(n, 1), kScanTile); }
 
-hipError_t launch_scan_exclusive(uint32_t* data, int64_t n, uint32_t* block_sums, int64_t cap_blocks,
-                                 hipStream_t s) {
+// Exclusive scan in place; with `pairs`, of the n_pairs concatenated cell
+// tables, written as pair-local positions.
+static hipError_t scan_exclusive(uint32_t* data, int64_t n, uint32_t* block_sums, int64_t cap_blocks,
+                                 const BuildPair* pairs, int n_pairs, hipStream_t s) {
   const int64_t nb = ceil_div(n, kScanTile);
-  if (nb > cap_blocks) return hipErrorInvalidValue;
+  if (nb > cap_blocks || (reinterpret_cast<uintptr_t>(data) & 15u) != 0) return hipErrorInvalidValue;
+  if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(scan_tile_sums_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n,
                      block_sums);
   hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(1024), 0, s, block_sums, nb);
-  hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n,
-                     block_sums);
+  if (pairs)
+    hipLaunchKernelGGL(scan_apply_kernel<true>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n,
+                       block_sums, pairs, n_pairs);
+  else
+    hipLaunchKernelGGL(scan_apply_kernel<false>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n,
+                       block_sums, nullptr, 0);
   return hipGetLastError();
+}
+
+hipError_t launch_scan_exclusive(uint32_t* data, int64_t n, uint32_t* block_sums, int64_t cap_blocks,
+                                 hipStream_t s) {
+  return scan_exclusive(data, n, block_sums, cap_blocks, nullptr, 0, s);
 }
 
 int64_t bbox_blocks(int64_t n) { return std::min<int64_t>(1024, std::max<int64_t>(1, ceil_div(n, 256))); }
@@ -513,45 +697,45 @@ hipError_t launch_seg_targets(const BuildPair* pairs, int n, const int64_t* blk_
                               int64_t total_blocks, const int64_t* tab_blk_off,
                               int64_t tab_blocks, uint64_t total_tab, uint32_t* counts,
                               uint32_t* key, uint32_t* rank, uint32_t* scan_tmp, int64_t scan_cap,
-                              hipStream_t s) {
+                              bool copy_tables, hipStream_t s) {
   hipError_t e = hipMemsetAsync(counts, 0, sizeof(uint32_t) * (size_t)total_tab, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(seg_target_key_kernel, dim3((unsigned)total_blocks), dim3(256), 0, s, pairs, n,
                      blk_off, counts, key, rank);
-  e = launch_scan_exclusive(counts, (int64_t)total_tab, scan_tmp, scan_cap, s);
+  e = scan_exclusive(counts, (int64_t)total_tab, scan_tmp, scan_cap, pairs, n, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(seg_target_scatter_kernel, dim3((unsigned)total_blocks), dim3(256), 0, s, pairs,
                      n, blk_off, key, rank, counts);
-  hipLaunchKernelGGL(seg_table_local_kernel, dim3((unsigned)tab_blocks), dim3(256), 0, s, pairs, n,
-                     tab_blk_off, counts);
+  if (copy_tables)
+    hipLaunchKernelGGL(seg_table_copy_kernel, dim3((unsigned)tab_blocks), dim3(256), 0, s, pairs, n,
+                       tab_blk_off, counts);
   return hipGetLastError();
 }
 
 int64_t voxel_scratch_words(int64_t total) { return total + 1; }
 
 int64_t radix_hist_needed(int64_t n) {
-  const int64_t h = 256 * ceil_div(std::max<int64_t>(n, 1), kSortTile);
-  return h + scan_block_sums_needed(h);
+  return (int64_t)kDigits * ceil_div(std::max<int64_t>(n, 1), kSortTile) + kDigits;
 }
 
-// Stable LSD sort of (lo, hi, val) triples by (hi, lo); returns the buffer
-// index (0 or 1) holding the result.
-static hipError_t radix_sort_2w(SortBufs sb, bool two, int64_t total, int lo_bits, int hi_from,
-                                int hi_bits, uint32_t* hist, int64_t hist_cap, hipStream_t s,
-                                int* out_cur) {
+// Stable LSD sort of (lo, hi, val) triples: 8-bit digits of lo from bit 0 up
+// to lo_bits, then of hi from bit hi_from up to hi_bits (hi only if `two`).
+// *out_cur receives the buffer index (0 or 1) holding the result.
+static hipError_t radix_sort(SortBufs sb, bool two, int64_t total, int lo_bits, int hi_from,
+                             int hi_bits, uint32_t* hist, int64_t hist_cap, hipStream_t s,
+                             int* out_cur) {
   const int nblk = (int)ceil_div(std::max<int64_t>(total, 1), kSortTile);
-  if ((int64_t)256 * nblk > hist_cap) return hipErrorInvalidValue;
-  uint32_t* scan_tmp = hist + (int64_t)256 * nblk;
-  const int64_t scan_cap = hist_cap - (int64_t)256 * nblk;
+  if ((int64_t)kDigits * nblk + kDigits > hist_cap) return hipErrorInvalidValue;
+  if (total >= (int64_t)UINT32_MAX) return hipErrorInvalidValue;
+  uint32_t* dtot = hist + (int64_t)kDigits * nblk;
   int cur = 0;
   auto pass = [&](bool on_hi, int shift) -> hipError_t {
     const uint32_t* dig = on_hi ? sb.khi[cur] : sb.klo[cur];
     hipLaunchKernelGGL(radix_hist_kernel, dim3(nblk), dim3(kSortThreads), 0, s, dig, total, shift,
                        hist, nblk);
-    hipError_t e = launch_scan_exclusive(hist, (int64_t)256 * nblk, scan_tmp, scan_cap, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(radix_scatter_kernel, dim3(nblk), dim3(kSortThreads), 0, s, dig, sb.klo[cur],
-                       two ? sb.khi[cur] : nullptr, sb.val[cur], total, shift, hist, nblk,
+    hipLaunchKernelGGL(radix_colscan_kernel, dim3(kDigits), dim3(256), 0, s, hist, nblk, dtot);
+    hipLaunchKernelGGL(radix_scatter_kernel, dim3(nblk), dim3(kSortThreads), 0, s, sb.klo[cur],
+                       two ? sb.khi[cur] : nullptr, sb.val[cur], total, on_hi, shift, hist, dtot, nblk,
                        sb.klo[cur ^ 1], two ? sb.khi[cur ^ 1] : nullptr, sb.val[cur ^ 1]);
     cur ^= 1;
     return hipGetLastError();
@@ -576,8 +760,8 @@ hipError_t launch_seg_voxel(const VoxCloud* clouds, int n, bool wide_keys, const
   int cloud_bits = 0;
   while ((1 << cloud_bits) < n) ++cloud_bits;
   int cur = 0;
-  hipError_t e = radix_sort_2w(sb, two, total, 32, wide_keys ? 0 : 16, 16 + cloud_bits, hist, hist_cap,
-                               s, &cur);
+  hipError_t e = radix_sort(sb, two, total, 32, wide_keys ? 0 : 16, 16 + cloud_bits, hist, hist_cap,
+                            s, &cur);
   if (e != hipSuccess) return e;
   const uint32_t* klo = sb.klo[cur];
   const uint32_t* khi = two ? sb.khi[cur] : nullptr;
@@ -609,29 +793,10 @@ hipError_t launch_seg_sources(const BuildPair* pairs, int n, const int64_t* blk_
                      blk_off, sb.klo[0], two ? sb.khi[0] : nullptr, sb.val[0]);
   int hi_bits = 0;
   while ((1 << hi_bits) < n) ++hi_bits;
-  const int nblk = (int)ceil_div(std::max<int64_t>(total, 1), kSortTile);
-  if ((int64_t)256 * nblk > hist_cap) return hipErrorInvalidValue;
-  uint32_t* scan_tmp = hist + (int64_t)256 * nblk;
-  const int64_t scan_cap = hist_cap - (int64_t)256 * nblk;
+  // Morton codes have 30 bits; pair indices hi_bits
   int cur = 0;
-  auto pass = [&](bool on_hi, int shift) -> hipError_t {
-    const uint32_t* dig = on_hi ? sb.khi[cur] : sb.klo[cur];
-    hipLaunchKernelGGL(radix_hist_kernel, dim3(nblk), dim3(kSortThreads), 0, s, dig, total, shift,
-                       hist, nblk);
-    hipError_t e = launch_scan_exclusive(hist, (int64_t)256 * nblk, scan_tmp, scan_cap, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(radix_scatter_kernel, dim3(nblk), dim3(kSortThreads), 0, s, dig, sb.klo[cur],
-                       two ? sb.khi[cur] : nullptr, sb.val[cur], total, shift, hist, nblk,
-                       sb.klo[cur ^ 1], two ? sb.khi[cur ^ 1] : nullptr, sb.val[cur ^ 1]);
-    cur ^= 1;
-    return hipGetLastError();
-  };
-  hipError_t e;
-  for (int shift = 0; shift < 30; shift += 8)
-    if ((e = pass(false, shift)) != hipSuccess) return e;
-  for (int shift = 0; shift < hi_bits; shift += 8)
-    if ((e = pass(true, shift)) != hipSuccess) return e;
-
+  const hipError_t e = radix_sort(sb, two, total, 30, 0, hi_bits, hist, hist_cap, s, &cur);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(source_gather_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, pairs,
                      n, src_off, total, sb.val[cur]);
   return hipGetLastError();

@@ -114,13 +114,15 @@ hipError_t launch_scan_exclusive(uint32_t* data, int64_t n, uint32_t* block_sums
 // out: 8 floats per cloud (min xyz, max xyz, non-finite flag)
 hipError_t launch_seg_bbox(const SegCloud* clouds, int n_clouds, const int64_t* blk_off,
                            int64_t total_blocks, float* block_out, float* out, hipStream_t s);
-// counts: scratch of total_tab entries; tab_blk_off: per-pair block offsets
-// over the tables (256 entries per block) for the localising copy.
+// counts: the concatenated tables (total_tab entries, 16-byte aligned); on
+// return they hold pair-local cell starts.  copy_tables: also copy each
+// pair's table to its cs_dst where that is not its slice of `counts`
+// (tab_blk_off: per-pair block offsets over the tables, 256 entries a block).
 hipError_t launch_seg_targets(const BuildPair* pairs, int n, const int64_t* blk_off,
                               int64_t total_blocks, const int64_t* tab_blk_off,
                               int64_t tab_blocks, uint64_t total_tab, uint32_t* counts,
                               uint32_t* key, uint32_t* rank, uint32_t* scan_tmp, int64_t scan_cap,
-                              hipStream_t s);
+                              bool copy_tables, hipStream_t s);
 hipError_t launch_seg_sources(const BuildPair* pairs, int n, const int64_t* blk_off,
                               int64_t total_blocks, const int64_t* src_off, int64_t total,
                               SortBufs sb, uint32_t* hist, int64_t hist_cap, hipStream_t s);

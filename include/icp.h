@@ -201,6 +201,30 @@ int icp_voxel_downsample(icp_ctx_t *ctx, const float *pts, const float *normals,
                          double voxel, float *out_pts, float *out_normals, int64_t cap,
                          int64_t *n_out);
 
+/* ---- normal estimation ----------------------------------------------------
+ * Normals of a point cloud with the hybrid neighbourhood that the paper's
+ * workflow passes to estimate_normals (Sec. 3.2 Fig. 1 and Sec. 3.3: a search
+ * radius and a maximum neighbour count), by the least-variance direction of
+ * [16].  Point i's neighbourhood is the max_nn smallest (d2, original index)
+ * among the points j, i included, with d2 <= (float)(radius^2), where d2 is
+ * the float32 expression (dx*dx + dy*dy) + dz*dz of d = p_i - p_j (no FMA).
+ * The normal is the unit eigenvector of the smallest eigenvalue of the
+ * neighbourhood's float64 covariance (about its mean, divided by the count),
+ * rounded to float32 and turned so that n . (viewpoint - p_i) >= 0.  Fewer than
+ * three neighbours give (0, 0, 0); when the smallest eigenvalue is repeated
+ * (collinear or isotropic neighbourhoods) any unit vector of its eigenspace
+ * may be returned.
+ *   pts          device (n, 3) float32, 4-byte aligned
+ *   radius       finite, > 0, with a finite float32 square (metres)
+ *   max_nn       1 .. 64
+ *   viewpoint    host, 3 finite doubles
+ *   normals_out  device (n, 3) float32, in the order of pts (caller-owned)
+ *   counts_out   device (n) int32 neighbourhood sizes, or NULL
+ * Synchronous on the context's stream.  Errors: INVALID_ARG, NONFINITE (a
+ * coordinate), TOO_LARGE, OOM, DEVICE; nothing is written on argument errors. */
+int icp_estimate_normals(icp_ctx_t *ctx, const float *pts, int64_t n, double radius, int32_t max_nn,
+                         const double viewpoint[3], float *normals_out, int32_t *counts_out);
+
 /* Coarse-to-fine registration (as in the fragment registration stage of the
  * reconstruction pipeline, Sec. 3.4): for each level l, both clouds are
  * downsampled with voxel[l] (0: the original clouds), then registered with

@@ -58,6 +58,13 @@ def lib():
         L.oracle_residual_jacobian.argtypes = [C.c_int, _f64p, _f64p, _f64p, _f64p, _f64p]
         L.oracle_residual_jacobian.restype = C.c_int
         L.oracle_solve6.argtypes = [_f64p, _f64p, _f64p]
+        L.oracle_estimate_normals.argtypes = [_f32p, C.c_int64, C.c_double, C.c_int, _f64p, C.c_int,
+                                              C.c_void_p, C.c_int64, _f32p,
+                                              np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS"),
+                                              C.c_void_p]
+        L.oracle_estimate_normals.restype = C.c_int
+        L.oracle_sym_eig3.argtypes = [_f64p, _f64p, _f64p]
+        L.oracle_sym_eig3.restype = None
         L.oracle_solve6.restype = C.c_int
         L.oracle_correspondences.argtypes = [_f32p, C.c_int64, _f64p, _f32p, C.c_int64, C.c_double,
                                              C.c_int, C.c_int, _i64p, _f32p, _f64p]
@@ -175,6 +182,38 @@ def voxel_downsample(pts, voxel, normals=None):
     if m < 0:
         raise ValueError("oracle_voxel_downsample: invalid arguments")
     return out[:m].copy(), (outn[:m].copy() if outn is not None else None)
+
+
+def estimate_normals(pts, radius, max_nn, viewpoint=(0.0, 0.0, 0.0), search=0, queries=None,
+                     with_evals=False):
+    """(normals float32 (q, 3), neighbourhood sizes int32 (q,)[, eigenvalues
+    float64 (q, 3) ascending]) with the hybrid neighbourhood: the max_nn
+    nearest points within radius by (pinned FP32 squared distance, index);
+    fewer than 3 neighbours give a zero normal; normals face the viewpoint.
+    queries: original indices to evaluate (default: all points)."""
+    pts = _pts(pts)
+    q = None if queries is None else np.ascontiguousarray(queries, np.int64)
+    nq = len(pts) if q is None else len(q)
+    out = np.empty((nq, 3), np.float32)
+    cnt = np.empty(nq, np.int32)
+    ev = np.empty((nq, 3), np.float64) if with_evals else None
+    rc = lib().oracle_estimate_normals(pts, len(pts), float(radius), int(max_nn),
+                                       np.ascontiguousarray(viewpoint, np.float64), int(search),
+                                       q.ctypes.data if q is not None else None, nq, out, cnt,
+                                       ev.ctypes.data if ev is not None else None)
+    if rc != 0:
+        raise ValueError("oracle_estimate_normals: invalid arguments")
+    return (out, cnt, ev) if with_evals else (out, cnt)
+
+
+def sym_eig3(A):
+    """Eigenvalues (ascending) and eigenvectors (columns) of a symmetric 3x3."""
+    A = np.asarray(A, np.float64)
+    a6 = np.array([A[0, 0], A[0, 1], A[0, 2], A[1, 1], A[1, 2], A[2, 2]], np.float64)
+    w = np.zeros(3)
+    V = np.zeros(9)
+    lib().oracle_sym_eig3(a6, w, V)
+    return w, V.reshape(3, 3)
 
 
 def register_multiscale(src, tgt, tgt_normals, T_init, voxels, iters, dists, rel_tol=0.0,

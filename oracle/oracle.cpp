@@ -33,6 +33,16 @@
 //     between consecutive passes <= rel_tol.
 //   - degeneracy: no inliers, or a Cholesky pivot <= 1e-12 * max(diag A).
 //
+// Normal estimation (Sec. 3.2, Fig. 1, and the Sec. 3.3 workflow: a hybrid
+// neighbourhood of at most max_nn points within a radius; the method of [16],
+// the normal being the direction of least variance of the neighbourhood).
+// Readings: the neighbourhood of point i is the max_nn lexicographically
+// smallest (pinned FP32 squared distance, original index) among the points j
+// (i included) with that distance <= (float)(radius^2); fewer than three
+// neighbours give the zero vector; mean and covariance (divided by the count)
+// in FP64; the normal is the unit eigenvector of the smallest eigenvalue,
+// turned so that n . (viewpoint - p_i) >= 0.
+//
 // Build: g++ -std=c++17 -O2 -ffp-contract=off -fopenmp -shared -fPIC.
 // Every function here is plain scalar code so it can be checked by eye.
 
@@ -424,6 +434,88 @@ bool bad_args(const float* src, int64_t n_src, const float* tgt, int64_t n_tgt, 
   return !src || !tgt || n_src < 1 || n_tgt < 1 || !(r > 0.0) || !std::isfinite(r);
 }
 
+// ---------------------------------------------------------------- normals
+// Cyclic Jacobi eigenvalue iteration on a symmetric 3x3 matrix (Golub & Van
+// Loan, Sec. 8.5): rotations zero each off-diagonal entry in turn until the
+// off-diagonal mass is negligible.  On return A is (numerically) diagonal
+// with the eigenvalues and the columns of V are the eigenvectors.
+void jacobi3(double A[3][3], double V[3][3]) {
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) V[r][c] = r == c ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 64; ++sweep) {
+    const double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+    const double diag = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
+    if (off <= 1e-36 * diag || off == 0.0) break;
+    for (int p = 0; p < 2; ++p)
+      for (int q = p + 1; q < 3; ++q) {
+        if (A[p][q] == 0.0) continue;
+        // rotation angle from tan(2 phi) = 2 a_pq / (a_qq - a_pp)
+        const double theta = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+        const double t = (theta >= 0.0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0);
+        const double sn = t * c;
+        // A <- J^T A J, V <- V J with J the rotation in the (p, q) plane
+        for (int k = 0; k < 3; ++k) {
+          const double akp = A[k][p], akq = A[k][q];
+          A[k][p] = c * akp - sn * akq;
+          A[k][q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < 3; ++k) {
+          const double apk = A[p][k], aqk = A[q][k];
+          A[p][k] = c * apk - sn * aqk;
+          A[q][k] = sn * apk + c * aqk;
+        }
+        for (int k = 0; k < 3; ++k) {
+          const double vkp = V[k][p], vkq = V[k][q];
+          V[k][p] = c * vkp - sn * vkq;
+          V[k][q] = sn * vkp + c * vkq;
+        }
+      }
+  }
+}
+
+// Normal of point i from its neighbourhood (original indices nb[0..m));
+// evals (or null) receives the covariance eigenvalues, ascending.
+void normal_of(const float* pts, const int64_t* nb, int m, const float pi[3], const double view[3],
+               float out[3], double* evals) {
+  if (m < 3) {
+    out[0] = out[1] = out[2] = 0.0f;
+    if (evals) evals[0] = evals[1] = evals[2] = 0.0;
+    return;
+  }
+  double mu[3] = {0.0, 0.0, 0.0};
+  for (int k = 0; k < m; ++k)
+    for (int a = 0; a < 3; ++a) mu[a] += (double)pts[3 * nb[k] + a];
+  for (int a = 0; a < 3; ++a) mu[a] /= (double)m;
+  double C[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+  for (int k = 0; k < m; ++k) {
+    double d[3];
+    for (int a = 0; a < 3; ++a) d[a] = (double)pts[3 * nb[k] + a] - mu[a];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) C[r][c] += d[r] * d[c];
+  }
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) C[r][c] /= (double)m;
+  double V[3][3];
+  jacobi3(C, V);
+  int lo = 0;
+  for (int a = 1; a < 3; ++a)
+    if (C[a][a] < C[lo][lo]) lo = a;
+  if (evals) {
+    double e[3] = {C[0][0], C[1][1], C[2][2]};
+    std::sort(e, e + 3);
+    for (int a = 0; a < 3; ++a) evals[a] = e[a];
+  }
+  double n[3] = {V[0][lo], V[1][lo], V[2][lo]};
+  const double len = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+  for (int a = 0; a < 3; ++a) n[a] /= len;
+  double dot = 0.0;
+  for (int a = 0; a < 3; ++a) dot += n[a] * (view[a] - (double)pi[a]);
+  if (dot < 0.0)
+    for (int a = 0; a < 3; ++a) n[a] = -n[a];
+  for (int a = 0; a < 3; ++a) out[a] = (float)n[a];
+}
+
 }  // namespace
 
 extern "C" {
@@ -611,6 +703,62 @@ int64_t oracle_voxel_downsample(const float* pts, const float* nrm, int64_t n, d
     s = e;
   }
   return v;
+}
+
+// Normals of the points of a cloud with the hybrid neighbourhood (radius,
+// max_nn): of all n points, or of the nq points listed in queries (original
+// indices) when queries is not null; output k belongs to query k.  counts
+// receives each neighbourhood size, evals (or null) the covariance
+// eigenvalues (3 per query, ascending).  search: 0 automatic, 1 brute force,
+// 2 k-d tree.  Returns 0, or -1 on invalid arguments.
+int oracle_estimate_normals(const float* pts, int64_t n, double radius, int max_nn,
+                            const double view[3], int search, const int64_t* queries, int64_t nq,
+                            float* normals, int32_t* counts, double* evals) {
+  if (!pts || n < 1 || !(radius > 0.0) || max_nn < 1 || !view || !normals || !counts) return -1;
+  if (!queries) nq = n;
+  if (nq < 0) return -1;
+  const bool use_tree = search == 2 || (search == 0 && n * nq > 20000000);
+  KdTree tree;
+  if (use_tree) tree.build(pts, n);
+  const float r2f = (float)(radius * radius);
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int64_t q = 0; q < nq; ++q) {
+    const int64_t i = queries ? queries[q] : q;
+    const float* pi = pts + 3 * i;
+    std::vector<std::pair<float, int64_t>> cand;
+    auto visit = [&](int64_t j) {
+      const float d = pinned_d2(pi, pts + 3 * j);
+      if (d <= r2f) cand.push_back({d, j});
+    };
+    if (use_tree) {
+      const double c[3] = {(double)pi[0], (double)pi[1], (double)pi[2]};
+      tree.range(c, radius * radius * (1.0 + 1e-5), visit);
+    } else {
+      for (int64_t j = 0; j < n; ++j) visit(j);
+    }
+    std::sort(cand.begin(), cand.end());  // by (distance, original index)
+    const int m = (int)std::min<size_t>(cand.size(), (size_t)max_nn);
+    std::vector<int64_t> nb((size_t)m);
+    for (int k = 0; k < m; ++k) nb[(size_t)k] = cand[(size_t)k].second;
+    counts[q] = m;
+    normal_of(pts, nb.data(), m, pi, view, normals + 3 * q, evals ? evals + 3 * q : nullptr);
+  }
+  return 0;
+}
+
+// Eigen-decomposition used by the normals (exposed for its pins): A6 is the
+// upper triangle (a00, a01, a02, a11, a12, a22); evals ascending, evecs
+// their eigenvectors as columns of a row-major 3x3.
+void oracle_sym_eig3(const double A6[6], double evals[3], double evecs[9]) {
+  double A[3][3] = {{A6[0], A6[1], A6[2]}, {A6[1], A6[3], A6[4]}, {A6[2], A6[4], A6[5]}};
+  double V[3][3];
+  jacobi3(A, V);
+  int ord[3] = {0, 1, 2};
+  std::sort(ord, ord + 3, [&](int a, int b) { return A[a][a] < A[b][b]; });
+  for (int k = 0; k < 3; ++k) {
+    evals[k] = A[ord[k]][ord[k]];
+    for (int r = 0; r < 3; ++r) evecs[3 * r + k] = V[r][ord[k]];
+  }
 }
 
 }  // extern "C"

@@ -827,6 +827,50 @@ int icp_voxel_downsample(icp_ctx_t* ctx, const float* pts, const float* normals,
   return ICP_SUCCESS;
 }
 
+int icp_estimate_normals(icp_ctx_t* ctx, const float* pts, int64_t n, double radius, int32_t max_nn,
+                         const double viewpoint[3], float* normals_out, int32_t* counts_out) {
+  int rc;
+  if ((rc = check_cloud(pts, n, "pts")) != 0) return rc;
+  if (!(radius > 0.0) || !std::isfinite(radius) || !std::isfinite((float)(radius * radius)))
+    return fail(ICP_E_INVALID_ARG, "radius must be > 0 with a finite float32 square");
+  if (max_nn < 1 || max_nn > kMaxNormalNN)
+    return fail(ICP_E_INVALID_ARG, "max_nn must be in [1, " + std::to_string(kMaxNormalNN) + "]");
+  if (!viewpoint || !std::isfinite(viewpoint[0]) || !std::isfinite(viewpoint[1]) ||
+      !std::isfinite(viewpoint[2]))
+    return fail(ICP_E_INVALID_ARG, "viewpoint is NULL or not finite");
+  if (!normals_out) return fail(ICP_E_INVALID_ARG, "normals_out is NULL");
+  if ((reinterpret_cast<uintptr_t>(normals_out) & 3u) || (reinterpret_cast<uintptr_t>(counts_out) & 3u))
+    return fail(ICP_E_INVALID_ARG, "output pointer is not 4-byte aligned");
+  icp_ctx* c = nullptr;
+  if ((rc = resolve_ctx(ctx, &c)) != 0) return rc;
+  DeviceGuard dg(c->device);
+  // the cloud is prepared as both the queries (Morton order) and the grid
+  const PairIn in{pts, n, pts, nullptr, n, radius};
+  Prep P;
+  if ((rc = prepare_pairs(c, 1, &in, &P)) != 0) return rc;
+  NormalArgs a;
+  memset(&a, 0, sizeof a);
+  a.sx = c->sx.as<float>();
+  a.sy = c->sy.as<float>();
+  a.sz = c->sz.as<float>();
+  a.sperm = c->perm.as<uint32_t>();
+  a.n = (int32_t)n;
+  a.tp = c->tp.as<float4>();
+  a.cs = c->cs.as<uint32_t>();
+  a.g = P.g[0];
+  a.r2f = (float)(radius * radius);
+  a.inv_h2 = (float)(P.g[0].inv_h * P.g[0].inv_h);
+  a.max_nn = max_nn;
+  a.vx = viewpoint[0];
+  a.vy = viewpoint[1];
+  a.vz = viewpoint[2];
+  a.normals = normals_out;
+  a.counts = counts_out;
+  HIP_TRY(launch_normals(a, P.g[0].sub, c->stream), "normals");
+  HIP_TRY(hipStreamSynchronize(c->stream), "sync");
+  return ICP_SUCCESS;
+}
+
 int icp_register_multiscale(icp_ctx_t* ctx, const float* src_xyz, int64_t n_src, const float* tgt_xyz,
                             const float* tgt_normals, int64_t n_tgt, const double T_init[16],
                             int32_t n_levels, const double* voxel, const int32_t* max_iter,

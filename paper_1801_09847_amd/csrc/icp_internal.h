@@ -60,6 +60,28 @@ struct PassArgs {
   float* d2_out;
 };
 
+// Normal estimation over one cloud that has been prepared as both source
+// (Morton-ordered queries) and target (cell-ordered grid, one float4 per
+// point).
+constexpr int kNormBlock = 64;    // threads per block of the normals kernel (one wave)
+constexpr int kMaxNormalNN = 64;  // largest max_nn (per-lane heap in LDS)
+struct NormalArgs {
+  const float* sx;        // Morton-ordered points
+  const float* sy;
+  const float* sz;
+  const uint32_t* sperm;  // Morton position -> original index
+  int32_t n;
+  const float4* tp;       // cell-ordered points (x, y, z, original index bits)
+  const uint32_t* cs;     // cell start table
+  GridDesc g;
+  float r2f;              // (float)(radius^2)
+  float inv_h2;
+  int32_t max_nn;
+  double vx, vy, vz;      // viewpoint
+  float* normals;         // (n, 3), original order
+  int32_t* counts;        // (n), original order, or null
+};
+
 struct SolveArgs {
   const double* part;
   int32_t n_blocks;
@@ -160,6 +182,8 @@ int64_t voxel_scratch_words(int64_t total);  // words needed for `flags` and `st
 
 // ---- loop (icp_kernels.hip) ---------------------------------------------
 hipError_t launch_state_init(IterState* st, const double T[16], hipStream_t s);
+// Normals of a prepared cloud (sub: the grid's neighbourhood radius in cells).
+hipError_t launch_normals(const NormalArgs& a, int sub, hipStream_t s);
 
 hipError_t launch_pass(const PassArgs& a, int variant, int precision, bool write_corr, hipStream_t s);
 // Solve of one pair.  `red` (kNumSums * 64 doubles of scratch, or null) lets

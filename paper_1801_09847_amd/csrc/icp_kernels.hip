@@ -757,6 +757,210 @@ __global__ void gather_states_kernel(const SolveArgs* __restrict__ arr, int n, I
   for (int k = threadIdx.x; k < (int)(sizeof(IterState) / sizeof(double)); k += blockDim.x) dst[k] = src[k];
 }
 
+// ------------------------------------------------------------------ normal estimation
+// Normal estimation with the hybrid neighbourhood of Sec. 3.2 / Sec. 3.3
+// (radius and max_nn) and the least-variance direction of [16]: the
+// neighbourhood of a point is the max_nn smallest (pinned float32 squared
+// distance, original index) keys among the points within the radius, the
+// point itself included; the normal is the eigenvector of the smallest
+// eigenvalue of their float64 covariance, turned towards the viewpoint; fewer
+// than three neighbours give the zero vector.
+//
+// A query's candidates are staged as row ranges exactly as in the pass.  Up to
+// three scans follow: count the points within the radius; only when that
+// exceeds max_nn, a max-heap of max_nn keys in LDS (this lane's column of the
+// block's heap array) finds the max_nn-th smallest key; then the covariance
+// sums over the keys not above it.
+
+template <class F>
+__device__ inline void for_each_candidate(const float4* tp, const uint2* lane_ranges, uint32_t total,
+                                          F&& f) {
+  if (total == 0) return;
+  uint2 e = lane_ranges[0];
+  uint32_t pos = e.x, end = e.y;
+  int slot = 0;
+  for (uint32_t k = 0; k < total; ++k) {
+    if (pos == end) {
+      ++slot;
+      e = lane_ranges[slot * kWave];
+      pos = e.x;
+      end = e.y;
+    }
+    f(ld4(tp, pos));
+    ++pos;
+  }
+}
+
+// One Jacobi rotation of the symmetric 3x3 (a, upper entries used) in the
+// (p, q) plane that zeroes a_pq, accumulated into the eigenvector matrix v
+// (classic symmetric update: a_pp -= t a_pq, a_qq += t a_pq, a_rp / a_rq
+// rotated for the third index r).
+template <int P, int Q>
+__device__ inline void jacobi_rotate(double (&a)[3][3], double (&v)[3][3]) {
+  constexpr int Rr = 3 - P - Q;
+  const double apq = a[P][Q];
+  if (apq == 0.0) return;
+  const double theta = (a[Q][Q] - a[P][P]) / (2.0 * apq);
+  const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+  const double c = 1.0 / sqrt(t * t + 1.0);
+  const double sn = t * c;
+  a[P][P] = a[P][P] - t * apq;
+  a[Q][Q] = a[Q][Q] + t * apq;
+  a[P][Q] = 0.0;
+  a[Q][P] = 0.0;
+  const double arp = a[Rr][P], arq = a[Rr][Q];
+  a[Rr][P] = c * arp - sn * arq;
+  a[Rr][Q] = sn * arp + c * arq;
+  a[P][Rr] = a[Rr][P];
+  a[Q][Rr] = a[Rr][Q];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double vkp = v[k][P], vkq = v[k][Q];
+    v[k][P] = c * vkp - sn * vkq;
+    v[k][Q] = sn * vkp + c * vkq;
+  }
+}
+
+// Unit eigenvector of the smallest eigenvalue of a symmetric 3x3 (cyclic
+// Jacobi sweeps until the off-diagonal mass is negligible).
+__device__ inline void least_eigvec3(double (&a)[3][3], double out[3]) {
+  double v[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
+  for (int sweep = 0; sweep < 32; ++sweep) {
+    const double off = (a[0][1] * a[0][1] + a[0][2] * a[0][2]) + a[1][2] * a[1][2];
+    const double dg = (a[0][0] * a[0][0] + a[1][1] * a[1][1]) + a[2][2] * a[2][2];
+    if (off == 0.0 || off <= 1e-36 * dg) break;
+    jacobi_rotate<0, 1>(a, v);
+    jacobi_rotate<0, 2>(a, v);
+    jacobi_rotate<1, 2>(a, v);
+  }
+  int lo = 0;
+  if (a[1][1] < a[lo][lo]) lo = 1;
+  if (a[2][2] < a[lo][lo]) lo = 2;
+  const double x = lo == 0 ? v[0][0] : (lo == 1 ? v[0][1] : v[0][2]);
+  const double y = lo == 0 ? v[1][0] : (lo == 1 ? v[1][1] : v[1][2]);
+  const double z = lo == 0 ? v[2][0] : (lo == 1 ? v[2][1] : v[2][2]);
+  const double len = sqrt((x * x + y * y) + z * z);
+  out[0] = x / len;
+  out[1] = y / len;
+  out[2] = z / len;
+}
+
+template <int R>
+__global__ __launch_bounds__(kNormBlock) void normals_kernel(NormalArgs na) {
+  extern __shared__ uint64_t nheap[];  // [max_nn][kNormBlock]: each lane's heap is a column
+  __shared__ __align__(16) uint32_t nscratch[kNormBlock / kWave][WaveScratch<R>::kRangeWords];
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  uint2* lane_ranges = reinterpret_cast<uint2*>(nscratch[w]) + lane;
+  const int64_t i = (int64_t)blockIdx.x * kNormBlock + threadIdx.x;
+  if (i >= na.n) return;  // no block-wide synchronisation below
+  const float qx = glb(na.sx)[i], qy = glb(na.sy)[i], qz = glb(na.sz)[i];
+  PassArgs pa{};
+  pa.g = na.g;
+  pa.r2f = na.r2f;
+  pa.inv_h2 = na.inv_h2;
+  pa.cs = na.cs;
+  const uint32_t total = stage_rows<R>(pa, qx, qy, qz, lane_ranges, ~0ull);
+  const float r2f = na.r2f;
+  auto dist2 = [&](const float4& p) {
+    const float dx = qx - p.x, dy = qy - p.y, dz = qz - p.z;
+    float d2 = dx * dx + dy * dy;
+    d2 = d2 + dz * dz;
+    return d2;
+  };
+
+  uint32_t within = 0;
+  for_each_candidate(na.tp, lane_ranges, total, [&](const float4& p) {
+    within += dist2(p) <= r2f ? 1u : 0u;
+  });
+  const uint32_t K = (uint32_t)na.max_nn;
+  uint64_t kth = ~0ull;
+  if (within > K) {
+    uint64_t* H = nheap + threadIdx.x;  // H[k * kNormBlock]
+    uint32_t size = 0;
+    for_each_candidate(na.tp, lane_ranges, total, [&](const float4& p) {
+      const float d2 = dist2(p);
+      if (!(d2 <= r2f)) return;
+      const uint64_t key = ((uint64_t)__float_as_uint(d2) << 32) | (uint64_t)__float_as_uint(p.w);
+      if (size < K) {
+        uint32_t at = size++;
+        while (at > 0) {  // sift up
+          const uint32_t up = (at - 1) >> 1;
+          const uint64_t hu = H[up * kNormBlock];
+          if (hu >= key) break;
+          H[at * kNormBlock] = hu;
+          at = up;
+        }
+        H[at * kNormBlock] = key;
+      } else if (key < H[0]) {
+        uint32_t at = 0;
+        for (;;) {  // sift down from the root
+          const uint32_t l = 2 * at + 1;
+          if (l >= K) break;
+          uint32_t c = l;
+          uint64_t hc = H[l * kNormBlock];
+          if (l + 1 < K) {
+            const uint64_t hr = H[(l + 1) * kNormBlock];
+            if (hr > hc) {
+              c = l + 1;
+              hc = hr;
+            }
+          }
+          if (hc <= key) break;
+          H[at * kNormBlock] = hc;
+          at = c;
+        }
+        H[at * kNormBlock] = key;
+      }
+    });
+    kth = H[0];
+  }
+
+  // float64 sums of the selected points, relative to the query point
+  double s1x = 0.0, s1y = 0.0, s1z = 0.0;
+  double sxx = 0.0, sxy = 0.0, sxz = 0.0, syy = 0.0, syz = 0.0, szz = 0.0;
+  uint32_t m = 0;
+  for_each_candidate(na.tp, lane_ranges, total, [&](const float4& p) {
+    const float d2 = dist2(p);
+    if (!(d2 <= r2f)) return;
+    const uint64_t key = ((uint64_t)__float_as_uint(d2) << 32) | (uint64_t)__float_as_uint(p.w);
+    if (key > kth) return;
+    const double dx = (double)p.x - (double)qx, dy = (double)p.y - (double)qy,
+                 dz = (double)p.z - (double)qz;
+    s1x += dx; s1y += dy; s1z += dz;
+    sxx += dx * dx; sxy += dx * dy; sxz += dx * dz;
+    syy += dy * dy; syz += dy * dz; szz += dz * dz;
+    ++m;
+  });
+  double nrm[3] = {0.0, 0.0, 0.0};
+  if (m >= 3) {
+    const double inv = 1.0 / (double)m;
+    const double mx = s1x * inv, my = s1y * inv, mz = s1z * inv;
+    double a[3][3];
+    a[0][0] = sxx * inv - mx * mx;
+    a[0][1] = sxy * inv - mx * my;
+    a[0][2] = sxz * inv - mx * mz;
+    a[1][1] = syy * inv - my * my;
+    a[1][2] = syz * inv - my * mz;
+    a[2][2] = szz * inv - mz * mz;
+    a[1][0] = a[0][1];
+    a[2][0] = a[0][2];
+    a[2][1] = a[1][2];
+    least_eigvec3(a, nrm);
+    const double dot = (nrm[0] * (na.vx - (double)qx) + nrm[1] * (na.vy - (double)qy)) +
+                       nrm[2] * (na.vz - (double)qz);
+    if (dot < 0.0) {
+      nrm[0] = -nrm[0];
+      nrm[1] = -nrm[1];
+      nrm[2] = -nrm[2];
+    }
+  }
+  const int64_t oi = glb(na.sperm)[i];
+  glb(na.normals)[3 * oi + 0] = (float)nrm[0];
+  glb(na.normals)[3 * oi + 1] = (float)nrm[1];
+  glb(na.normals)[3 * oi + 2] = (float)nrm[2];
+  if (na.counts) glb(na.counts)[oi] = (int32_t)m;
+}
+
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 }  // namespace
@@ -818,6 +1022,18 @@ hipError_t launch_batch_pass(const PassArgs* pairs, const uint2* items, int n_it
     launch_batch_pass_r<2>(pairs, items, n_items, variant, precision, s);
   else
     launch_batch_pass_r<1>(pairs, items, n_items, variant, precision, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_normals(const NormalArgs& a, int sub, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  if (a.max_nn < 1 || a.max_nn > kMaxNormalNN) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)ceil_div(a.n, kNormBlock)), block(kNormBlock);
+  const size_t heap = sizeof(uint64_t) * (size_t)a.max_nn * kNormBlock;
+  if (sub == 2)
+    hipLaunchKernelGGL(normals_kernel<2>, grid, block, heap, s, a);
+  else
+    hipLaunchKernelGGL(normals_kernel<1>, grid, block, heap, s, a);
   return hipGetLastError();
 }
 

@@ -111,6 +111,7 @@ def lib():
         L.icp_voxel_downsample.argtypes = [vp, vp, vp, i64, dbl, vp, vp, i64, C.POINTER(C.c_int64)]
         L.icp_register_multiscale.argtypes = [vp, vp, i64, vp, vp, i64, vp, i32, vp, vp, vp, dbl, i32,
                                               i32, C.POINTER(icp_result_t)]
+        L.icp_estimate_normals.argtypes = [vp, vp, i64, dbl, i32, vp, vp, vp]
         L.icp_server_create.argtypes = [C.POINTER(icp_server_cfg_t), C.POINTER(vp)]
         L.icp_server_submit.argtypes = [vp, C.POINTER(icp_request_t), C.POINTER(C.c_uint64)]
         L.icp_server_step.argtypes = [vp, C.POINTER(C.c_int32)]
@@ -122,6 +123,7 @@ def lib():
         for name in ("icp_ctx_create", "icp_ctx_destroy", "icp_register", "icp_correspondences",
                      "icp_normal_equations", "icp_ctx_set_profiling", "icp_ctx_get_profile",
                      "icp_register_batch", "icp_voxel_downsample", "icp_register_multiscale",
+                     "icp_estimate_normals",
                      "icp_server_create", "icp_server_submit", "icp_server_step", "icp_server_poll",
                      "icp_server_wait", "icp_server_destroy"):
             getattr(L, name).restype = C.c_int
@@ -304,6 +306,26 @@ def voxel_downsample(pts, voxel, normals=None, ctx: Context | None = None):
     m = icp_voxel_downsample(ctx.handle if ctx else None, pp, npn, n, voxel, out.data_ptr(),
                              outn.data_ptr() if outn is not None else None, n)
     return out[:m], (outn[:m] if outn is not None else None)
+
+
+def icp_estimate_normals(ctx, pts_ptr, n, radius, max_nn, viewpoint, normals_ptr, counts_ptr) -> None:
+    v = np.ascontiguousarray(np.asarray(viewpoint, dtype=np.float64).reshape(3))
+    _check(lib().icp_estimate_normals(ctx, pts_ptr, int(n), float(radius), int(max_nn),
+                                      v.ctypes.data, normals_ptr, counts_ptr))
+
+
+def estimate_normals(pts, radius, max_nn=30, viewpoint=(0.0, 0.0, 0.0), ctx: Context | None = None,
+                     with_counts=False):
+    """Normals (device (N, 3) float32) of a device cloud with the hybrid
+    (radius, max_nn) neighbourhood, facing `viewpoint`; with_counts also
+    returns the neighbourhood sizes (device int32)."""
+    import torch
+    pp, n = _dev_pts(pts, "pts")
+    out = torch.empty((n, 3), dtype=torch.float32, device=pts.device)
+    cnt = torch.empty((n,), dtype=torch.int32, device=pts.device) if with_counts else None
+    icp_estimate_normals(ctx.handle if ctx else None, pp, n, radius, max_nn, viewpoint, out.data_ptr(),
+                         cnt.data_ptr() if cnt is not None else None)
+    return (out, cnt) if with_counts else out
 
 
 def register_multiscale(src, tgt, tgt_normals, T_init, voxels, iters, dists, rel_tol=0.0,

@@ -10,7 +10,8 @@ inputs already resident in device memory.  The default workload is the
 Printed: one JSON line with corr-evals/s (sum over executed passes of n_src,
 per second of wall time), the dominant kernel's roofline figures (algorithmic
 bytes per launch over its event-timed average duration) and the CPU oracle
-timed on a bounded sample of the same workload.
+timed on a bounded sample of the same workload; then (default workload) the
+normal-estimation, 256-pair batched and served sections.
 
   python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1] [--variant ...]
 """
@@ -87,6 +88,52 @@ def cpu_baseline(data, variant, passes, min_seconds=10.0):
             "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"same pair, first {passes} passes (max_iter={passes - 1}) run {runs}x, FP64 oracle "
                       f"with k-d tree, {dt:.1f} s wall incl. tree builds"}
+
+
+def normals_section(args, icp, synth, np, torch, data):
+    """Normal estimation (hybrid radius / max_nn neighbourhood) on the room
+    target: the paper's workflow setting (5 cm voxel downsample, radius 10 cm,
+    max_nn 30) and the full-density cloud (radius 5 cm, max_nn 30, where the
+    max_nn limit binds).  Each call includes its grid build; the oracle runs
+    on a bounded sample of the same queries."""
+    dev = torch.device("cuda:0")
+    ctx = icp.Context(0)
+    full = torch.from_numpy(data["tgt"]).to(dev)
+    down, _ = icp.voxel_downsample(full, 0.05, ctx=ctx)
+    down = down.contiguous()
+    view = (6.0, 4.0, 1.5)
+    out = []
+    for name, pts, radius in (("room target, 5 cm voxel downsample", down, 0.10),
+                              ("room target, full density", full, 0.05)):
+        n = pts.shape[0]
+        for _ in range(2):
+            icp.estimate_normals(pts, radius, 30, view, ctx=ctx)
+        torch.cuda.synchronize()
+        reps = 10
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            nrm, cnt = icp.estimate_normals(pts, radius, 30, view, ctx=ctx, with_counts=True)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        entry = {"workload": f"{name}: {n} points, radius {radius} m, max_nn 30",
+                 "points": n, "ms_per_call": dt * 1e3, "normals_per_s": n / dt,
+                 "mean_neighbours": float(cnt.double().mean().item()),
+                 "max_nn_binds_frac": float((cnt == 30).double().mean().item())}
+        if not args.no_cpu_baseline:
+            import oracle
+            oracle.build(force=False)
+            P = pts.cpu().numpy()
+            q = np.random.default_rng(0).choice(n, min(n, 200000), replace=False)
+            t1 = time.perf_counter()
+            oracle.estimate_normals(P, radius, 30, view, queries=q)
+            ct = time.perf_counter() - t1
+            entry["cpu_baseline"] = {"value": len(q) / ct, "unit": "normals/s", "cores": oracle.num_threads(),
+                                     "kind": "oracle", "sample": f"{len(q)} random queries of the same cloud, "
+                                     f"k-d tree build included, {ct:.1f} s wall"}
+        out.append(entry)
+        print(f"bench: normals {name}: {n / dt:.3e} normals/s ({dt * 1e3:.2f} ms per call)",
+              file=sys.stderr, flush=True)
+    return out
 
 
 def batched_section(args, icp, synth, np, torch, oracle_sample=8):
@@ -295,6 +342,7 @@ def main():
     ap.add_argument("--batch-pairs", type=int, default=256)
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--no-served", action="store_true", help="skip the served (request server) section")
+    ap.add_argument("--no-normals", action="store_true", help="skip the normal-estimation section")
     ap.add_argument("--served-requests", type=int, default=400)
     ap.add_argument("--served-pool", type=int, default=64)
     ap.add_argument("--served-rates", type=float, nargs="+", default=[1.0, 8.0])
@@ -406,6 +454,8 @@ def main():
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(data, args.variant, args.cpu_passes)
     del s, t, n
+    if not args.no_normals and args.workload == "c3":
+        out["normals"] = normals_section(args, icp, synth, np, torch, data)
     if not args.no_batched:
         out["batched"] = batched_section(args, icp, synth, np, torch)
     if not args.no_served:

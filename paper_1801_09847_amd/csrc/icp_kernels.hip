@@ -767,11 +767,18 @@ __global__ void gather_states_kernel(const SolveArgs* __restrict__ arr, int n, I
 // than three neighbours give the zero vector.
 //
 // A query's candidates are staged as row ranges exactly as in the pass.  Up to
-// three scans follow: count the points within the radius; only when that
-// exceeds max_nn, a max-heap of max_nn keys in LDS (this lane's column of the
-// block's heap array) finds the max_nn-th smallest key; then the covariance
-// sums over the keys not above it.
+// three scans follow, each with eight candidate loads in flight per lane:
+// count the points within the radius; only when that exceeds max_nn, a
+// max-heap of max_nn keys in LDS (this lane's column of the block's heap
+// array) finds the max_nn-th smallest key; then the covariance sums over the
+// keys not above it.  (A single scan that pushes every point within the
+// radius through a heap of (key, position) entries and gathers the
+// neighbourhood from it measured slower: the heap traffic, not the candidate
+// loads, is the cost, and the common sparse case then pays it too.)
 
+// Visits the `total` candidates of the lane's staged ranges in order, loading
+// kChunk of them before using any.
+constexpr int kChunk = 8;
 template <class F>
 __device__ inline void for_each_candidate(const float4* tp, const uint2* lane_ranges, uint32_t total,
                                           F&& f) {
@@ -779,15 +786,31 @@ __device__ inline void for_each_candidate(const float4* tp, const uint2* lane_ra
   uint2 e = lane_ranges[0];
   uint32_t pos = e.x, end = e.y;
   int slot = 0;
-  for (uint32_t k = 0; k < total; ++k) {
-    if (pos == end) {
-      ++slot;
-      e = lane_ranges[slot * kWave];
-      pos = e.x;
-      end = e.y;
+  for (uint32_t k0 = 0; k0 < total; k0 += kChunk) {
+    // positions first, then unconditional loads (a slot past the end rereads
+    // the chunk's first candidate and is not used): a load under a branch
+    // would be waited for before the branch joins
+    uint32_t at[kChunk];
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) {
+      at[u] = at[0];
+      if (k0 + u < total) {
+        if (pos == end) {
+          ++slot;
+          e = lane_ranges[slot * kWave];
+          pos = e.x;
+          end = e.y;
+        }
+        at[u] = pos;
+        ++pos;
+      }
     }
-    f(ld4(tp, pos));
-    ++pos;
+    float4 p[kChunk];
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) p[u] = ld4(tp, at[u]);
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u)
+      if (k0 + u < total) f(p[u], at[u]);
   }
 }
 
@@ -869,7 +892,7 @@ __global__ __launch_bounds__(kNormBlock) void normals_kernel(NormalArgs na) {
   };
 
   uint32_t within = 0;
-  for_each_candidate(na.tp, lane_ranges, total, [&](const float4& p) {
+  for_each_candidate(na.tp, lane_ranges, total, [&](const float4& p, uint32_t) {
     within += dist2(p) <= r2f ? 1u : 0u;
   });
   const uint32_t K = (uint32_t)na.max_nn;
@@ -877,7 +900,7 @@ __global__ __launch_bounds__(kNormBlock) void normals_kernel(NormalArgs na) {
   if (within > K) {
     uint64_t* H = nheap + threadIdx.x;  // H[k * kNormBlock]
     uint32_t size = 0;
-    for_each_candidate(na.tp, lane_ranges, total, [&](const float4& p) {
+    for_each_candidate(na.tp, lane_ranges, total, [&](const float4& p, uint32_t) {
       const float d2 = dist2(p);
       if (!(d2 <= r2f)) return;
       const uint64_t key = ((uint64_t)__float_as_uint(d2) << 32) | (uint64_t)__float_as_uint(p.w);
@@ -919,7 +942,7 @@ __global__ __launch_bounds__(kNormBlock) void normals_kernel(NormalArgs na) {
   double s1x = 0.0, s1y = 0.0, s1z = 0.0;
   double sxx = 0.0, sxy = 0.0, sxz = 0.0, syy = 0.0, syz = 0.0, szz = 0.0;
   uint32_t m = 0;
-  for_each_candidate(na.tp, lane_ranges, total, [&](const float4& p) {
+  for_each_candidate(na.tp, lane_ranges, total, [&](const float4& p, uint32_t) {
     const float d2 = dist2(p);
     if (!(d2 <= r2f)) return;
     const uint64_t key = ((uint64_t)__float_as_uint(d2) << 32) | (uint64_t)__float_as_uint(p.w);

@@ -75,6 +75,11 @@ extern "C" {
 /* precision */
 #define ICP_PREC_F32_KAHAN_F64 0
 #define ICP_PREC_F64 1
+/* robust loss of icp_register_robust / icp_normal_equations_robust */
+#define ICP_LOSS_NONE 0
+#define ICP_LOSS_HUBER 1
+#define ICP_LOSS_TUKEY 2
+#define ICP_LOSS_CAUCHY 3
 
 typedef struct {
   double T[16];        /* row-major final pose (source -> target) */
@@ -150,6 +155,35 @@ int icp_normal_equations(icp_ctx_t *ctx, const float *src_xyz, int64_t n_src, co
                          const float *tgt_xyz, const float *tgt_normals, int64_t n_tgt,
                          double max_corr_dist, int32_t variant, int32_t precision,
                          double AtA21[21], double Atb6[6], double *sum_d2, int64_t *n_in);
+
+/* ---- robust variants -----------------------------------------------------
+ * The paper's ICP module offers "other ICP variants" beside point-to-point and
+ * point-to-plane (Sec. 3.3) without naming them; these are robust
+ * (iteratively reweighted least squares) versions of both.  Each inlier's
+ * terms of J^T J and J^T r are multiplied by w = rho'(s) / s at its residual
+ * magnitude s at the current pose (|n . (q - p)| point-to-plane, |q - p|
+ * point-to-point), so each Gauss-Newton step minimises the weighted squares
+ * whose gradient is that of sum rho(s):
+ *   ICP_LOSS_HUBER   w = 1 for s <= k, k / s beyond
+ *   ICP_LOSS_TUKEY   w = (1 - (s/k)^2)^2 for s <= k, 0 beyond
+ *   ICP_LOSS_CAUCHY  w = 1 / (1 + (s/k)^2)
+ * The weight is computed in the precision of the terms (float32 in
+ * ICP_PREC_F32_KAHAN_F64, float64 in ICP_PREC_F64).  Correspondences, inlier
+ * gating by max_corr_dist, fitness, inlier_rmse (unweighted) and the stopping
+ * rules are those of icp_register; ICP_LOSS_NONE gives icp_register exactly.
+ *   loss    ICP_LOSS_*
+ *   loss_k  scale k (metres): finite, > 0, also as float32 (ignored for NONE)
+ * Other arguments, outputs and errors as icp_register / icp_normal_equations. */
+int icp_register_robust(icp_ctx_t *ctx, const float *src_xyz, int64_t n_src, const float *tgt_xyz,
+                        const float *tgt_normals, int64_t n_tgt, const double T_init[16],
+                        double max_corr_dist, int32_t max_iter, double rel_tol, int32_t variant,
+                        int32_t precision, int32_t loss, double loss_k, icp_result_t *out);
+
+int icp_normal_equations_robust(icp_ctx_t *ctx, const float *src_xyz, int64_t n_src,
+                                const double T[16], const float *tgt_xyz, const float *tgt_normals,
+                                int64_t n_tgt, double max_corr_dist, int32_t variant,
+                                int32_t precision, int32_t loss, double loss_k, double AtA21[21],
+                                double Atb6[6], double *sum_d2, int64_t *n_in);
 
 /* ---- batched form -------------------------------------------------------- */
 typedef struct {

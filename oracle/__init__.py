@@ -79,6 +79,18 @@ def lib():
             C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
             C.POINTER(C.c_int32), C.c_void_p, C.c_void_p, C.c_void_p]
         L.oracle_icp_register.restype = C.c_int
+        L.oracle_normal_equations_robust.argtypes = [
+            _f32p, C.c_int64, _f64p, _f32p, C.c_void_p, C.c_int64, C.c_double, C.c_int, C.c_int,
+            C.c_int, C.c_int, C.c_double, _f64p, _f64p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.oracle_normal_equations_robust.restype = C.c_int
+        L.oracle_icp_register_robust.argtypes = [
+            _f32p, C.c_int64, _f32p, C.c_void_p, C.c_int64, _f64p, C.c_double, C.c_int32,
+            C.c_double, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, _f64p,
+            C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int64),
+            C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_void_p, C.c_void_p, C.c_void_p]
+        L.oracle_icp_register_robust.restype = C.c_int
+        L.oracle_loss_weight.argtypes = [C.c_int, C.c_double, C.c_double]
+        L.oracle_loss_weight.restype = C.c_double
         L.oracle_voxel_downsample.argtypes = [_f32p, C.c_void_p, C.c_int64, C.c_double, _f32p,
                                               C.c_void_p]
         L.oracle_voxel_downsample.restype = C.c_int64
@@ -153,19 +165,29 @@ def correspondences(src, T, tgt, max_corr_dist, selection=SEL_PINNED_F32, search
     return idx, d2f, d2d
 
 
+LOSSES = {"none": 0, "huber": 1, "tukey": 2, "cauchy": 3}
+
+
+def loss_weight(loss, k, s):
+    """IRLS weight rho'(s) / s of a robust loss at residual magnitude s."""
+    return lib().oracle_loss_weight(LOSSES[loss], float(k), float(s))
+
+
 def normal_equations(src, T, tgt, tgt_normals, max_corr_dist, variant="point_to_plane",
-                     selection=SEL_PINNED_F32, search=0):
-    """Returns (A21, b6, sum_d2, n_in)."""
+                     selection=SEL_PINNED_F32, search=0, loss="none", loss_k=1.0):
+    """Returns (A21, b6, sum_d2, n_in); with a robust loss the terms carry the
+    IRLS weight of each correspondence."""
     src, tgt = _pts(src), _pts(tgt)
     nrm = _pts(tgt_normals) if tgt_normals is not None else None
     A21 = np.zeros(21, np.float64)
     b6 = np.zeros(6, np.float64)
     sd2 = C.c_double()
     nin = C.c_int64()
-    rc = lib().oracle_normal_equations(src, len(src), _T(T), tgt,
-                                       nrm.ctypes.data if nrm is not None else None, len(tgt),
-                                       float(max_corr_dist), _VARIANTS[variant], selection, search,
-                                       A21, b6, C.byref(sd2), C.byref(nin))
+    rc = lib().oracle_normal_equations_robust(src, len(src), _T(T), tgt,
+                                              nrm.ctypes.data if nrm is not None else None, len(tgt),
+                                              float(max_corr_dist), _VARIANTS[variant], selection,
+                                              search, LOSSES[loss], float(loss_k), A21, b6,
+                                              C.byref(sd2), C.byref(nin))
     if rc != 0:
         raise ValueError("oracle_normal_equations: invalid arguments")
     return A21, b6, sd2.value, nin.value
@@ -253,7 +275,7 @@ class OracleResult:
 
 def icp_register(src, tgt, tgt_normals, T_init, max_corr_dist, max_iter, rel_tol=0.0,
                  variant="point_to_plane", selection=SEL_PINNED_F32, search=0,
-                 trajectory=False) -> OracleResult:
+                 trajectory=False, loss="none", loss_k=1.0) -> OracleResult:
     src, tgt = _pts(src), _pts(tgt)
     nrm = _pts(tgt_normals) if tgt_normals is not None else None
     T = np.zeros(16, np.float64)
@@ -265,10 +287,10 @@ def icp_register(src, tgt, tgt_normals, T_init, max_corr_dist, max_iter, rel_tol
         tT = np.zeros((max_iter + 1, 16), np.float64)
         tn = np.zeros(max_iter + 1, np.int64)
         tr = np.zeros(max_iter + 1, np.float64)
-    rc = lib().oracle_icp_register(
+    rc = lib().oracle_icp_register_robust(
         src, len(src), tgt, nrm.ctypes.data if nrm is not None else None, len(tgt), _T(T_init),
         float(max_corr_dist), int(max_iter), float(rel_tol), _VARIANTS[variant], selection, search,
-        T, C.byref(fit), C.byref(rmse), C.byref(nin), C.byref(nit), C.byref(st),
+        LOSSES[loss], float(loss_k), T, C.byref(fit), C.byref(rmse), C.byref(nin), C.byref(nit), C.byref(st),
         tT.ctypes.data if trajectory else None, tn.ctypes.data if trajectory else None,
         tr.ctypes.data if trajectory else None)
     if rc != 0:

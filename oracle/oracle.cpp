@@ -33,6 +33,13 @@
 //     between consecutive passes <= rel_tol.
 //   - degeneracy: no inliers, or a Cholesky pivot <= 1e-12 * max(diag A).
 //
+// Robust variants (the paper mentions "other ICP variants" without naming
+// them): iteratively reweighted least squares.  Each correspondence's terms
+// are multiplied by w(s) = rho'(s) / s at its residual magnitude s (|n . d|
+// point-to-plane, |d| point-to-point) at the current pose, for the Huber,
+// Tukey (biweight) and Cauchy losses of scale k; fitness and rmse stay
+// unweighted.
+//
 // Normal estimation (Sec. 3.2, Fig. 1, and the Sec. 3.3 workflow: a hybrid
 // neighbourhood of at most max_nn points within a radius; the method of [16],
 // the normal being the direction of least variance of the neighbourhood).
@@ -287,13 +294,41 @@ struct PassResult {
   Sums s;
 };
 
+// Robust loss: kind 0 none (w = 1), 1 Huber, 2 Tukey, 3 Cauchy, scale k > 0.
+constexpr int kLossNone = 0, kLossHuber = 1, kLossTukey = 2, kLossCauchy = 3;
+struct Loss {
+  int kind = kLossNone;
+  double k = 1.0;
+};
+
+// IRLS weight rho'(s) / s of the loss at residual magnitude s >= 0:
+//   Huber  rho = s^2 / 2 (s <= k), k (s - k / 2) otherwise  -> w = 1 or k / s
+//   Tukey  rho = k^2 / 6 (1 - (1 - (s/k)^2)^3) (s <= k), k^2 / 6 otherwise
+//          -> w = (1 - (s/k)^2)^2 or 0
+//   Cauchy rho = k^2 / 2 log(1 + (s/k)^2)  -> w = 1 / (1 + (s/k)^2)
+double loss_weight(const Loss& L, double s) {
+  switch (L.kind) {
+    case kLossHuber:
+      return s <= L.k ? 1.0 : L.k / s;
+    case kLossTukey: {
+      if (s > L.k) return 0.0;
+      const double u = 1.0 - (s / L.k) * (s / L.k);
+      return u * u;
+    }
+    case kLossCauchy:
+      return 1.0 / (1.0 + (s / L.k) * (s / L.k));
+    default:
+      return 1.0;
+  }
+}
+
 // One correspondence pass at T: fills per-source matches (optional) and the
 // normal-equation sums.  Summation is in fixed chunks of kChunk source points,
 // chunk partials are added in chunk order, so the result does not depend on
 // the number of threads.
 void pass(const Selector& sel, const float* src, int64_t n_src, const float* tgt_n,
           const double T[16], int variant, Sums* out, int64_t* idx_out, float* d2f_out,
-          double* d2d_out) {
+          double* d2d_out, const Loss& loss = Loss()) {
   const int64_t n_chunks = (n_src + kChunk - 1) / kChunk;
   std::vector<Sums> part((size_t)n_chunks);
 #pragma omp parallel for schedule(dynamic, 1)
@@ -318,11 +353,17 @@ void pass(const Selector& sel, const float* src, int64_t n_src, const float* tgt
       }
       double res[3], J[18];
       const int rows = residual_jacobian(variant, q, p, nrm, res, J);
+      double w = 1.0;
+      if (loss.kind != kLossNone) {
+        double s2 = 0.0;
+        for (int a = 0; a < rows; ++a) s2 += res[a] * res[a];
+        w = loss_weight(loss, std::sqrt(s2));
+      }
       for (int a = 0; a < rows; ++a) {
         const double* Ja = J + 6 * a;
         for (int u = 0; u < 6; ++u) {
-          for (int v = u; v < 6; ++v) S.A[6 * u + v] += Ja[u] * Ja[v];
-          S.b[u] += Ja[u] * res[a];
+          for (int v = u; v < 6; ++v) S.A[6 * u + v] += w * (Ja[u] * Ja[v]);
+          S.b[u] += w * (Ja[u] * res[a]);
         }
       }
       S.sd2 += m.d2d;
@@ -572,20 +613,41 @@ int oracle_correspondences(const float* src, int64_t n_src, const double T[16], 
 
 // Normal equations at T: A (upper triangle, 21, row-major), b (6), sum of FP64
 // squared distances and the inlier count.
-int oracle_normal_equations(const float* src, int64_t n_src, const double T[16], const float* tgt,
-                            const float* tgt_n, int64_t n_tgt, double r, int variant, int selection,
-                            int search, double A21[21], double b6[6], double* sum_d2,
-                            int64_t* n_in) {
+int oracle_normal_equations_robust(const float* src, int64_t n_src, const double T[16],
+                                   const float* tgt, const float* tgt_n, int64_t n_tgt, double r,
+                                   int variant, int selection, int search, int loss_kind,
+                                   double loss_k, double A21[21], double b6[6], double* sum_d2,
+                                   int64_t* n_in) {
   if (bad_args(src, n_src, tgt, n_tgt, r)) return -1;
   if (variant == kPointToPlane && !tgt_n) return -1;
+  if (loss_kind < kLossNone || loss_kind > kLossCauchy || !(loss_k > 0.0)) return -1;
   const bool tree = search == 2 || (search == 0 && (double)n_src * (double)n_tgt > 2e7);
   Selector sel(tgt, n_tgt, r, selection, tree);
   Sums S;
-  pass(sel, src, n_src, tgt_n, T, variant, &S, nullptr, nullptr, nullptr);
+  Loss L;
+  L.kind = loss_kind;
+  L.k = loss_k;
+  pass(sel, src, n_src, tgt_n, T, variant, &S, nullptr, nullptr, nullptr, L);
   pack21(S, A21, b6);
   *sum_d2 = S.sd2;
   *n_in = S.n;
   return 0;
+}
+
+int oracle_normal_equations(const float* src, int64_t n_src, const double T[16], const float* tgt,
+                            const float* tgt_n, int64_t n_tgt, double r, int variant, int selection,
+                            int search, double A21[21], double b6[6], double* sum_d2,
+                            int64_t* n_in) {
+  return oracle_normal_equations_robust(src, n_src, T, tgt, tgt_n, n_tgt, r, variant, selection,
+                                        search, kLossNone, 1.0, A21, b6, sum_d2, n_in);
+}
+
+// IRLS weight of a loss at residual magnitude s (exposed for its pins).
+double oracle_loss_weight(int loss_kind, double loss_k, double s) {
+  Loss L;
+  L.kind = loss_kind;
+  L.k = loss_k;
+  return loss_weight(L, s);
 }
 
 // The ICP loop.  Pass k = 0..max_iter computes correspondences at T_k and the
@@ -594,13 +656,18 @@ int oracle_normal_equations(const float* src, int64_t n_src, const double T[16],
 // otherwise it solves the normal equations (DEGENERATE on a failed pivot) and
 // sets T_{k+1} = Exp(xi) T_k.  Optional trajectory outputs hold T_k, n_k and
 // rmse_k for every executed pass (capacity max_iter + 1).
-int oracle_icp_register(const float* src, int64_t n_src, const float* tgt, const float* tgt_n,
-                        int64_t n_tgt, const double T_init[16], double r, int32_t max_iter,
-                        double rel_tol, int variant, int selection, int search, double T_out[16],
-                        double* fitness, double* rmse, int64_t* n_inliers, int32_t* n_iter,
-                        int32_t* status, double* traj_T, int64_t* traj_n, double* traj_rmse) {
+int oracle_icp_register_robust(const float* src, int64_t n_src, const float* tgt, const float* tgt_n,
+                               int64_t n_tgt, const double T_init[16], double r, int32_t max_iter,
+                               double rel_tol, int variant, int selection, int search,
+                               int loss_kind, double loss_k, double T_out[16], double* fitness,
+                               double* rmse, int64_t* n_inliers, int32_t* n_iter, int32_t* status,
+                               double* traj_T, int64_t* traj_n, double* traj_rmse) {
   if (bad_args(src, n_src, tgt, n_tgt, r) || max_iter < 0 || !(rel_tol >= 0.0)) return -1;
   if (variant == kPointToPlane && !tgt_n) return -1;
+  if (loss_kind < kLossNone || loss_kind > kLossCauchy || !(loss_k > 0.0)) return -1;
+  Loss L;
+  L.kind = loss_kind;
+  L.k = loss_k;
   const bool tree = search == 2 || (search == 0 && (double)n_src * (double)n_tgt > 2e7);
   Selector sel(tgt, n_tgt, r, selection, tree);
   double T[16];
@@ -609,7 +676,7 @@ int oracle_icp_register(const float* src, int64_t n_src, const float* tgt, const
   double e_prev = 0.0;
   for (int32_t k = 0;; ++k) {
     Sums S;
-    pass(sel, src, n_src, tgt_n, T, variant, &S, nullptr, nullptr, nullptr);
+    pass(sel, src, n_src, tgt_n, T, variant, &S, nullptr, nullptr, nullptr, L);
     const int64_t nk = S.n;
     const double fk = (double)nk / (double)n_src;
     const double ek = nk > 0 ? std::sqrt(S.sd2 / (double)nk) : 0.0;
@@ -646,6 +713,16 @@ int oracle_icp_register(const float* src, int64_t n_src, const float* tgt, const
     n_prev = nk;
     e_prev = ek;
   }
+}
+
+int oracle_icp_register(const float* src, int64_t n_src, const float* tgt, const float* tgt_n,
+                        int64_t n_tgt, const double T_init[16], double r, int32_t max_iter,
+                        double rel_tol, int variant, int selection, int search, double T_out[16],
+                        double* fitness, double* rmse, int64_t* n_inliers, int32_t* n_iter,
+                        int32_t* status, double* traj_T, int64_t* traj_n, double* traj_rmse) {
+  return oracle_icp_register_robust(src, n_src, tgt, tgt_n, n_tgt, T_init, r, max_iter, rel_tol,
+                                    variant, selection, search, kLossNone, 1.0, T_out, fitness, rmse,
+                                    n_inliers, n_iter, status, traj_T, traj_n, traj_rmse);
 }
 
 // Voxel downsampling (Sec. 3.3, voxel_down_sample): voxel indices

@@ -495,7 +495,22 @@ struct LoopIn {
   double r;
   int32_t max_iter;
   double rel_tol;
+  int32_t loss = 0;      // robust loss (0: none)
+  double loss_k = 1.0;
 };
+
+int check_loss(int32_t loss, double k) {
+  if (loss < ICP_LOSS_NONE || loss > ICP_LOSS_CAUCHY) return fail(ICP_E_INVALID_ARG, "unknown loss");
+  if (loss != ICP_LOSS_NONE && !(k > 0.0 && std::isfinite(k) && (float)k > 0.0f && std::isfinite((float)k)))
+    return fail(ICP_E_INVALID_ARG, "loss_k must be finite and > 0 (also in float32)");
+  return ICP_SUCCESS;
+}
+
+void set_loss(PassArgs* a, int32_t loss, double k) {
+  a->loss = loss;
+  a->loss_k = k;
+  a->loss_k32 = (float)k;
+}
 
 // Steps 3 and 4 for n prepared pairs: initial states, loop, readback.  A
 // single pair runs the per-pair kernels with arguments by value; several pairs
@@ -518,6 +533,7 @@ int run_loop(icp_ctx* c, const Prep& P, const LoopIn* in, bool normals, int vari
   int64_t item = 0;
   for (int p = 0; p < n; ++p) {
     hp[p] = pass_args(c, P, p, in[p].r, true, normals);
+    set_loss(&hp[p], in[p].loss, in[p].loss_k);
     hs[p] = SolveArgs{hp[p].part, hp[p].n_blocks, const_cast<IterState*>(hp[p].st),
                       P.src_off[p + 1] - P.src_off[p], in[p].max_iter, in[p].rel_tol, 0};
     memset(&hst[p], 0, sizeof(IterState));
@@ -564,9 +580,11 @@ int run_loop(icp_ctx* c, const Prep& P, const LoopIn* in, bool normals, int vari
 
 // One pass at a given pose for a single prepared pair (test hooks).
 int single_pass(icp_ctx* c, const Prep& P, double r, const double T[16], bool normals, int variant,
-                int precision, int32_t* idx_out, float* d2_out, bool reduce, IterState* st_out) {
+                int precision, int32_t* idx_out, float* d2_out, bool reduce, IterState* st_out,
+                int32_t loss, double loss_k) {
   hipStream_t s = c->stream;
   PassArgs a = pass_args(c, P, 0, r, false, normals);
+  set_loss(&a, loss, loss_k);
   a.idx_out = idx_out;
   a.d2_out = d2_out;
   HIP_TRY(launch_state_init(const_cast<IterState*>(a.st), T, s), "state init");
@@ -750,10 +768,19 @@ int icp_register(icp_ctx_t* ctx, const float* src_xyz, int64_t n_src, const floa
                  const float* tgt_normals, int64_t n_tgt, const double T_init[16],
                  double max_corr_dist, int32_t max_iter, double rel_tol, int32_t variant,
                  int32_t precision, icp_result_t* out) {
+  return icp_register_robust(ctx, src_xyz, n_src, tgt_xyz, tgt_normals, n_tgt, T_init, max_corr_dist,
+                             max_iter, rel_tol, variant, precision, ICP_LOSS_NONE, 1.0, out);
+}
+
+int icp_register_robust(icp_ctx_t* ctx, const float* src_xyz, int64_t n_src, const float* tgt_xyz,
+                        const float* tgt_normals, int64_t n_tgt, const double T_init[16],
+                        double max_corr_dist, int32_t max_iter, double rel_tol, int32_t variant,
+                        int32_t precision, int32_t loss, double loss_k, icp_result_t* out) {
   int rc = check_common(src_xyz, n_src, tgt_xyz, tgt_normals, n_tgt, T_init, max_corr_dist, variant,
                         precision, true);
   if (rc) return rc;
   if ((rc = check_iteration(max_iter, rel_tol)) != 0) return rc;
+  if ((rc = check_loss(loss, loss_k)) != 0) return rc;
   if (!out) return fail(ICP_E_INVALID_ARG, "out is NULL");
   icp_ctx* c = nullptr;
   if ((rc = resolve_ctx(ctx, &c)) != 0) return rc;
@@ -762,7 +789,9 @@ int icp_register(icp_ctx_t* ctx, const float* src_xyz, int64_t n_src, const floa
   const PairIn in{src_xyz, n_src, tgt_xyz, plane ? tgt_normals : nullptr, n_tgt, max_corr_dist};
   Prep P;
   if ((rc = prepare_pairs(c, 1, &in, &P)) != 0) return rc;
-  const LoopIn li{T_init, max_corr_dist, max_iter, rel_tol};
+  LoopIn li{T_init, max_corr_dist, max_iter, rel_tol};
+  li.loss = loss;
+  li.loss_k = loss_k;
   return run_loop(c, P, &li, plane, variant, precision, out);
 }
 
@@ -948,16 +977,27 @@ int icp_correspondences(icp_ctx_t* ctx, const float* src_xyz, int64_t n_src, con
   Prep P;
   if ((rc = prepare_pairs(c, 1, &in, &P)) != 0) return rc;
   return single_pass(c, P, max_corr_dist, T, false, ICP_POINT_TO_POINT, ICP_PREC_F32_KAHAN_F64,
-                     idx_out, d2_out, false, nullptr);
+                     idx_out, d2_out, false, nullptr, ICP_LOSS_NONE, 1.0);
 }
 
 int icp_normal_equations(icp_ctx_t* ctx, const float* src_xyz, int64_t n_src, const double T[16],
                          const float* tgt_xyz, const float* tgt_normals, int64_t n_tgt,
                          double max_corr_dist, int32_t variant, int32_t precision, double AtA21[21],
                          double Atb6[6], double* sum_d2, int64_t* n_in) {
+  return icp_normal_equations_robust(ctx, src_xyz, n_src, T, tgt_xyz, tgt_normals, n_tgt,
+                                     max_corr_dist, variant, precision, ICP_LOSS_NONE, 1.0, AtA21,
+                                     Atb6, sum_d2, n_in);
+}
+
+int icp_normal_equations_robust(icp_ctx_t* ctx, const float* src_xyz, int64_t n_src,
+                                const double T[16], const float* tgt_xyz, const float* tgt_normals,
+                                int64_t n_tgt, double max_corr_dist, int32_t variant,
+                                int32_t precision, int32_t loss, double loss_k, double AtA21[21],
+                                double Atb6[6], double* sum_d2, int64_t* n_in) {
   int rc = check_common(src_xyz, n_src, tgt_xyz, tgt_normals, n_tgt, T, max_corr_dist, variant,
                         precision, true);
   if (rc) return rc;
+  if ((rc = check_loss(loss, loss_k)) != 0) return rc;
   if (!AtA21 || !Atb6 || !sum_d2 || !n_in) return fail(ICP_E_INVALID_ARG, "output pointer is NULL");
   icp_ctx* c = nullptr;
   if ((rc = resolve_ctx(ctx, &c)) != 0) return rc;
@@ -968,7 +1008,7 @@ int icp_normal_equations(icp_ctx_t* ctx, const float* src_xyz, int64_t n_src, co
   if ((rc = prepare_pairs(c, 1, &in, &P)) != 0) return rc;
   IterState st;
   if ((rc = single_pass(c, P, max_corr_dist, T, plane, variant, precision, nullptr, nullptr, true,
-                        &st)) != 0)
+                        &st, loss, loss_k)) != 0)
     return rc;
   for (int k = 0; k < 21; ++k) AtA21[k] = st.sums[k];
   for (int k = 0; k < 6; ++k) Atb6[k] = st.sums[21 + k];

@@ -58,6 +58,10 @@ struct PassArgs {
   int32_t n_blocks;
   int32_t* idx_out;       // optional (correspondence hook)
   float* d2_out;
+  // robust loss (IRLS): 0 none, 1 Huber, 2 Tukey, 3 Cauchy, scale k
+  int32_t loss;
+  float loss_k32;
+  double loss_k;
 };
 
 // Normal estimation over one cloud that has been prepared as both source

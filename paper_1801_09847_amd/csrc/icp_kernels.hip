@@ -133,6 +133,21 @@ __device__ inline void record_terms(F qx, F qy, F qz, F rx, F ry, F rz, F nx, F 
   }
 }
 
+// IRLS weight rho'(s) / s of the robust loss at residual magnitude s >= 0:
+// Huber 1 (s <= k) or k / s; Tukey (1 - (s/k)^2)^2 (s <= k) or 0; Cauchy
+// 1 / (1 + (s/k)^2).  A query without a correspondence has s = 0 and w = 1.
+template <class F>
+__device__ inline F loss_weight(int kind, F k, F s) {
+  if (kind == 1) return s <= k ? F(1) : k / s;
+  if (kind == 2) {
+    if (s > k) return F(0);
+    const F u = F(1) - (s / k) * (s / k);
+    return u * u;
+  }
+  if (kind == 3) return F(1) / (F(1) + (s / k) * (s / k));
+  return F(1);
+}
+
 // Correspondence search of one query on the dense grid (cells of edge
 // h >= r (1 + 2^-10) / R, neighbourhood of (2R+1)^3 cells).  Cells are pruned
 // when their box lies farther from the query than the best distance known so
@@ -400,6 +415,12 @@ __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
       record_terms<VAR, float>(q32x, q32y, q32z, fx, fy, fz, nx, ny, nz, v);
       const float d2 = fx * fx + fy * fy;
       v[27] = d2 + fz * fz;
+      if (a.loss != 0) {  // robust variant: the same for the whole launch
+        const float sr = VAR == 1 ? fabsf((nx * fx + ny * fy) + nz * fz) : sqrtf(v[27]);
+        const float wr = loss_weight<float>(a.loss, a.loss_k32, sr);
+#pragma unroll
+        for (int k = 0; k < 27; ++k) v[k] = v[k] * wr;
+      }
       if (VAR != 1) {
 #pragma unroll
         for (int k = 0; k < 27; ++k) v[k] = inl ? v[k] : 0.f;
@@ -420,6 +441,12 @@ __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
           }
           record_terms<VAR, double>(q64x, q64y, q64z, rx, ry, rz, nx, ny, nz, v);
           v[27] = (rx * rx + ry * ry) + rz * rz;
+          if (a.loss != 0) {
+            const double sr = VAR == 1 ? fabs((nx * rx + ny * ry) + nz * rz) : sqrt(v[27]);
+            const double wr = loss_weight<double>(a.loss, a.loss_k, sr);
+#pragma unroll
+            for (int k = 0; k < 27; ++k) v[k] = v[k] * wr;
+          }
         } else {
 #pragma unroll
           for (int k = 0; k < 28; ++k) v[k] = 0.0;

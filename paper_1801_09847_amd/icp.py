@@ -37,6 +37,9 @@ VARIANTS = {"point_to_point": ICP_POINT_TO_POINT, "point_to_plane": ICP_POINT_TO
 PRECISIONS = {"kahan32": ICP_PREC_F32_KAHAN_F64, "f32_kahan_f64": ICP_PREC_F32_KAHAN_F64,
               "f64": ICP_PREC_F64, ICP_PREC_F32_KAHAN_F64: ICP_PREC_F32_KAHAN_F64,
               ICP_PREC_F64: ICP_PREC_F64}
+ICP_LOSS_NONE, ICP_LOSS_HUBER, ICP_LOSS_TUKEY, ICP_LOSS_CAUCHY = 0, 1, 2, 3
+LOSSES = {"none": ICP_LOSS_NONE, "huber": ICP_LOSS_HUBER, "tukey": ICP_LOSS_TUKEY,
+          "cauchy": ICP_LOSS_CAUCHY, 0: 0, 1: 1, 2: 2, 3: 3}
 
 
 class IcpError(RuntimeError):
@@ -106,6 +109,11 @@ def lib():
         L.icp_correspondences.argtypes = [vp, vp, i64, vp, vp, i64, dbl, vp, vp]
         L.icp_normal_equations.argtypes = [vp, vp, i64, vp, vp, vp, i64, dbl, i32, i32, vp, vp,
                                            C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.icp_register_robust.argtypes = [vp, vp, i64, vp, vp, i64, vp, dbl, i32, dbl, i32, i32, i32,
+                                          dbl, C.POINTER(icp_result_t)]
+        L.icp_normal_equations_robust.argtypes = [vp, vp, i64, vp, vp, vp, i64, dbl, i32, i32, i32,
+                                                  dbl, vp, vp, C.POINTER(C.c_double),
+                                                  C.POINTER(C.c_int64)]
         L.icp_register_batch.argtypes = [vp, C.POINTER(icp_pair_t), i32, i32, i32,
                                          C.POINTER(icp_result_t)]
         L.icp_voxel_downsample.argtypes = [vp, vp, vp, i64, dbl, vp, vp, i64, C.POINTER(C.c_int64)]
@@ -123,7 +131,7 @@ def lib():
         for name in ("icp_ctx_create", "icp_ctx_destroy", "icp_register", "icp_correspondences",
                      "icp_normal_equations", "icp_ctx_set_profiling", "icp_ctx_get_profile",
                      "icp_register_batch", "icp_voxel_downsample", "icp_register_multiscale",
-                     "icp_estimate_normals",
+                     "icp_estimate_normals", "icp_register_robust", "icp_normal_equations_robust",
                      "icp_server_create", "icp_server_submit", "icp_server_step", "icp_server_poll",
                      "icp_server_wait", "icp_server_destroy"):
             getattr(L, name).restype = C.c_int
@@ -158,12 +166,19 @@ def icp_ctx_destroy(ctx: int | None) -> None:
 
 
 def icp_register(ctx, src_ptr, n_src, tgt_ptr, tgt_n_ptr, n_tgt, T_init, max_corr_dist, max_iter,
-                 rel_tol, variant, precision) -> icp_result_t:
+                 rel_tol, variant, precision, loss=0, loss_k=1.0) -> icp_result_t:
+    """icp_register, or icp_register_robust when loss is not ICP_LOSS_NONE."""
     out = icp_result_t()
     T = _pose(T_init)
-    _check(lib().icp_register(ctx, src_ptr, int(n_src), tgt_ptr, tgt_n_ptr, int(n_tgt),
-                              T.ctypes.data, float(max_corr_dist), int(max_iter), float(rel_tol),
-                              int(variant), int(precision), C.byref(out)))
+    if loss == ICP_LOSS_NONE:
+        _check(lib().icp_register(ctx, src_ptr, int(n_src), tgt_ptr, tgt_n_ptr, int(n_tgt),
+                                  T.ctypes.data, float(max_corr_dist), int(max_iter), float(rel_tol),
+                                  int(variant), int(precision), C.byref(out)))
+    else:
+        _check(lib().icp_register_robust(ctx, src_ptr, int(n_src), tgt_ptr, tgt_n_ptr, int(n_tgt),
+                                         T.ctypes.data, float(max_corr_dist), int(max_iter),
+                                         float(rel_tol), int(variant), int(precision), int(loss),
+                                         float(loss_k), C.byref(out)))
     return out
 
 
@@ -183,16 +198,23 @@ def icp_correspondences(ctx, src_ptr, n_src, T, tgt_ptr, n_tgt, max_corr_dist, i
 
 
 def icp_normal_equations(ctx, src_ptr, n_src, T, tgt_ptr, tgt_n_ptr, n_tgt, max_corr_dist, variant,
-                         precision):
+                         precision, loss=0, loss_k=1.0):
     T = _pose(T)
     A = np.zeros(21, np.float64)
     b = np.zeros(6, np.float64)
     sd2 = C.c_double()
     nin = C.c_int64()
-    _check(lib().icp_normal_equations(ctx, src_ptr, int(n_src), T.ctypes.data, tgt_ptr, tgt_n_ptr,
-                                      int(n_tgt), float(max_corr_dist), int(variant),
-                                      int(precision), A.ctypes.data, b.ctypes.data, C.byref(sd2),
-                                      C.byref(nin)))
+    if loss == ICP_LOSS_NONE:
+        _check(lib().icp_normal_equations(ctx, src_ptr, int(n_src), T.ctypes.data, tgt_ptr, tgt_n_ptr,
+                                          int(n_tgt), float(max_corr_dist), int(variant),
+                                          int(precision), A.ctypes.data, b.ctypes.data, C.byref(sd2),
+                                          C.byref(nin)))
+    else:
+        _check(lib().icp_normal_equations_robust(ctx, src_ptr, int(n_src), T.ctypes.data, tgt_ptr,
+                                                 tgt_n_ptr, int(n_tgt), float(max_corr_dist),
+                                                 int(variant), int(precision), int(loss),
+                                                 float(loss_k), A.ctypes.data, b.ctypes.data,
+                                                 C.byref(sd2), C.byref(nin)))
     return A, b, sd2.value, nin.value
 
 
@@ -249,7 +271,10 @@ class IcpResult:
 
 
 def register(src, tgt, tgt_normals, T_init, max_corr_dist, max_iter=30, rel_tol=0.0,
-             variant="point_to_plane", precision="kahan32", ctx: Context | None = None) -> IcpResult:
+             variant="point_to_plane", precision="kahan32", ctx: Context | None = None,
+             loss="none", loss_k=1.0) -> IcpResult:
+    """ICP registration; loss "huber" / "tukey" / "cauchy" with scale loss_k
+    gives the robust (IRLS) variant."""
     sp, ns = _dev_pts(src, "src")
     tp, nt = _dev_pts(tgt, "tgt")
     npn = None
@@ -258,7 +283,7 @@ def register(src, tgt, tgt_normals, T_init, max_corr_dist, max_iter=30, rel_tol=
         if nn != nt:
             raise IcpError(ICP_E_INVALID_ARG, "tgt_normals must have as many rows as tgt")
     r = icp_register(ctx.handle if ctx else None, sp, ns, tp, npn, nt, T_init, max_corr_dist,
-                     max_iter, rel_tol, VARIANTS[variant], PRECISIONS[precision])
+                     max_iter, rel_tol, VARIANTS[variant], PRECISIONS[precision], LOSSES[loss], loss_k)
     return IcpResult(np.array(r.T[:], dtype=np.float64).reshape(4, 4), r.fitness, r.inlier_rmse,
                      r.n_inliers, r.n_iter, r.status)
 
@@ -361,13 +386,13 @@ def correspondences(src, T, tgt, max_corr_dist, ctx: Context | None = None):
 
 
 def normal_equations(src, T, tgt, tgt_normals, max_corr_dist, variant="point_to_plane",
-                     precision="kahan32", ctx: Context | None = None):
-    """(AtA21, Atb6, sum_d2, n_in) at pose T."""
+                     precision="kahan32", ctx: Context | None = None, loss="none", loss_k=1.0):
+    """(AtA21, Atb6, sum_d2, n_in) at pose T (IRLS-weighted with a robust loss)."""
     sp, ns = _dev_pts(src, "src")
     tp, nt = _dev_pts(tgt, "tgt")
     npn = _dev_pts(tgt_normals, "tgt_normals")[0] if tgt_normals is not None else None
     return icp_normal_equations(ctx.handle if ctx else None, sp, ns, T, tp, npn, nt, max_corr_dist,
-                                VARIANTS[variant], PRECISIONS[precision])
+                                VARIANTS[variant], PRECISIONS[precision], LOSSES[loss], loss_k)
 
 
 def full_matrix(A21) -> np.ndarray:

@@ -75,6 +75,11 @@ def test_register_validation_codes():
     assert _reg(precision=3) == icp.ICP_E_INVALID_ARG
     assert _reg(src_ptr=MISALIGNED) == icp.ICP_E_INVALID_ARG
     assert "aligned" in icp.lib().icp_last_error().decode()
+    # robust variant: loss kind and scale
+    assert _reg(loss=9, loss_k=0.01) == icp.ICP_E_INVALID_ARG
+    assert _reg(loss=icp.ICP_LOSS_TUKEY, loss_k=0.0) == icp.ICP_E_INVALID_ARG
+    assert _reg(loss=icp.ICP_LOSS_HUBER, loss_k=float("inf")) == icp.ICP_E_INVALID_ARG
+    assert _reg(loss=icp.ICP_LOSS_CAUCHY, loss_k=1e-300) == icp.ICP_E_INVALID_ARG  # 0 in float32
 
 
 def test_null_out_and_hooks_validation():

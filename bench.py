@@ -10,7 +10,8 @@ inputs already resident in device memory.  The default workload is the
 Printed: one JSON line with corr-evals/s (sum over executed passes of n_src,
 per second of wall time), the dominant kernel's roofline figures (algorithmic
 bytes per launch over its event-timed average duration) and the CPU oracle
-timed on a bounded sample of the same workload; then (default workload) the
+timed on a bounded sample of the same workload; then the robust-loss
+variants of the same registration and (default workload) the
 normal-estimation, 256-pair batched and served sections.
 
   python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1] [--variant ...]
@@ -88,6 +89,37 @@ def cpu_baseline(data, variant, passes, min_seconds=10.0):
             "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"same pair, first {passes} passes (max_iter={passes - 1}) run {runs}x, FP64 oracle "
                       f"with k-d tree, {dt:.1f} s wall incl. tree builds"}
+
+
+def robust_section(args, icp, np, torch, s, t, n, data, K, r, steps=3):
+    """The same registration with the robust (IRLS) losses, scale 1 cm."""
+    out = []
+    for loss in ("huber", "tukey", "cauchy"):
+        ctx = icp.Context(0)
+
+        def step():
+            return icp.register(s, t, n, np.eye(4), r, K, 0.0, args.variant, args.precision, ctx=ctx,
+                                loss=loss, loss_k=0.01)
+
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = []
+        for k in range(steps):
+            if k == steps - 1:
+                ctx.set_profiling(True)
+            res.append(step())
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = ctx.profile()
+        evals = sum((x.n_iter + 1) * len(data["src"]) for x in res)
+        out.append({"loss": loss, "loss_k": 0.01, "value": evals / dt, "unit": "corr-evals/s",
+                    "ms_per_step": dt * 1e3 / steps,
+                    "pass_avg_us": prof["pass_ms"] * 1000.0 / max(1, prof["pass_launches"]),
+                    "result": {"fitness": res[-1].fitness, "inlier_rmse": res[-1].inlier_rmse,
+                               "n_iter": res[-1].n_iter, "status": res[-1].status}})
+        print(f"bench: robust {loss}: {evals / dt:.3e} corr-evals/s", file=sys.stderr, flush=True)
+    return out
 
 
 def normals_section(args, icp, synth, np, torch, data):
@@ -343,6 +375,7 @@ def main():
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--no-served", action="store_true", help="skip the served (request server) section")
     ap.add_argument("--no-normals", action="store_true", help="skip the normal-estimation section")
+    ap.add_argument("--no-robust", action="store_true", help="skip the robust-loss section")
     ap.add_argument("--served-requests", type=int, default=400)
     ap.add_argument("--served-pool", type=int, default=64)
     ap.add_argument("--served-rates", type=float, nargs="+", default=[1.0, 8.0])
@@ -453,6 +486,8 @@ def main():
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(data, args.variant, args.cpu_passes)
+    if not args.no_robust:
+        out["robust"] = robust_section(args, icp, np, torch, s, t, n, data, K, r)
     del s, t, n
     if not args.no_normals and args.workload == "c3":
         out["normals"] = normals_section(args, icp, synth, np, torch, data)

@@ -309,7 +309,7 @@ __device__ inline void wave_sync() {
 // mode does the transposed sum every round, in float64.  The two halves and
 // the block's waves are then merged in a fixed order and one float64 partial
 // per term is written, so results do not depend on timing.
-template <int VAR, int PREC, bool WRITE, int R>
+template <int VAR, int PREC, bool WRITE, int R, bool ROBUST>
 __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
   __shared__ __align__(16) uint32_t scratch[kBlock / kWave][WaveScratch<R>::kWords];
   __shared__ float red_s[kBlock / kWave][kNumSums];
@@ -415,7 +415,7 @@ __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
       record_terms<VAR, float>(q32x, q32y, q32z, fx, fy, fz, nx, ny, nz, v);
       const float d2 = fx * fx + fy * fy;
       v[27] = d2 + fz * fz;
-      if (a.loss != 0) {  // robust variant: the same for the whole launch
+      if (ROBUST) {  // robust variant (IRLS weight of the loss)
         const float sr = VAR == 1 ? fabsf((nx * fx + ny * fy) + nz * fz) : sqrtf(v[27]);
         const float wr = loss_weight<float>(a.loss, a.loss_k32, sr);
 #pragma unroll
@@ -441,7 +441,7 @@ __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
           }
           record_terms<VAR, double>(q64x, q64y, q64z, rx, ry, rz, nx, ny, nz, v);
           v[27] = (rx * rx + ry * ry) + rz * rz;
-          if (a.loss != 0) {
+          if (ROBUST) {
             const double sr = VAR == 1 ? fabs((nx * rx + ny * ry) + nz * rz) : sqrt(v[27]);
             const double wr = loss_weight<double>(a.loss, a.loss_k, sr);
 #pragma unroll
@@ -537,10 +537,10 @@ __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
   }
 }
 
-template <int VAR, int PREC, bool WRITE, int R>
+template <int VAR, int PREC, bool WRITE, int R, bool ROBUST>
 __global__ __launch_bounds__(kBlock) void pass_kernel(PassArgs a) {
   if (glb(a.st)->done) return;
-  pass_tile<VAR, PREC, WRITE, R>(a, blockIdx.x);
+  pass_tile<VAR, PREC, WRITE, R, ROBUST>(a, blockIdx.x);
 }
 
 // Batched form: block b handles tile items[b].y of pair items[b].x.  Tiles and
@@ -552,7 +552,7 @@ __global__ __launch_bounds__(kBlock) void batch_pass_kernel(const PassArgs* __re
   const uint2 it = items[blockIdx.x];
   const PassArgs a = pairs[it.x];  // by value: uniform, kept in scalar registers
   if (glb(a.st)->done) return;
-  pass_tile<VAR, PREC, false, R>(a, it.y);
+  pass_tile<VAR, PREC, false, R, false>(a, it.y);
 }
 
 // ------------------------------------------------------------------ solve + pose update
@@ -1023,10 +1023,10 @@ hipError_t launch_state_init(IterState* st, const double T[16], hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int R>
+template <int R, bool ROBUST>
 void launch_pass_r(const PassArgs& a, int variant, int precision, bool write_corr, hipStream_t s) {
   const dim3 grid((unsigned)a.n_blocks), block(kBlock);
-#define ICP_PASS(V, P, W) hipLaunchKernelGGL((pass_kernel<V, P, W, R>), grid, block, 0, s, a)
+#define ICP_PASS(V, P, W) hipLaunchKernelGGL((pass_kernel<V, P, W, R, ROBUST>), grid, block, 0, s, a)
   if (write_corr) {
     if (variant == 1) { if (precision == 0) ICP_PASS(1, 0, true); else ICP_PASS(1, 1, true); }
     else { if (precision == 0) ICP_PASS(0, 0, true); else ICP_PASS(0, 1, true); }
@@ -1038,10 +1038,15 @@ void launch_pass_r(const PassArgs& a, int variant, int precision, bool write_cor
 }
 
 hipError_t launch_pass(const PassArgs& a, int variant, int precision, bool write_corr, hipStream_t s) {
-  if (a.g.sub == 2)
-    launch_pass_r<2>(a, variant, precision, write_corr, s);
-  else
-    launch_pass_r<1>(a, variant, precision, write_corr, s);
+  // the robust weight is compiled only into the robust kernels
+  const bool robust = a.loss != 0;
+  if (a.g.sub == 2) {
+    if (robust) launch_pass_r<2, true>(a, variant, precision, write_corr, s);
+    else launch_pass_r<2, false>(a, variant, precision, write_corr, s);
+  } else {
+    if (robust) launch_pass_r<1, true>(a, variant, precision, write_corr, s);
+    else launch_pass_r<1, false>(a, variant, precision, write_corr, s);
+  }
   return hipGetLastError();
 }
 

@@ -272,6 +272,53 @@ int icp_register_multiscale(icp_ctx_t *ctx, const float *src_xyz, int64_t n_src,
                             const double *max_corr_dist, double rel_tol, int32_t variant,
                             int32_t precision, icp_result_t *out);
 
+/* ---- multiway registration: pose-graph optimisation ---------------------
+ * Multiway registration (Sec. 3.3) by pose-graph optimisation with
+ * Gauss-Newton or Levenberg-Marquardt (the in-house solvers of Sec. 2).  Node
+ * k has pose T_k (node frame -> world, row-major 4x4); edge (i, j) holds a
+ * measured relative pose Z ~ T_i^-1 T_j (e.g. an icp_register result that maps
+ * fragment j onto fragment i) and a symmetric positive semi-definite 6x6
+ * information matrix (row-major, twist order (omega, v)).  The residual is
+ * e = Log(Z^-1 T_i^-1 T_j), the objective F = sum e^T information e.  Node 0
+ * stays fixed; the others move by left perturbations T <- Exp(d) T with the
+ * edge Jacobians +-Ad(T_j^-1) (exact where e = 0, so consistent graphs are
+ * recovered exactly).  Gauss-Newton solves H d = -g; Levenberg-Marquardt
+ * solves (H + lambda diag H) d = -g, lambda starting at 1e-4, keeps a step
+ * that lowers F (lambda / 10) and otherwise refuses it (lambda * 10).  The run
+ * stops after max_iter kept steps (ICP_OK), when a kept step changes F by at
+ * most rel_tol * F or after 10 refusals in a row (ICP_CONVERGED), or on a
+ * Cholesky pivot <= 1e-12 max diag (ICP_DEGENERATE, poses of the last kept
+ * step).  Rotation angles of the residuals must stay below pi. */
+#define ICP_PG_GAUSS_NEWTON 0
+#define ICP_PG_LEVENBERG_MARQUARDT 1
+
+typedef struct {
+  int32_t i, j;           /* node indices, 0 <= i, j < n_nodes, i != j */
+  double Z[16];           /* row-major rigid transform, ~ T_i^-1 T_j */
+  double information[36]; /* row-major 6x6 */
+} icp_pose_edge_t;
+
+typedef struct {
+  double F_initial;  /* objective at the given poses */
+  double F_final;    /* objective at the returned poses */
+  int32_t steps;     /* kept steps */
+  int32_t status;    /* ICP_OK, ICP_CONVERGED or ICP_DEGENERATE */
+} icp_pose_graph_result_t;
+
+/* Optimises the poses in place.
+ *   n_nodes  2 .. 256
+ *   poses    host (n_nodes, 16) float64, finite rigid transforms; overwritten
+ *   edges    host array of n_edges >= 1 edges
+ *   method   ICP_PG_GAUSS_NEWTON or ICP_PG_LEVENBERG_MARQUARDT
+ *   max_iter >= 0; rel_tol finite, >= 0
+ *   out      host result
+ * Synchronous on the context's stream.  Errors: INVALID_ARG (bad sizes,
+ * indices, non-finite or non-rigid transforms, non-finite information), OOM,
+ * DEVICE; on errors the poses are untouched. */
+int icp_pose_graph_optimize(icp_ctx_t *ctx, int32_t n_nodes, double *poses, int32_t n_edges,
+                            const icp_pose_edge_t *edges, int32_t method, int32_t max_iter,
+                            double rel_tol, icp_pose_graph_result_t *out);
+
 /* ---- served form: continuous batching of registration requests ----------
  * Requests (pairs of clouds, as produced one by one by a reconstruction
  * pipeline's fragment registration stage, Sec. 3.4) are submitted at any

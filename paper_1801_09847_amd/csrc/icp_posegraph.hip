@@ -1,0 +1,525 @@
+// Pose-graph optimisation (multiway registration) on gfx950.
+//
+// Method: Open3D paper Sec. 3.3 (multiway registration by pose-graph
+// optimisation) with the in-house Gauss-Newton / Levenberg-Marquardt solvers
+// of Sec. 2.  Nodes carry poses T_i (node frame -> world); an edge (i, j, Z, L)
+// carries a measured relative pose Z ~ T_i^-1 T_j and a 6x6 information
+// matrix L.  The residual is e = Log(Z^-1 T_i^-1 T_j) (rotation first, the
+// twist order of the ICP step), the objective F = sum e^T L e; node 0 is held
+// fixed and the others move by left perturbations T_k <- Exp(d_k) T_k, with
+// de/dd_j = Ad(T_j^-1) and de/dd_i = -Ad(T_j^-1) (exact where e = 0).
+//
+// Per iteration: one thread per edge forms K = J^T L J, u = J^T L e and
+// f = e^T L e in float64; the dense normal equations over the free nodes are
+// assembled block by block from host-built incidence lists (fixed order, no
+// atomics); F is a fixed-order reduction; one workgroup factorises H (plus the
+// Levenberg-Marquardt damping) by Cholesky and solves for the step; one thread
+// per node applies it.  The host keeps or refuses the step from F alone.
+
+#include <math.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "icp_runtime.h"
+
+#pragma clang fp contract(off)
+
+using namespace icp;
+using namespace icp_rt;
+
+namespace {
+
+constexpr int kTerms = 43;       // K (36), u (6), f
+constexpr int kSolveThreads = 1024;
+constexpr int kMaxPgNodes = 256;
+
+struct PgEdge {
+  int32_t i, j;
+  double Z[16];
+  double L[36];
+};
+
+struct PgBlock {  // one 6x6 block (a, b), a <= b, of H over the free nodes
+  int32_t a, b;   // free-node indices (node - 1)
+  int32_t start, count;  // contributions in the (edge, sign) list
+};
+
+__device__ inline void rigid_inverse(const double* T, double* Ti) {
+  for (int r = 0; r < 3; ++r) {
+    for (int c = 0; c < 3; ++c) Ti[4 * r + c] = T[4 * c + r];
+    Ti[4 * r + 3] = -((T[4 * 0 + r] * T[3] + T[4 * 1 + r] * T[7]) + T[4 * 2 + r] * T[11]);
+  }
+  Ti[12] = 0.0; Ti[13] = 0.0; Ti[14] = 0.0; Ti[15] = 1.0;
+}
+
+__device__ inline void mul4(const double* X, const double* Y, double* Z) {
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 4; ++c) {
+      double s = (X[4 * r] * Y[c] + X[4 * r + 1] * Y[4 + c]) + X[4 * r + 2] * Y[8 + c];
+      if (c == 3) s += X[4 * r + 3];
+      Z[4 * r + c] = s;
+    }
+  Z[12] = 0.0; Z[13] = 0.0; Z[14] = 0.0; Z[15] = 1.0;
+}
+
+// Log of a rigid transform (rotation angle below pi): omega from the
+// antisymmetric part of R scaled by theta / (2 sin theta), v = V^-1 t with
+// V^-1 = I - W / 2 + k W^2, k = (1 - theta sin theta / (2 (1 - cos theta))) / theta^2
+// (series near 0).
+__device__ inline void log_rigid(const double* E, double* e) {
+  const double tr = (E[0] + E[5]) + E[10];
+  const double c = fmin(fmax(0.5 * (tr - 1.0), -1.0), 1.0);
+  const double th = acos(c);
+  const double ax = E[9] - E[6], ay = E[2] - E[8], az = E[4] - E[1];
+  double s, k;
+  if (th < 1e-4) {
+    s = 0.5 * (1.0 + th * th / 6.0);
+    k = 1.0 / 12.0 + th * th / 720.0;
+  } else {
+    const double sn = sin(th);
+    s = th / (2.0 * sn);
+    k = (1.0 - th * sn / (2.0 * (1.0 - cos(th)))) / (th * th);
+  }
+  const double wx = s * ax, wy = s * ay, wz = s * az;
+  const double tx = E[3], ty = E[7], tz = E[11];
+  // W t and W (W t) with W = [w]_x
+  const double p0 = wy * tz - wz * ty, p1 = wz * tx - wx * tz, p2 = wx * ty - wy * tx;
+  const double q0 = wy * p2 - wz * p1, q1 = wz * p0 - wx * p2, q2 = wx * p1 - wy * p0;
+  e[0] = wx; e[1] = wy; e[2] = wz;
+  e[3] = (tx - 0.5 * p0) + k * q0;
+  e[4] = (ty - 0.5 * p1) + k * q1;
+  e[5] = (tz - 0.5 * p2) + k * q2;
+}
+
+// Exp of (omega, v) applied on the left of T (same closed form as the ICP
+// pose update).
+__device__ inline void exp_left(const double* xi, const double* T, double* out) {
+  const double wx = xi[0], wy = xi[1], wz = xi[2];
+  const double th2 = (wx * wx + wy * wy) + wz * wz;
+  const double th = sqrt(th2);
+  double A, B, C;
+  if (th < 1e-4) {
+    A = 1.0 - th2 / 6.0 + th2 * th2 / 120.0;
+    B = 0.5 - th2 / 24.0 + th2 * th2 / 720.0;
+    C = 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0;
+  } else {
+    const double sn = sin(th), sh = sin(0.5 * th);
+    A = sn / th;
+    B = 2.0 * sh * sh / th2;
+    C = (th - sn) / (th2 * th);
+  }
+  const double W[3][3] = {{0.0, -wz, wy}, {wz, 0.0, -wx}, {-wy, wx, 0.0}};
+  double E[16];
+  for (int r = 0; r < 3; ++r) {
+    double vr = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      double w2 = 0.0;
+      for (int m = 0; m < 3; ++m) w2 += W[r][m] * W[m][c];
+      const double I = r == c ? 1.0 : 0.0;
+      E[4 * r + c] = I + A * W[r][c] + B * w2;
+      vr += (I + B * W[r][c] + C * w2) * xi[3 + c];
+    }
+    E[4 * r + 3] = vr;
+  }
+  E[12] = 0.0; E[13] = 0.0; E[14] = 0.0; E[15] = 1.0;
+  mul4(E, T, out);
+}
+
+// One edge: e, J = Ad(T_j^-1) (rows of (omega, v) = [[R', 0], [[t']_x R', R']]
+// with (R', t') = T_j^-1), K = J^T L J, u = J^T L e, f = e^T L e.
+__global__ __launch_bounds__(64) void pg_edge_kernel(const double* __restrict__ poses,
+                                                     const PgEdge* __restrict__ edges, int m,
+                                                     double* __restrict__ terms) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  const PgEdge& ed = edges[k];
+  const double* Ti = poses + 16 * ed.i;
+  const double* Tj = poses + 16 * ed.j;
+  double Tii[16], Zi[16], A[16], E[16], Tji[16];
+  rigid_inverse(Ti, Tii);
+  mul4(Tii, Tj, A);
+  rigid_inverse(ed.Z, Zi);
+  mul4(Zi, A, E);
+  double e[6];
+  log_rigid(E, e);
+  rigid_inverse(Tj, Tji);
+  double J[6][6];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      const double R = Tji[4 * r + c];
+      J[r][c] = R;
+      J[r][3 + c] = 0.0;
+      J[3 + r][3 + c] = R;
+    }
+  const double tx = Tji[3], ty = Tji[7], tz = Tji[11];
+  for (int c = 0; c < 3; ++c) {  // [t]_x R'
+    const double r0 = Tji[c], r1 = Tji[4 + c], r2 = Tji[8 + c];
+    J[3][c] = ty * r2 - tz * r1;
+    J[4][c] = tz * r0 - tx * r2;
+    J[5][c] = tx * r1 - ty * r0;
+  }
+  double LJ[6][6], Le[6];
+  for (int r = 0; r < 6; ++r) {
+    double s = 0.0;
+    for (int c = 0; c < 6; ++c) {
+      double a = 0.0;
+      for (int m2 = 0; m2 < 6; ++m2) a += ed.L[6 * r + m2] * J[m2][c];
+      LJ[r][c] = a;
+      s += ed.L[6 * r + c] * e[c];
+    }
+    Le[r] = s;
+  }
+  double* out = terms + (int64_t)k * kTerms;
+  double f = 0.0;
+  for (int r = 0; r < 6; ++r) {
+    for (int c = 0; c < 6; ++c) {
+      double a = 0.0;
+      for (int m2 = 0; m2 < 6; ++m2) a += J[m2][r] * LJ[m2][c];
+      out[6 * r + c] = a;
+    }
+    double u = 0.0;
+    for (int m2 = 0; m2 < 6; ++m2) u += J[m2][r] * Le[m2];
+    out[36 + r] = u;
+    f += e[r] * Le[r];
+  }
+  out[42] = f;
+}
+
+// H block (a, b): sum of sign * K over its contributions, in list order;
+// the transposed block is written too.
+__global__ __launch_bounds__(64) void pg_assemble_h_kernel(const PgBlock* __restrict__ blocks,
+                                                           const int2* __restrict__ contrib,
+                                                           const double* __restrict__ terms,
+                                                           double* __restrict__ H, int n) {
+  const PgBlock bl = blocks[blockIdx.x];
+  const int t = threadIdx.x;
+  if (t >= 36) return;
+  const int r = t / 6, c = t % 6;
+  double s = 0.0;
+  for (int k = 0; k < bl.count; ++k) {
+    const int2 ce = contrib[bl.start + k];
+    const double v = terms[(int64_t)ce.x * kTerms + 6 * r + c];
+    s += ce.y > 0 ? v : -v;
+  }
+  H[(int64_t)(6 * bl.a + r) * n + 6 * bl.b + c] = s;
+  if (bl.a != bl.b) H[(int64_t)(6 * bl.b + c) * n + 6 * bl.a + r] = s;
+}
+
+// g over the free nodes: sum of sign * u over each node's incident edges.
+__global__ void pg_assemble_g_kernel(const int2* __restrict__ node_range,
+                                     const int2* __restrict__ contrib,
+                                     const double* __restrict__ terms, double* __restrict__ g,
+                                     int n_free) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= 6 * n_free) return;
+  const int a = q / 6, comp = q % 6;
+  const int2 rg = node_range[a];
+  double s = 0.0;
+  for (int k = 0; k < rg.y; ++k) {
+    const int2 ce = contrib[rg.x + k];
+    const double v = terms[(int64_t)ce.x * kTerms + 36 + comp];
+    s += ce.y > 0 ? v : -v;
+  }
+  g[q] = s;
+}
+
+// F = sum of the edges' f: per-thread sums over a fixed stride, then a fixed
+// tree in LDS.
+__global__ __launch_bounds__(256) void pg_objective_kernel(const double* __restrict__ terms, int m,
+                                                           double* __restrict__ F) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int k = threadIdx.x; k < m; k += 256) s += terms[(int64_t)k * kTerms + 42];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *F = sh[0];
+}
+
+// One workgroup: A = H with the diagonal scaled by (1 + lambda), Cholesky
+// A = L L^T in place (right-looking, lower triangle), then L y = -g and
+// L^T d = y.  A pivot <= 1e-12 * max(diag A) sets *flag and stops.
+__global__ __launch_bounds__(kSolveThreads) void pg_cholesky_solve_kernel(
+    const double* __restrict__ H, double* __restrict__ A, const double* __restrict__ g,
+    double* __restrict__ d, int n, double lambda, int* __restrict__ flag) {
+  __shared__ double sdiag;
+  __shared__ int sbad;
+  const int t = threadIdx.x;
+  for (int q = t; q < n * n; q += kSolveThreads) {  // n * n < 2^31 for n <= 6 * 255
+    const int r = q / n, c = q - r * n;
+    A[q] = r == c ? H[q] * (1.0 + lambda) : H[q];
+  }
+  for (int r = t; r < n; r += kSolveThreads) d[r] = -g[r];
+  __syncthreads();
+  if (t == 0) {
+    double mx = 0.0;
+    for (int r = 0; r < n; ++r) mx = fmax(mx, A[(int64_t)r * n + r]);
+    sdiag = mx;
+    sbad = 0;
+  }
+  __syncthreads();
+  const double thr = 1e-12 * sdiag;
+  for (int k = 0; k < n; ++k) {
+    if (t == 0) {
+      const double p = A[(int64_t)k * n + k];
+      if (!(p > thr)) sbad = 1;
+      A[(int64_t)k * n + k] = sqrt(fmax(p, 0.0));
+    }
+    __syncthreads();
+    if (sbad) break;
+    const double lkk = A[(int64_t)k * n + k];
+    for (int i = k + 1 + t; i < n; i += kSolveThreads) A[(int64_t)i * n + k] /= lkk;
+    __syncthreads();
+    const int mrem = n - k - 1;
+    for (int q = t; q < mrem * mrem; q += kSolveThreads) {
+      const int i = q / mrem, j = q - i * mrem;
+      if (j > i) continue;
+      const int64_t ii = k + 1 + i, jj = k + 1 + j;
+      A[ii * n + jj] -= A[ii * n + k] * A[jj * n + k];
+    }
+    __syncthreads();
+  }
+  if (sbad) {
+    if (t == 0) *flag = 1;
+    return;
+  }
+  // forward: L y = -g (column oriented), then back: L^T d = y
+  for (int k = 0; k < n; ++k) {
+    if (t == 0) d[k] /= A[(int64_t)k * n + k];
+    __syncthreads();
+    const double yk = d[k];
+    for (int i = k + 1 + t; i < n; i += kSolveThreads) d[i] -= A[(int64_t)i * n + k] * yk;
+    __syncthreads();
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    if (t == 0) d[k] /= A[(int64_t)k * n + k];
+    __syncthreads();
+    const double xk = d[k];
+    for (int i = t; i < k; i += kSolveThreads) d[i] -= A[(int64_t)k * n + i] * xk;
+    __syncthreads();
+  }
+  if (t == 0) *flag = 0;
+}
+
+__global__ void pg_update_kernel(const double* __restrict__ poses, const double* __restrict__ d,
+                                 int n_nodes, double* __restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_nodes) return;
+  if (k == 0) {
+    for (int q = 0; q < 16; ++q) out[q] = poses[q];
+    return;
+  }
+  exp_left(d + 6 * (k - 1), poses + 16 * k, out + 16 * k);
+}
+
+bool rigid_ok(const double* T) {
+  for (int k = 0; k < 16; ++k)
+    if (!std::isfinite(T[k])) return false;
+  return T[12] == 0.0 && T[13] == 0.0 && T[14] == 0.0 && T[15] == 1.0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int icp_pose_graph_optimize(icp_ctx_t* ctx, int32_t n_nodes, double* poses, int32_t n_edges,
+                            const icp_pose_edge_t* edges, int32_t method, int32_t max_iter,
+                            double rel_tol, icp_pose_graph_result_t* out) {
+  if (n_nodes < 2 || n_nodes > kMaxPgNodes)
+    return fail(ICP_E_INVALID_ARG, "n_nodes must be in [2, " + std::to_string(kMaxPgNodes) + "]");
+  if (!poses || !edges || !out || n_edges < 1) return fail(ICP_E_INVALID_ARG, "NULL pointer or no edges");
+  if (method != ICP_PG_GAUSS_NEWTON && method != ICP_PG_LEVENBERG_MARQUARDT)
+    return fail(ICP_E_INVALID_ARG, "unknown method");
+  if (max_iter < 0 || !(rel_tol >= 0.0) || !std::isfinite(rel_tol))
+    return fail(ICP_E_INVALID_ARG, "max_iter must be >= 0 and rel_tol finite and >= 0");
+  for (int k = 0; k < n_nodes; ++k)
+    if (!rigid_ok(poses + 16 * k)) return fail(ICP_E_INVALID_ARG, "pose " + std::to_string(k) + " is not a finite rigid transform");
+  for (int k = 0; k < n_edges; ++k) {
+    const icp_pose_edge_t& e = edges[k];
+    if (e.i < 0 || e.j < 0 || e.i >= n_nodes || e.j >= n_nodes || e.i == e.j)
+      return fail(ICP_E_INVALID_ARG, "edge " + std::to_string(k) + " has a bad node index");
+    if (!rigid_ok(e.Z)) return fail(ICP_E_INVALID_ARG, "edge " + std::to_string(k) + ": Z is not a finite rigid transform");
+    for (int q = 0; q < 36; ++q)
+      if (!std::isfinite(e.information[q])) return fail(ICP_E_INVALID_ARG, "edge " + std::to_string(k) + ": information not finite");
+  }
+  int rc;
+  icp_ctx* c = nullptr;
+  if ((rc = resolve_ctx(ctx, &c)) != 0) return rc;
+  DeviceGuard dg(c->device);
+  hipStream_t s = c->stream;
+  const int nf = n_nodes - 1, n = 6 * nf, m = n_edges;
+
+  // incidence lists (host): H blocks (diagonal and one per connected pair of
+  // free nodes) and per-node g contributions, each in edge order
+  std::vector<PgBlock> blocks;
+  std::vector<int2> hcontrib, gcontrib;
+  std::vector<int2> node_range(nf);
+  {
+    std::vector<std::vector<int2>> inc(nf);
+    for (int k = 0; k < m; ++k) {
+      if (edges[k].i > 0) inc[edges[k].i - 1].push_back(make_int2(k, -1));
+      if (edges[k].j > 0) inc[edges[k].j - 1].push_back(make_int2(k, +1));
+    }
+    for (int a = 0; a < nf; ++a) {
+      node_range[a] = make_int2((int)gcontrib.size(), (int)inc[a].size());
+      gcontrib.insert(gcontrib.end(), inc[a].begin(), inc[a].end());
+      // diagonal block: sign * sign = +1 for every incident edge
+      PgBlock b{a, a, (int)hcontrib.size(), (int)inc[a].size()};
+      for (const int2& ce : inc[a]) hcontrib.push_back(make_int2(ce.x, +1));
+      blocks.push_back(b);
+    }
+    std::vector<std::pair<std::pair<int, int>, int>> off;  // ((a, b), edge), a < b
+    for (int k = 0; k < m; ++k) {
+      const int a = edges[k].i - 1, b = edges[k].j - 1;
+      if (a < 0 || b < 0) continue;
+      off.push_back({{std::min(a, b), std::max(a, b)}, k});
+    }
+    std::stable_sort(off.begin(), off.end(),
+                     [](const auto& x, const auto& y) { return x.first < y.first; });
+    for (size_t q = 0; q < off.size();) {
+      size_t r = q;
+      PgBlock b{off[q].first.first, off[q].first.second, (int)hcontrib.size(), 0};
+      while (r < off.size() && off[r].first == off[q].first) {
+        hcontrib.push_back(make_int2(off[r].second, -1));  // J_i^T L J_j = -K
+        ++r;
+      }
+      b.count = (int)(r - q);
+      blocks.push_back(b);
+      q = r;
+    }
+  }
+  std::vector<PgEdge> hedges(m);
+  for (int k = 0; k < m; ++k) {
+    hedges[k].i = edges[k].i;
+    hedges[k].j = edges[k].j;
+    for (int q = 0; q < 16; ++q) hedges[k].Z[q] = edges[k].Z[q];
+    for (int q = 0; q < 36; ++q) hedges[k].L[q] = edges[k].information[q];
+  }
+
+  // device layout
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = align256(off);
+    off = o + bytes;
+    return o;
+  };
+  const size_t o_p = take(sizeof(double) * 16 * n_nodes), o_c = take(sizeof(double) * 16 * n_nodes);
+  const size_t o_e = take(sizeof(PgEdge) * m);
+  const size_t o_t = take(sizeof(double) * kTerms * m), o_tc = take(sizeof(double) * kTerms * m);
+  const size_t o_h = take(sizeof(double) * (size_t)n * n), o_a = take(sizeof(double) * (size_t)n * n);
+  const size_t o_g = take(sizeof(double) * n), o_d = take(sizeof(double) * n);
+  const size_t o_b = take(sizeof(PgBlock) * blocks.size());
+  const size_t o_hc = take(sizeof(int2) * std::max<size_t>(hcontrib.size(), 1));
+  const size_t o_gc = take(sizeof(int2) * std::max<size_t>(gcontrib.size(), 1));
+  const size_t o_nr = take(sizeof(int2) * nf);
+  const size_t o_s = take(64);  // F (double), flag (int)
+  const size_t total = align256(off);
+  HIP_TRY(c->pg.ensure(total), "alloc");
+  char* dd = c->pg.as<char>();
+  if ((rc = ensure_host(c, 64)) != 0) return rc;
+  char* hs = static_cast<char*>(c->host);
+  HIP_TRY(hipMemcpyAsync(dd + o_p, poses, sizeof(double) * 16 * n_nodes, hipMemcpyHostToDevice, s), "upload");
+  HIP_TRY(hipMemcpyAsync(dd + o_e, hedges.data(), sizeof(PgEdge) * m, hipMemcpyHostToDevice, s), "upload");
+  HIP_TRY(hipMemcpyAsync(dd + o_b, blocks.data(), sizeof(PgBlock) * blocks.size(), hipMemcpyHostToDevice, s), "upload");
+  if (!hcontrib.empty())
+    HIP_TRY(hipMemcpyAsync(dd + o_hc, hcontrib.data(), sizeof(int2) * hcontrib.size(), hipMemcpyHostToDevice, s), "upload");
+  if (!gcontrib.empty())
+    HIP_TRY(hipMemcpyAsync(dd + o_gc, gcontrib.data(), sizeof(int2) * gcontrib.size(), hipMemcpyHostToDevice, s), "upload");
+  HIP_TRY(hipMemcpyAsync(dd + o_nr, node_range.data(), sizeof(int2) * nf, hipMemcpyHostToDevice, s), "upload");
+
+  double* P = reinterpret_cast<double*>(dd + o_p);
+  double* Cn = reinterpret_cast<double*>(dd + o_c);
+  double* TT = reinterpret_cast<double*>(dd + o_t);
+  double* TC = reinterpret_cast<double*>(dd + o_tc);
+  double* H = reinterpret_cast<double*>(dd + o_h);
+  double* A = reinterpret_cast<double*>(dd + o_a);
+  double* g = reinterpret_cast<double*>(dd + o_g);
+  double* dv = reinterpret_cast<double*>(dd + o_d);
+  double* Fd = reinterpret_cast<double*>(dd + o_s);
+  int* flag = reinterpret_cast<int*>(dd + o_s + 8);
+  const PgEdge* E = reinterpret_cast<const PgEdge*>(dd + o_e);
+  const PgBlock* B = reinterpret_cast<const PgBlock*>(dd + o_b);
+  const int2* HC = reinterpret_cast<const int2*>(dd + o_hc);
+  const int2* GC = reinterpret_cast<const int2*>(dd + o_gc);
+  const int2* NR = reinterpret_cast<const int2*>(dd + o_nr);
+  const unsigned eb = (unsigned)((m + 63) / 64);
+
+  auto terms_and_F = [&](const double* poses_d, double* terms_d) -> int {
+    hipLaunchKernelGGL(pg_edge_kernel, dim3(eb), dim3(64), 0, s, poses_d, E, m, terms_d);
+    hipLaunchKernelGGL(pg_objective_kernel, dim3(1), dim3(256), 0, s, terms_d, m, Fd);
+    HIP_TRY(hipGetLastError(), "pose graph terms");
+    return ICP_SUCCESS;
+  };
+  auto assemble = [&](const double* terms_d) -> int {
+    HIP_TRY(hipMemsetAsync(H, 0, sizeof(double) * (size_t)n * n, s), "memset");
+    hipLaunchKernelGGL(pg_assemble_h_kernel, dim3((unsigned)blocks.size()), dim3(64), 0, s, B, HC, terms_d, H, n);
+    hipLaunchKernelGGL(pg_assemble_g_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, NR, GC, terms_d, g, nf);
+    HIP_TRY(hipGetLastError(), "pose graph assembly");
+    return ICP_SUCCESS;
+  };
+  auto read_scalars = [&](double* F, int* fl) -> int {
+    HIP_TRY(hipMemcpyAsync(hs, dd + o_s, 16, hipMemcpyDeviceToHost, s), "readback");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    *F = *reinterpret_cast<double*>(hs);
+    *fl = *reinterpret_cast<int*>(hs + 8);
+    return ICP_SUCCESS;
+  };
+
+  int fl = 0;
+  double F = 0.0;
+  HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), s), "memset");
+  if ((rc = terms_and_F(P, TT)) != 0) return rc;
+  if ((rc = assemble(TT)) != 0) return rc;
+  if ((rc = read_scalars(&F, &fl)) != 0) return rc;
+  const double F0 = F;
+  const bool lm = method == ICP_PG_LEVENBERG_MARQUARDT;
+  double lambda = 1e-4;
+  int steps = 0, refusals = 0, status = ICP_OK;
+  while (steps < max_iter) {
+    hipLaunchKernelGGL(pg_cholesky_solve_kernel, dim3(1), dim3(kSolveThreads), 0, s, H, A, g, dv, n,
+                       lm ? lambda : 0.0, flag);
+    hipLaunchKernelGGL(pg_update_kernel, dim3((unsigned)((n_nodes + 63) / 64)), dim3(64), 0, s, P, dv,
+                       n_nodes, Cn);
+    HIP_TRY(hipGetLastError(), "pose graph step");
+    if ((rc = terms_and_F(Cn, TC)) != 0) return rc;
+    double Fn = 0.0;
+    if ((rc = read_scalars(&Fn, &fl)) != 0) return rc;
+    if (fl) {
+      status = ICP_DEGENERATE;
+      break;
+    }
+    if (lm && !(Fn < F)) {
+      lambda *= 10.0;
+      if (++refusals >= 10) {
+        status = ICP_CONVERGED;
+        break;
+      }
+      continue;
+    }
+    refusals = 0;
+    if (lm) lambda /= 10.0;
+    ++steps;
+    const bool done = fabs(F - Fn) <= rel_tol * F;
+    std::swap(P, Cn);
+    std::swap(TT, TC);
+    F = Fn;
+    if ((rc = assemble(TT)) != 0) return rc;
+    if (done) {
+      status = ICP_CONVERGED;
+      break;
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(poses, P, sizeof(double) * 16 * n_nodes, hipMemcpyDeviceToHost, s), "readback");
+  HIP_TRY(hipStreamSynchronize(s), "sync");
+  out->F_initial = F0;
+  out->F_final = F;
+  out->steps = steps;
+  out->status = status;
+  return ICP_SUCCESS;
+}
+
+}  // extern "C"

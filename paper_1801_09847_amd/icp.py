@@ -48,6 +48,16 @@ class IcpError(RuntimeError):
         self.code = code
 
 
+class icp_pose_edge_t(C.Structure):
+    _fields_ = [("i", C.c_int32), ("j", C.c_int32), ("Z", C.c_double * 16),
+                ("information", C.c_double * 36)]
+
+
+class icp_pose_graph_result_t(C.Structure):
+    _fields_ = [("F_initial", C.c_double), ("F_final", C.c_double), ("steps", C.c_int32),
+                ("status", C.c_int32)]
+
+
 class icp_result_t(C.Structure):
     _fields_ = [("T", C.c_double * 16), ("fitness", C.c_double), ("inlier_rmse", C.c_double),
                 ("n_inliers", C.c_int64), ("n_iter", C.c_int32), ("status", C.c_int32)]
@@ -120,6 +130,8 @@ def lib():
         L.icp_register_multiscale.argtypes = [vp, vp, i64, vp, vp, i64, vp, i32, vp, vp, vp, dbl, i32,
                                               i32, C.POINTER(icp_result_t)]
         L.icp_estimate_normals.argtypes = [vp, vp, i64, dbl, i32, vp, vp, vp]
+        L.icp_pose_graph_optimize.argtypes = [vp, i32, vp, i32, C.POINTER(icp_pose_edge_t), i32, i32,
+                                              dbl, C.POINTER(icp_pose_graph_result_t)]
         L.icp_server_create.argtypes = [C.POINTER(icp_server_cfg_t), C.POINTER(vp)]
         L.icp_server_submit.argtypes = [vp, C.POINTER(icp_request_t), C.POINTER(C.c_uint64)]
         L.icp_server_step.argtypes = [vp, C.POINTER(C.c_int32)]
@@ -132,6 +144,7 @@ def lib():
                      "icp_normal_equations", "icp_ctx_set_profiling", "icp_ctx_get_profile",
                      "icp_register_batch", "icp_voxel_downsample", "icp_register_multiscale",
                      "icp_estimate_normals", "icp_register_robust", "icp_normal_equations_robust",
+                     "icp_pose_graph_optimize",
                      "icp_server_create", "icp_server_submit", "icp_server_step", "icp_server_poll",
                      "icp_server_wait", "icp_server_destroy"):
             getattr(L, name).restype = C.c_int
@@ -351,6 +364,28 @@ def estimate_normals(pts, radius, max_nn=30, viewpoint=(0.0, 0.0, 0.0), ctx: Con
     icp_estimate_normals(ctx.handle if ctx else None, pp, n, radius, max_nn, viewpoint, out.data_ptr(),
                          cnt.data_ptr() if cnt is not None else None)
     return (out, cnt) if with_counts else out
+
+
+PG_METHODS = {"gn": 0, "lm": 1, 0: 0, 1: 1}
+
+
+def pose_graph_optimize(poses, edges, method="lm", max_iter=50, rel_tol=1e-10,
+                        ctx: Context | None = None):
+    """Multiway registration: optimise node poses (array (N, 4, 4), node 0
+    fixed) over edges (i, j, Z ~ T_i^-1 T_j, 6x6 information).  Returns the
+    new poses and a dict (F_initial, F_final, steps, status)."""
+    P = np.ascontiguousarray(np.asarray(poses, np.float64).reshape(-1, 16)).copy()
+    arr = (icp_pose_edge_t * len(edges))()
+    for k, (i, j, Z, L) in enumerate(edges):
+        arr[k].i, arr[k].j = int(i), int(j)
+        arr[k].Z[:] = list(np.asarray(Z, np.float64).reshape(16))
+        arr[k].information[:] = list(np.asarray(L, np.float64).reshape(36))
+    out = icp_pose_graph_result_t()
+    _check(lib().icp_pose_graph_optimize(ctx.handle if ctx else None, len(P), P.ctypes.data, len(edges),
+                                         arr, int(PG_METHODS.get(method, method)), int(max_iter), float(rel_tol),
+                                         C.byref(out)))
+    return P.reshape(-1, 4, 4), {"F_initial": out.F_initial, "F_final": out.F_final,
+                                 "steps": out.steps, "status": out.status}
 
 
 def register_multiscale(src, tgt, tgt_normals, T_init, voxels, iters, dists, rel_tol=0.0,

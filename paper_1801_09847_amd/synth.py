@@ -427,3 +427,49 @@ def poisson_arrivals(n: int, rate: float, seed: int = 0) -> np.ndarray:
     """Arrival times (s) of a Poisson process of ``rate`` requests/s."""
     rng = _rng(seed, "arrivals")
     return np.cumsum(rng.exponential(1.0 / rate, n))
+
+
+def pose_graph(seed: int, n: int, closures: int, noise_deg: float = 0.5, noise_m: float = 0.02,
+               init_deg: float = 5.0, init_m: float = 0.2) -> dict:
+    """A pose graph like the fragment graph of a scene reconstruction: n
+    fragment poses along a closed loop (radius ~ n / (2 pi) * 0.5 m), an
+    odometry edge between consecutive fragments, the loop-closing edge, and
+    `closures` extra edges between random pairs.  Measurements are the true
+    relative poses times a random rotation (axis uniform, angle N(0, noise_deg))
+    and translation (N(0, noise_m) per axis); information matrices are random
+    symmetric positive definite.  Initial poses are the truth perturbed the same
+    way with init_deg / init_m, node 0 exact.  Rotations come from
+    scipy.spatial.transform.Rotation (rotation vectors)."""
+    from scipy.spatial.transform import Rotation
+    rng = _rng(seed, "pose-graph")
+
+    def rigid(rotvec, t):
+        T = np.eye(4)
+        T[:3, :3] = Rotation.from_rotvec(rotvec).as_matrix()
+        T[:3, 3] = t
+        return T
+
+    def noise(deg, m):
+        ax = unit_vector(rng)
+        return rigid(ax * math.radians(rng.normal(0.0, deg)), rng.normal(0.0, m, 3))
+
+    gt = [np.eye(4)]
+    for k in range(1, n):
+        step = rigid(np.array([0.0, 0.0, 2 * math.pi / n]) + rng.normal(0.0, 0.02, 3),
+                     np.array([0.5, 0.0, 0.0]) + rng.normal(0.0, 0.02, 3))
+        gt.append(gt[-1] @ step)
+    pairs = [(k, k + 1) for k in range(n - 1)] + [(n - 1, 0)]
+    seen = set(pairs)
+    while len(pairs) < n + closures:
+        i, j = (int(x) for x in sorted(rng.choice(n, 2, replace=False)))
+        if (i, j) not in seen:
+            seen.add((i, j))
+            pairs.append((i, j))
+    edges = []
+    for i, j in pairs:
+        Z = np.linalg.inv(gt[i]) @ gt[j] @ noise(noise_deg, noise_m)
+        Q, _ = np.linalg.qr(rng.normal(size=(6, 6)))
+        L = Q @ np.diag(rng.uniform(0.5, 5.0, 6)) @ Q.T
+        edges.append((i, j, Z, 0.5 * (L + L.T)))
+    init = [gt[0]] + [noise(init_deg, init_m) @ T for T in gt[1:]]
+    return {"gt": np.array(gt), "init": np.array(init), "edges": edges}

@@ -160,3 +160,21 @@ def test_server_create_validation():
             cfg.voxel[0] = 0.0
         assert L.icp_server_create(C.byref(cfg), C.byref(h)) == icp.ICP_E_INVALID_ARG, field
     assert L.icp_server_destroy(None) == 0
+
+
+def test_pose_graph_validation():
+    eye = np.eye(4)
+    good = [(0, 1, eye, np.eye(6))]
+    for poses, edges, kw in (
+        (np.array([eye]), good, {}),                               # one node
+        (np.array([eye] * 257), good, {}),                         # too many nodes
+        (np.array([eye, eye]), [(0, 2, eye, np.eye(6))], {}),      # bad index
+        (np.array([eye, eye]), [(1, 1, eye, np.eye(6))], {}),      # self edge
+        (np.array([eye, eye]), [(0, 1, eye * 2, np.eye(6))], {}),  # not rigid
+        (np.array([eye, eye]), [(0, 1, eye, np.full((6, 6), np.nan))], {}),
+        (np.array([eye, eye]), good, {"method": 7}),
+        (np.array([eye, eye]), good, {"max_iter": -1}),
+    ):
+        with pytest.raises(icp.IcpError) as e:
+            icp.pose_graph_optimize(poses, edges, **kw)
+        assert e.value.code == icp.ICP_E_INVALID_ARG

@@ -12,7 +12,7 @@ per second of wall time), the dominant kernel's roofline figures (algorithmic
 bytes per launch over its event-timed average duration) and the CPU oracle
 timed on a bounded sample of the same workload; then the robust-loss
 variants of the same registration and (default workload) the
-normal-estimation, 256-pair batched and served sections.
+normal-estimation, pose-graph, 256-pair batched and served sections.
 
   python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1] [--variant ...]
 """
@@ -119,6 +119,39 @@ def robust_section(args, icp, np, torch, s, t, n, data, K, r, steps=3):
                     "result": {"fitness": res[-1].fitness, "inlier_rmse": res[-1].inlier_rmse,
                                "n_iter": res[-1].n_iter, "status": res[-1].status}})
         print(f"bench: robust {loss}: {evals / dt:.3e} corr-evals/s", file=sys.stderr, flush=True)
+    return out
+
+
+def pose_graph_section(args, icp, synth, np, torch):
+    """Multiway registration: LM pose-graph optimisation of synthetic fragment
+    graphs (a loop of n fragments with odometry edges and n random closures),
+    GPU against the numpy oracle on the same graph."""
+    out = []
+    ctx = icp.Context(0)
+    for n in (64, 256):
+        d = synth.pose_graph(7, n, n)
+        icp.pose_graph_optimize(d["init"], d["edges"], "lm", 100, 1e-12, ctx=ctx)
+        torch.cuda.synchronize()
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            _, res = icp.pose_graph_optimize(d["init"], d["edges"], "lm", 100, 1e-12, ctx=ctx)
+        dt = (time.perf_counter() - t0) / reps
+        entry = {"workload": f"pose graph: {n} fragments on a loop, {len(d['edges'])} edges "
+                             "(odometry, loop closure, random closures), LM",
+                 "nodes": n, "edges": len(d["edges"]), "ms_per_optimisation": dt * 1e3,
+                 "steps": res["steps"], "status": res["status"],
+                 "F_initial": res["F_initial"], "F_final": res["F_final"]}
+        if not args.no_cpu_baseline:
+            from oracle import posegraph as opg
+            t1 = time.perf_counter()
+            _, _, F, steps, _ = opg.optimize(list(d["init"]), d["edges"], "lm", 100, 1e-12)
+            entry["cpu_baseline"] = {"value": (time.perf_counter() - t1) * 1e3, "unit": "ms",
+                                     "cores": 1, "kind": "oracle",
+                                     "sample": f"the same graph, numpy float64, {steps} steps"}
+        out.append(entry)
+        print(f"bench: pose graph n={n}: {dt * 1e3:.1f} ms ({res['steps']} steps)", file=sys.stderr,
+              flush=True)
     return out
 
 
@@ -376,6 +409,7 @@ def main():
     ap.add_argument("--no-served", action="store_true", help="skip the served (request server) section")
     ap.add_argument("--no-normals", action="store_true", help="skip the normal-estimation section")
     ap.add_argument("--no-robust", action="store_true", help="skip the robust-loss section")
+    ap.add_argument("--no-pose-graph", action="store_true", help="skip the pose-graph section")
     ap.add_argument("--served-requests", type=int, default=400)
     ap.add_argument("--served-pool", type=int, default=64)
     ap.add_argument("--served-rates", type=float, nargs="+", default=[1.0, 8.0])
@@ -491,6 +525,8 @@ def main():
     del s, t, n
     if not args.no_normals and args.workload == "c3":
         out["normals"] = normals_section(args, icp, synth, np, torch, data)
+    if not args.no_pose_graph and args.workload == "c3":
+        out["pose_graph"] = pose_graph_section(args, icp, synth, np, torch)
     if not args.no_batched:
         out["batched"] = batched_section(args, icp, synth, np, torch)
     if not args.no_served:

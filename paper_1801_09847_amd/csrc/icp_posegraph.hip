@@ -12,14 +12,18 @@
 // Per iteration: one thread per edge forms K = J^T L J, u = J^T L e and
 // f = e^T L e in float64; the dense normal equations over the free nodes are
 // assembled block by block from host-built incidence lists (fixed order, no
-// atomics); F is a fixed-order reduction; one workgroup factorises H (plus the
-// Levenberg-Marquardt damping) by Cholesky and solves for the step; one thread
-// per node applies it.  The host keeps or refuses the step from F alone.
+// atomics); F is a fixed-order reduction; the damped system is factorised and
+// solved by rocSOLVER's dense Cholesky (dpotrf / dpotrs, a plain library
+// factorisation) on the context's stream, with the pivot rule checked on the
+// factor; one thread per node applies the step.  The host keeps or refuses the
+// step from F alone.
 
 #include <math.h>
 
 #include <algorithm>
 #include <vector>
+
+#include <rocsolver/rocsolver.h>
 
 #include "icp_runtime.h"
 
@@ -31,7 +35,6 @@ using namespace icp_rt;
 namespace {
 
 constexpr int kTerms = 43;       // K (36), u (6), f
-constexpr int kSolveThreads = 1024;
 constexpr int kMaxPgNodes = 256;
 
 struct PgEdge {
@@ -240,69 +243,49 @@ __global__ __launch_bounds__(256) void pg_objective_kernel(const double* __restr
   if (threadIdx.x == 0) *F = sh[0];
 }
 
-// One workgroup: A = H with the diagonal scaled by (1 + lambda), Cholesky
-// A = L L^T in place (right-looking, lower triangle), then L y = -g and
-// L^T d = y.  A pivot <= 1e-12 * max(diag A) sets *flag and stops.
-__global__ __launch_bounds__(kSolveThreads) void pg_cholesky_solve_kernel(
-    const double* __restrict__ H, double* __restrict__ A, const double* __restrict__ g,
-    double* __restrict__ d, int n, double lambda, int* __restrict__ flag) {
-  __shared__ double sdiag;
-  __shared__ int sbad;
-  const int t = threadIdx.x;
-  for (int q = t; q < n * n; q += kSolveThreads) {  // n * n < 2^31 for n <= 6 * 255
-    const int r = q / n, c = q - r * n;
-    A[q] = r == c ? H[q] * (1.0 + lambda) : H[q];
-  }
-  for (int r = t; r < n; r += kSolveThreads) d[r] = -g[r];
+// A = H with the diagonal scaled by (1 + lambda), d = -g.
+__global__ void pg_damp_kernel(const double* __restrict__ H, double* __restrict__ A,
+                               const double* __restrict__ g, double* __restrict__ d, int n,
+                               double lambda) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;  // n * n < 2^31 for n <= 6 * 255
+  if (q >= n * n) return;
+  const int r = q / n, c = q - r * n;
+  A[q] = r == c ? H[q] * (1.0 + lambda) : H[q];
+  if (q < n) d[q] = -g[q];
+}
+
+// Largest diagonal entry of the damped A (before the factorisation).
+__global__ __launch_bounds__(256) void pg_diag_max_kernel(const double* __restrict__ A, int n,
+                                                          double* __restrict__ dmax) {
+  __shared__ double sh[256];
+  double m = 0.0;
+  for (int r = threadIdx.x; r < n; r += 256) m = fmax(m, A[(int64_t)r * n + r]);
+  sh[threadIdx.x] = m;
   __syncthreads();
-  if (t == 0) {
-    double mx = 0.0;
-    for (int r = 0; r < n; ++r) mx = fmax(mx, A[(int64_t)r * n + r]);
-    sdiag = mx;
-    sbad = 0;
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
   }
+  if (threadIdx.x == 0) *dmax = sh[0];
+}
+
+// Pivot rule on the factor: failed factorisation, or some L_kk^2 <= 1e-12 max diag.
+__global__ __launch_bounds__(256) void pg_pivot_check_kernel(const double* __restrict__ L, int n,
+                                                             const double* __restrict__ dmax,
+                                                             const rocblas_int* __restrict__ info,
+                                                             int* __restrict__ flag) {
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = *info != 0 ? 1 : 0;
   __syncthreads();
-  const double thr = 1e-12 * sdiag;
-  for (int k = 0; k < n; ++k) {
-    if (t == 0) {
-      const double p = A[(int64_t)k * n + k];
-      if (!(p > thr)) sbad = 1;
-      A[(int64_t)k * n + k] = sqrt(fmax(p, 0.0));
-    }
-    __syncthreads();
-    if (sbad) break;
-    const double lkk = A[(int64_t)k * n + k];
-    for (int i = k + 1 + t; i < n; i += kSolveThreads) A[(int64_t)i * n + k] /= lkk;
-    __syncthreads();
-    const int mrem = n - k - 1;
-    for (int q = t; q < mrem * mrem; q += kSolveThreads) {
-      const int i = q / mrem, j = q - i * mrem;
-      if (j > i) continue;
-      const int64_t ii = k + 1 + i, jj = k + 1 + j;
-      A[ii * n + jj] -= A[ii * n + k] * A[jj * n + k];
-    }
-    __syncthreads();
+  const double thr = 1e-12 * *dmax;
+  int mine = 0;
+  for (int r = threadIdx.x; r < n; r += 256) {
+    const double l = L[(int64_t)r * n + r];
+    if (!(l * l > thr)) mine = 1;
   }
-  if (sbad) {
-    if (t == 0) *flag = 1;
-    return;
-  }
-  // forward: L y = -g (column oriented), then back: L^T d = y
-  for (int k = 0; k < n; ++k) {
-    if (t == 0) d[k] /= A[(int64_t)k * n + k];
-    __syncthreads();
-    const double yk = d[k];
-    for (int i = k + 1 + t; i < n; i += kSolveThreads) d[i] -= A[(int64_t)i * n + k] * yk;
-    __syncthreads();
-  }
-  for (int k = n - 1; k >= 0; --k) {
-    if (t == 0) d[k] /= A[(int64_t)k * n + k];
-    __syncthreads();
-    const double xk = d[k];
-    for (int i = t; i < k; i += kSolveThreads) d[i] -= A[(int64_t)k * n + i] * xk;
-    __syncthreads();
-  }
-  if (t == 0) *flag = 0;
+  if (mine) atomicOr(&bad, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) *flag = bad;
 }
 
 __global__ void pg_update_kernel(const double* __restrict__ poses, const double* __restrict__ d,
@@ -323,6 +306,13 @@ bool rigid_ok(const double* T) {
 }
 
 }  // namespace
+
+namespace icp_rt {
+void pg_release(icp_ctx* c) {
+  if (c->solver) (void)rocblas_destroy_handle(static_cast<rocblas_handle>(c->solver));
+  c->solver = nullptr;
+}
+}  // namespace icp_rt
 
 extern "C" {
 
@@ -416,7 +406,7 @@ int icp_pose_graph_optimize(icp_ctx_t* ctx, int32_t n_nodes, double* poses, int3
   const size_t o_hc = take(sizeof(int2) * std::max<size_t>(hcontrib.size(), 1));
   const size_t o_gc = take(sizeof(int2) * std::max<size_t>(gcontrib.size(), 1));
   const size_t o_nr = take(sizeof(int2) * nf);
-  const size_t o_s = take(64);  // F (double), flag (int)
+  const size_t o_s = take(64);  // F (double), flag (int), max diag (double), info (int)
   const size_t total = align256(off);
   HIP_TRY(c->pg.ensure(total), "alloc");
   char* dd = c->pg.as<char>();
@@ -441,6 +431,17 @@ int icp_pose_graph_optimize(icp_ctx_t* ctx, int32_t n_nodes, double* poses, int3
   double* dv = reinterpret_cast<double*>(dd + o_d);
   double* Fd = reinterpret_cast<double*>(dd + o_s);
   int* flag = reinterpret_cast<int*>(dd + o_s + 8);
+  double* dmax = reinterpret_cast<double*>(dd + o_s + 16);
+  rocblas_int* info = reinterpret_cast<rocblas_int*>(dd + o_s + 24);
+  if (!c->solver) {
+    rocblas_handle h = nullptr;
+    if (rocblas_create_handle(&h) != rocblas_status_success)
+      return fail(ICP_E_DEVICE, "rocblas_create_handle failed");
+    c->solver = h;
+  }
+  rocblas_handle rb = static_cast<rocblas_handle>(c->solver);
+  if (rocblas_set_stream(rb, s) != rocblas_status_success)
+    return fail(ICP_E_DEVICE, "rocblas_set_stream failed");
   const PgEdge* E = reinterpret_cast<const PgEdge*>(dd + o_e);
   const PgBlock* B = reinterpret_cast<const PgBlock*>(dd + o_b);
   const int2* HC = reinterpret_cast<const int2*>(dd + o_hc);
@@ -480,8 +481,15 @@ int icp_pose_graph_optimize(icp_ctx_t* ctx, int32_t n_nodes, double* poses, int3
   double lambda = 1e-4;
   int steps = 0, refusals = 0, status = ICP_OK;
   while (steps < max_iter) {
-    hipLaunchKernelGGL(pg_cholesky_solve_kernel, dim3(1), dim3(kSolveThreads), 0, s, H, A, g, dv, n,
-                       lm ? lambda : 0.0, flag);
+    hipLaunchKernelGGL(pg_damp_kernel, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, s, H, A, g,
+                       dv, n, lm ? lambda : 0.0);
+    hipLaunchKernelGGL(pg_diag_max_kernel, dim3(1), dim3(256), 0, s, A, n, dmax);
+    // A is symmetric: its row-major storage is also its column-major one
+    if (rocsolver_dpotrf(rb, rocblas_fill_lower, n, A, n, info) != rocblas_status_success)
+      return fail(ICP_E_DEVICE, "rocsolver_dpotrf failed");
+    hipLaunchKernelGGL(pg_pivot_check_kernel, dim3(1), dim3(256), 0, s, A, n, dmax, info, flag);
+    if (rocsolver_dpotrs(rb, rocblas_fill_lower, n, 1, A, n, dv, n) != rocblas_status_success)
+      return fail(ICP_E_DEVICE, "rocsolver_dpotrs failed");
     hipLaunchKernelGGL(pg_update_kernel, dim3((unsigned)((n_nodes + 63) / 64)), dim3(64), 0, s, P, dv,
                        n_nodes, Cn);
     HIP_TRY(hipGetLastError(), "pose graph step");

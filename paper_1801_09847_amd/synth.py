@@ -473,3 +473,44 @@ def pose_graph(seed: int, n: int, closures: int, noise_deg: float = 0.5, noise_m
         edges.append((i, j, Z, 0.5 * (L + L.T)))
     init = [gt[0]] + [noise(init_deg, init_m) @ T for T in gt[1:]]
     return {"gt": np.array(gt), "init": np.array(init), "edges": edges}
+
+
+def fpfh_like_features(rng: np.random.Generator, n: int, dim: int = 33, alpha: float = 0.6) -> np.ndarray:
+    """Random descriptors shaped like FPFH: dim / 11 sub-histograms of 11 bins,
+    each a Dirichlet(alpha) draw scaled to sum to 100."""
+    assert dim % 11 == 0
+    parts = [100.0 * rng.dirichlet(np.full(11, alpha), size=n) for _ in range(dim // 11)]
+    return np.concatenate(parts, axis=1) if n else np.zeros((0, dim))
+
+
+def ransac_pair(seed: int = 0, n_tgt: int = 20_000, n_src: int = 20_000, dim: int = 33,
+                match_frac: float = 0.3, feat_noise: float = 1.0, W: float = 4.0, D: float = 3.0,
+                H: float = 2.5, n_box: int = 10, n_sph: int = 5, overlap: float = 0.7,
+                max_deg: float = 60.0, max_trans: float = 1.0) -> dict:
+    """Input of feature-based global registration: a downsampled room pair
+    (``room_pair_random``: uniform samples by area, ~5 cm spacing at the
+    default sizes) moved by a large rigid motion, with FPFH-shaped features.
+    Target features are random (``fpfh_like_features``).  A source point whose
+    true counterpart (the nearest target point to its true position, if within
+    5 cm) exists receives that counterpart's feature plus N(0, feat_noise^2)
+    noise (clipped at 0) with probability ``match_frac``, else a fresh random
+    feature, so its nearest feature is a random target point.  The true
+    counterparts come from ``scipy.spatial.cKDTree``.
+
+    Keys: src, tgt, tgt_normals (float32 (N, 3)), src_feat, tgt_feat (float32
+    (N, dim)), T_gt, G, true_match (int64, -1 where the feature is random),
+    meta."""
+    from scipy.spatial import cKDTree
+    d = room_pair_random(seed, n_tgt, n_src, W, D, H, n_box, n_sph, overlap=overlap,
+                         max_deg=max_deg, max_trans=max_trans)
+    rf = _rng(seed, "features")
+    ft = fpfh_like_features(rf, len(d["tgt"]), dim)
+    home = apply(d["T_gt"], d["src"].astype(np.float64))
+    dist, j = cKDTree(d["tgt"].astype(np.float64)).query(home)
+    good = (dist < 0.05) & (rf.random(len(home)) < match_frac)
+    fs = fpfh_like_features(rf, len(home), dim)
+    noisy = ft[j] + rf.normal(0.0, feat_noise, (len(home), dim))
+    fs[good] = np.maximum(noisy[good], 0.0)
+    d.update(src_feat=_f32(fs), tgt_feat=_f32(ft), true_match=np.where(good, j, -1).astype(np.int64))
+    d["meta"].update(kind="ransac-room", dim=dim, match_frac=match_frac, feat_noise=feat_noise)
+    return d

@@ -319,6 +319,100 @@ int icp_pose_graph_optimize(icp_ctx_t *ctx, int32_t n_nodes, double *poses, int3
                             const icp_pose_edge_t *edges, int32_t method, int32_t max_iter,
                             double rel_tol, icp_pose_graph_result_t *out);
 
+/* ---- global registration: RANSAC on feature matches ---------------------
+ * The global step of the pairwise workflow (Sec. 3.3, the RANSAC-based
+ * registration on feature matches [17] that supplies ICP's initial pose, with
+ * the point-to-point estimate, the edge-length and distance correspondence
+ * checkers and the (max_iteration, max_validation) criterion; validating a
+ * hypothesis dominates its cost).  Definitions:
+ *   feature match  c(i) = argmin_j (D_ij, j), D_ij the float32 squared
+ *                  feature distance summed over the dimensions in index
+ *                  order without FMA (ties: smallest j);
+ *   hypothesis h   ransac_n source indices from Philox4x64-10 (Salmon et al.,
+ *                  SC'11), block b = Philox(counter (h, b, 0, 0), key (seed,
+ *                  0)), draw k = word k % 4 of block k / 4 mapped to [0, n_src)
+ *                  by ((z >> 32) * n_src) >> 32; the pairs (i, corr[i]);
+ *                  rejected if an index repeats or corr[i] is outside
+ *                  [0, n_tgt);
+ *   edge length    for every two pairs a, b: ds2 >= sigma^2 dt2 and
+ *                  dt2 >= sigma^2 ds2 (squared lengths in float64);
+ *   fit            the rigid transform (no scale) minimising the sampled
+ *                  pairs' squared distances;
+ *   distance       every sampled pair within d under the fit (float64);
+ *   validation     every source point matched to its nearest target point
+ *                  under T by the same rule as icp_correspondences; score
+ *                  (count, sumq), sumq = sum over inliers of
+ *                  floor(d2 * 2^shift), shift = 40 - e with
+ *                  fl32(max_corr_dist^2) = m 2^e, m in [0.5, 1): an exact
+ *                  integer;
+ *   selection      the first max_validation hypotheses (in h order) that
+ *                  pass both checkers are validated; the loop ends there or
+ *                  after max_iteration hypotheses; the best is the
+ *                  lexicographic minimum of (-count, sumq, h). */
+#define ICP_RANSAC_NO_HYPOTHESIS 3  /* no hypothesis passed the checkers; T = identity */
+
+typedef struct {
+  double max_corr_dist;    /* validation radius r > 0 */
+  double edge_length;      /* edge-length similarity sigma (paper: 0.9); <= 0: checker off */
+  double distance;         /* distance checker threshold d (paper: = r); <= 0: checker off */
+  int64_t max_iteration;   /* >= 1 hypotheses at most */
+  int32_t max_validation;  /* 1 .. 65535 validated hypotheses at most */
+  int32_t ransac_n;        /* 3 .. 8 pairs per hypothesis */
+  uint64_t seed;           /* Philox key word 0 */
+} icp_ransac_params_t;
+
+typedef struct {
+  double T[16];             /* row-major transform of the best hypothesis (source -> target) */
+  double fitness;           /* n_inliers / n_src */
+  double inlier_rmse;       /* sqrt(sumq 2^-shift / n_inliers) */
+  int64_t n_inliers;
+  uint64_t sumq;            /* the best score's fixed-point sum */
+  int32_t shift;
+  int32_t status;           /* ICP_OK or ICP_RANSAC_NO_HYPOTHESIS */
+  int64_t n_iterations;     /* hypotheses consumed: (h of the max_validation-th validated) + 1, else max_iteration */
+  int64_t n_validated;
+  int64_t best_hypothesis;  /* h of the best, -1 if none */
+} icp_ransac_result_t;
+
+/* Optional per-hypothesis outputs of icp_ransac_register: device arrays with
+ * room for max_validation entries (any may be NULL), in validation order. */
+typedef struct {
+  int64_t *h;       /* hypothesis indices */
+  double *T;        /* (16) row-major transforms */
+  int64_t *count;   /* inlier counts */
+  uint64_t *sumq;   /* fixed-point sums */
+} icp_ransac_trace_t;
+
+/* Nearest-feature matching (row-major float32 features, device memory).
+ *   src_feat  (n_src, dim), tgt_feat (n_tgt, dim); n_src, n_tgt >= 0;
+ *             dim 1 .. 64; features must be finite (not checked)
+ *   match_out device (n_src) int32: c(i), -1 if n_tgt = 0
+ *   dist_out  device (n_src) float32 D_i(c(i)), or NULL
+ * Synchronous.  Errors: INVALID_ARG, TOO_LARGE, OOM, DEVICE. */
+int icp_feature_match(icp_ctx_t *ctx, const float *src_feat, int64_t n_src, const float *tgt_feat,
+                      int64_t n_tgt, int32_t dim, int32_t *match_out, float *dist_out);
+
+/* Scores n_hyp given transforms (the validation step).
+ *   src_xyz, tgt_xyz  device (n, 3) float32; 1 <= n_src <= 2^23
+ *   T                 host (n_hyp, 16) rigid transforms, n_hyp 1 .. 65535
+ *   count_out, sumq_out  host (n_hyp)
+ * Synchronous.  Errors: INVALID_ARG, NONFINITE, TOO_LARGE, OOM, DEVICE. */
+int icp_ransac_validate(icp_ctx_t *ctx, const float *src_xyz, int64_t n_src, const float *tgt_xyz,
+                        int64_t n_tgt, double max_corr_dist, int32_t n_hyp, const double *T,
+                        int64_t *count_out, uint64_t *sumq_out);
+
+/* RANSAC registration of src onto tgt from putative pairs (i, corr[i]).
+ *   src_xyz, tgt_xyz  device (n, 3) float32 in original order; n_src <= 2^23
+ *   corr              device (n_src) int32 target index per source point
+ *                     (e.g. icp_feature_match's output; values outside
+ *                     [0, n_tgt) mark a point without a match)
+ *   prm, out          host; trace: optional device outputs, or NULL
+ * Synchronous (one readback per chunk of hypotheses).  Errors: INVALID_ARG,
+ * NONFINITE, TOO_LARGE, OOM, DEVICE. */
+int icp_ransac_register(icp_ctx_t *ctx, const float *src_xyz, int64_t n_src, const float *tgt_xyz,
+                        int64_t n_tgt, const int32_t *corr, const icp_ransac_params_t *prm,
+                        icp_ransac_result_t *out, const icp_ransac_trace_t *trace);
+
 /* ---- served form: continuous batching of registration requests ----------
  * Requests (pairs of clouds, as produced one by one by a reconstruction
  * pipeline's fragment registration stage, Sec. 3.4) are submitted at any
@@ -419,6 +513,9 @@ typedef struct {
   int64_t pass_points;     /* sum of n_src over counted launches */
   double call_ms;          /* summed duration from first to last launch of each call */
   int64_t calls;
+  double validate_ms;        /* RANSAC validation launches (pass and per-hypothesis sum) */
+  int64_t validate_launches;
+  int64_t validate_evals;    /* hypotheses x source points scored */
 } icp_profile_t;
 
 /* Enables (1) or disables (0) kernel timing on ctx; resets the counters.

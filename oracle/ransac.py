@@ -207,6 +207,47 @@ def validate(src, tgt, T, max_corr_dist, search=0):
     return int(m.sum()), int(q.sum(dtype=np.uint64))
 
 
+def hypotheses(src, tgt, corr, ransac_n=4, edge_sim=0.9, dist=0.075, max_iteration=100_000,
+               max_validation=500, seed=0, chunk=8192):
+    """The first max_validation hypotheses (in h order) that pass both
+    checkers: (h list, (k, 4, 4) transforms, n_iterations, smallest relative
+    margin of the distance checker's decisions)."""
+    src = np.ascontiguousarray(src, np.float32)
+    tgt = np.ascontiguousarray(tgt, np.float32)
+    corr = np.asarray(corr, np.int64)
+    n_src = len(src)
+    d2 = float(dist) * float(dist)
+    hs_out, Ts_out = [], []
+    margin = np.inf
+    h0 = 0
+    while h0 < max_iteration and len(hs_out) < max_validation and n_src > 0:
+        hs = np.arange(h0, min(h0 + chunk, max_iteration), dtype=np.int64)
+        I = sample_indices(seed, hs, ransac_n, n_src)
+        ok = np.ones(len(hs), bool)
+        srt = np.sort(I, axis=1)
+        ok &= np.all(srt[:, 1:] != srt[:, :-1], axis=1)
+        C = corr[I]
+        ok &= np.all(C >= 0, axis=1)
+        S, P = src[I], tgt[np.where(C >= 0, C, 0)]
+        ok &= edge_length_ok(S, P, edge_sim)
+        cand = np.nonzero(ok)[0]
+        Ts = rigid_fit(S[cand], P[cand]) if len(cand) else np.zeros((0, 4, 4))
+        if dist > 0 and len(cand):
+            e2 = distance_residuals(Ts, S[cand], P[cand])
+            margin = min(margin, float(np.min(np.abs(e2 - d2) / d2)))
+            keep = np.all(e2 <= d2, axis=1)
+        else:
+            keep = np.ones(len(cand), bool)
+        for c, T in zip(cand[keep], Ts[keep]):
+            hs_out.append(int(hs[c]))
+            Ts_out.append(T)
+            if len(hs_out) == max_validation:
+                break
+        h0 += len(hs)
+    n_iter = hs_out[-1] + 1 if len(hs_out) == max_validation else (max_iteration if n_src > 0 else 0)
+    return np.array(hs_out, np.int64), np.array(Ts_out).reshape(-1, 4, 4), n_iter, margin
+
+
 def ransac(src, tgt, corr, max_corr_dist, ransac_n=4, edge_sim=0.9, dist=None,
            max_iteration=100_000, max_validation=500, seed=0, chunk=8192):
     """RANSAC on putative correspondences corr (source i -> target corr[i]).
@@ -216,62 +257,27 @@ def ransac(src, tgt, corr, max_corr_dist, ransac_n=4, edge_sim=0.9, dist=None,
     validated hypotheses (h, T, count, sumq) in order, plus the smallest
     relative margin of the distance checker's decisions (for judging how
     close a comparison with another implementation's fit may come)."""
-    src = np.ascontiguousarray(src, np.float32)
-    tgt = np.ascontiguousarray(tgt, np.float32)
-    corr = np.asarray(corr, np.int64)
-    n_src = len(src)
     d = max_corr_dist if dist is None else dist
-    d2 = float(d) * float(d)
-    trace_h, trace_T, trace_c, trace_q = [], [], [], []
+    hs, Ts, n_iter, margin = hypotheses(src, tgt, corr, ransac_n, edge_sim, d, max_iteration,
+                                        max_validation, seed, chunk)
+    counts, sums = [], []
     best = None
-    n_iter = max_iteration
-    margin = np.inf
-    h0 = 0
-    done = False
-    while h0 < max_iteration and not done and n_src > 0:
-        hs = np.arange(h0, min(h0 + chunk, max_iteration), dtype=np.int64)
-        I = sample_indices(seed, hs, ransac_n, n_src)
-        ok = np.ones(len(hs), bool)
-        srt = np.sort(I, axis=1)
-        ok &= np.all(srt[:, 1:] != srt[:, :-1], axis=1)
-        C = corr[I]
-        ok &= np.all(C >= 0, axis=1)
-        Cc = np.where(C >= 0, C, 0)
-        S, P = src[I], tgt[Cc]
-        ok &= edge_length_ok(S, P, edge_sim)
-        cand = np.nonzero(ok)[0]
-        Ts = rigid_fit(S[cand], P[cand]) if len(cand) else np.zeros((0, 4, 4))
-        if d > 0 and len(cand):
-            e2 = distance_residuals(Ts, S[cand], P[cand])
-            margin = min(margin, float(np.min(np.abs(e2 - d2) / d2)))
-            keep = np.all(e2 <= d2, axis=1)
-        else:
-            keep = np.ones(len(cand), bool)
-        for c, T in zip(cand[keep], Ts[keep]):
-            h = int(hs[c])
-            cnt, sq = validate(src, tgt, T, max_corr_dist)
-            trace_h.append(h)
-            trace_T.append(T)
-            trace_c.append(cnt)
-            trace_q.append(sq)
-            key = (-cnt, sq, h)
-            if best is None or key < best[0]:
-                best = (key, T)
-            if len(trace_h) == max_validation:
-                n_iter = h + 1
-                done = True
-                break
-        h0 += len(hs)
+    for h, T in zip(hs, Ts):
+        cnt, sq = validate(src, tgt, T, max_corr_dist)
+        counts.append(cnt)
+        sums.append(sq)
+        key = (-cnt, sq, int(h))
+        if best is None or key < best[0]:
+            best = (key, T)
     S = score_shift(max_corr_dist)
-    res = {"n_iterations": n_iter if n_src > 0 else 0, "n_validated": len(trace_h),
-           "trace_h": np.array(trace_h, np.int64), "trace_T": np.array(trace_T).reshape(-1, 4, 4),
-           "trace_count": np.array(trace_c, np.int64), "trace_sumq": np.array(trace_q, np.uint64),
+    res = {"n_iterations": n_iter, "n_validated": len(hs), "trace_h": hs, "trace_T": Ts,
+           "trace_count": np.array(counts, np.int64), "trace_sumq": np.array(sums, np.uint64),
            "min_distance_margin": margin, "shift": S}
     if best is None:
         res.update(T=np.eye(4), fitness=0.0, rmse=0.0, count=0, sumq=0, best_h=-1, status=NO_HYPOTHESIS)
     else:
         (negc, sq, h), T = best
         cnt = -negc
-        res.update(T=T, fitness=cnt / n_src, rmse=math.sqrt(sq * 2.0 ** -S / cnt) if cnt else 0.0,
+        res.update(T=T, fitness=cnt / len(src), rmse=math.sqrt(sq * 2.0 ** -S / cnt) if cnt else 0.0,
                    count=cnt, sumq=sq, best_h=h, status=OK)
     return res

@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libicp.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["icp_kernels.hip", "icp_build.hip", "icp_api.hip", "icp_server.hip", "icp_posegraph.hip"]
+SOURCES = ["icp_kernels.hip", "icp_build.hip", "icp_api.hip", "icp_server.hip", "icp_posegraph.hip",
+           "icp_ransac.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -61,7 +61,7 @@ void ctx_free(icp_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   Buf* bufs[] = {&c->desc, &c->bbox_part, &c->t_key, &c->t_rank, &c->scan_tmp, &c->s_hist,
                  &c->cs, &c->tp, &c->tn, &c->sx, &c->sy, &c->sz, &c->perm, &c->vdesc,
-                 &c->vflags, &c->vstarts, &c->lvl_src, &c->lvl_tgt, &c->lvl_tn, &c->pg};
+                 &c->vflags, &c->vstarts, &c->lvl_src, &c->lvl_tgt, &c->lvl_tn, &c->pg, &c->rs};
   for (Buf* b : bufs) b->release();
   for (Buf& b : c->sk) b.release();
   pg_release(c);

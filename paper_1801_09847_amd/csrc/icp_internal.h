@@ -86,6 +86,24 @@ struct NormalArgs {
   int32_t* counts;        // (n), original order, or null
 };
 
+// RANSAC validation: hypothesis v's transform T[v] (3x4 row-major, FP64) is
+// scored over every source point of a prepared pair with the pass's
+// correspondence rule: count of inliers and sumq = sum of floor(d2 * 2^shift)
+// over them (exact integers).  Blocks write per-tile partials
+// [v][tile]; the reduction writes one (count, sumq) per hypothesis.
+struct ValidateArgs {
+  PassArgs p;                // prepared pair (st, part, jprev, outputs unused)
+  const double* T;           // [n_hyp][12]
+  int32_t n_hyp;
+  int32_t n_tiles;
+  double scale;              // 2^shift
+  uint32_t* part_cnt;        // [n_hyp][n_tiles]
+  uint64_t* part_sq;         // [n_hyp][n_tiles]
+  int64_t* cnt_out;          // [n_hyp]
+  uint64_t* sq_out;          // [n_hyp]
+};
+constexpr int kMaxValidateHyp = 65535;  // hypotheses per validation launch
+
 struct SolveArgs {
   const double* part;
   int32_t n_blocks;
@@ -190,6 +208,8 @@ hipError_t launch_state_init(IterState* st, const double T[16], hipStream_t s);
 hipError_t launch_normals(const NormalArgs& a, int sub, hipStream_t s);
 
 hipError_t launch_pass(const PassArgs& a, int variant, int precision, bool write_corr, hipStream_t s);
+// Scores of a.n_hyp <= kMaxValidateHyp hypotheses (pass kernel and reduction).
+hipError_t launch_validate(const ValidateArgs& a, int sub, hipStream_t s);
 // Solve of one pair.  `red` (kNumSums * 64 doubles of scratch, or null) lets
 // a pair of many pass blocks reduce its partials with many blocks first; the
 // result is the same bits either way.

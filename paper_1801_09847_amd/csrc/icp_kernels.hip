@@ -546,6 +546,99 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(PassArgs a) {
 // Batched form: block b handles tile items[b].y of pair items[b].x.  Tiles and
 // their partial slots are the same as when the pair is registered alone, so a
 // pair's result does not depend on the rest of the batch.
+// ---- RANSAC validation --------------------------------------------------
+// Block (tile, v) scores hypothesis v over kTile Morton-ordered source points:
+// the same transform, candidate rows and selection as the pass (no warm
+// start: every hypothesis is a new pose), then the block's inlier count and
+// fixed-point squared-distance sum.  floor(d2 * 2^shift) of a float32 d2 is
+// exact in float64 (a power-of-two scale) and below 2^40, so the sums are
+// exact integers whatever the order.
+template <int R>
+__global__ __launch_bounds__(kBlock) void validate_kernel(ValidateArgs v) {
+  __shared__ __align__(16) uint32_t scratch[kBlock / kWave][WaveScratch<R>::kRangeWords];
+  __shared__ uint32_t red_n[kBlock / kWave];
+  __shared__ uint64_t red_q[kBlock / kWave];
+  const PassArgs& a = v.p;
+  const uint32_t tile = blockIdx.x, hyp = blockIdx.y;
+  const ICP_G double* Th = glb(v.T) + (size_t)hyp * 12;
+  double T[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) T[k] = Th[k];
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  uint2* lane_ranges = reinterpret_cast<uint2*>(scratch[w]) + lane;
+  uint32_t cnt = 0;
+  uint64_t sq = 0;
+  const int64_t base = (int64_t)tile * kTile;
+  for (int round = 0; round < kRounds; ++round) {
+    const int64_t i = base + round * kBlock + threadIdx.x;
+    bool inl = false;
+    float bd = 0.f;
+    if (i < a.n_src) {
+      const double sx = glb(a.sx)[i], sy = glb(a.sy)[i], sz = glb(a.sz)[i];
+      double t;
+      t = T[0] * sx; t = t + T[1] * sy; t = t + T[2] * sz; const double qx = t + T[3];
+      t = T[4] * sx; t = t + T[5] * sy; t = t + T[6] * sz; const double qy = t + T[7];
+      t = T[8] * sx; t = t + T[9] * sy; t = t + T[10] * sz; const double qz = t + T[11];
+      const float q32x = (float)qx, q32y = (float)qy, q32z = (float)qz;
+      uint64_t best = ~0ull;
+      uint32_t bj = 0xffffffffu;
+      const uint32_t total = stage_rows<R>(a, q32x, q32y, q32z, lane_ranges, best);
+      scan_ranges(a, q32x, q32y, q32z, lane_ranges, total, best, bj);
+      bd = __uint_as_float((uint32_t)(best >> 32));
+      inl = best != ~0ull && bd <= a.r2f;
+    }
+    cnt += (uint32_t)__popcll(__ballot(inl));
+    if (inl) sq += (uint64_t)((double)bd * v.scale);
+  }
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) sq += __shfl_xor(sq, off, kWave);
+  if (lane == 0) {
+    red_n[w] = cnt;
+    red_q[w] = sq;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t n = 0;
+    uint64_t q = 0;
+    for (int ww = 0; ww < kBlock / kWave; ++ww) {
+      n += red_n[ww];
+      q += red_q[ww];
+    }
+    glb(v.part_cnt)[(size_t)hyp * v.n_tiles + tile] = n;
+    glb(v.part_sq)[(size_t)hyp * v.n_tiles + tile] = q;
+  }
+}
+
+// One block per hypothesis: integer sums of its tiles' partials.
+__global__ __launch_bounds__(256) void validate_reduce_kernel(ValidateArgs v) {
+  __shared__ uint64_t sn[256 / kWave], sq_s[256 / kWave];
+  const uint32_t hyp = blockIdx.x;
+  uint64_t n = 0, q = 0;
+  for (int t = threadIdx.x; t < v.n_tiles; t += 256) {
+    n += glb(v.part_cnt)[(size_t)hyp * v.n_tiles + t];
+    q += glb(v.part_sq)[(size_t)hyp * v.n_tiles + t];
+  }
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    n += __shfl_xor(n, off, kWave);
+    q += __shfl_xor(q, off, kWave);
+  }
+  if (lane_id() == 0) {
+    sn[threadIdx.x / kWave] = n;
+    sq_s[threadIdx.x / kWave] = q;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t N = 0, Q = 0;
+    for (int ww = 0; ww < 256 / kWave; ++ww) {
+      N += sn[ww];
+      Q += sq_s[ww];
+    }
+    glb(v.cnt_out)[hyp] = (int64_t)N;
+    glb(v.sq_out)[hyp] = Q;
+  }
+}
+
 template <int VAR, int PREC, int R>
 __global__ __launch_bounds__(kBlock) void batch_pass_kernel(const PassArgs* __restrict__ pairs,
                                                             const uint2* __restrict__ items) {
@@ -1047,6 +1140,19 @@ hipError_t launch_pass(const PassArgs& a, int variant, int precision, bool write
     if (robust) launch_pass_r<1, true>(a, variant, precision, write_corr, s);
     else launch_pass_r<1, false>(a, variant, precision, write_corr, s);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_validate(const ValidateArgs& a, int sub, hipStream_t s) {
+  if (a.n_hyp <= 0) return hipSuccess;
+  const dim3 grid((unsigned)a.n_tiles, (unsigned)a.n_hyp);
+  if (sub == 2)
+    hipLaunchKernelGGL(validate_kernel<2>, grid, dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(validate_kernel<1>, grid, dim3(kBlock), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(validate_reduce_kernel, dim3((unsigned)a.n_hyp), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

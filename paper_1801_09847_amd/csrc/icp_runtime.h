@@ -79,6 +79,8 @@ struct icp_ctx {
   // pose-graph optimisation: poses, edges, terms, normal equations; dense
   // solver library handle (created on first use)
   icp_rt::Buf pg;
+  // RANSAC: hypothesis flags, survivors, validation partials, feature-match keys
+  icp_rt::Buf rs;
   void* solver = nullptr;
   void* host = nullptr;  // pinned staging
   size_t host_cap = 0;

@@ -28,7 +28,7 @@ ICP_E_OOM = -4
 ICP_E_DEVICE = -5
 ICP_E_CANCELLED = -6
 ICP_E_NOT_FOUND = -7
-ICP_OK, ICP_CONVERGED, ICP_DEGENERATE = 0, 1, 2
+ICP_OK, ICP_CONVERGED, ICP_DEGENERATE, ICP_RANSAC_NO_HYPOTHESIS = 0, 1, 2, 3
 ICP_POINT_TO_POINT, ICP_POINT_TO_PLANE = 0, 1
 ICP_PREC_F32_KAHAN_F64, ICP_PREC_F64 = 0, 1
 
@@ -93,7 +93,24 @@ class icp_completion_t(C.Structure):
 
 class icp_profile_t(C.Structure):
     _fields_ = [("pass_ms", C.c_double), ("pass_launches", C.c_int64), ("pass_points", C.c_int64),
-                ("call_ms", C.c_double), ("calls", C.c_int64)]
+                ("call_ms", C.c_double), ("calls", C.c_int64), ("validate_ms", C.c_double),
+                ("validate_launches", C.c_int64), ("validate_evals", C.c_int64)]
+
+
+class icp_ransac_params_t(C.Structure):
+    _fields_ = [("max_corr_dist", C.c_double), ("edge_length", C.c_double), ("distance", C.c_double),
+                ("max_iteration", C.c_int64), ("max_validation", C.c_int32), ("ransac_n", C.c_int32),
+                ("seed", C.c_uint64)]
+
+
+class icp_ransac_result_t(C.Structure):
+    _fields_ = [("T", C.c_double * 16), ("fitness", C.c_double), ("inlier_rmse", C.c_double),
+                ("n_inliers", C.c_int64), ("sumq", C.c_uint64), ("shift", C.c_int32), ("status", C.c_int32),
+                ("n_iterations", C.c_int64), ("n_validated", C.c_int64), ("best_hypothesis", C.c_int64)]
+
+
+class icp_ransac_trace_t(C.Structure):
+    _fields_ = [("h", C.c_void_p), ("T", C.c_void_p), ("count", C.c_void_p), ("sumq", C.c_void_p)]
 
 
 _lib = None
@@ -132,6 +149,10 @@ def lib():
         L.icp_estimate_normals.argtypes = [vp, vp, i64, dbl, i32, vp, vp, vp]
         L.icp_pose_graph_optimize.argtypes = [vp, i32, vp, i32, C.POINTER(icp_pose_edge_t), i32, i32,
                                               dbl, C.POINTER(icp_pose_graph_result_t)]
+        L.icp_feature_match.argtypes = [vp, vp, i64, vp, i64, i32, vp, vp]
+        L.icp_ransac_validate.argtypes = [vp, vp, i64, vp, i64, dbl, i32, vp, vp, vp]
+        L.icp_ransac_register.argtypes = [vp, vp, i64, vp, i64, vp, C.POINTER(icp_ransac_params_t),
+                                          C.POINTER(icp_ransac_result_t), C.POINTER(icp_ransac_trace_t)]
         L.icp_server_create.argtypes = [C.POINTER(icp_server_cfg_t), C.POINTER(vp)]
         L.icp_server_submit.argtypes = [vp, C.POINTER(icp_request_t), C.POINTER(C.c_uint64)]
         L.icp_server_step.argtypes = [vp, C.POINTER(C.c_int32)]
@@ -144,7 +165,8 @@ def lib():
                      "icp_normal_equations", "icp_ctx_set_profiling", "icp_ctx_get_profile",
                      "icp_register_batch", "icp_voxel_downsample", "icp_register_multiscale",
                      "icp_estimate_normals", "icp_register_robust", "icp_normal_equations_robust",
-                     "icp_pose_graph_optimize",
+                     "icp_pose_graph_optimize", "icp_feature_match", "icp_ransac_validate",
+                     "icp_ransac_register",
                      "icp_server_create", "icp_server_submit", "icp_server_step", "icp_server_poll",
                      "icp_server_wait", "icp_server_destroy"):
             getattr(L, name).restype = C.c_int
@@ -386,6 +408,89 @@ def pose_graph_optimize(poses, edges, method="lm", max_iter=50, rel_tol=1e-10,
                                          C.byref(out)))
     return P.reshape(-1, 4, 4), {"F_initial": out.F_initial, "F_final": out.F_final,
                                  "steps": out.steps, "status": out.status}
+
+
+def feature_match(src_feat, tgt_feat, ctx: Context | None = None, with_dist=False):
+    """Nearest target feature per source feature (device (N, dim) float32
+    tensors): device int32 indices (-1 without targets), and with_dist the
+    float32 squared feature distances."""
+    import torch
+    for name, t in (("src_feat", src_feat), ("tgt_feat", tgt_feat)):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 or t.dim() != 2 \
+                or not t.is_contiguous():
+            raise IcpError(ICP_E_INVALID_ARG, f"{name} must be a contiguous 2-D float32 CUDA (HIP) tensor")
+    if src_feat.shape[1] != tgt_feat.shape[1]:
+        raise IcpError(ICP_E_INVALID_ARG, "feature dimensions differ")
+    n = src_feat.shape[0]
+    match = torch.empty((n,), dtype=torch.int32, device=src_feat.device)
+    dist = torch.empty((n,), dtype=torch.float32, device=src_feat.device) if with_dist else None
+    _check(lib().icp_feature_match(ctx.handle if ctx else None, src_feat.data_ptr(), n, tgt_feat.data_ptr(),
+                                   tgt_feat.shape[0], int(src_feat.shape[1]), match.data_ptr(),
+                                   dist.data_ptr() if dist is not None else None))
+    return (match, dist) if with_dist else match
+
+
+def ransac_validate(src, tgt, max_corr_dist, Ts, ctx: Context | None = None):
+    """Scores (count int64, sumq uint64 arrays) of host transforms Ts (K, 4, 4)."""
+    sp, ns = _dev_pts(src, "src")
+    tp, nt = _dev_pts(tgt, "tgt")
+    T = np.ascontiguousarray(np.asarray(Ts, np.float64).reshape(-1, 16))
+    cnt = np.zeros(len(T), np.int64)
+    sq = np.zeros(len(T), np.uint64)
+    _check(lib().icp_ransac_validate(ctx.handle if ctx else None, sp, ns, tp, nt, float(max_corr_dist), len(T),
+                                     T.ctypes.data, cnt.ctypes.data, sq.ctypes.data))
+    return cnt, sq
+
+
+class RansacResult:
+    def __init__(self, r: icp_ransac_result_t, trace=None):
+        self.T = np.array(r.T[:], np.float64).reshape(4, 4)
+        self.fitness, self.inlier_rmse = r.fitness, r.inlier_rmse
+        self.n_inliers, self.sumq, self.shift, self.status = r.n_inliers, r.sumq, r.shift, r.status
+        self.n_iterations, self.n_validated, self.best_hypothesis = r.n_iterations, r.n_validated, r.best_hypothesis
+        self.trace = trace
+
+    def __repr__(self):
+        return (f"RansacResult(fitness={self.fitness:.4f}, rmse={self.inlier_rmse:.3e}, inliers={self.n_inliers}, "
+                f"iterations={self.n_iterations}, validated={self.n_validated}, best={self.best_hypothesis}, "
+                f"status={self.status})")
+
+
+def ransac_register(src, tgt, corr, max_corr_dist, ransac_n=4, edge_length=0.9, distance=None,
+                    max_iteration=4_000_000, max_validation=500, seed=0, trace=False,
+                    ctx: Context | None = None) -> RansacResult:
+    """RANSAC registration from putative pairs (i, corr[i]) (device int32).
+    distance defaults to max_corr_dist; trace=True also returns the validated
+    hypotheses (h, T, count, sumq) as host arrays in result.trace."""
+    import torch
+    sp, ns = _dev_pts(src, "src")
+    tp, nt = _dev_pts(tgt, "tgt")
+    if not isinstance(corr, torch.Tensor) or not corr.is_cuda or corr.dtype != torch.int32 \
+            or corr.shape != (ns,) or not corr.is_contiguous():
+        raise IcpError(ICP_E_INVALID_ARG, "corr must be a contiguous (n_src,) int32 CUDA (HIP) tensor")
+    prm = icp_ransac_params_t(float(max_corr_dist), float(edge_length),
+                              float(max_corr_dist if distance is None else distance), int(max_iteration),
+                              int(max_validation), int(ransac_n), int(seed))
+    out = icp_ransac_result_t()
+    tr = None
+    bufs = None
+    if trace:
+        m = max(1, int(max_validation))
+        dev = src.device
+        bufs = {"h": torch.empty(m, dtype=torch.int64, device=dev),
+                "T": torch.empty((m, 4, 4), dtype=torch.float64, device=dev),
+                "count": torch.empty(m, dtype=torch.int64, device=dev),
+                "sumq": torch.empty(m, dtype=torch.int64, device=dev)}
+        tr = icp_ransac_trace_t(bufs["h"].data_ptr(), bufs["T"].data_ptr(), bufs["count"].data_ptr(),
+                                bufs["sumq"].data_ptr())
+    _check(lib().icp_ransac_register(ctx.handle if ctx else None, sp, ns, tp, nt, corr.data_ptr(), C.byref(prm),
+                                     C.byref(out), C.byref(tr) if tr is not None else None))
+    t = None
+    if bufs is not None:
+        k = out.n_validated
+        t = {"h": bufs["h"][:k].cpu().numpy(), "T": bufs["T"][:k].cpu().numpy(),
+             "count": bufs["count"][:k].cpu().numpy(), "sumq": bufs["sumq"][:k].cpu().numpy().view(np.uint64)}
+    return RansacResult(out, t)
 
 
 def register_multiscale(src, tgt, tgt_normals, T_init, voxels, iters, dists, rel_tol=0.0,

@@ -178,3 +178,55 @@ def test_pose_graph_validation():
         with pytest.raises(icp.IcpError) as e:
             icp.pose_graph_optimize(poses, edges, **kw)
         assert e.value.code == icp.ICP_E_INVALID_ARG
+
+
+def _ransac_rc(**kw):
+    prm = dict(max_corr_dist=0.075, edge_length=0.9, distance=0.075, max_iteration=1000,
+               max_validation=10, ransac_n=4, seed=0)
+    args = dict(src=FAKE, n_src=100, tgt=FAKE, n_tgt=100, corr=FAKE)
+    for k, v in kw.items():
+        (prm if k in prm else args)[k] = v
+    p = icp.icp_ransac_params_t(**prm)
+    out = icp.icp_ransac_result_t()
+    return icp.lib().icp_ransac_register(None, args["src"], args["n_src"], args["tgt"], args["n_tgt"],
+                                         args["corr"], C.byref(p), C.byref(out), None)
+
+
+def test_ransac_validation():
+    E = icp.ICP_E_INVALID_ARG
+    assert _ransac_rc(src=None) == E
+    assert _ransac_rc(corr=None) == E
+    assert _ransac_rc(corr=MISALIGNED) == E
+    assert _ransac_rc(n_src=0) == E
+    assert _ransac_rc(n_src=(1 << 23) + 1) == icp.ICP_E_TOO_LARGE
+    assert _ransac_rc(max_corr_dist=0.0) == E
+    assert _ransac_rc(max_corr_dist=float("nan")) == E
+    assert _ransac_rc(ransac_n=2) == E
+    assert _ransac_rc(ransac_n=9) == E
+    assert _ransac_rc(edge_length=float("inf")) == E
+    assert _ransac_rc(distance=float("nan")) == E
+    assert _ransac_rc(max_iteration=0) == E
+    assert _ransac_rc(max_validation=0) == E
+    assert _ransac_rc(max_validation=65536) == E
+    L = icp.lib()
+    cnt = np.zeros(2, np.int64)
+    sq = np.zeros(2, np.uint64)
+    T = np.stack([np.eye(4)] * 2)
+    bad = T.copy()
+    bad[1, 0, 1] = 0.5
+    for args in ((FAKE, 100, FAKE, 100, 0.05, 0, T), (FAKE, 100, FAKE, 100, 0.05, 65536, T),
+                 (FAKE, 100, FAKE, 100, -1.0, 2, T), (FAKE, 100, FAKE, 100, 0.05, 2, bad),
+                 (None, 100, FAKE, 100, 0.05, 2, T)):
+        s, ns, t, nt, r, k, TT = args
+        TT = np.ascontiguousarray(TT)
+        assert L.icp_ransac_validate(None, s, ns, t, nt, r, k, TT.ctypes.data, cnt.ctypes.data,
+                                     sq.ctypes.data) == E
+    assert L.icp_ransac_validate(None, FAKE, 100, FAKE, 100, 0.05, 2, None, cnt.ctypes.data,
+                                 sq.ctypes.data) == E
+    m = np.zeros(4, np.int32)
+    assert L.icp_feature_match(None, FAKE, 10, FAKE, 10, 0, m.ctypes.data, None) == E
+    assert L.icp_feature_match(None, FAKE, 10, FAKE, 10, 65, m.ctypes.data, None) == E
+    assert L.icp_feature_match(None, None, 10, FAKE, 10, 33, m.ctypes.data, None) == E
+    assert L.icp_feature_match(None, FAKE, -1, FAKE, 10, 33, m.ctypes.data, None) == E
+    assert L.icp_feature_match(None, FAKE, 10, FAKE, 10, 33, None, None) == E
+    assert L.icp_feature_match(None, FAKE, 10, FAKE, 10, 33, MISALIGNED, None) == E

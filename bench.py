@@ -12,7 +12,8 @@ per second of wall time), the dominant kernel's roofline figures (algorithmic
 bytes per launch over its event-timed average duration) and the CPU oracle
 timed on a bounded sample of the same workload; then the robust-loss
 variants of the same registration and (default workload) the
-normal-estimation, pose-graph, 256-pair batched and served sections.
+normal-estimation, pose-graph, RANSAC global-registration, 256-pair batched
+and served sections.
 
   python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1] [--variant ...]
 """
@@ -198,6 +199,90 @@ def normals_section(args, icp, synth, np, torch, data):
         out.append(entry)
         print(f"bench: normals {name}: {n / dt:.3e} normals/s ({dt * 1e3:.2f} ms per call)",
               file=sys.stderr, flush=True)
+    return out
+
+
+def ransac_section(args, icp, synth, np, torch):
+    """Global registration as in the paper's pairwise workflow: nearest-feature
+    matching of 33-dimensional FPFH-shaped features, then RANSAC with
+    ransac_n 4, edge length 0.9, distance 0.075 m, max_iteration 4e6 and
+    max_validation 500, on a 20k/20k downsampled room pair (~6 cm spacing)
+    under a large motion.  Each RANSAC call includes its grid build; the
+    validation launches are timed with HIP events on the context's stream."""
+    dev = torch.device("cuda:0")
+    d = synth.ransac_pair(0)
+    ctx = icp.Context(0)
+    s = torch.from_numpy(d["src"]).to(dev)
+    t = torch.from_numpy(d["tgt"]).to(dev)
+    fs = torch.from_numpy(d["src_feat"]).to(dev)
+    ft = torch.from_numpy(d["tgt_feat"]).to(dev)
+    ns, nt, dim = len(d["src"]), len(d["tgt"]), d["src_feat"].shape[1]
+    prm = dict(ransac_n=4, edge_length=0.9, distance=0.075, max_iteration=4_000_000, max_validation=500, seed=0)
+    for _ in range(2):
+        corr = icp.feature_match(fs, ft, ctx=ctx)
+    torch.cuda.synchronize()
+    reps = 10
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        corr = icp.feature_match(fs, ft, ctx=ctx)
+    torch.cuda.synchronize()
+    fm = (time.perf_counter() - t0) / reps
+    # float32 subtract, multiply and add per dimension and pair.  Peak of
+    # non-FMA float32 operations: 256 CUs x 128 lanes x 2.4 GHz with packed
+    # float32 (the chip's ceiling), half that (64 lanes) for the unpacked
+    # instructions this library is built with
+    alu_peak = 256 * 128 * 2.4e9
+    fm_ops = 3.0 * dim * ns * nt
+    res = icp.ransac_register(s, t, corr, 0.075, ctx=ctx, **prm)
+    torch.cuda.synchronize()
+    ctx.set_profiling(True)
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        res = icp.ransac_register(s, t, corr, 0.075, ctx=ctx, **prm)
+    torch.cuda.synchronize()
+    rs = (time.perf_counter() - t0) / reps
+    prof = ctx.profile()
+    ctx.set_profiling(False)
+    G = d["T_gt"]
+    dR = res.T[:3, :3].T @ G[:3, :3]
+    ang = float(np.degrees(np.arccos(np.clip((np.trace(dR) - 1) / 2, -1, 1))))
+    v_us = prof["validate_ms"] * 1e3 / max(1, prof["validate_launches"])
+    v_evals = prof["validate_evals"] / max(1, prof["validate_launches"])
+    out = {"workload": f"room pair {ns}/{nt} points (~6 cm spacing), {dim}-d FPFH-shaped features, "
+                       "r 0.075 m, ransac_n 4, edge length 0.9, distance 0.075 m, 4e6 iterations, 500 validations",
+           "feature_match": {"ms_per_call": fm * 1e3, "pairs_per_s": ns * nt / fm,
+                             "roofline": {"bound": "alu", "achieved": fm_ops / fm / 1e12, "peak": alu_peak / 1e12,
+                                          "unit": "Tops/s", "frac": fm_ops / fm / alu_peak,
+                                          "frac_of_unpacked_peak": fm_ops / fm / (alu_peak / 2)}},
+           "ransac": {"ms_per_call": rs * 1e3, "n_iterations": res.n_iterations, "n_validated": res.n_validated,
+                      "fitness": res.fitness, "inlier_rmse": res.inlier_rmse, "rot_err_deg": ang,
+                      "trans_err_m": float(np.linalg.norm(res.T[:3, 3] - G[:3, 3])),
+                      "validate_avg_launch_us": v_us, "validate_evals_per_launch": v_evals,
+                      "validate_corr_evals_per_s": v_evals / (v_us * 1e-6) if v_us > 0 else None}}
+    print(f"bench: feature match {fm * 1e3:.2f} ms; ransac {rs * 1e3:.2f} ms per call "
+          f"({res.n_iterations} iterations, {res.n_validated} validated, validation {v_us:.0f} us)",
+          file=sys.stderr, flush=True)
+    if not args.no_cpu_baseline:
+        from oracle import ransac as R
+        c = corr.cpu().numpy()
+        rows = np.random.default_rng(0).choice(ns, 500, replace=False)
+        t1 = time.perf_counter()
+        R.feature_match(d["src_feat"][rows], d["tgt_feat"])
+        fm_cpu = (time.perf_counter() - t1) * ns / len(rows)
+        t1 = time.perf_counter()
+        hs, Ts, _, _ = R.hypotheses(d["src"], d["tgt"], c, 4, 0.9, 0.075, 4_000_000, 500, 0, chunk=65536)
+        hyp_cpu = time.perf_counter() - t1
+        k = min(50, len(Ts))
+        t1 = time.perf_counter()
+        for T in Ts[:k]:
+            R.validate(d["src"], d["tgt"], T, 0.075)
+        val_cpu = (time.perf_counter() - t1) * len(Ts) / max(1, k)
+        out["cpu_baseline"] = {
+            "value": (hyp_cpu + val_cpu) * 1e3, "unit": "ms per RANSAC call", "cores": 1, "kind": "oracle",
+            "feature_match_ms": fm_cpu * 1e3,
+            "sample": f"hypothesis checks run whole ({hyp_cpu:.2f} s, numpy); validation timed on {k} of "
+                      f"{len(Ts)} hypotheses (k-d tree, scaled); feature match timed on {len(rows)} rows, scaled"}
     return out
 
 
@@ -410,6 +495,7 @@ def main():
     ap.add_argument("--no-normals", action="store_true", help="skip the normal-estimation section")
     ap.add_argument("--no-robust", action="store_true", help="skip the robust-loss section")
     ap.add_argument("--no-pose-graph", action="store_true", help="skip the pose-graph section")
+    ap.add_argument("--no-ransac", action="store_true", help="skip the RANSAC global-registration section")
     ap.add_argument("--served-requests", type=int, default=400)
     ap.add_argument("--served-pool", type=int, default=64)
     ap.add_argument("--served-rates", type=float, nargs="+", default=[1.0, 8.0])
@@ -527,6 +613,8 @@ def main():
         out["normals"] = normals_section(args, icp, synth, np, torch, data)
     if not args.no_pose_graph and args.workload == "c3":
         out["pose_graph"] = pose_graph_section(args, icp, synth, np, torch)
+    if not args.no_ransac and args.workload == "c3":
+        out["ransac"] = ransac_section(args, icp, synth, np, torch)
     if not args.no_batched:
         out["batched"] = batched_section(args, icp, synth, np, torch)
     if not args.no_served:

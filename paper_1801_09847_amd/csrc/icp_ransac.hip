@@ -26,9 +26,10 @@ namespace {
 
 constexpr int kHypBlock = 256;
 constexpr int kMinRansacN = 3, kMaxRansacN = 8;
-constexpr int64_t kMaxChunk = int64_t(1) << 22;   // hypotheses per check launch
+constexpr int64_t kMaxChunk = int64_t(1) << 20;   // hypotheses per check launch
 constexpr int64_t kFirstChunk = int64_t(1) << 16;
-constexpr int kFmBlock = 256;  // queries per feature-match block (one per thread)
+constexpr int kFmBlock = 256;  // threads per feature-match block
+constexpr int kFmQ = 2;        // queries per thread
 constexpr int kFmTile = 64;    // target features staged in LDS at a time
 constexpr int kMaxFeatureDim = 64;
 constexpr int64_t kMaxRansacSrc = int64_t(1) << 23;  // keeps sumq below 2^63
@@ -73,6 +74,7 @@ struct HypArgs {
   int64_t h0;            // first hypothesis of the chunk
   int64_t count;         // hypotheses in the chunk
   uint32_t* flags;       // count + 1 words: 1 = passed; scanned in place
+  double* Tc;            // [count][12]: the fit of each passing hypothesis
   // emission of the survivors (second launch)
   int64_t base;          // survivors before this chunk
   int32_t max_valid;
@@ -277,14 +279,17 @@ __global__ __launch_bounds__(kHypBlock) void hyp_check_kernel(HypArgs a) {
   uint32_t f = 0;
   if (g < a.count) {
     double T[12];
-    f = hypothesis<N>(a, a.h0 + g, T) ? 1u : 0u;
+    if (hypothesis<N>(a, a.h0 + g, T)) {
+      f = 1u;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) a.Tc[12 * g + k] = T[k];
+    }
   }
   a.flags[g] = f;
 }
 
-// After the scan: each survivor whose rank is below max_valid recomputes its
-// (deterministic) fit and stores it at its rank.
-template <int N>
+// After the scan: each survivor whose rank is below max_valid moves its fit
+// to its rank.
 __global__ __launch_bounds__(kHypBlock) void hyp_emit_kernel(HypArgs a) {
   const int64_t g = (int64_t)blockIdx.x * kHypBlock + threadIdx.x;
   if (g >= a.count) return;
@@ -292,11 +297,9 @@ __global__ __launch_bounds__(kHypBlock) void hyp_emit_kernel(HypArgs a) {
   if (p1 == p) return;
   const int64_t v = a.base + p;
   if (v >= a.max_valid) return;
-  double T[12];
-  hypothesis<N>(a, a.h0 + g, T);
   double* o = a.T_list + 16 * v;
 #pragma unroll
-  for (int k = 0; k < 12; ++k) o[k] = T[k];
+  for (int k = 0; k < 12; ++k) o[k] = a.Tc[12 * g + k];
   o[12] = 0.0; o[13] = 0.0; o[14] = 0.0; o[15] = 1.0;
   a.h_list[v] = a.h0 + g;
 }
@@ -362,35 +365,45 @@ __global__ __launch_bounds__(1024) void ransac_select_kernel(const int64_t* cnt,
 }
 
 // ---------------------------------------------------------------- feature matching
-// Block (x, y): kFmBlock queries against target split y.  Each thread holds its
-// query (zero-padded to 4 * D4 dimensions: zeros add exact zeros to a
-// float32 sum) and walks the split's targets staged in LDS, kFmTile at a time,
-// accumulating the squared distance dimension by dimension in float32 without
-// FMA; strict < over increasing j keeps the smallest index of equal
-// distances.  Splits merge through a 64-bit atomic minimum of (distance bits,
-// index): the order of non-negative float bit patterns is the numeric order.
+// Block (x, y): kFmBlock * kFmQ queries against target split y.  Each thread
+// holds kFmQ queries (zero-padded to 4 * D4 dimensions: zeros add exact zeros
+// to a float32 sum) and walks the split's targets staged in LDS, kFmTile at a
+// time, so one LDS read of a target feeds kFmQ distances; each distance is
+// accumulated dimension by dimension in float32 without FMA, and strict <
+// over increasing j keeps the smallest index of equal distances.  Splits
+// merge through a 64-bit atomic minimum of (distance bits, index): the order
+// of non-negative float bit patterns is the numeric order.
 template <int D4>
 __global__ __launch_bounds__(kFmBlock) void feature_match_kernel(const float* __restrict__ fs, int64_t n_src,
                                                                  const float* __restrict__ ft, int64_t n_tgt,
                                                                  int dim, int64_t per_split,
                                                                  unsigned long long* __restrict__ keys) {
   __shared__ float4 tile[kFmTile][D4];
-  const int64_t i = (int64_t)blockIdx.x * kFmBlock + threadIdx.x;
-  float4 q[D4];
+  float4 q[kFmQ][D4];
+  int64_t qi[kFmQ];
 #pragma unroll
-  for (int k4 = 0; k4 < D4; ++k4) {
-    float e[4];
+  for (int u = 0; u < kFmQ; ++u) {
+    qi[u] = ((int64_t)blockIdx.x * kFmQ + u) * kFmBlock + threadIdx.x;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int k = 4 * k4 + c;
-      e[c] = (i < n_src && k < dim) ? fs[i * dim + k] : 0.f;
+    for (int k4 = 0; k4 < D4; ++k4) {
+      float e[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int k = 4 * k4 + c;
+        e[c] = (qi[u] < n_src && k < dim) ? fs[qi[u] * dim + k] : 0.f;
+      }
+      q[u][k4] = make_float4(e[0], e[1], e[2], e[3]);
     }
-    q[k4] = make_float4(e[0], e[1], e[2], e[3]);
   }
   const int64_t j0 = (int64_t)blockIdx.y * per_split;
   const int64_t j1 = min(n_tgt, j0 + per_split);
-  float best = INFINITY;
-  int64_t bj = -1;
+  float best[kFmQ];
+  int64_t bj[kFmQ];
+#pragma unroll
+  for (int u = 0; u < kFmQ; ++u) {
+    best[u] = INFINITY;
+    bj[u] = -1;
+  }
   float* tf = reinterpret_cast<float*>(&tile[0][0]);
   for (int64_t jt = j0; jt < j1; jt += kFmTile) {
     __syncthreads();
@@ -402,24 +415,33 @@ __global__ __launch_bounds__(kFmBlock) void feature_match_kernel(const float* __
     __syncthreads();
     const int nt = (int)min<int64_t>(kFmTile, j1 - jt);
     for (int t = 0; t < nt; ++t) {
-      float acc = 0.f;
+      float acc[kFmQ];
+#pragma unroll
+      for (int u = 0; u < kFmQ; ++u) acc[u] = 0.f;
 #pragma unroll
       for (int k4 = 0; k4 < D4; ++k4) {
         const float4 b = tile[t][k4];
-        float d;
-        d = q[k4].x - b.x; acc = acc + d * d;
-        d = q[k4].y - b.y; acc = acc + d * d;
-        d = q[k4].z - b.z; acc = acc + d * d;
-        d = q[k4].w - b.w; acc = acc + d * d;
+#pragma unroll
+        for (int u = 0; u < kFmQ; ++u) {
+          float d;
+          d = q[u][k4].x - b.x; acc[u] = acc[u] + d * d;
+          d = q[u][k4].y - b.y; acc[u] = acc[u] + d * d;
+          d = q[u][k4].z - b.z; acc[u] = acc[u] + d * d;
+          d = q[u][k4].w - b.w; acc[u] = acc[u] + d * d;
+        }
       }
-      if (acc < best) {
-        best = acc;
-        bj = jt + t;
-      }
+#pragma unroll
+      for (int u = 0; u < kFmQ; ++u)
+        if (acc[u] < best[u]) {
+          best[u] = acc[u];
+          bj[u] = jt + t;
+        }
     }
   }
-  if (i < n_src && bj >= 0)
-    atomicMin(&keys[i], ((unsigned long long)__float_as_uint(best) << 32) | (unsigned long long)bj);
+#pragma unroll
+  for (int u = 0; u < kFmQ; ++u)
+    if (qi[u] < n_src && bj[u] >= 0)
+      atomicMin(&keys[qi[u]], ((unsigned long long)__float_as_uint(best[u]) << 32) | (unsigned long long)bj[u]);
 }
 
 __global__ void fill_u64_kernel(unsigned long long* p, int64_t n, unsigned long long v) {
@@ -447,7 +469,7 @@ hipError_t launch_feature_match(const float* fs, int64_t n_src, const float* ft,
   const int64_t nb = (n_src + 255) / 256;
   hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)nb), dim3(256), 0, s, keys, n_src, ~0ull);
   if (n_tgt > 0) {
-    const int64_t qb = (n_src + kFmBlock - 1) / kFmBlock;
+    const int64_t qb = (n_src + kFmBlock * kFmQ - 1) / (kFmBlock * kFmQ);
     const int64_t max_splits = (n_tgt + kFmTile - 1) / kFmTile;
     const int64_t splits = std::max<int64_t>(1, std::min<int64_t>(max_splits, (2048 + qb - 1) / qb));
     int64_t per = (n_tgt + splits - 1) / splits;
@@ -468,23 +490,19 @@ hipError_t launch_feature_match(const float* fs, int64_t n_src, const float* ft,
   return hipGetLastError();
 }
 
-template <int N>
-void launch_hyp_n(const HypArgs& a, bool emit, hipStream_t s) {
-  const int64_t nb = (a.count + 1 + kHypBlock - 1) / kHypBlock;
-  if (emit)
-    hipLaunchKernelGGL(hyp_emit_kernel<N>, dim3((unsigned)nb), dim3(kHypBlock), 0, s, a);
-  else
-    hipLaunchKernelGGL(hyp_check_kernel<N>, dim3((unsigned)nb), dim3(kHypBlock), 0, s, a);
-}
-
 hipError_t launch_hyp(const HypArgs& a, int n, bool emit, hipStream_t s) {
+  const dim3 grid((unsigned)((a.count + 1 + kHypBlock - 1) / kHypBlock));
+  if (emit) {
+    hipLaunchKernelGGL(hyp_emit_kernel, grid, dim3(kHypBlock), 0, s, a);
+    return hipGetLastError();
+  }
   switch (n) {
-    case 3: launch_hyp_n<3>(a, emit, s); break;
-    case 4: launch_hyp_n<4>(a, emit, s); break;
-    case 5: launch_hyp_n<5>(a, emit, s); break;
-    case 6: launch_hyp_n<6>(a, emit, s); break;
-    case 7: launch_hyp_n<7>(a, emit, s); break;
-    case 8: launch_hyp_n<8>(a, emit, s); break;
+    case 3: hipLaunchKernelGGL(hyp_check_kernel<3>, grid, dim3(kHypBlock), 0, s, a); break;
+    case 4: hipLaunchKernelGGL(hyp_check_kernel<4>, grid, dim3(kHypBlock), 0, s, a); break;
+    case 5: hipLaunchKernelGGL(hyp_check_kernel<5>, grid, dim3(kHypBlock), 0, s, a); break;
+    case 6: hipLaunchKernelGGL(hyp_check_kernel<6>, grid, dim3(kHypBlock), 0, s, a); break;
+    case 7: hipLaunchKernelGGL(hyp_check_kernel<7>, grid, dim3(kHypBlock), 0, s, a); break;
+    case 8: hipLaunchKernelGGL(hyp_check_kernel<8>, grid, dim3(kHypBlock), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -521,7 +539,7 @@ int score_shift(double r) {
 
 // Device workspace of one RANSAC / validation call, carved from ctx->rs.
 struct RsLayout {
-  size_t flags, sums, T_list, h_list, cnt, sq, part_cnt, part_sq, Tdev, out, total;
+  size_t flags, Tc, sums, T_list, h_list, cnt, sq, part_cnt, part_sq, Tdev, out, total;
 };
 
 RsLayout rs_layout(int64_t chunk, int64_t max_valid, int64_t part_entries) {
@@ -533,6 +551,7 @@ RsLayout rs_layout(int64_t chunk, int64_t max_valid, int64_t part_entries) {
     return o;
   };
   L.flags = take(sizeof(uint32_t) * (size_t)(chunk + 4));
+  L.Tc = take(sizeof(double) * 12 * (size_t)chunk);
   L.sums = take(sizeof(uint32_t) * (size_t)scan_block_sums_needed(chunk + 1));
   L.T_list = take(sizeof(double) * 16 * (size_t)max_valid);
   L.h_list = take(sizeof(int64_t) * (size_t)max_valid);
@@ -744,6 +763,7 @@ int icp_ransac_register(icp_ctx_t* ctx, const float* src_xyz, int64_t n_src, con
   a.sig2 = prm->edge_length > 0.0 ? prm->edge_length * prm->edge_length : 0.0;
   a.d2 = prm->distance > 0.0 ? prm->distance * prm->distance : 0.0;
   a.flags = reinterpret_cast<uint32_t*>(base + L.flags);
+  a.Tc = reinterpret_cast<double*>(base + L.Tc);
   a.max_valid = (int32_t)max_valid;
   a.T_list = reinterpret_cast<double*>(base + L.T_list);
   a.h_list = reinterpret_cast<int64_t*>(base + L.h_list);

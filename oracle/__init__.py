@@ -94,6 +94,9 @@ def lib():
         L.oracle_voxel_downsample.argtypes = [_f32p, C.c_void_p, C.c_int64, C.c_double, _f32p,
                                               C.c_void_p]
         L.oracle_voxel_downsample.restype = C.c_int64
+        L.oracle_hybrid_neighbors.argtypes = [_f32p, C.c_int64, C.c_double, C.c_int, C.c_int,
+                                              C.c_void_p, C.c_void_p]
+        L.oracle_hybrid_neighbors.restype = C.c_int
         _lib = L
     return _lib
 
@@ -226,6 +229,19 @@ def estimate_normals(pts, radius, max_nn, viewpoint=(0.0, 0.0, 0.0), search=0, q
     if rc != 0:
         raise ValueError("oracle_estimate_normals: invalid arguments")
     return (out, cnt, ev) if with_evals else (out, cnt)
+
+
+def hybrid_neighbors(pts, radius, max_nn, search=0):
+    """(n, max_nn) int64 neighbour lists (sorted by (pinned distance, index),
+    -1 padded, the point itself included) and their lengths."""
+    pts = _pts(pts)
+    n = len(pts)
+    idx = np.empty((n, max_nn), np.int64)
+    cnt = np.empty(n, np.int32)
+    if lib().oracle_hybrid_neighbors(pts, n, float(radius), int(max_nn), int(search), idx.ctypes.data,
+                                     cnt.ctypes.data) != 0:
+        raise ValueError("oracle_hybrid_neighbors: invalid arguments")
+    return idx, cnt
 
 
 def sym_eig3(A):

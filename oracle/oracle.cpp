@@ -823,6 +823,39 @@ int oracle_estimate_normals(const float* pts, int64_t n, double radius, int max_
   return 0;
 }
 
+// Hybrid neighbourhoods (the selection of oracle_estimate_normals) of all n
+// points: row i of idx (n x max_nn, original indices, -1 padded) lists the
+// max_nn smallest (pinned float32 squared distance, index) within radius,
+// the point itself included, in that order; counts[i] its length.
+int oracle_hybrid_neighbors(const float* pts, int64_t n, double radius, int max_nn, int search,
+                            int64_t* idx, int32_t* counts) {
+  if (!pts || n < 1 || !(radius > 0.0) || max_nn < 1 || !idx || !counts) return -1;
+  const bool use_tree = search == 2 || (search == 0 && n * n > 20000000);
+  KdTree tree;
+  if (use_tree) tree.build(pts, n);
+  const float r2f = (float)(radius * radius);
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int64_t i = 0; i < n; ++i) {
+    const float* pi = pts + 3 * i;
+    std::vector<std::pair<float, int64_t>> cand;
+    auto visit = [&](int64_t j) {
+      const float d = pinned_d2(pi, pts + 3 * j);
+      if (d <= r2f) cand.push_back({d, j});
+    };
+    if (use_tree) {
+      const double c[3] = {(double)pi[0], (double)pi[1], (double)pi[2]};
+      tree.range(c, radius * radius * (1.0 + 1e-5), visit);
+    } else {
+      for (int64_t j = 0; j < n; ++j) visit(j);
+    }
+    std::sort(cand.begin(), cand.end());
+    const int m = (int)std::min<size_t>(cand.size(), (size_t)max_nn);
+    for (int k = 0; k < max_nn; ++k) idx[i * max_nn + k] = k < m ? cand[(size_t)k].second : -1;
+    counts[i] = m;
+  }
+  return 0;
+}
+
 // Eigen-decomposition used by the normals (exposed for its pins): A6 is the
 // upper triangle (a00, a01, a02, a11, a12, a22); evals ascending, evecs
 // their eigenvectors as columns of a row-major 3x3.

@@ -383,6 +383,29 @@ typedef struct {
   uint64_t *sumq;   /* fixed-point sums */
 } icp_ransac_trace_t;
 
+/* FPFH descriptors (Sec. 3.3, compute_fpfh_feature with a hybrid (radius,
+ * max_nn) neighbourhood; the Fast Point Feature Histogram of [17]).  The
+ * neighbourhood of point i is the normal estimation's: the max_nn smallest
+ * (pinned float32 squared distance, index) within radius, i included.  For a
+ * neighbour j != i at non-zero distance, in float64 from the float32 inputs:
+ * the source s is the end whose normal makes the smaller angle with the line
+ * to the other (s = i iff n_i . (p_j - p_i) >= -n_j . (p_j - p_i)), e the
+ * unit line from s, u = n_s, v = unit(u x e) (pair skipped if u x e = 0),
+ * w = u x v; alpha = v . n_t, phi = u . e, theta = atan2(w . n_t, u . n_t);
+ * bins floor((alpha + 1) 5.5), 11 + floor((phi + 1) 5.5),
+ * 22 + floor((theta + pi) 11 / (2 pi)), each sub-bin clamped to [0, 10].
+ * SPFH(i) = bin counts * 100 / k_i (k_i pairs counted; zero if none);
+ * FPFH(i) = SPFH(i) + (1 / k') sum over those neighbours of SPFH(j) / |p_j - p_i|
+ * (k' their number), rounded to float32.
+ *   pts, normals  device (n, 3) float32; normals unit length (not checked)
+ *   radius > 0; max_nn 1 .. 128
+ *   features_out  device (n, 33) float32 (caller-owned)
+ *   nn_out        device (n) int32 neighbourhood sizes (i included), or NULL
+ * Synchronous.  Errors: INVALID_ARG, NONFINITE (a coordinate), TOO_LARGE, OOM,
+ * DEVICE. */
+int icp_compute_fpfh(icp_ctx_t *ctx, const float *pts, const float *normals, int64_t n, double radius,
+                     int32_t max_nn, float *features_out, int32_t *nn_out);
+
 /* Nearest-feature matching (row-major float32 features, device memory).
  *   src_feat  (n_src, dim), tgt_feat (n_tgt, dim); n_src, n_tgt >= 0;
  *             dim 1 .. 64; features must be finite (not checked)

@@ -104,6 +104,34 @@ struct ValidateArgs {
 };
 constexpr int kMaxValidateHyp = 65535;  // hypotheses per validation launch
 
+// FPFH descriptors of one cloud prepared as both queries and grid (as for
+// normals).  Pass 1 (per point): the hybrid neighbourhood, its list and the
+// SPFH bin counts; pass 2: the distance-weighted sum over the neighbours.
+constexpr int kFpfhBlock = 64;    // threads per block of the SPFH pass (one wave)
+constexpr int kMaxFpfhNN = 128;   // largest max_nn (per-lane heap in LDS; counts fit a byte)
+constexpr int kFpfhBins = 33;     // three 11-bin sub-histograms
+constexpr int kFpfhCountWords = 9;  // 33 byte counts padded to 9 words per point
+struct FpfhArgs {
+  const float* sx;        // Morton-ordered points
+  const float* sy;
+  const float* sz;
+  const uint32_t* sperm;  // Morton position -> original index
+  int32_t n;
+  const float4* tp;       // cell-ordered points (x, y, z, original index bits)
+  const uint32_t* cs;     // cell start table
+  GridDesc g;
+  float r2f;              // (float)(radius^2)
+  float inv_h2;
+  int32_t max_nn;
+  const float* pts;       // (n, 3) original order
+  const float* nrm;       // (n, 3) original order, unit normals
+  uint32_t* counts;       // (n, 9) words: byte b = SPFH count of bin b
+  int32_t* k;             // (n) pairs counted
+  int32_t* nbr;           // (n, max_nn) neighbour original indices
+  int32_t* nn;            // (n) neighbourhood sizes
+  float* out;             // (n, 33) descriptors
+};
+
 struct SolveArgs {
   const double* part;
   int32_t n_blocks;
@@ -204,6 +232,8 @@ int64_t voxel_scratch_words(int64_t total);  // words needed for `flags` and `st
 
 // ---- loop (icp_kernels.hip) ---------------------------------------------
 hipError_t launch_state_init(IterState* st, const double T[16], hipStream_t s);
+// FPFH descriptors of a prepared cloud (both passes).
+hipError_t launch_fpfh(const FpfhArgs& a, int sub, hipStream_t s);
 // Normals of a prepared cloud (sub: the grid's neighbourhood radius in cells).
 hipError_t launch_normals(const NormalArgs& a, int sub, hipStream_t s);
 

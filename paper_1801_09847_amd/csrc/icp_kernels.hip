@@ -1104,6 +1104,209 @@ __global__ __launch_bounds__(kNormBlock) void normals_kernel(NormalArgs na) {
   if (na.counts) glb(na.counts)[oi] = (int32_t)m;
 }
 
+// ---- FPFH ---------------------------------------------------------------
+// Pair features of (p_i, n_i) and (p_j, n_j), in float64 from the float32
+// inputs with every dot and cross product evaluated left to right: the
+// source is the end whose normal makes the smaller angle with the line to
+// the other end; Darboux frame u = n_s, v = unit(u x e), w = u x v; features
+// alpha = v . n_t, phi = u . e, theta = atan2(w . n_t, u . n_t), binned into
+// 11 bins each.  False for a pair at zero distance or with u parallel to e.
+__device__ inline double dot3(const double a[3], const double b[3]) {
+  return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2];
+}
+__device__ inline void cross3(const double a[3], const double b[3], double c[3]) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+__device__ inline int fpfh_bin(double x) {
+  const double f = floor(x);
+  return f < 0.0 ? 0 : (f > 10.0 ? 10 : (int)f);
+}
+__device__ inline bool pair_bins(const double pi[3], const double ni[3], const double pj[3], const double nj[3],
+                                 int bins[3]) {
+  double delta[3] = {pj[0] - pi[0], pj[1] - pi[1], pj[2] - pi[2]};
+  const double d = sqrt(dot3(delta, delta));
+  const bool fwd = dot3(ni, delta) >= -dot3(nj, delta);
+  const double* u = fwd ? ni : nj;
+  const double* nt = fwd ? nj : ni;
+  double e[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) e[a] = (fwd ? delta[a] : -delta[a]) / d;
+  double c[3];
+  cross3(u, e, c);
+  const double cn = sqrt(dot3(c, c));
+  if (!(d > 0.0) || !(cn > 0.0)) return false;
+  const double v[3] = {c[0] / cn, c[1] / cn, c[2] / cn};
+  double w[3];
+  cross3(u, v, w);
+  const double alpha = dot3(v, nt), phi = dot3(u, e);
+  const double theta = atan2(dot3(w, nt), dot3(u, nt));
+  constexpr double kThetaScale = 11.0 / (2.0 * M_PI);
+  bins[0] = fpfh_bin((alpha + 1.0) * 5.5);
+  bins[1] = 11 + fpfh_bin((phi + 1.0) * 5.5);
+  bins[2] = 22 + fpfh_bin((theta + M_PI) * kThetaScale);
+  return true;
+}
+
+// Pass 1: neighbourhood selection exactly as the normals kernel (count, LDS
+// heap when the radius holds more than max_nn, then the key bound), then the
+// selected neighbours' pair bins, counted in the lane's LDS column (the heap
+// is dead by then).  Writes the neighbour list (grid order), its size, the
+// bin counts and the number of pairs counted.
+template <int R>
+__global__ __launch_bounds__(kFpfhBlock) void fpfh_spfh_kernel(FpfhArgs fa) {
+  extern __shared__ uint64_t fheap[];  // [max(max_nn, 33)][kFpfhBlock]: each lane's heap is a column
+  __shared__ __align__(16) uint32_t fscratch[kFpfhBlock / kWave][WaveScratch<R>::kRangeWords];
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  uint2* lane_ranges = reinterpret_cast<uint2*>(fscratch[w]) + lane;
+  const int64_t i = (int64_t)blockIdx.x * kFpfhBlock + threadIdx.x;
+  if (i >= fa.n) return;  // no block-wide synchronisation below
+  const float qx = glb(fa.sx)[i], qy = glb(fa.sy)[i], qz = glb(fa.sz)[i];
+  PassArgs pa{};
+  pa.g = fa.g;
+  pa.r2f = fa.r2f;
+  pa.inv_h2 = fa.inv_h2;
+  pa.cs = fa.cs;
+  const uint32_t total = stage_rows<R>(pa, qx, qy, qz, lane_ranges, ~0ull);
+  const float r2f = fa.r2f;
+  auto key_of = [&](const float4& p) {
+    const float dx = qx - p.x, dy = qy - p.y, dz = qz - p.z;
+    float d2 = dx * dx + dy * dy;
+    d2 = d2 + dz * dz;
+    return d2 <= r2f ? ((uint64_t)__float_as_uint(d2) << 32) | (uint64_t)__float_as_uint(p.w) : ~0ull;
+  };
+  uint32_t within = 0;
+  for_each_candidate(fa.tp, lane_ranges, total, [&](const float4& p, uint32_t) {
+    within += key_of(p) != ~0ull ? 1u : 0u;
+  });
+  const uint32_t K = (uint32_t)fa.max_nn;
+  uint64_t* H = fheap + threadIdx.x;  // H[k * kFpfhBlock]
+  uint64_t kth = ~0ull - 1;           // every in-radius key is below it
+  if (within > K) {
+    uint32_t size = 0;
+    for_each_candidate(fa.tp, lane_ranges, total, [&](const float4& p, uint32_t) {
+      const uint64_t key = key_of(p);
+      if (key == ~0ull) return;
+      if (size < K) {
+        uint32_t at = size++;
+        while (at > 0) {  // sift up
+          const uint32_t up = (at - 1) >> 1;
+          const uint64_t hu = H[up * kFpfhBlock];
+          if (hu >= key) break;
+          H[at * kFpfhBlock] = hu;
+          at = up;
+        }
+        H[at * kFpfhBlock] = key;
+      } else if (key < H[0]) {
+        uint32_t at = 0;
+        for (;;) {  // sift down from the root
+          const uint32_t l = 2 * at + 1;
+          if (l >= K) break;
+          uint32_t c = l;
+          uint64_t hc = H[l * kFpfhBlock];
+          if (l + 1 < K) {
+            const uint64_t hr = H[(l + 1) * kFpfhBlock];
+            if (hr > hc) {
+              c = l + 1;
+              hc = hr;
+            }
+          }
+          if (hc <= key) break;
+          H[at * kFpfhBlock] = hc;
+          at = c;
+        }
+        H[at * kFpfhBlock] = key;
+      }
+    });
+    kth = H[0];
+  }
+  // the lane's histogram: the first 33 entries of its own (now free) heap
+  // column, so no lane touches another's
+  uint64_t* hist = H;  // hist[b * kFpfhBlock]
+#pragma unroll
+  for (int b = 0; b < kFpfhBins; ++b) hist[b * kFpfhBlock] = 0ull;
+  const int64_t oi = glb(fa.sperm)[i];
+  const double pi[3] = {(double)qx, (double)qy, (double)qz};
+  const double ni[3] = {(double)glb(fa.nrm)[3 * oi], (double)glb(fa.nrm)[3 * oi + 1], (double)glb(fa.nrm)[3 * oi + 2]};
+  ICP_G int32_t* list = glb(fa.nbr) + oi * (int64_t)fa.max_nn;
+  uint32_t m = 0, pairs = 0;
+  for_each_candidate(fa.tp, lane_ranges, total, [&](const float4& p, uint32_t) {
+    const uint64_t key = key_of(p);
+    if (key > kth) return;
+    const int32_t j = (int32_t)__float_as_uint(p.w);
+    list[m++] = j;
+    if ((int64_t)j == oi) return;
+    const double pj[3] = {(double)p.x, (double)p.y, (double)p.z};
+    const double nj[3] = {(double)glb(fa.nrm)[3 * (int64_t)j], (double)glb(fa.nrm)[3 * (int64_t)j + 1],
+                          (double)glb(fa.nrm)[3 * (int64_t)j + 2]};
+    int bins[3];
+    if (!pair_bins(pi, ni, pj, nj, bins)) return;
+    ++pairs;
+#pragma unroll
+    for (int f = 0; f < 3; ++f) hist[bins[f] * kFpfhBlock] += 1ull;
+  });
+  ICP_G uint32_t* cw = glb(fa.counts) + oi * kFpfhCountWords;
+#pragma unroll
+  for (int wd = 0; wd < kFpfhCountWords; ++wd) {
+    uint32_t word = 0;
+#pragma unroll
+    for (int by = 0; by < 4; ++by) {
+      const int b = 4 * wd + by;
+      if (b < kFpfhBins) word |= ((uint32_t)hist[b * kFpfhBlock] & 0xffu) << (8 * by);
+    }
+    cw[wd] = word;
+  }
+  glb(fa.k)[oi] = (int32_t)pairs;
+  glb(fa.nn)[oi] = (int32_t)m;
+}
+
+// Pass 2: FPFH(i) = SPFH(i) + (1 / k') sum over the neighbours j != i at
+// non-zero distance w of SPFH(j) / w, SPFH = counts * (100 / k) (zero
+// without pairs), in float64, rounded to float32.
+__global__ __launch_bounds__(256) void fpfh_final_kernel(FpfhArgs fa) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= fa.n) return;
+  const int64_t oi = glb(fa.sperm)[i];
+  const double pi[3] = {(double)glb(fa.pts)[3 * oi], (double)glb(fa.pts)[3 * oi + 1], (double)glb(fa.pts)[3 * oi + 2]};
+  double acc[kFpfhBins];
+#pragma unroll
+  for (int b = 0; b < kFpfhBins; ++b) acc[b] = 0.0;
+  const int32_t m = glb(fa.nn)[oi];
+  const ICP_G int32_t* list = glb(fa.nbr) + oi * (int64_t)fa.max_nn;
+  int32_t kp = 0;
+  for (int32_t s = 0; s < m; ++s) {
+    const int64_t j = list[s];
+    if (j == oi) continue;
+    const double d[3] = {(double)glb(fa.pts)[3 * j] - pi[0], (double)glb(fa.pts)[3 * j + 1] - pi[1],
+                         (double)glb(fa.pts)[3 * j + 2] - pi[2]};
+    const double wgt = sqrt(dot3(d, d));
+    if (!(wgt > 0.0)) continue;
+    ++kp;
+    const int32_t kj = glb(fa.k)[j];
+    const double qj = kj > 0 ? 100.0 / (double)kj : 0.0;
+    uint32_t cw[kFpfhCountWords];
+#pragma unroll
+    for (int wd = 0; wd < kFpfhCountWords; ++wd) cw[wd] = glb(fa.counts)[j * kFpfhCountWords + wd];
+#pragma unroll
+    for (int b = 0; b < kFpfhBins; ++b) {
+      const double sj = (double)((cw[b >> 2] >> (8 * (b & 3))) & 0xffu) * qj;
+      acc[b] = acc[b] + sj / wgt;
+    }
+  }
+  const int32_t ki = glb(fa.k)[oi];
+  const double qi = ki > 0 ? 100.0 / (double)ki : 0.0;
+  uint32_t ci[kFpfhCountWords];
+#pragma unroll
+  for (int wd = 0; wd < kFpfhCountWords; ++wd) ci[wd] = glb(fa.counts)[oi * kFpfhCountWords + wd];
+  ICP_G float* o = glb(fa.out) + oi * kFpfhBins;
+#pragma unroll
+  for (int b = 0; b < kFpfhBins; ++b) {
+    const double si = (double)((ci[b >> 2] >> (8 * (b & 3))) & 0xffu) * qi;
+    o[b] = (float)(kp > 0 ? si + acc[b] / (double)kp : si);
+  }
+}
+
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 }  // namespace
@@ -1195,6 +1398,22 @@ hipError_t launch_normals(const NormalArgs& a, int sub, hipStream_t s) {
     hipLaunchKernelGGL(normals_kernel<2>, grid, block, heap, s, a);
   else
     hipLaunchKernelGGL(normals_kernel<1>, grid, block, heap, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fpfh(const FpfhArgs& a, int sub, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  if (a.max_nn < 1 || a.max_nn > kMaxFpfhNN) return hipErrorInvalidValue;
+  const int rows = a.max_nn > kFpfhBins ? a.max_nn : kFpfhBins;  // the histogram reuses 33 entries of the column
+  const size_t lds = sizeof(uint64_t) * (size_t)rows * kFpfhBlock;
+  const dim3 grid((unsigned)ceil_div(a.n, kFpfhBlock));
+  if (sub == 2)
+    hipLaunchKernelGGL(fpfh_spfh_kernel<2>, grid, dim3(kFpfhBlock), lds, s, a);
+  else
+    hipLaunchKernelGGL(fpfh_spfh_kernel<1>, grid, dim3(kFpfhBlock), lds, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fpfh_final_kernel, dim3((unsigned)ceil_div(a.n, 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

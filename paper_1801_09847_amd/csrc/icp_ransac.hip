@@ -669,6 +669,62 @@ int icp_feature_match(icp_ctx_t* ctx, const float* src_feat, int64_t n_src, cons
   return ICP_SUCCESS;
 }
 
+int icp_compute_fpfh(icp_ctx_t* ctx, const float* pts, const float* normals, int64_t n, double radius,
+                     int32_t max_nn, float* features_out, int32_t* nn_out) {
+  int rc;
+  if ((rc = check_cloud(pts, n, "pts")) != 0) return rc;
+  if (!normals || (reinterpret_cast<uintptr_t>(normals) & 3u))
+    return fail(ICP_E_INVALID_ARG, "normals is NULL or not 4-byte aligned");
+  if (!(radius > 0.0) || !std::isfinite(radius) || !std::isfinite((float)(radius * radius)))
+    return fail(ICP_E_INVALID_ARG, "radius must be > 0 with a finite float32 square");
+  if (max_nn < 1 || max_nn > kMaxFpfhNN)
+    return fail(ICP_E_INVALID_ARG, "max_nn must be in [1, " + std::to_string(kMaxFpfhNN) + "]");
+  if (!features_out) return fail(ICP_E_INVALID_ARG, "features_out is NULL");
+  if ((reinterpret_cast<uintptr_t>(features_out) & 3u) || (reinterpret_cast<uintptr_t>(nn_out) & 3u))
+    return fail(ICP_E_INVALID_ARG, "output pointer is not 4-byte aligned");
+  icp_ctx* c = nullptr;
+  if ((rc = resolve_ctx(ctx, &c)) != 0) return rc;
+  DeviceGuard dg(c->device);
+  const PairIn in{pts, n, pts, nullptr, n, radius};
+  Prep P;
+  if ((rc = prepare_pairs(c, 1, &in, &P)) != 0) return rc;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = align256(off);
+    off = o + bytes;
+    return o;
+  };
+  const size_t o_counts = take(sizeof(uint32_t) * kFpfhCountWords * (size_t)n);
+  const size_t o_k = take(sizeof(int32_t) * (size_t)n);
+  const size_t o_nbr = take(sizeof(int32_t) * (size_t)max_nn * (size_t)n);
+  const size_t o_nn = take(sizeof(int32_t) * (size_t)n);
+  HIP_TRY(c->rs.ensure(align256(off)), "hipMalloc");
+  char* base = c->rs.as<char>();
+  FpfhArgs a;
+  memset(&a, 0, sizeof a);
+  a.sx = c->sx.as<float>();
+  a.sy = c->sy.as<float>();
+  a.sz = c->sz.as<float>();
+  a.sperm = c->perm.as<uint32_t>();
+  a.n = (int32_t)n;
+  a.tp = c->tp.as<float4>();
+  a.cs = c->cs.as<uint32_t>();
+  a.g = P.g[0];
+  a.r2f = (float)(radius * radius);
+  a.inv_h2 = (float)(P.g[0].inv_h * P.g[0].inv_h);
+  a.max_nn = max_nn;
+  a.pts = pts;
+  a.nrm = normals;
+  a.counts = reinterpret_cast<uint32_t*>(base + o_counts);
+  a.k = reinterpret_cast<int32_t*>(base + o_k);
+  a.nbr = reinterpret_cast<int32_t*>(base + o_nbr);
+  a.nn = nn_out ? nn_out : reinterpret_cast<int32_t*>(base + o_nn);
+  a.out = features_out;
+  HIP_TRY(launch_fpfh(a, P.g[0].sub, c->stream), "fpfh");
+  HIP_TRY(hipStreamSynchronize(c->stream), "sync");
+  return ICP_SUCCESS;
+}
+
 int icp_ransac_validate(icp_ctx_t* ctx, const float* src_xyz, int64_t n_src, const float* tgt_xyz,
                         int64_t n_tgt, double max_corr_dist, int32_t n_hyp, const double* T,
                         int64_t* count_out, uint64_t* sumq_out) {

@@ -149,6 +149,7 @@ def lib():
         L.icp_estimate_normals.argtypes = [vp, vp, i64, dbl, i32, vp, vp, vp]
         L.icp_pose_graph_optimize.argtypes = [vp, i32, vp, i32, C.POINTER(icp_pose_edge_t), i32, i32,
                                               dbl, C.POINTER(icp_pose_graph_result_t)]
+        L.icp_compute_fpfh.argtypes = [vp, vp, vp, i64, dbl, i32, vp, vp]
         L.icp_feature_match.argtypes = [vp, vp, i64, vp, i64, i32, vp, vp]
         L.icp_ransac_validate.argtypes = [vp, vp, i64, vp, i64, dbl, i32, vp, vp, vp]
         L.icp_ransac_register.argtypes = [vp, vp, i64, vp, i64, vp, C.POINTER(icp_ransac_params_t),
@@ -165,7 +166,7 @@ def lib():
                      "icp_normal_equations", "icp_ctx_set_profiling", "icp_ctx_get_profile",
                      "icp_register_batch", "icp_voxel_downsample", "icp_register_multiscale",
                      "icp_estimate_normals", "icp_register_robust", "icp_normal_equations_robust",
-                     "icp_pose_graph_optimize", "icp_feature_match", "icp_ransac_validate",
+                     "icp_pose_graph_optimize", "icp_feature_match", "icp_ransac_validate", "icp_compute_fpfh",
                      "icp_ransac_register",
                      "icp_server_create", "icp_server_submit", "icp_server_step", "icp_server_poll",
                      "icp_server_wait", "icp_server_destroy"):
@@ -408,6 +409,22 @@ def pose_graph_optimize(poses, edges, method="lm", max_iter=50, rel_tol=1e-10,
                                          C.byref(out)))
     return P.reshape(-1, 4, 4), {"F_initial": out.F_initial, "F_final": out.F_final,
                                  "steps": out.steps, "status": out.status}
+
+
+def compute_fpfh(pts, normals, radius, max_nn=100, ctx: Context | None = None, with_nn=False):
+    """FPFH descriptors (device (N, 33) float32) of a device cloud with unit
+    normals, hybrid (radius, max_nn) neighbourhood; with_nn also returns the
+    neighbourhood sizes (device int32)."""
+    import torch
+    pp, n = _dev_pts(pts, "pts")
+    npn, nn_ = _dev_pts(normals, "normals")
+    if nn_ != n:
+        raise IcpError(ICP_E_INVALID_ARG, "normals must have one row per point")
+    out = torch.empty((n, 33), dtype=torch.float32, device=pts.device)
+    cnt = torch.empty((n,), dtype=torch.int32, device=pts.device) if with_nn else None
+    _check(lib().icp_compute_fpfh(ctx.handle if ctx else None, pp, npn, n, float(radius), int(max_nn),
+                                  out.data_ptr(), cnt.data_ptr() if cnt is not None else None))
+    return (out, cnt) if with_nn else out
 
 
 def feature_match(src_feat, tgt_feat, ctx: Context | None = None, with_dist=False):

@@ -230,3 +230,19 @@ def test_ransac_validation():
     assert L.icp_feature_match(None, FAKE, -1, FAKE, 10, 33, m.ctypes.data, None) == E
     assert L.icp_feature_match(None, FAKE, 10, FAKE, 10, 33, None, None) == E
     assert L.icp_feature_match(None, FAKE, 10, FAKE, 10, 33, MISALIGNED, None) == E
+
+
+def test_fpfh_validation():
+    L = icp.lib()
+    E = icp.ICP_E_INVALID_ARG
+    out = FAKE
+    assert L.icp_compute_fpfh(None, None, FAKE, 10, 0.25, 100, out, None) == E
+    assert L.icp_compute_fpfh(None, FAKE, None, 10, 0.25, 100, out, None) == E
+    assert L.icp_compute_fpfh(None, FAKE, MISALIGNED, 10, 0.25, 100, out, None) == E
+    assert L.icp_compute_fpfh(None, FAKE, FAKE, 0, 0.25, 100, out, None) == E
+    assert L.icp_compute_fpfh(None, FAKE, FAKE, 10, 0.0, 100, out, None) == E
+    assert L.icp_compute_fpfh(None, FAKE, FAKE, 10, float("inf"), 100, out, None) == E
+    assert L.icp_compute_fpfh(None, FAKE, FAKE, 10, 0.25, 0, out, None) == E
+    assert L.icp_compute_fpfh(None, FAKE, FAKE, 10, 0.25, 129, out, None) == E
+    assert L.icp_compute_fpfh(None, FAKE, FAKE, 10, 0.25, 100, None, None) == E
+    assert L.icp_compute_fpfh(None, FAKE, FAKE, 10, 0.25, 100, MISALIGNED, None) == E

@@ -105,12 +105,12 @@ struct ValidateArgs {
 constexpr int kMaxValidateHyp = 65535;  // hypotheses per validation launch
 
 // FPFH descriptors of one cloud prepared as both queries and grid (as for
-// normals).  Pass 1 (per point): the hybrid neighbourhood, its list and the
-// SPFH bin counts; pass 2: the distance-weighted sum over the neighbours.
-constexpr int kFpfhBlock = 64;    // threads per block of the SPFH pass (one wave)
-constexpr int kMaxFpfhNN = 128;   // largest max_nn (per-lane heap in LDS; counts fit a byte)
+// normals), one wave per point: the hybrid neighbourhood and its list, the
+// SPFH bin counts of the pairs, then the distance-weighted sum.
+constexpr int kFpfhBlock = 256;   // threads per block of the FPFH kernels (one wave per point)
+constexpr int kMaxFpfhNN = 128;   // largest max_nn (counts fit a byte)
 constexpr int kFpfhBins = 33;     // three 11-bin sub-histograms
-constexpr int kFpfhCountWords = 9;  // 33 byte counts padded to 9 words per point
+constexpr int kFpfhCountBytes = 36;  // 33 byte counts per point, padded
 struct FpfhArgs {
   const float* sx;        // Morton-ordered points
   const float* sy;
@@ -125,7 +125,7 @@ struct FpfhArgs {
   int32_t max_nn;
   const float* pts;       // (n, 3) original order
   const float* nrm;       // (n, 3) original order, unit normals
-  uint32_t* counts;       // (n, 9) words: byte b = SPFH count of bin b
+  uint8_t* counts;        // (n, 36) bytes: SPFH count of bin b at byte b
   int32_t* k;             // (n) pairs counted
   int32_t* nbr;           // (n, max_nn) neighbour original indices
   int32_t* nn;            // (n) neighbourhood sizes

@@ -1149,131 +1149,148 @@ __device__ inline bool pair_bins(const double pi[3], const double ni[3], const d
   return true;
 }
 
-// Pass 1: neighbourhood selection exactly as the normals kernel (count, LDS
-// heap when the radius holds more than max_nn, then the key bound), then the
-// selected neighbours' pair bins, counted in the lane's LDS column (the heap
-// is dead by then).  Writes the neighbour list (grid order), its size, the
-// bin counts and the number of pairs counted.
+// FPFH runs one wave per point in three launches (a thread per point would
+// leave most SIMDs idle at the point counts of a downsampled cloud).
+//
+// Selection: every lane stages the point's candidate rows (the same rows, so
+// the table loads are broadcasts) and the wave walks the flattened candidate
+// list 64 at a time, lane L taking candidate base + L.  The in-radius count
+// is a ballot sum; when it exceeds max_nn the max_nn-th smallest (pinned
+// float32 squared distance, index) key is found by a binary search over the
+// key space (64 counting passes, only for such points); the selected
+// candidates are then written in candidate order by ballot-prefix compaction.
 template <int R>
-__global__ __launch_bounds__(kFpfhBlock) void fpfh_spfh_kernel(FpfhArgs fa) {
-  extern __shared__ uint64_t fheap[];  // [max(max_nn, 33)][kFpfhBlock]: each lane's heap is a column
+__global__ __launch_bounds__(kFpfhBlock) void fpfh_select_kernel(FpfhArgs fa) {
   __shared__ __align__(16) uint32_t fscratch[kFpfhBlock / kWave][WaveScratch<R>::kRangeWords];
   const int w = threadIdx.x / kWave, lane = lane_id();
-  uint2* lane_ranges = reinterpret_cast<uint2*>(fscratch[w]) + lane;
-  const int64_t i = (int64_t)blockIdx.x * kFpfhBlock + threadIdx.x;
-  if (i >= fa.n) return;  // no block-wide synchronisation below
+  uint2* ranges = reinterpret_cast<uint2*>(fscratch[w]) + lane;  // this lane's copy: ranges[slot * kWave]
+  const int64_t i = (int64_t)blockIdx.x * (kFpfhBlock / kWave) + w;
+  if (i >= fa.n) return;  // whole waves; no block-wide synchronisation below
   const float qx = glb(fa.sx)[i], qy = glb(fa.sy)[i], qz = glb(fa.sz)[i];
   PassArgs pa{};
   pa.g = fa.g;
   pa.r2f = fa.r2f;
   pa.inv_h2 = fa.inv_h2;
   pa.cs = fa.cs;
-  const uint32_t total = stage_rows<R>(pa, qx, qy, qz, lane_ranges, ~0ull);
+  const uint32_t total = stage_rows<R>(pa, qx, qy, qz, ranges, ~0ull);
   const float r2f = fa.r2f;
-  auto key_of = [&](const float4& p) {
+  // candidate base + lane: the lane's (slot, position) advance monotonically
+  struct Walker {
+    const uint2* ranges;
+    int slot;
+    uint32_t before;  // candidates in slots before `slot`
+    uint2 e;
+    __device__ uint32_t at(uint32_t k) {
+      while (k >= before + (e.y - e.x)) {
+        before += e.y - e.x;
+        ++slot;
+        e = ranges[slot * kWave];
+      }
+      return e.x + (k - before);
+    }
+  };
+  auto key_at = [&](uint32_t pos) {
+    const float4 p = ld4(fa.tp, pos);
     const float dx = qx - p.x, dy = qy - p.y, dz = qz - p.z;
     float d2 = dx * dx + dy * dy;
     d2 = d2 + dz * dz;
     return d2 <= r2f ? ((uint64_t)__float_as_uint(d2) << 32) | (uint64_t)__float_as_uint(p.w) : ~0ull;
   };
-  uint32_t within = 0;
-  for_each_candidate(fa.tp, lane_ranges, total, [&](const float4& p, uint32_t) {
-    within += key_of(p) != ~0ull ? 1u : 0u;
-  });
-  const uint32_t K = (uint32_t)fa.max_nn;
-  uint64_t* H = fheap + threadIdx.x;  // H[k * kFpfhBlock]
-  uint64_t kth = ~0ull - 1;           // every in-radius key is below it
-  if (within > K) {
-    uint32_t size = 0;
-    for_each_candidate(fa.tp, lane_ranges, total, [&](const float4& p, uint32_t) {
-      const uint64_t key = key_of(p);
-      if (key == ~0ull) return;
-      if (size < K) {
-        uint32_t at = size++;
-        while (at > 0) {  // sift up
-          const uint32_t up = (at - 1) >> 1;
-          const uint64_t hu = H[up * kFpfhBlock];
-          if (hu >= key) break;
-          H[at * kFpfhBlock] = hu;
-          at = up;
-        }
-        H[at * kFpfhBlock] = key;
-      } else if (key < H[0]) {
-        uint32_t at = 0;
-        for (;;) {  // sift down from the root
-          const uint32_t l = 2 * at + 1;
-          if (l >= K) break;
-          uint32_t c = l;
-          uint64_t hc = H[l * kFpfhBlock];
-          if (l + 1 < K) {
-            const uint64_t hr = H[(l + 1) * kFpfhBlock];
-            if (hr > hc) {
-              c = l + 1;
-              hc = hr;
-            }
-          }
-          if (hc <= key) break;
-          H[at * kFpfhBlock] = hc;
-          at = c;
-        }
-        H[at * kFpfhBlock] = key;
-      }
-    });
-    kth = H[0];
-  }
-  // the lane's histogram: the first 33 entries of its own (now free) heap
-  // column, so no lane touches another's
-  uint64_t* hist = H;  // hist[b * kFpfhBlock]
-#pragma unroll
-  for (int b = 0; b < kFpfhBins; ++b) hist[b * kFpfhBlock] = 0ull;
-  const int64_t oi = glb(fa.sperm)[i];
-  const double pi[3] = {(double)qx, (double)qy, (double)qz};
-  const double ni[3] = {(double)glb(fa.nrm)[3 * oi], (double)glb(fa.nrm)[3 * oi + 1], (double)glb(fa.nrm)[3 * oi + 2]};
-  ICP_G int32_t* list = glb(fa.nbr) + oi * (int64_t)fa.max_nn;
-  uint32_t m = 0, pairs = 0;
-  for_each_candidate(fa.tp, lane_ranges, total, [&](const float4& p, uint32_t) {
-    const uint64_t key = key_of(p);
-    if (key > kth) return;
-    const int32_t j = (int32_t)__float_as_uint(p.w);
-    list[m++] = j;
-    if ((int64_t)j == oi) return;
-    const double pj[3] = {(double)p.x, (double)p.y, (double)p.z};
-    const double nj[3] = {(double)glb(fa.nrm)[3 * (int64_t)j], (double)glb(fa.nrm)[3 * (int64_t)j + 1],
-                          (double)glb(fa.nrm)[3 * (int64_t)j + 2]};
-    int bins[3];
-    if (!pair_bins(pi, ni, pj, nj, bins)) return;
-    ++pairs;
-#pragma unroll
-    for (int f = 0; f < 3; ++f) hist[bins[f] * kFpfhBlock] += 1ull;
-  });
-  ICP_G uint32_t* cw = glb(fa.counts) + oi * kFpfhCountWords;
-#pragma unroll
-  for (int wd = 0; wd < kFpfhCountWords; ++wd) {
-    uint32_t word = 0;
-#pragma unroll
-    for (int by = 0; by < 4; ++by) {
-      const int b = 4 * wd + by;
-      if (b < kFpfhBins) word |= ((uint32_t)hist[b * kFpfhBlock] & 0xffu) << (8 * by);
+  auto count_le = [&](uint64_t bound) {
+    uint32_t c = 0;
+    if (total == 0) return c;
+    Walker wk{ranges, 0, 0u, ranges[0]};
+    for (uint32_t base = 0; base < total; base += kWave) {
+      const uint32_t k = base + (uint32_t)lane;
+      bool hit = false;
+      if (k < total) hit = key_at(wk.at(k)) <= bound;
+      c += (uint32_t)__popcll(__ballot(hit));
     }
-    cw[wd] = word;
+    return c;
+  };
+  const uint32_t K = (uint32_t)fa.max_nn;
+  const uint32_t within = count_le(~0ull - 1);
+  uint64_t kth = ~0ull - 1;
+  if (within > K) {
+    uint64_t lo = 0, hi = ~0ull - 1;  // count_le(hi) >= K
+    while (lo < hi) {
+      const uint64_t mid = lo + ((hi - lo) >> 1);
+      if (count_le(mid) >= K) hi = mid; else lo = mid + 1;
+    }
+    kth = lo;
   }
-  glb(fa.k)[oi] = (int32_t)pairs;
-  glb(fa.nn)[oi] = (int32_t)m;
+  const int64_t oi = glb(fa.sperm)[i];
+  ICP_G int32_t* list = glb(fa.nbr) + oi * (int64_t)fa.max_nn;
+  uint32_t m = 0;
+  if (total > 0) {
+    Walker wk{ranges, 0, 0u, ranges[0]};
+    for (uint32_t base = 0; base < total; base += kWave) {
+      const uint32_t k = base + (uint32_t)lane;
+      bool sel = false;
+      int32_t j = 0;
+      if (k < total) {
+        const uint32_t pos = wk.at(k);
+        sel = key_at(pos) <= kth;
+        j = (int32_t)__float_as_uint(ld4(fa.tp, pos).w);
+      }
+      const uint64_t b = __ballot(sel);
+      if (sel) list[m + (uint32_t)__popcll(b & ((1ull << lane) - 1ull))] = j;
+      m += (uint32_t)__popcll(b);
+    }
+  }
+  if (lane == 0) glb(fa.nn)[oi] = (int32_t)m;
 }
 
-// Pass 2: FPFH(i) = SPFH(i) + (1 / k') sum over the neighbours j != i at
-// non-zero distance w of SPFH(j) / w, SPFH = counts * (100 / k) (zero
-// without pairs), in float64, rounded to float32.
-__global__ __launch_bounds__(256) void fpfh_final_kernel(FpfhArgs fa) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+// Pair bins: lane s takes neighbour s (two rounds for max_nn > 64); the
+// point's 33 counts are ballot sums, written by lanes 0..32.
+__global__ __launch_bounds__(kFpfhBlock) void fpfh_pairs_kernel(FpfhArgs fa) {
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  const int64_t i = (int64_t)blockIdx.x * (kFpfhBlock / kWave) + w;
   if (i >= fa.n) return;
   const int64_t oi = glb(fa.sperm)[i];
-  const double pi[3] = {(double)glb(fa.pts)[3 * oi], (double)glb(fa.pts)[3 * oi + 1], (double)glb(fa.pts)[3 * oi + 2]};
-  double acc[kFpfhBins];
-#pragma unroll
-  for (int b = 0; b < kFpfhBins; ++b) acc[b] = 0.0;
   const int32_t m = glb(fa.nn)[oi];
   const ICP_G int32_t* list = glb(fa.nbr) + oi * (int64_t)fa.max_nn;
+  const double pi[3] = {(double)glb(fa.sx)[i], (double)glb(fa.sy)[i], (double)glb(fa.sz)[i]};
+  const double ni[3] = {(double)glb(fa.nrm)[3 * oi], (double)glb(fa.nrm)[3 * oi + 1], (double)glb(fa.nrm)[3 * oi + 2]};
+  uint32_t mine = 0, pairs = 0;
+  for (int32_t base = 0; base < m; base += kWave) {
+    const int32_t s = base + lane;
+    int bins[3] = {-1, -1, -1};
+    bool ok = false;
+    if (s < m) {
+      const int64_t j = list[s];
+      if (j != oi) {
+        const double pj[3] = {(double)glb(fa.pts)[3 * j], (double)glb(fa.pts)[3 * j + 1], (double)glb(fa.pts)[3 * j + 2]};
+        const double nj[3] = {(double)glb(fa.nrm)[3 * j], (double)glb(fa.nrm)[3 * j + 1], (double)glb(fa.nrm)[3 * j + 2]};
+        ok = pair_bins(pi, ni, pj, nj, bins);
+      }
+    }
+    if (!ok) bins[0] = bins[1] = bins[2] = -1;
+    pairs += (uint32_t)__popcll(__ballot(ok));
+#pragma unroll
+    for (int b = 0; b < kFpfhBins; ++b) {
+      const int f = b / 11;
+      const uint32_t c = (uint32_t)__popcll(__ballot(bins[f] == b));
+      if (lane == b) mine += c;
+    }
+  }
+  if (lane < kFpfhBins) glb(fa.counts)[oi * kFpfhCountBytes + lane] = (uint8_t)mine;
+  if (lane == 0) glb(fa.k)[oi] = (int32_t)pairs;
+}
+
+// FPFH(i) = SPFH(i) + (1 / k') sum over the neighbours j != i at non-zero
+// distance w of SPFH(j) / w, SPFH = counts * (100 / k) (zero without pairs),
+// in float64 in neighbour-list order, rounded to float32; lane b owns bin b.
+__global__ __launch_bounds__(kFpfhBlock) void fpfh_final_kernel(FpfhArgs fa) {
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  const int64_t i = (int64_t)blockIdx.x * (kFpfhBlock / kWave) + w;
+  if (i >= fa.n) return;
+  const int64_t oi = glb(fa.sperm)[i];
+  const int b = lane < kFpfhBins ? lane : 0;
+  const double pi[3] = {(double)glb(fa.sx)[i], (double)glb(fa.sy)[i], (double)glb(fa.sz)[i]};
+  const int32_t m = glb(fa.nn)[oi];
+  const ICP_G int32_t* list = glb(fa.nbr) + oi * (int64_t)fa.max_nn;
+  double acc = 0.0;
   int32_t kp = 0;
   for (int32_t s = 0; s < m; ++s) {
     const int64_t j = list[s];
@@ -1285,26 +1302,13 @@ __global__ __launch_bounds__(256) void fpfh_final_kernel(FpfhArgs fa) {
     ++kp;
     const int32_t kj = glb(fa.k)[j];
     const double qj = kj > 0 ? 100.0 / (double)kj : 0.0;
-    uint32_t cw[kFpfhCountWords];
-#pragma unroll
-    for (int wd = 0; wd < kFpfhCountWords; ++wd) cw[wd] = glb(fa.counts)[j * kFpfhCountWords + wd];
-#pragma unroll
-    for (int b = 0; b < kFpfhBins; ++b) {
-      const double sj = (double)((cw[b >> 2] >> (8 * (b & 3))) & 0xffu) * qj;
-      acc[b] = acc[b] + sj / wgt;
-    }
+    const double sj = (double)glb(fa.counts)[j * kFpfhCountBytes + b] * qj;
+    acc = acc + sj / wgt;
   }
   const int32_t ki = glb(fa.k)[oi];
   const double qi = ki > 0 ? 100.0 / (double)ki : 0.0;
-  uint32_t ci[kFpfhCountWords];
-#pragma unroll
-  for (int wd = 0; wd < kFpfhCountWords; ++wd) ci[wd] = glb(fa.counts)[oi * kFpfhCountWords + wd];
-  ICP_G float* o = glb(fa.out) + oi * kFpfhBins;
-#pragma unroll
-  for (int b = 0; b < kFpfhBins; ++b) {
-    const double si = (double)((ci[b >> 2] >> (8 * (b & 3))) & 0xffu) * qi;
-    o[b] = (float)(kp > 0 ? si + acc[b] / (double)kp : si);
-  }
+  const double si = (double)glb(fa.counts)[oi * kFpfhCountBytes + b] * qi;
+  if (lane < kFpfhBins) glb(fa.out)[oi * kFpfhBins + lane] = (float)(kp > 0 ? si + acc / (double)kp : si);
 }
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -1404,16 +1408,16 @@ hipError_t launch_normals(const NormalArgs& a, int sub, hipStream_t s) {
 hipError_t launch_fpfh(const FpfhArgs& a, int sub, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
   if (a.max_nn < 1 || a.max_nn > kMaxFpfhNN) return hipErrorInvalidValue;
-  const int rows = a.max_nn > kFpfhBins ? a.max_nn : kFpfhBins;  // the histogram reuses 33 entries of the column
-  const size_t lds = sizeof(uint64_t) * (size_t)rows * kFpfhBlock;
-  const dim3 grid((unsigned)ceil_div(a.n, kFpfhBlock));
+  const dim3 grid((unsigned)ceil_div(a.n, kFpfhBlock / kWave)), block(kFpfhBlock);
   if (sub == 2)
-    hipLaunchKernelGGL(fpfh_spfh_kernel<2>, grid, dim3(kFpfhBlock), lds, s, a);
+    hipLaunchKernelGGL(fpfh_select_kernel<2>, grid, block, 0, s, a);
   else
-    hipLaunchKernelGGL(fpfh_spfh_kernel<1>, grid, dim3(kFpfhBlock), lds, s, a);
+    hipLaunchKernelGGL(fpfh_select_kernel<1>, grid, block, 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(fpfh_final_kernel, dim3((unsigned)ceil_div(a.n, 256)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(fpfh_pairs_kernel, grid, block, 0, s, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(fpfh_final_kernel, grid, block, 0, s, a);
   return hipGetLastError();
 }
 

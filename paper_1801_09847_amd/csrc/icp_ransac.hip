@@ -694,7 +694,7 @@ int icp_compute_fpfh(icp_ctx_t* ctx, const float* pts, const float* normals, int
     off = o + bytes;
     return o;
   };
-  const size_t o_counts = take(sizeof(uint32_t) * kFpfhCountWords * (size_t)n);
+  const size_t o_counts = take((size_t)kFpfhCountBytes * (size_t)n);
   const size_t o_k = take(sizeof(int32_t) * (size_t)n);
   const size_t o_nbr = take(sizeof(int32_t) * (size_t)max_nn * (size_t)n);
   const size_t o_nn = take(sizeof(int32_t) * (size_t)n);
@@ -715,7 +715,7 @@ int icp_compute_fpfh(icp_ctx_t* ctx, const float* pts, const float* normals, int
   a.max_nn = max_nn;
   a.pts = pts;
   a.nrm = normals;
-  a.counts = reinterpret_cast<uint32_t*>(base + o_counts);
+  a.counts = reinterpret_cast<uint8_t*>(base + o_counts);
   a.k = reinterpret_cast<int32_t*>(base + o_k);
   a.nbr = reinterpret_cast<int32_t*>(base + o_nbr);
   a.nn = nn_out ? nn_out : reinterpret_cast<int32_t*>(base + o_nn);

@@ -210,6 +210,12 @@ typedef struct {
  *   out    host array of n_pairs results
  * All pairs share `variant` and `precision`.  Errors: as icp_register; on any
  * error no result is written; icp_last_error() names the offending pair. */
+/* icp_register_batch with one robust loss for every pair (the IRLS weights of
+ * icp_register_robust); a pair's result equals icp_register_robust's for it
+ * alone, bitwise.  Errors: as icp_register_batch, INVALID_ARG for the loss. */
+int icp_register_batch_robust(icp_ctx_t *ctx, const icp_pair_t *pairs, int32_t n_pairs, int32_t variant,
+                              int32_t precision, int32_t loss, double loss_k, icp_result_t *out);
+
 int icp_register_batch(icp_ctx_t *ctx, const icp_pair_t *pairs, int32_t n_pairs, int32_t variant,
                        int32_t precision, icp_result_t *out);
 

@@ -532,7 +532,9 @@ int run_loop(icp_ctx* c, const Prep& P, const LoopIn* in, bool normals, int vari
   uint2* hit = reinterpret_cast<uint2*>(hh + L.items);
   int32_t iters = 0;
   int64_t item = 0;
+  bool robust = false;
   for (int p = 0; p < n; ++p) {
+    robust = robust || in[p].loss != ICP_LOSS_NONE;
     hp[p] = pass_args(c, P, p, in[p].r, true, normals);
     set_loss(&hp[p], in[p].loss, in[p].loss_k);
     hs[p] = SolveArgs{hp[p].part, hp[p].n_blocks, const_cast<IterState*>(hp[p].st),
@@ -556,7 +558,7 @@ int run_loop(icp_ctx* c, const Prep& P, const LoopIn* in, bool normals, int vari
     if (n == 1)
       HIP_TRY(launch_pass(hp[0], variant, precision, false, s), "pass");
     else
-      HIP_TRY(launch_batch_pass(dp, di, (int)P.total_tiles, P.sub, variant, precision, s), "pass");
+      HIP_TRY(launch_batch_pass(dp, di, (int)P.total_tiles, P.sub, variant, precision, robust, s), "pass");
     if (prof) HIP_TRY(hipEventRecord(c->ev[3 + 2 * k], s), "hipEventRecord");
     if (n == 1)
       HIP_TRY(launch_solve(hs[0], reinterpret_cast<double*>(dd + L.red), s), "solve");
@@ -798,9 +800,15 @@ int icp_register_robust(icp_ctx_t* ctx, const float* src_xyz, int64_t n_src, con
 
 int icp_register_batch(icp_ctx_t* ctx, const icp_pair_t* pairs, int32_t n_pairs, int32_t variant,
                        int32_t precision, icp_result_t* out) {
+  return icp_register_batch_robust(ctx, pairs, n_pairs, variant, precision, ICP_LOSS_NONE, 1.0, out);
+}
+
+int icp_register_batch_robust(icp_ctx_t* ctx, const icp_pair_t* pairs, int32_t n_pairs, int32_t variant,
+                              int32_t precision, int32_t loss, double loss_k, icp_result_t* out) {
   if (!pairs || !out) return fail(ICP_E_INVALID_ARG, "pairs / out is NULL");
   if (n_pairs < 1) return fail(ICP_E_INVALID_ARG, "n_pairs must be >= 1");
   int rc;
+  if ((rc = check_loss(loss, loss_k)) != 0) return rc;
   int64_t total_src = 0, total_tgt = 0;
   for (int p = 0; p < n_pairs; ++p) {
     const icp_pair_t& q = pairs[p];
@@ -827,7 +835,7 @@ int icp_register_batch(icp_ctx_t* ctx, const icp_pair_t* pairs, int32_t n_pairs,
     const icp_pair_t& q = pairs[p];
     in[p] = PairIn{q.src_xyz, q.n_src, q.tgt_xyz, plane ? q.tgt_normals : nullptr, q.n_tgt,
                    q.max_corr_dist};
-    li[p] = LoopIn{q.T_init, q.max_corr_dist, q.max_iter, q.rel_tol};
+    li[p] = LoopIn{q.T_init, q.max_corr_dist, q.max_iter, q.rel_tol, loss, loss_k};
   }
   Prep P;
   if ((rc = prepare_pairs(c, n_pairs, in.data(), &P)) != 0) return rc;

@@ -246,8 +246,9 @@ hipError_t launch_validate(const ValidateArgs& a, int sub, hipStream_t s);
 hipError_t launch_solve(const SolveArgs& a, double* red, hipStream_t s);
 
 // Batched forms: `pairs` / `items` / `arr` are device arrays.
+// robust: the pairs' PassArgs carry a loss (the IRLS-weighted kernels).
 hipError_t launch_batch_pass(const PassArgs* pairs, const uint2* items, int n_items, int sub,
-                             int variant, int precision, hipStream_t s);
+                             int variant, int precision, bool robust, hipStream_t s);
 hipError_t launch_batch_solve(const SolveArgs* arr, int n_pairs, hipStream_t s);
 
 // Graph-node forms of the batched launches: kernel, block and shared memory

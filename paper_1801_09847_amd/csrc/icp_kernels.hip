@@ -639,13 +639,13 @@ __global__ __launch_bounds__(256) void validate_reduce_kernel(ValidateArgs v) {
   }
 }
 
-template <int VAR, int PREC, int R>
+template <int VAR, int PREC, int R, bool ROBUST = false>
 __global__ __launch_bounds__(kBlock) void batch_pass_kernel(const PassArgs* __restrict__ pairs,
                                                             const uint2* __restrict__ items) {
   const uint2 it = items[blockIdx.x];
   const PassArgs a = pairs[it.x];  // by value: uniform, kept in scalar registers
   if (glb(a.st)->done) return;
-  pass_tile<VAR, PREC, false, R, false>(a, it.y);
+  pass_tile<VAR, PREC, false, R, ROBUST>(a, it.y);
 }
 
 // ------------------------------------------------------------------ solve + pose update
@@ -1373,23 +1373,26 @@ hipError_t launch_solve(const SolveArgs& a, double* red, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int R>
+template <int R, bool ROBUST>
 void launch_batch_pass_r(const PassArgs* pairs, const uint2* items, int n_items, int variant,
                          int precision, hipStream_t s) {
   const dim3 grid((unsigned)n_items), block(kBlock);
-#define ICP_BPASS(V, P) hipLaunchKernelGGL((batch_pass_kernel<V, P, R>), grid, block, 0, s, pairs, items)
+#define ICP_BPASS(V, P) hipLaunchKernelGGL((batch_pass_kernel<V, P, R, ROBUST>), grid, block, 0, s, pairs, items)
   if (variant == 1) { if (precision == 0) ICP_BPASS(1, 0); else ICP_BPASS(1, 1); }
   else { if (precision == 0) ICP_BPASS(0, 0); else ICP_BPASS(0, 1); }
 #undef ICP_BPASS
 }
 
 hipError_t launch_batch_pass(const PassArgs* pairs, const uint2* items, int n_items, int sub,
-                             int variant, int precision, hipStream_t s) {
+                             int variant, int precision, bool robust, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  if (sub == 2)
-    launch_batch_pass_r<2>(pairs, items, n_items, variant, precision, s);
-  else
-    launch_batch_pass_r<1>(pairs, items, n_items, variant, precision, s);
+  if (sub == 2) {
+    if (robust) launch_batch_pass_r<2, true>(pairs, items, n_items, variant, precision, s);
+    else launch_batch_pass_r<2, false>(pairs, items, n_items, variant, precision, s);
+  } else {
+    if (robust) launch_batch_pass_r<1, true>(pairs, items, n_items, variant, precision, s);
+    else launch_batch_pass_r<1, false>(pairs, items, n_items, variant, precision, s);
+  }
   return hipGetLastError();
 }
 

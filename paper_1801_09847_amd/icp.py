@@ -143,6 +143,8 @@ def lib():
                                                   C.POINTER(C.c_int64)]
         L.icp_register_batch.argtypes = [vp, C.POINTER(icp_pair_t), i32, i32, i32,
                                          C.POINTER(icp_result_t)]
+        L.icp_register_batch_robust.argtypes = [vp, C.POINTER(icp_pair_t), i32, i32, i32, i32, dbl,
+                                                C.POINTER(icp_result_t)]
         L.icp_voxel_downsample.argtypes = [vp, vp, vp, i64, dbl, vp, vp, i64, C.POINTER(C.c_int64)]
         L.icp_register_multiscale.argtypes = [vp, vp, i64, vp, vp, i64, vp, i32, vp, vp, vp, dbl, i32,
                                               i32, C.POINTER(icp_result_t)]
@@ -164,7 +166,7 @@ def lib():
         L.icp_ctx_get_profile.argtypes = [vp, C.POINTER(icp_profile_t)]
         for name in ("icp_ctx_create", "icp_ctx_destroy", "icp_register", "icp_correspondences",
                      "icp_normal_equations", "icp_ctx_set_profiling", "icp_ctx_get_profile",
-                     "icp_register_batch", "icp_voxel_downsample", "icp_register_multiscale",
+                     "icp_register_batch", "icp_register_batch_robust", "icp_voxel_downsample", "icp_register_multiscale",
                      "icp_estimate_normals", "icp_register_robust", "icp_normal_equations_robust",
                      "icp_pose_graph_optimize", "icp_feature_match", "icp_ransac_validate", "icp_compute_fpfh",
                      "icp_ransac_register",
@@ -218,12 +220,16 @@ def icp_register(ctx, src_ptr, n_src, tgt_ptr, tgt_n_ptr, n_tgt, T_init, max_cor
     return out
 
 
-def icp_register_batch(ctx, pairs, variant, precision):
+def icp_register_batch(ctx, pairs, variant, precision, loss=ICP_LOSS_NONE, loss_k=1.0):
     """pairs: sequence of icp_pair_t; returns a list of icp_result_t."""
     n = len(pairs)
     arr = (icp_pair_t * n)(*pairs)
     out = (icp_result_t * n)()
-    _check(lib().icp_register_batch(ctx, arr, n, int(variant), int(precision), out))
+    if loss == ICP_LOSS_NONE:
+        _check(lib().icp_register_batch(ctx, arr, n, int(variant), int(precision), out))
+    else:
+        _check(lib().icp_register_batch_robust(ctx, arr, n, int(variant), int(precision), int(loss),
+                                               float(loss_k), out))
     return list(out)
 
 
@@ -342,10 +348,11 @@ def make_pair(src, tgt, tgt_normals, T_init, max_corr_dist, max_iter=30, rel_tol
 
 
 def register_batch(pairs, variant="point_to_plane", precision="kahan32",
-                   ctx: Context | None = None) -> list[IcpResult]:
-    """pairs: list of icp_pair_t (see make_pair)."""
+                   ctx: Context | None = None, loss="none", loss_k=1.0) -> list[IcpResult]:
+    """pairs: list of icp_pair_t (see make_pair); loss: a robust loss for every
+    pair (as register)."""
     res = icp_register_batch(ctx.handle if ctx else None, pairs, VARIANTS[variant],
-                             PRECISIONS[precision])
+                             PRECISIONS[precision], LOSSES[loss], loss_k)
     return [IcpResult(np.array(r.T[:], dtype=np.float64).reshape(4, 4), r.fitness, r.inlier_rmse,
                       r.n_inliers, r.n_iter, r.status) for r in res]
 

@@ -246,3 +246,14 @@ def test_fpfh_validation():
     assert L.icp_compute_fpfh(None, FAKE, FAKE, 10, 0.25, 129, out, None) == E
     assert L.icp_compute_fpfh(None, FAKE, FAKE, 10, 0.25, 100, None, None) == E
     assert L.icp_compute_fpfh(None, FAKE, FAKE, 10, 0.25, 100, MISALIGNED, None) == E
+
+
+def test_batch_robust_validation():
+    p = _pair()
+    out = (icp.icp_result_t * 1)()
+    arr = (icp.icp_pair_t * 1)(p)
+    L = icp.lib()
+    assert L.icp_register_batch_robust(None, arr, 1, 1, 0, 7, 1.0, out) == icp.ICP_E_INVALID_ARG
+    assert L.icp_register_batch_robust(None, arr, 1, 1, 0, icp.ICP_LOSS_TUKEY, 0.0, out) == icp.ICP_E_INVALID_ARG
+    assert L.icp_register_batch_robust(None, arr, 1, 1, 0, icp.ICP_LOSS_TUKEY, float("nan"), out) == \
+        icp.ICP_E_INVALID_ARG

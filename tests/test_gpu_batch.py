@@ -130,3 +130,22 @@ def test_large_pair_two_level_sum_same_bits(icp, precision):
     descs = [icp.make_pair(*ts, np.eye(4), 0.05, 12, 0.0), icp.make_pair(*tb, np.eye(4), 0.03, 12, 0.0)]
     mix = icp.register_batch(descs, "point_to_plane", precision)
     _same(mix[1], alone)
+
+
+@pytest.mark.parametrize("variant", ["point_to_plane", "point_to_point"])
+@pytest.mark.parametrize("loss,k", [("huber", 0.005), ("tukey", 0.02), ("cauchy", 0.005)])
+def test_robust_batch_equals_alone(icp, pairs_data, loss, k, variant):
+    """icp_register_batch_robust: each pair bitwise as icp_register_robust
+    alone, and different from the plain batch (the weights act)."""
+    keep = [_tensors(d) for d in pairs_data]
+    iters = [12, 10, 12, 15, 12, 15]
+    descs = [icp.make_pair(*t, d["T0"], d["max_corr_dist"], it, 0.0)
+             for t, d, it in zip(keep, pairs_data, iters)]
+    mix = icp.register_batch(descs, variant, "kahan32", loss=loss, loss_k=k)
+    plain_mix = icp.register_batch(descs, variant, "kahan32")
+    differs = 0
+    for m, t, d, it, pm in zip(mix, keep, pairs_data, iters, plain_mix):
+        alone = icp.register(*t, d["T0"], d["max_corr_dist"], it, 0.0, variant, "kahan32", loss=loss, loss_k=k)
+        _same(m, alone)
+        differs += int(not np.array_equal(m.T, pm.T))
+    assert differs >= 4

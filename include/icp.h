@@ -272,6 +272,15 @@ int icp_estimate_normals(icp_ctx_t *ctx, const float *pts, int64_t n, double rad
  * A DEGENERATE level ends the call.  `out` is the last level's result with
  * n_iter = the total number of pose updates.  n_levels in [1, 16]; arrays are
  * host memory.  Errors as icp_register / icp_voxel_downsample. */
+/* icp_register_multiscale with a robust loss at every level (the IRLS
+ * weights of icp_register_robust).  Errors: as icp_register_multiscale,
+ * INVALID_ARG for the loss. */
+int icp_register_multiscale_robust(icp_ctx_t *ctx, const float *src_xyz, int64_t n_src, const float *tgt_xyz,
+                                   const float *tgt_normals, int64_t n_tgt, const double T_init[16],
+                                   int32_t n_levels, const double *voxel, const int32_t *max_iter,
+                                   const double *max_corr_dist, double rel_tol, int32_t variant,
+                                   int32_t precision, int32_t loss, double loss_k, icp_result_t *out);
+
 int icp_register_multiscale(icp_ctx_t *ctx, const float *src_xyz, int64_t n_src, const float *tgt_xyz,
                             const float *tgt_normals, int64_t n_tgt, const double T_init[16],
                             int32_t n_levels, const double *voxel, const int32_t *max_iter,
@@ -453,7 +462,8 @@ int icp_ransac_register(icp_ctx_t *ctx, const float *src_xyz, int64_t n_src, con
  * iterations of all running requests together (one HIP graph replay: per
  * iteration one batched pass launch over every running request's tiles and
  * one batched solve launch), then retires finished levels and requests.  A request's result is bitwise the
- * one icp_register_multiscale gives for it alone.
+ * one icp_register_multiscale (icp_register_multiscale_robust with a loss)
+ * gives for it alone.
  * Level l of a request uses max_corr_dist = corr_dist[l] if > 0, else
  * corr_factor * max(voxel[l], spacing) with the request's target spacing. */
 typedef struct icp_server icp_server_t;
@@ -471,6 +481,8 @@ typedef struct {
   int32_t precision;          /* ICP_PREC_* */
   int32_t iters_per_step;     /* iterations per server step, 1..64 */
   int32_t background_thread;  /* 1: a server thread runs steps; 0: caller drives icp_server_step */
+  int32_t loss;               /* ICP_LOSS_* for every request (0: plain ICP) */
+  double loss_k;              /* its scale (ignored for ICP_LOSS_NONE) */
 } icp_server_cfg_t;
 
 typedef struct {

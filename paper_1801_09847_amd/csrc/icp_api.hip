@@ -914,6 +914,17 @@ int icp_register_multiscale(icp_ctx_t* ctx, const float* src_xyz, int64_t n_src,
                             int32_t n_levels, const double* voxel, const int32_t* max_iter,
                             const double* max_corr_dist, double rel_tol, int32_t variant,
                             int32_t precision, icp_result_t* out) {
+  return icp_register_multiscale_robust(ctx, src_xyz, n_src, tgt_xyz, tgt_normals, n_tgt, T_init, n_levels,
+                                        voxel, max_iter, max_corr_dist, rel_tol, variant, precision,
+                                        ICP_LOSS_NONE, 1.0, out);
+}
+
+int icp_register_multiscale_robust(icp_ctx_t* ctx, const float* src_xyz, int64_t n_src, const float* tgt_xyz,
+                                   const float* tgt_normals, int64_t n_tgt, const double T_init[16],
+                                   int32_t n_levels, const double* voxel, const int32_t* max_iter,
+                                   const double* max_corr_dist, double rel_tol, int32_t variant,
+                                   int32_t precision, int32_t loss, double loss_k, icp_result_t* out) {
+  if (check_loss(loss, loss_k) != 0) return ICP_E_INVALID_ARG;
   if (n_levels < 1 || n_levels > 16 || !voxel || !max_iter || !max_corr_dist)
     return fail(ICP_E_INVALID_ARG, "n_levels must be in [1, 16] with voxel / max_iter / max_corr_dist given");
   int rc;
@@ -961,7 +972,7 @@ int icp_register_multiscale(icp_ctx_t* ctx, const float* src_xyz, int64_t n_src,
     const PairIn in{s, ns, t, tn, nt, max_corr_dist[l]};
     Prep P;
     if ((rc = prepare_pairs(c, 1, &in, &P)) != 0) return rc;
-    const LoopIn li{T, max_corr_dist[l], max_iter[l], rel_tol};
+    const LoopIn li{T, max_corr_dist[l], max_iter[l], rel_tol, loss, loss_k};
     if ((rc = run_loop(c, P, &li, plane, variant, precision, &res)) != 0) return rc;
     iters_total += res.n_iter;
     memcpy(T, res.T, sizeof T);

@@ -254,7 +254,7 @@ hipError_t launch_batch_solve(const SolveArgs* arr, int n_pairs, hipStream_t s);
 // Graph-node forms of the batched launches: kernel, block and shared memory
 // filled in; the caller sets gridDim (work items / pairs) and kernelParams
 // ({&pairs, &items} / {&arr}).
-void batch_pass_node(int sub, int variant, int precision, hipKernelNodeParams* p);
+void batch_pass_node(int sub, int variant, int precision, bool robust, hipKernelNodeParams* p);
 void batch_solve_node(hipKernelNodeParams* p);
 // Copies the loop states of `n` batched pairs into one array (one readback).
 hipError_t launch_gather_states(const SolveArgs* arr, int n, IterState* out, hipStream_t s);

@@ -1436,9 +1436,11 @@ hipError_t launch_batch_solve(const SolveArgs* arr, int n_pairs, hipStream_t s) 
   return hipGetLastError();
 }
 
-void batch_pass_node(int sub, int variant, int precision, hipKernelNodeParams* p) {
+void batch_pass_node(int sub, int variant, int precision, bool robust, hipKernelNodeParams* p) {
   void* f;
-#define ICP_F(R, V, P) f = reinterpret_cast<void*>(&batch_pass_kernel<V, P, R>)
+#define ICP_F(R, V, P)                                                                       \
+  f = robust ? reinterpret_cast<void*>(&batch_pass_kernel<V, P, R, true>)                   \
+             : reinterpret_cast<void*>(&batch_pass_kernel<V, P, R, false>)
   if (sub == 2) {
     if (variant == 1) { if (precision == 0) ICP_F(2, 1, 0); else ICP_F(2, 1, 1); }
     else { if (precision == 0) ICP_F(2, 0, 0); else ICP_F(2, 0, 1); }

@@ -118,6 +118,10 @@ int check_common(const float* src, int64_t n_src, const float* tgt, const float*
                  int64_t n_tgt, const double* T, double r, int32_t variant, int32_t precision,
                  bool need_normals_for_plane);
 int check_iteration(int32_t max_iter, double rel_tol);
+// Robust loss arguments (kind in ICP_LOSS_*, finite positive scale).
+int check_loss(int32_t loss, double k);
+// Sets a pass's loss (and its float32 scale).
+void set_loss(PassArgs* a, int32_t loss, double k);
 size_t align256(size_t x);
 int64_t tiles_of(int64_t n);
 

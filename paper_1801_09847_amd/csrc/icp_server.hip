@@ -378,6 +378,7 @@ int prepare_level(icp_server* s, std::vector<Req*>& list, std::vector<std::pair<
     a.st = st;
     a.part = part;
     a.n_blocks = (int32_t)tiles;
+    set_loss(&a, s->cfg.loss, s->cfg.loss_k);
     r->sa = SolveArgs{part, (int32_t)tiles, st, r->lns, s->cfg.iters[r->level], r->rel_tol, 0};
   }
   if ((rc = build_pairs(c, &P, dst.data())) != 0) return rc;
@@ -552,7 +553,7 @@ int build_graph(icp_server* s) {
       batch_solve_node(&p);
       p.kernelParams = s->solve_args;
     } else {
-      batch_pass_node(grid_sub(), s->cfg.variant, s->cfg.precision, &p);
+      batch_pass_node(grid_sub(), s->cfg.variant, s->cfg.precision, s->cfg.loss != ICP_LOSS_NONE, &p);
       p.kernelParams = s->pass_args;
     }
     const hipGraphNode_t* dep = k ? &s->nodes[k - 1] : nullptr;
@@ -585,6 +586,7 @@ int icp_server_create(const icp_server_cfg_t* cfg, icp_server_t** out) {
   if (!cfg || !out) return fail(ICP_E_INVALID_ARG, "cfg / out is NULL");
   const icp_server_cfg_t& k = *cfg;
   if (k.max_slots < 1 || k.max_slots > 65535) return fail(ICP_E_INVALID_ARG, "max_slots must be in [1, 65535]");
+  if (check_loss(k.loss, k.loss_k) != 0) return ICP_E_INVALID_ARG;
   if (k.n_levels < 1 || k.n_levels > 4) return fail(ICP_E_INVALID_ARG, "n_levels must be in [1, 4]");
   if (k.iters_per_step < 1 || k.iters_per_step > 64)
     return fail(ICP_E_INVALID_ARG, "iters_per_step must be in [1, 64]");

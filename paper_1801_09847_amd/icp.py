@@ -75,7 +75,7 @@ class icp_server_cfg_t(C.Structure):
                 ("n_levels", C.c_int32), ("iters", C.c_int32 * 4), ("voxel", C.c_double * 4),
                 ("corr_dist", C.c_double * 4), ("corr_factor", C.c_double), ("variant", C.c_int32),
                 ("precision", C.c_int32), ("iters_per_step", C.c_int32),
-                ("background_thread", C.c_int32)]
+                ("background_thread", C.c_int32), ("loss", C.c_int32), ("loss_k", C.c_double)]
 
 
 class icp_request_t(C.Structure):
@@ -148,6 +148,8 @@ def lib():
         L.icp_voxel_downsample.argtypes = [vp, vp, vp, i64, dbl, vp, vp, i64, C.POINTER(C.c_int64)]
         L.icp_register_multiscale.argtypes = [vp, vp, i64, vp, vp, i64, vp, i32, vp, vp, vp, dbl, i32,
                                               i32, C.POINTER(icp_result_t)]
+        L.icp_register_multiscale_robust.argtypes = [vp, vp, i64, vp, vp, i64, vp, i32, vp, vp, vp, dbl, i32,
+                                                     i32, i32, dbl, C.POINTER(icp_result_t)]
         L.icp_estimate_normals.argtypes = [vp, vp, i64, dbl, i32, vp, vp, vp]
         L.icp_pose_graph_optimize.argtypes = [vp, i32, vp, i32, C.POINTER(icp_pose_edge_t), i32, i32,
                                               dbl, C.POINTER(icp_pose_graph_result_t)]
@@ -166,7 +168,7 @@ def lib():
         L.icp_ctx_get_profile.argtypes = [vp, C.POINTER(icp_profile_t)]
         for name in ("icp_ctx_create", "icp_ctx_destroy", "icp_register", "icp_correspondences",
                      "icp_normal_equations", "icp_ctx_set_profiling", "icp_ctx_get_profile",
-                     "icp_register_batch", "icp_register_batch_robust", "icp_voxel_downsample", "icp_register_multiscale",
+                     "icp_register_batch", "icp_register_batch_robust", "icp_voxel_downsample", "icp_register_multiscale", "icp_register_multiscale_robust",
                      "icp_estimate_normals", "icp_register_robust", "icp_normal_equations_robust",
                      "icp_pose_graph_optimize", "icp_feature_match", "icp_ransac_validate", "icp_compute_fpfh",
                      "icp_ransac_register",
@@ -519,7 +521,7 @@ def ransac_register(src, tgt, corr, max_corr_dist, ransac_n=4, edge_length=0.9, 
 
 def register_multiscale(src, tgt, tgt_normals, T_init, voxels, iters, dists, rel_tol=0.0,
                         variant="point_to_plane", precision="kahan32",
-                        ctx: Context | None = None) -> IcpResult:
+                        ctx: Context | None = None, loss="none", loss_k=1.0) -> IcpResult:
     sp, ns = _dev_pts(src, "src")
     tp, nt = _dev_pts(tgt, "tgt")
     npn = _dev_pts(tgt_normals, "tgt_normals")[0] if tgt_normals is not None else None
@@ -529,10 +531,10 @@ def register_multiscale(src, tgt, tgt_normals, T_init, voxels, iters, dists, rel
     r = np.ascontiguousarray(dists, dtype=np.float64)
     out = icp_result_t()
     T = _pose(T_init)
-    _check(lib().icp_register_multiscale(ctx.handle if ctx else None, sp, ns, tp, npn, nt, T.ctypes.data,
-                                         L, v.ctypes.data, k.ctypes.data, r.ctypes.data,
-                                         float(rel_tol), VARIANTS[variant], PRECISIONS[precision],
-                                         C.byref(out)))
+    _check(lib().icp_register_multiscale_robust(ctx.handle if ctx else None, sp, ns, tp, npn, nt, T.ctypes.data,
+                                                L, v.ctypes.data, k.ctypes.data, r.ctypes.data,
+                                                float(rel_tol), VARIANTS[variant], PRECISIONS[precision],
+                                                LOSSES[loss], float(loss_k), C.byref(out)))
     return IcpResult(np.array(out.T[:], dtype=np.float64).reshape(4, 4), out.fitness, out.inlier_rmse,
                      out.n_inliers, out.n_iter, out.status)
 
@@ -594,7 +596,8 @@ class Server:
 
     def __init__(self, voxels=(0.04, 0.02, 0.01), iters=(30, 20, 10), corr_dist=None,
                  corr_factor=2.0, max_slots=64, budget_bytes=8 << 30, variant="point_to_plane",
-                 precision="kahan32", iters_per_step=5, background_thread=False, device=0):
+                 precision="kahan32", iters_per_step=5, background_thread=False, device=0, loss="none",
+                 loss_k=1.0):
         cfg = icp_server_cfg_t()
         cfg.device, cfg.max_slots, cfg.hbm_budget_bytes = device, max_slots, int(budget_bytes)
         cfg.n_levels = len(voxels)
@@ -604,6 +607,7 @@ class Server:
         cfg.corr_factor = float(corr_factor)
         cfg.variant, cfg.precision = VARIANTS[variant], PRECISIONS[precision]
         cfg.iters_per_step, cfg.background_thread = int(iters_per_step), int(background_thread)
+        cfg.loss, cfg.loss_k = LOSSES[loss], float(loss_k)
         h = C.c_void_p()
         _check(lib().icp_server_create(C.byref(cfg), C.byref(h)))
         self.handle = h.value

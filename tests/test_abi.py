@@ -257,3 +257,13 @@ def test_batch_robust_validation():
     assert L.icp_register_batch_robust(None, arr, 1, 1, 0, icp.ICP_LOSS_TUKEY, 0.0, out) == icp.ICP_E_INVALID_ARG
     assert L.icp_register_batch_robust(None, arr, 1, 1, 0, icp.ICP_LOSS_TUKEY, float("nan"), out) == \
         icp.ICP_E_INVALID_ARG
+
+
+def test_server_rejects_bad_loss():
+    for loss, k in ((7, 1.0), (icp.ICP_LOSS_TUKEY, 0.0), (icp.ICP_LOSS_CAUCHY, float("nan"))):
+        cfg = icp.icp_server_cfg_t()
+        cfg.max_slots, cfg.hbm_budget_bytes, cfg.n_levels = 1, 1 << 30, 1
+        cfg.iters[0], cfg.corr_factor, cfg.variant, cfg.iters_per_step = 5, 2.0, icp.ICP_POINT_TO_PLANE, 1
+        cfg.loss, cfg.loss_k = loss, k
+        h = C.c_void_p()
+        assert icp.lib().icp_server_create(C.byref(cfg), C.byref(h)) == icp.ICP_E_INVALID_ARG

@@ -161,3 +161,36 @@ def test_server_rejects_and_cancels(icp, requests):
     t = srv.submit(dev(small["src"]), dev(small["tgt"]), dev(small["tgt_normals"]), spacing=small["spacing"])
     assert srv.wait(t).error == 0
     srv.close()
+
+
+@pytest.mark.parametrize("loss,k", [("tukey", 0.03), ("huber", 0.01)])
+def test_server_robust_equals_multiscale_robust(icp, requests, loss, k):
+    """A server configured with a robust loss: every request bitwise equal to
+    icp_register_multiscale_robust alone, and not equal to the plain result."""
+    alone, plain = [], []
+    for d in requests:
+        dists = [2.0 * max(v, d["spacing"]) for v in VOX]
+        args = (dev(d["src"]), dev(d["tgt"]), dev(d["tgt_normals"]), np.eye(4), VOX, ITS, dists)
+        alone.append(icp.register_multiscale(*args, loss=loss, loss_k=k))
+        plain.append(icp.register_multiscale(*args))
+    srv = icp.Server(VOX, ITS, max_slots=3, budget_bytes=1 << 30, iters_per_step=4, loss=loss, loss_k=k)
+    keep = [(dev(d["src"]), dev(d["tgt"]), dev(d["tgt_normals"])) for d in requests]
+    tickets = {}
+    for q, (d, t) in enumerate(zip(requests, keep)):
+        tickets[srv.submit(*t, spacing=d["spacing"], tag=q)] = q
+        srv.step()
+    done = []
+    for _ in range(500):
+        done += srv.poll()
+        if len(done) == len(requests):
+            break
+        srv.step()
+    assert len(done) == len(requests)
+    differs = 0
+    for c in done:
+        q = tickets[c.ticket]
+        _same(c, alone[q])
+        differs += int(not np.array_equal(c.result.T, plain[q].T))
+    assert differs >= len(requests) - 1
+    srv.close()
+

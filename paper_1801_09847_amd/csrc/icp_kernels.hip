@@ -1156,12 +1156,15 @@ __device__ inline bool pair_bins(const double pi[3], const double ni[3], const d
 // the table loads are broadcasts) and the wave walks the flattened candidate
 // list 64 at a time, lane L taking candidate base + L.  The in-radius count
 // is a ballot sum; when it exceeds max_nn the max_nn-th smallest (pinned
-// float32 squared distance, index) key is found by a binary search over the
-// key space (64 counting passes, only for such points); the selected
-// candidates are then written in candidate order by ballot-prefix compaction.
+// float32 squared distance, index) key is found by a radix select over its
+// eight bytes, most significant first (per pass a 256-bin LDS histogram of
+// the candidates that share the digits found so far; only for such points);
+// the selected candidates are then written in candidate order by
+// ballot-prefix compaction.
 template <int R>
 __global__ __launch_bounds__(kFpfhBlock) void fpfh_select_kernel(FpfhArgs fa) {
   __shared__ __align__(16) uint32_t fscratch[kFpfhBlock / kWave][WaveScratch<R>::kRangeWords];
+  __shared__ uint32_t fhist[kFpfhBlock / kWave][256];
   const int w = threadIdx.x / kWave, lane = lane_id();
   uint2* ranges = reinterpret_cast<uint2*>(fscratch[w]) + lane;  // this lane's copy: ranges[slot * kWave]
   const int64_t i = (int64_t)blockIdx.x * (kFpfhBlock / kWave) + w;
@@ -1212,12 +1215,59 @@ __global__ __launch_bounds__(kFpfhBlock) void fpfh_select_kernel(FpfhArgs fa) {
   const uint32_t within = count_le(~0ull - 1);
   uint64_t kth = ~0ull - 1;
   if (within > K) {
-    uint64_t lo = 0, hi = ~0ull - 1;  // count_le(hi) >= K
-    while (lo < hi) {
-      const uint64_t mid = lo + ((hi - lo) >> 1);
-      if (count_le(mid) >= K) hi = mid; else lo = mid + 1;
+    uint32_t* hist = fhist[w];
+    uint64_t prefix = 0, mask = 0;
+    uint32_t rem = K;  // rank of the wanted key among those matching `prefix` (1-based)
+    for (int dg = 7; dg >= 0; --dg) {
+      const int sh = 8 * dg;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) hist[4 * lane + q] = 0u;
+      wave_sync();
+      Walker wk{ranges, 0, 0u, ranges[0]};
+      for (uint32_t base = 0; base < total; base += kWave) {
+        const uint32_t k = base + (uint32_t)lane;
+        if (k < total) {
+          const uint64_t key = key_at(wk.at(k));
+          if (key != ~0ull && (key & mask) == prefix) atomicAdd(&hist[(key >> sh) & 255u], 1u);
+        }
+      }
+      wave_sync();
+      uint32_t c[4], own = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        c[q] = hist[4 * lane + q];
+        own += c[q];
+      }
+      uint32_t incl = own;  // inclusive scan of the lanes' four-bin sums
+#pragma unroll
+      for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t t = __shfl_up(incl, off, kWave);
+        if (lane >= off) incl += t;
+      }
+      const uint32_t before = incl - own;
+      const bool mine = before < rem && rem <= incl;
+      uint32_t digit = 0, below = before;
+      if (mine) {
+        uint32_t run = before;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (run + c[q] >= rem) {
+            digit = 4 * lane + q;
+            below = run;
+            break;
+          }
+          run += c[q];
+        }
+      }
+      const int src = __ffsll((unsigned long long)__ballot(mine)) - 1;
+      digit = __shfl(digit, src, kWave);
+      below = __shfl(below, src, kWave);
+      rem -= below;
+      prefix |= (uint64_t)digit << sh;
+      mask |= 255ull << sh;
+      wave_sync();
     }
-    kth = lo;
+    kth = prefix;
   }
   const int64_t oi = glb(fa.sperm)[i];
   ICP_G int32_t* list = glb(fa.nbr) + oi * (int64_t)fa.max_nn;
@@ -1280,8 +1330,12 @@ __global__ __launch_bounds__(kFpfhBlock) void fpfh_pairs_kernel(FpfhArgs fa) {
 
 // FPFH(i) = SPFH(i) + (1 / k') sum over the neighbours j != i at non-zero
 // distance w of SPFH(j) / w, SPFH = counts * (100 / k) (zero without pairs),
-// in float64 in neighbour-list order, rounded to float32; lane b owns bin b.
+// in float64 in neighbour-list order, rounded to float32.  Per round of 64
+// neighbours, lane s fetches neighbour s (its distance, 100 / k and count
+// row, the row into LDS); then lane b adds bin b's terms of the round's
+// neighbours in list order.
 __global__ __launch_bounds__(kFpfhBlock) void fpfh_final_kernel(FpfhArgs fa) {
+  __shared__ uint32_t crow[kFpfhBlock / kWave][kWave][kFpfhCountBytes / 4];
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int64_t i = (int64_t)blockIdx.x * (kFpfhBlock / kWave) + w;
   if (i >= fa.n) return;
@@ -1290,20 +1344,39 @@ __global__ __launch_bounds__(kFpfhBlock) void fpfh_final_kernel(FpfhArgs fa) {
   const double pi[3] = {(double)glb(fa.sx)[i], (double)glb(fa.sy)[i], (double)glb(fa.sz)[i]};
   const int32_t m = glb(fa.nn)[oi];
   const ICP_G int32_t* list = glb(fa.nbr) + oi * (int64_t)fa.max_nn;
+  const ICP_G uint32_t* cw = reinterpret_cast<const ICP_G uint32_t*>(glb(fa.counts));
   double acc = 0.0;
   int32_t kp = 0;
-  for (int32_t s = 0; s < m; ++s) {
-    const int64_t j = list[s];
-    if (j == oi) continue;
-    const double d[3] = {(double)glb(fa.pts)[3 * j] - pi[0], (double)glb(fa.pts)[3 * j + 1] - pi[1],
-                         (double)glb(fa.pts)[3 * j + 2] - pi[2]};
-    const double wgt = sqrt(dot3(d, d));
-    if (!(wgt > 0.0)) continue;
-    ++kp;
-    const int32_t kj = glb(fa.k)[j];
-    const double qj = kj > 0 ? 100.0 / (double)kj : 0.0;
-    const double sj = (double)glb(fa.counts)[j * kFpfhCountBytes + b] * qj;
-    acc = acc + sj / wgt;
+  for (int32_t base = 0; base < m; base += kWave) {
+    const int32_t s = base + lane;
+    bool ok = false;
+    double wgt = 1.0, qj = 0.0;
+    if (s < m) {
+      const int64_t j = list[s];
+      if (j != oi) {
+        const double d[3] = {(double)glb(fa.pts)[3 * j] - pi[0], (double)glb(fa.pts)[3 * j + 1] - pi[1],
+                             (double)glb(fa.pts)[3 * j + 2] - pi[2]};
+        wgt = sqrt(dot3(d, d));
+        ok = wgt > 0.0;
+        if (ok) {
+          const int32_t kj = glb(fa.k)[j];
+          qj = kj > 0 ? 100.0 / (double)kj : 0.0;
+#pragma unroll
+          for (int wd = 0; wd < kFpfhCountBytes / 4; ++wd) crow[w][lane][wd] = cw[j * (kFpfhCountBytes / 4) + wd];
+        }
+      }
+    }
+    uint64_t okm = __ballot(ok);
+    kp += __popcll(okm);
+    wave_sync();
+    while (okm) {
+      const int src = __ffsll((unsigned long long)okm) - 1;
+      okm &= okm - 1;
+      const double ww = __shfl(wgt, src, kWave), qq = __shfl(qj, src, kWave);
+      const uint32_t c = (crow[w][src][b >> 2] >> (8 * (b & 3))) & 0xffu;
+      acc = acc + ((double)c * qq) / ww;
+    }
+    wave_sync();
   }
   const int32_t ki = glb(fa.k)[oi];
   const double qi = ki > 0 ? 100.0 / (double)ki : 0.0;

@@ -176,3 +176,26 @@ def test_register_checkers_off_and_limits(icp, R, small):
     assert g3.status == icp.ICP_RANSAC_NO_HYPOTHESIS and g3.n_validated == 0 and g3.n_iterations == 5000
     np.testing.assert_array_equal(g3.T, np.eye(4))
     assert g3.best_hypothesis == -1 and g3.n_inliers == 0
+
+
+def test_register_tiny_and_chunk_edges(icp, R, small):
+    rng = np.random.default_rng(21)
+    # one source point: every sample repeats it, nothing passes
+    one = {"src": small["src"][:1], "tgt": small["tgt"]}
+    g = icp.ransac_register(dev(one["src"]), dev(one["tgt"]), dev(np.zeros(1), np.int32), 0.075,
+                            max_iteration=3000, max_validation=5)
+    assert g.status == icp.ICP_RANSAC_NO_HYPOTHESIS and g.n_iterations == 3000
+    # three points, ransac_n 3, exact matches: the permutations of {0, 1, 2} pass
+    T = np.eye(4)
+    T[:3, 3] = [0.1, -0.2, 0.05]
+    src = rng.random((3, 3)).astype(np.float32)
+    tgt = (src.astype(np.float64) + T[:3, 3]).astype(np.float32)
+    three = {"src": src, "tgt": tgt}
+    g, hs = _compare(icp, R, three, np.arange(3), ransac_n=3, max_validation=4, max_iteration=200)
+    assert len(hs) == 4 and g.n_inliers == 3
+    np.testing.assert_allclose(g.T, T, atol=1e-6)
+    # one validation; iteration caps at and just past the first chunk
+    corr = np.where(small["true_match"] >= 0, small["true_match"], 0)
+    _compare(icp, R, small, corr, max_validation=1)
+    for cap in (65536, 65537, 131072 + 65536 + 1):
+        _compare(icp, R, small, corr, edge_length=0.99, max_validation=65535, max_iteration=cap)

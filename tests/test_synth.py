@@ -43,3 +43,36 @@ def test_c4_c5_sizes_in_range():
     assert min(rng_sizes) >= 5000 and max(rng_sizes) <= 500000
     t = synth.poisson_arrivals(100, 10.0)
     assert np.all(np.diff(t) > 0)
+
+
+def test_ransac_pair_structure():
+    a = synth.ransac_pair(4, 3000, 2500)
+    b = synth.ransac_pair(4, 3000, 2500)
+    for k in ("src", "tgt", "src_feat", "tgt_feat", "true_match"):
+        np.testing.assert_array_equal(a[k], b[k])
+    assert a["src_feat"].shape == (2500, 33) and a["tgt_feat"].shape == (3000, 33)
+    assert a["src_feat"].dtype == np.float32 and (a["src_feat"] >= 0).all()
+    # three 11-bin sub-histograms summing to 100 for the targets
+    s = a["tgt_feat"].reshape(-1, 3, 11).sum(axis=2)
+    np.testing.assert_allclose(s, 100.0, rtol=1e-5)
+    planted = a["true_match"] >= 0
+    assert 0.0 < planted.mean() <= 0.3  # match_frac of the points whose counterpart is within 5 cm
+    full = synth.ransac_pair(0)  # ~6 cm spacing: most points have a counterpart
+    assert 0.2 < (full["true_match"] >= 0).mean() < 0.3
+    # a planted feature is its counterpart's plus small noise
+    diff = np.abs(a["src_feat"][planted] - a["tgt_feat"][a["true_match"][planted]])
+    assert np.median(diff) < 2.0
+    # the planted counterparts lie near the moved source points
+    home = synth.apply(a["T_gt"], a["src"].astype(np.float64))
+    dist = np.linalg.norm(home[planted] - a["tgt"][a["true_match"][planted]], axis=1)
+    assert dist.max() < 0.05
+
+
+def test_bench_refuses_several_gpus():
+    import subprocess
+    import sys
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0 and "one GPU" in (r.stdout + r.stderr)

@@ -549,7 +549,9 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(PassArgs a) {
 // ---- RANSAC validation --------------------------------------------------
 // Block (tile, v) scores hypothesis v over kTile Morton-ordered source points:
 // the same transform, candidate rows and selection as the pass (no warm
-// start: every hypothesis is a new pose), then the block's inlier count and
+// start: every hypothesis is a new pose; instead the query's own cell is
+// scanned first and its nearest point bounds the row pruning), then the
+// block's inlier count and
 // fixed-point squared-distance sum.  floor(d2 * 2^shift) of a float32 d2 is
 // exact in float64 (a power-of-two scale) and below 2^40, so the sums are
 // exact integers whatever the order.
@@ -582,6 +584,25 @@ __global__ __launch_bounds__(kBlock) void validate_kernel(ValidateArgs v) {
       const float q32x = (float)qx, q32y = (float)qy, q32z = (float)qz;
       uint64_t best = ~0ull;
       uint32_t bj = 0xffffffffu;
+      {
+        // the query's own cell first: its nearest point bounds the search and
+        // prunes the other rows (the bound is conservative, the result exact)
+        const GridDesc& g = a.g;
+        const double ux = ((double)q32x - g.ox) * g.inv_h, uy = ((double)q32y - g.oy) * g.inv_h,
+                     uz = ((double)q32z - g.oz) * g.inv_h;
+        if (ux >= 0.0 && uy >= 0.0 && uz >= 0.0 && ux < (double)g.dx && uy < (double)g.dy && uz < (double)g.dz) {
+          const uint32_t cell = ((uint32_t)uz * (uint32_t)g.dy + (uint32_t)uy) * (uint32_t)g.dx + (uint32_t)ux;
+          const uint32_t b0 = ld_cell(a.cs, cell), b1 = ld_cell(a.cs, cell + 1u);
+          for (uint32_t pos = b0; pos < b1; ++pos) {
+            const float4 p = ld4(a.tp, pos);
+            const float dx = q32x - p.x, dy = q32y - p.y, dz = q32z - p.z;
+            float d2 = dx * dx + dy * dy;
+            d2 = d2 + dz * dz;
+            const uint64_t key = ((uint64_t)__float_as_uint(d2) << 32) | (uint64_t)__float_as_uint(p.w);
+            if (d2 <= a.r2f && key < best) best = key;
+          }
+        }
+      }
       const uint32_t total = stage_rows<R>(a, q32x, q32y, q32z, lane_ranges, best);
       scan_ranges(a, q32x, q32y, q32z, lane_ranges, total, best, bj);
       bd = __uint_as_float((uint32_t)(best >> 32));

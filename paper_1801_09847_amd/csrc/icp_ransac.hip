@@ -26,7 +26,7 @@ namespace {
 
 constexpr int kHypBlock = 256;
 constexpr int kMinRansacN = 3, kMaxRansacN = 8;
-constexpr int64_t kMaxChunk = int64_t(1) << 20;   // hypotheses per check launch
+constexpr int64_t kMaxChunk = int64_t(1) << 21;   // hypotheses per check launch (96 B of fit each)
 constexpr int64_t kFirstChunk = int64_t(1) << 16;
 constexpr int kFmBlock = 256;  // threads per feature-match block
 constexpr int kFmQ = 2;        // queries per thread
@@ -826,7 +826,9 @@ int icp_ransac_register(icp_ctx_t* ctx, const float* src_xyz, int64_t n_src, con
   uint32_t* sums = reinterpret_cast<uint32_t*>(base + L.sums);
   uint32_t* hflag = static_cast<uint32_t*>(c->host);
 
-  // hypothesis chunks, growing geometrically, until max_validation survivors
+  // hypothesis chunks until max_validation survivors: after the first, each
+  // chunk is sized from the survivor rate so far to finish in one more
+  // (at most kMaxChunk); the result does not depend on the chunking
   int64_t valid = 0, h0 = 0, chunk = std::min<int64_t>(kFirstChunk, chunk_cap);
   while (h0 < prm->max_iteration && valid < max_valid) {
     const int64_t cnt = std::min<int64_t>(chunk, prm->max_iteration - h0);
@@ -840,7 +842,11 @@ int icp_ransac_register(icp_ctx_t* ctx, const float* src_xyz, int64_t n_src, con
     HIP_TRY(hipStreamSynchronize(s), "sync");
     valid += *hflag;
     h0 += cnt;
-    chunk = std::min<int64_t>(chunk * 2, chunk_cap);
+    if (valid < max_valid) {
+      const double rate = (double)valid / (double)h0;
+      const double want = rate > 0.0 ? 1.25 * (double)(max_valid - valid) / rate + 1024.0 : (double)chunk_cap;
+      chunk = std::min<int64_t>(chunk_cap, std::max<int64_t>(kFirstChunk, (int64_t)std::min(want, 1e18)));
+    }
   }
   const int64_t n_val = std::min<int64_t>(valid, max_valid);
 

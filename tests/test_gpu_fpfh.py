@@ -103,3 +103,13 @@ def test_pairwise_workflow_end_to_end(icp):
     print(f"RANSAC fitness {g.fitness:.3f} after {g.n_iterations} iterations; ICP fitness {res.fitness:.3f}, "
           f"rotation error {ang:.3f} deg, translation error {np.linalg.norm(res.T[:3, 3] - G[:3, 3]):.4f} m")
     assert g.status == icp.ICP_OK and ang < 0.5 and np.linalg.norm(res.T[:3, 3] - G[:3, 3]) < 0.02
+
+
+def test_fpfh_from_estimated_normals(icp, F):
+    """FPFH of the room target with normals estimated on the GPU (radius 0.1 m,
+    max_nn 30, the paper's workflow; isolated points get zero normals, whose
+    pairs are skipped on both sides)."""
+    d = synth.ransac_pair(2, 12000, 100)
+    t = dev(d["tgt"])
+    nrm = icp.estimate_normals(t, 0.1, 30, (2.0, 1.5, 1.2)).cpu().numpy()
+    _compare(icp, F, d["tgt"], nrm, 0.25, 100)

@@ -684,30 +684,45 @@ __device__ bool cholesky_solve6(const double* up21, const double* b, double* x) 
   double dmax = A[0][0];
   for (int r = 1; r < 6; ++r) dmax = fmax(dmax, A[r][r]);
   const double tol = 1e-12 * dmax;
+  // one reciprocal per pivot instead of a division per entry: the solve
+  // runs on a single thread between passes, and float64 divisions dominate
+  // its latency
   double L[6][6];
+  double inv[6];
+#pragma unroll
   for (int r = 0; r < 6; ++r)
+#pragma unroll
     for (int c = 0; c < 6; ++c) L[r][c] = 0.0;
+#pragma unroll
   for (int c = 0; c < 6; ++c) {
     double d = A[c][c];
+#pragma unroll
     for (int m = 0; m < c; ++m) d -= L[c][m] * L[c][m];
     if (!(d > tol)) return false;
     L[c][c] = sqrt(d);
+    inv[c] = 1.0 / L[c][c];
+#pragma unroll
     for (int r = c + 1; r < 6; ++r) {
       double s = A[r][c];
+#pragma unroll
       for (int m = 0; m < c; ++m) s -= L[r][m] * L[c][m];
-      L[r][c] = s / L[c][c];
+      L[r][c] = s * inv[c];
     }
   }
   double y[6];
+#pragma unroll
   for (int r = 0; r < 6; ++r) {
     double s = -b[r];
+#pragma unroll
     for (int m = 0; m < r; ++m) s -= L[r][m] * y[m];
-    y[r] = s / L[r][r];
+    y[r] = s * inv[r];
   }
+#pragma unroll
   for (int r = 5; r >= 0; --r) {
     double s = y[r];
+#pragma unroll
     for (int m = r + 1; m < 6; ++m) s -= L[m][r] * x[m];
-    x[r] = s / L[r][r];
+    x[r] = s * inv[r];
   }
   return true;
 }
@@ -723,10 +738,15 @@ __device__ void apply_exp(const double* xi, double* T) {
     B = 0.5 - th2 / 24.0 + th2 * th2 / 720.0;
     C = 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0;
   } else {
-    const double s = sin(th), sh = sin(0.5 * th);
-    A = s / th;
-    B = 2.0 * sh * sh / th2;
-    C = (th - s) / (th2 * th);
+    // one sincos of th / 2 (sin th = 2 sin(th/2) cos(th/2); 1 - cos th =
+    // 2 sin^2(th/2) without cancellation) and one reciprocal
+    double sh, ch;
+    sincos(0.5 * th, &sh, &ch);
+    const double s = 2.0 * sh * ch;
+    const double it = 1.0 / th, it2 = it * it;
+    A = s * it;
+    B = 2.0 * sh * sh * it2;
+    C = (th - s) * (it2 * it);
   }
   const double W[3][3] = {{0.0, -wz, wy}, {wz, 0.0, -wx}, {-wy, wx, 0.0}};
   double W2[3][3];

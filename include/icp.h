@@ -445,8 +445,11 @@ int icp_ransac_validate(icp_ctx_t *ctx, const float *src_xyz, int64_t n_src, con
  *                     (e.g. icp_feature_match's output; values outside
  *                     [0, n_tgt) mark a point without a match)
  *   prm, out          host; trace: optional device outputs, or NULL
- * Synchronous (one readback per chunk of hypotheses).  Errors: INVALID_ARG,
- * NONFINITE, TOO_LARGE, OOM, DEVICE. */
+ * Synchronous (one readback per chunk of hypotheses).  The context's device
+ * workspace grows to about 100 B per hypothesis of the largest chunk (at
+ * most 2^21 hypotheses, ~210 MB) plus the validation partials.  Run time
+ * grows with max_iteration when few hypotheses pass the checkers.  Errors:
+ * INVALID_ARG, NONFINITE, TOO_LARGE, OOM, DEVICE. */
 int icp_ransac_register(icp_ctx_t *ctx, const float *src_xyz, int64_t n_src, const float *tgt_xyz,
                         int64_t n_tgt, const int32_t *corr, const icp_ransac_params_t *prm,
                         icp_ransac_result_t *out, const icp_ransac_trace_t *trace);

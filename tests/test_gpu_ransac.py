@@ -199,3 +199,22 @@ def test_register_tiny_and_chunk_edges(icp, R, small):
     _compare(icp, R, small, corr, max_validation=1)
     for cap in (65536, 65537, 131072 + 65536 + 1):
         _compare(icp, R, small, corr, edge_length=0.99, max_validation=65535, max_iteration=cap)
+
+
+def test_validation_in_several_launches(icp, R):
+    """300k source points: 586 tiles, so 9543 hypotheses per launch; 10000
+    hypotheses take two launches.  Scores at both ends of each launch and a
+    few inside match the oracle bit for bit."""
+    d = synth.room_pair_random(77, 300_000, 300_000, 6.0, 4.0, 3.0, 20, 10)
+    rng = np.random.default_rng(77)
+    from scipy.spatial.transform import Rotation
+    Ts = np.empty((10_000, 4, 4))
+    for k in range(len(Ts)):
+        T = np.eye(4)
+        T[:3, :3] = Rotation.from_rotvec(rng.normal(size=3) * 0.01).as_matrix()
+        T[:3, 3] = rng.normal(size=3) * 0.01
+        Ts[k] = T @ d["T_gt"]
+    cnt, sq = icp.ransac_validate(dev(d["src"]), dev(d["tgt"]), 0.03, Ts)
+    assert (cnt > 0).all()
+    for k in (0, 9542, 9543, 9999, 4321):
+        assert (cnt[k], int(sq[k])) == R.validate(d["src"], d["tgt"], Ts[k], 0.03), k

@@ -218,3 +218,20 @@ def test_validation_in_several_launches(icp, R):
     assert (cnt > 0).all()
     for k in (0, 9542, 9543, 9999, 4321):
         assert (cnt[k], int(sq[k])) == R.validate(d["src"], d["tgt"], Ts[k], 0.03), k
+
+
+def test_nonfinite_inputs_are_rejected(icp, small):
+    src = small["src"].copy()
+    src[17, 1] = np.nan
+    corr = dev(np.zeros(len(src)), np.int32)
+    with pytest.raises(icp.IcpError) as e:
+        icp.ransac_register(dev(src), dev(small["tgt"]), corr, 0.075, max_iteration=100, max_validation=5)
+    assert e.value.code == icp.ICP_E_NONFINITE
+    tgt = small["tgt"].copy()
+    tgt[3, 0] = np.inf
+    with pytest.raises(icp.IcpError) as e:
+        icp.ransac_validate(dev(small["src"]), dev(tgt), 0.075, np.eye(4)[None])
+    assert e.value.code == icp.ICP_E_NONFINITE
+    with pytest.raises(icp.IcpError) as e:
+        icp.compute_fpfh(dev(src), dev(np.tile([0.0, 0.0, 1.0], (len(src), 1))), 0.25, 30)
+    assert e.value.code == icp.ICP_E_NONFINITE

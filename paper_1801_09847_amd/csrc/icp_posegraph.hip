@@ -12,10 +12,11 @@
 // Per iteration: one thread per edge forms K = J^T L J, u = J^T L e and
 // f = e^T L e in float64; the dense normal equations over the free nodes are
 // assembled block by block from host-built incidence lists (fixed order, no
-// atomics); F is a fixed-order reduction; the damped system is factorised and
-// solved by rocSOLVER's dense Cholesky (dpotrf / dpotrs, a plain library
-// factorisation) on the context's stream, with the pivot rule checked on the
-// factor; one thread per node applies the step.  The host keeps or refuses the
+// atomics); F is a fixed-order reduction; the damped system is factorised by
+// a right-looking blocked Cholesky (64x64 diagonal blocks factorised in LDS by
+// one workgroup, the panel solved one row per thread, the trailing update in
+// 64x64 tiles) and solved by rocSOLVER's dpotrs, on the context's stream, with the pivot
+// rule checked on the factor; one thread per node applies the step.  The host keeps or refuses the
 // step from F alone.
 
 #include <math.h>
@@ -269,6 +270,123 @@ __global__ __launch_bounds__(256) void pg_diag_max_kernel(const double* __restri
   if (threadIdx.x == 0) *dmax = sh[0];
 }
 
+// Diagonal block [k0, k0 + nb) of the column-major lower factor, nb <= 64,
+// in LDS: column by column, the pivot's square root, the column below it
+// scaled by its reciprocal, and the rank-1 update of the block's trailing
+// part.  A non-positive pivot records its 1-based position in `info` (first
+// one only), is replaced by 1 so that nothing becomes NaN, and the run is
+// flagged degenerate by the pivot rule afterwards.
+constexpr int kPgNb = 64;
+__global__ __launch_bounds__(256) void pg_chol_diag_kernel(double* __restrict__ A, int n, int k0, int nb,
+                                                           rocblas_int* __restrict__ info) {
+  __shared__ double T[kPgNb][kPgNb + 1];
+  __shared__ double sinv;
+  const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+  for (int r = ty; r < nb; r += 16)
+    for (int c = tx; c < nb; c += 16) T[r][c] = r >= c ? A[(int64_t)(k0 + c) * n + (k0 + r)] : 0.0;
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    if (t == 0) {
+      const double d = T[j][j];
+      if (!(d > 0.0)) {
+        if (*info == 0) *info = k0 + j + 1;
+        T[j][j] = 1.0;
+      } else {
+        T[j][j] = sqrt(d);
+      }
+      sinv = 1.0 / T[j][j];
+    }
+    __syncthreads();
+    const double inv = sinv;
+    for (int r = j + 1 + t; r < nb; r += 256) T[r][j] = T[r][j] * inv;
+    __syncthreads();
+    for (int r = j + 1 + ty; r < nb; r += 16)
+      for (int c = j + 1 + tx; c <= r; c += 16) T[r][c] = fma(-T[r][j], T[c][j], T[r][c]);
+    __syncthreads();
+  }
+  for (int r = ty; r < nb; r += 16)
+    for (int c = tx; c <= r; c += 16) A[(int64_t)(k0 + c) * n + (k0 + r)] = T[r][c];
+}
+
+// Panel below a factorised diagonal block: row i of X = B L_kk^-T, one thread
+// per row, right-looking in registers (x_c = b_c / L_cc, then b_m -= x_c L_mc
+// for m > c: a critical path of nb steps), L_kk and the reciprocals of its
+// diagonal in LDS.
+__global__ __launch_bounds__(256) void pg_chol_panel_kernel(double* __restrict__ A, int n, int k0, int nb,
+                                                            int rem) {
+  __shared__ double L[kPgNb][kPgNb + 1];
+  __shared__ double rinv[kPgNb];
+  const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+  for (int r = ty; r < nb; r += 16)
+    for (int c = tx; c <= r; c += 16) L[r][c] = A[(int64_t)(k0 + c) * n + (k0 + r)];
+  __syncthreads();
+  if (t < nb) rinv[t] = 1.0 / L[t][t];
+  __syncthreads();
+  const int i = blockIdx.x * 256 + t;
+  if (i >= rem) return;
+  double* row = A + (int64_t)k0 * n + (k0 + nb + i);  // element c at row[c * n]
+  double b[kPgNb];
+#pragma unroll
+  for (int c = 0; c < kPgNb; ++c) b[c] = c < nb ? row[(int64_t)c * n] : 0.0;
+#pragma unroll
+  for (int c = 0; c < kPgNb; ++c) {
+    if (c < nb) {
+      const double xc = b[c] * rinv[c];
+      b[c] = xc;
+#pragma unroll
+      for (int m = c + 1; m < kPgNb; ++m)
+        if (m < nb) b[m] = fma(-xc, L[m][c], b[m]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < kPgNb; ++c)
+    if (c < nb) row[(int64_t)c * n] = b[c];
+}
+
+// Trailing update C -= P P^T (lower part) after a panel P (rem x nb, column
+// k0 .. k0 + nb, rows below the block): block (bj, bi), bj <= bi, computes the
+// 64 x 64 output tile (bi, bj) from the two 64-row slices of P in LDS, 4 x 4
+// outputs per thread.
+__global__ __launch_bounds__(256) void pg_chol_update_kernel(double* __restrict__ A, int n, int k0, int nb,
+                                                             int rem) {
+  const int bi = blockIdx.y, bj = blockIdx.x;
+  if (bj > bi) return;  // upper tiles: nothing (uniform per block)
+  __shared__ double Pi[kPgNb][kPgNb + 1];
+  __shared__ double Pj[kPgNb][kPgNb + 1];
+  const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+  const int64_t col0 = (int64_t)k0 * n, row0 = k0 + nb;
+  for (int c = ty; c < nb; c += 16)
+    for (int q = tx; q < kPgNb; q += 16) {
+      const int ri = bi * kPgNb + q, rj = bj * kPgNb + q;
+      Pi[q][c] = ri < rem ? A[col0 + (int64_t)c * n + row0 + ri] : 0.0;
+      Pj[q][c] = rj < rem ? A[col0 + (int64_t)c * n + row0 + rj] : 0.0;
+    }
+  __syncthreads();
+  double acc[4][4] = {};
+  for (int c = 0; c < nb; ++c) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = Pi[4 * ty + u][c];
+      b[u] = Pj[4 * tx + u][c];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = bi * kPgNb + 4 * ty + u, q = bj * kPgNb + 4 * tx + v;
+      if (r < rem && q <= r) {
+        double* e = A + (int64_t)(row0 + q) * n + row0 + r;
+        *e = *e - acc[u][v];
+      }
+    }
+}
+
 // Pivot rule on the factor: failed factorisation, or some L_kk^2 <= 1e-12 max diag.
 __global__ __launch_bounds__(256) void pg_pivot_check_kernel(const double* __restrict__ L, int n,
                                                              const double* __restrict__ dmax,
@@ -440,8 +558,9 @@ int icp_pose_graph_optimize(icp_ctx_t* ctx, int32_t n_nodes, double* poses, int3
     c->solver = h;
   }
   rocblas_handle rb = static_cast<rocblas_handle>(c->solver);
-  if (rocblas_set_stream(rb, s) != rocblas_status_success)
-    return fail(ICP_E_DEVICE, "rocblas_set_stream failed");
+  if (rocblas_set_stream(rb, s) != rocblas_status_success ||
+      rocblas_set_pointer_mode(rb, rocblas_pointer_mode_host) != rocblas_status_success)
+    return fail(ICP_E_DEVICE, "rocblas_set_stream / rocblas_set_pointer_mode failed");
   const PgEdge* E = reinterpret_cast<const PgEdge*>(dd + o_e);
   const PgBlock* B = reinterpret_cast<const PgBlock*>(dd + o_b);
   const int2* HC = reinterpret_cast<const int2*>(dd + o_hc);
@@ -484,9 +603,21 @@ int icp_pose_graph_optimize(icp_ctx_t* ctx, int32_t n_nodes, double* poses, int3
     hipLaunchKernelGGL(pg_damp_kernel, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, s, H, A, g,
                        dv, n, lm ? lambda : 0.0);
     hipLaunchKernelGGL(pg_diag_max_kernel, dim3(1), dim3(256), 0, s, A, n, dmax);
-    // A is symmetric: its row-major storage is also its column-major one
-    if (rocsolver_dpotrf(rb, rocblas_fill_lower, n, A, n, info) != rocblas_status_success)
-      return fail(ICP_E_DEVICE, "rocsolver_dpotrf failed");
+    // A is symmetric: its row-major storage is also its column-major one.
+    // Blocked right-looking Cholesky of its lower triangle.
+    HIP_TRY(hipMemsetAsync(info, 0, sizeof(rocblas_int), s), "memset");
+    for (int k0 = 0; k0 < n; k0 += kPgNb) {
+      const int nb = std::min(kPgNb, n - k0), rem = n - k0 - nb;
+      hipLaunchKernelGGL(pg_chol_diag_kernel, dim3(1), dim3(256), 0, s, A, n, k0, nb, info);
+      HIP_TRY(hipGetLastError(), "pose graph factorisation");
+      if (rem == 0) break;
+      hipLaunchKernelGGL(pg_chol_panel_kernel, dim3((unsigned)((rem + 255) / 256)), dim3(256), 0, s, A, n, k0, nb,
+                         rem);
+      HIP_TRY(hipGetLastError(), "pose graph factorisation");
+      const unsigned tiles = (unsigned)((rem + kPgNb - 1) / kPgNb);
+      hipLaunchKernelGGL(pg_chol_update_kernel, dim3(tiles, tiles), dim3(256), 0, s, A, n, k0, nb, rem);
+      HIP_TRY(hipGetLastError(), "pose graph factorisation");
+    }
     hipLaunchKernelGGL(pg_pivot_check_kernel, dim3(1), dim3(256), 0, s, A, n, dmax, info, flag);
     if (rocsolver_dpotrs(rb, rocblas_fill_lower, n, 1, A, n, dv, n) != rocblas_status_success)
       return fail(ICP_E_DEVICE, "rocsolver_dpotrs failed");

@@ -64,7 +64,6 @@ void ctx_free(icp_ctx* c) {
                  &c->vflags, &c->vstarts, &c->lvl_src, &c->lvl_tgt, &c->lvl_tn, &c->pg, &c->rs};
   for (Buf* b : bufs) b->release();
   for (Buf& b : c->sk) b.release();
-  pg_release(c);
   if (c->host) (void)hipHostFree(c->host);
   c->host = nullptr;
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);

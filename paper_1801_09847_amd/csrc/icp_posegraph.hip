@@ -13,18 +13,17 @@
 // f = e^T L e in float64; the dense normal equations over the free nodes are
 // assembled block by block from host-built incidence lists (fixed order, no
 // atomics); F is a fixed-order reduction; the damped system is factorised by
-// a right-looking blocked Cholesky (64x64 diagonal blocks factorised in LDS by
-// one workgroup, the panel solved one row per thread, the trailing update in
-// 64x64 tiles) and solved by rocSOLVER's dpotrs, on the context's stream, with the pivot
-// rule checked on the factor; one thread per node applies the step.  The host keeps or refuses the
+// a right-looking blocked Cholesky (64x64 diagonal blocks factorised by one
+// wavefront in registers, the panel solved one row per thread, the trailing
+// update in 64x64 tiles) and solved by blocked forward and backward
+// substitution, on the context's stream, with the pivot rule checked on the
+// factor; one thread per node applies the step.  The host keeps or refuses the
 // step from F alone.
 
 #include <math.h>
 
 #include <algorithm>
 #include <vector>
-
-#include <rocsolver/rocsolver.h>
 
 #include "icp_runtime.h"
 
@@ -271,82 +270,153 @@ __global__ __launch_bounds__(256) void pg_diag_max_kernel(const double* __restri
 }
 
 // Diagonal block [k0, k0 + nb) of the column-major lower factor, nb <= 64,
-// in LDS: column by column, the pivot's square root, the column below it
-// scaled by its reciprocal, and the rank-1 update of the block's trailing
-// part.  A non-positive pivot records its 1-based position in `info` (first
-// one only), is replaced by 1 so that nothing becomes NaN, and the run is
-// flagged degenerate by the pivot rule afterwards.
+// by one wavefront: lane r keeps row r of the block in registers.  Column by
+// column: the pivot's square root (read from the lane that holds it), the
+// column below it scaled by the reciprocal square root of the pivot (within
+// an ulp or two of dividing by the root) and published in LDS, and
+// the rank-1 update of every lane's row (entries right of the diagonal are
+// updated too and never stored).  A non-positive pivot records its 1-based
+// position in `info` (first one only), is replaced by 1 so that nothing
+// becomes NaN, and the run is flagged degenerate by the pivot rule afterwards.
 constexpr int kPgNb = 64;
-__global__ __launch_bounds__(256) void pg_chol_diag_kernel(double* __restrict__ A, int n, int k0, int nb,
-                                                           rocblas_int* __restrict__ info) {
-  __shared__ double T[kPgNb][kPgNb + 1];
-  __shared__ double sinv;
-  const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
-  for (int r = ty; r < nb; r += 16)
-    for (int c = tx; c < nb; c += 16) T[r][c] = r >= c ? A[(int64_t)(k0 + c) * n + (k0 + r)] : 0.0;
-  __syncthreads();
-  for (int j = 0; j < nb; ++j) {
-    if (t == 0) {
-      const double d = T[j][j];
-      if (!(d > 0.0)) {
-        if (*info == 0) *info = k0 + j + 1;
-        T[j][j] = 1.0;
-      } else {
-        T[j][j] = sqrt(d);
-      }
-      sinv = 1.0 / T[j][j];
-    }
-    __syncthreads();
-    const double inv = sinv;
-    for (int r = j + 1 + t; r < nb; r += 256) T[r][j] = T[r][j] * inv;
-    __syncthreads();
-    for (int r = j + 1 + ty; r < nb; r += 16)
-      for (int c = j + 1 + tx; c <= r; c += 16) T[r][c] = fma(-T[r][j], T[c][j], T[r][c]);
-    __syncthreads();
-  }
-  for (int r = ty; r < nb; r += 16)
-    for (int c = tx; c <= r; c += 16) A[(int64_t)(k0 + c) * n + (k0 + r)] = T[r][c];
+
+__device__ inline void pg_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Panel below a factorised diagonal block: row i of X = B L_kk^-T, one thread
-// per row, right-looking in registers (x_c = b_c / L_cc, then b_m -= x_c L_mc
-// for m > c: a critical path of nb steps), L_kk and the reciprocals of its
-// diagonal in LDS.
-__global__ __launch_bounds__(256) void pg_chol_panel_kernel(double* __restrict__ A, int n, int k0, int nb,
-                                                            int rem) {
-  __shared__ double L[kPgNb][kPgNb + 1];
-  __shared__ double rinv[kPgNb];
-  const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
-  for (int r = ty; r < nb; r += 16)
-    for (int c = tx; c <= r; c += 16) L[r][c] = A[(int64_t)(k0 + c) * n + (k0 + r)];
-  __syncthreads();
-  if (t < nb) rinv[t] = 1.0 / L[t][t];
-  __syncthreads();
-  const int i = blockIdx.x * 256 + t;
-  if (i >= rem) return;
-  double* row = A + (int64_t)k0 * n + (k0 + nb + i);  // element c at row[c * n]
+// Value of lane `lane` (uniform) to the whole wavefront, read into scalar
+// registers (no LDS round trip).
+__device__ inline double lane_value(double v, int lane) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)u, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__global__ __launch_bounds__(kPgNb) void pg_chol_diag_kernel(double* __restrict__ A, int n, int k0, int nb,
+                                                             int* __restrict__ info) {
+  __shared__ double col[kPgNb];
+  const int r = threadIdx.x;
+  // every load is issued before any is used: addresses are clamped into the
+  // block and the entries outside its lower triangle are zeroed afterwards
+  // (a load under a per-lane branch would be waited for at the branch)
   double b[kPgNb];
+  const int rc = min(r, nb - 1);
 #pragma unroll
-  for (int c = 0; c < kPgNb; ++c) b[c] = c < nb ? row[(int64_t)c * n] : 0.0;
+  for (int c = 0; c < kPgNb; ++c) b[c] = A[(int64_t)(k0 + min(c, nb - 1)) * n + (k0 + rc)];
 #pragma unroll
-  for (int c = 0; c < kPgNb; ++c) {
-    if (c < nb) {
-      const double xc = b[c] * rinv[c];
-      b[c] = xc;
+  for (int c = 0; c < kPgNb; ++c) b[c] = c < nb && r < nb && c <= r ? b[c] : 0.0;
 #pragma unroll
-      for (int m = c + 1; m < kPgNb; ++m)
-        if (m < nb) b[m] = fma(-xc, L[m][c], b[m]);
+  for (int j = 0; j < kPgNb; ++j) {
+    if (j < nb) {
+      const double d = lane_value(b[j], j);
+      const bool bad = !(d > 0.0);
+      // the square root and its reciprocal are formed side by side, so the
+      // step's critical path holds one of them instead of both in turn
+      const double piv = bad ? 1.0 : sqrt(d);
+      const double inv = bad ? 1.0 : rsqrt(d);
+      if (bad && r == 0 && *info == 0) *info = k0 + j + 1;
+      b[j] = r == j ? piv : b[j] * inv;
+      col[r] = b[j];
+      pg_wave_sync();
+#pragma unroll
+      for (int c = j + 1; c < kPgNb; ++c) b[c] = fma(-b[j], col[c], b[c]);
+      pg_wave_sync();
     }
   }
 #pragma unroll
   for (int c = 0; c < kPgNb; ++c)
-    if (c < nb) row[(int64_t)c * n] = b[c];
+    if (c < nb && r < nb && c <= r) A[(int64_t)(k0 + c) * n + (k0 + r)] = b[c];
+}
+
+// Value of lane Q of each group of four lanes, to all four (a DPP quad
+// permutation of both halves of the double).
+template <int Q>
+__device__ inline double quad_bcast_q(double v) {
+  constexpr int ctrl = Q | (Q << 2) | (Q << 4) | (Q << 6);
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)u, ctrl, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), ctrl, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ inline double quad_bcast(double v, int q) {  // q folds to a constant in unrolled loops
+  switch (q) {
+    case 0: return quad_bcast_q<0>(v);
+    case 1: return quad_bcast_q<1>(v);
+    case 2: return quad_bcast_q<2>(v);
+    default: return quad_bcast_q<3>(v);
+  }
+}
+
+// Panel below a factorised diagonal block: row i of X = B L_kk^-T, four
+// lanes per row, lane q holding columns 4k + q, right-looking in registers:
+// at column c the lane that holds it forms x_c = b_c / L_cc and passes it to
+// the other three (a DPP quad broadcast), and each lane applies
+// b_m -= x_c L_mc to its columns m > c.  The critical path is nb steps of a
+// quarter of the row's work.  L_kk sits in LDS as Lq[c][q][k] = L_(4k+q),c,
+// each lane's values along k contiguous (rows padded against bank conflicts),
+// with the reciprocals of its diagonal.  FULL: nb == 64 (every block but the
+// last), which removes the per-entry bounds from the unrolled loops.
+constexpr int kPgPanelRows = 64;  // rows per block of 256 threads
+constexpr int kPgLqPad = 18;
+template <bool FULL>
+__global__ __launch_bounds__(256) void pg_chol_panel_kernel(double* __restrict__ A, int n, int k0, int nb_arg,
+                                                            int rem) {
+  const int nb = FULL ? kPgNb : nb_arg;
+  __shared__ __align__(16) double Lq[kPgNb][4][kPgLqPad];
+  __shared__ double rinv[kPgNb];
+  const int t = threadIdx.x;
+  {
+    // all loads in flight at once (clamped addresses; entries above the
+    // diagonal and past nb are stored but never read)
+    const int m = t & 63, mc = min(m, nb - 1);
+    double v[16];
+#pragma unroll
+    for (int a = 0; a < 16; ++a) {
+      const int c = (t >> 6) + 4 * a;
+      v[a] = A[(int64_t)(k0 + min(c, nb - 1)) * n + (k0 + mc)];
+    }
+#pragma unroll
+    for (int a = 0; a < 16; ++a) Lq[(t >> 6) + 4 * a][m & 3][m >> 2] = v[a];
+  }
+  __syncthreads();
+  if (t < nb) rinv[t] = 1.0 / Lq[t][t & 3][t >> 2];
+  __syncthreads();
+  const int q = t & 3;
+  const int i = blockIdx.x * kPgPanelRows + (t >> 2);
+  if (i >= rem) return;  // whole quads leave together
+  double* row = A + (int64_t)k0 * n + (k0 + nb + i);  // element c at row[c * n]
+  double b[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) b[k] = row[(int64_t)min(4 * k + q, nb - 1) * n];
+#pragma unroll
+  for (int c = 0; c < kPgNb; ++c) {
+    if (c < nb) {
+      const int kc = c >> 2, qc = c & 3;
+      const double x = quad_bcast(b[kc] * rinv[c], qc);
+      if (q == qc) b[kc] = x;
+      const double* lrow = &Lq[c][q][0];
+#pragma unroll
+      for (int k = kc; k < 16; ++k) {
+        const int m = 4 * k + q;
+        const bool upd = (k > kc || q > qc) && (FULL || m < nb);
+        const double nv = fma(-x, lrow[k], b[k]);
+        b[k] = upd ? nv : b[k];
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 16; ++k)
+    if (FULL || 4 * k + q < nb) row[(int64_t)(4 * k + q) * n] = b[k];
 }
 
 // Trailing update C -= P P^T (lower part) after a panel P (rem x nb, column
 // k0 .. k0 + nb, rows below the block): block (bj, bi), bj <= bi, computes the
-// 64 x 64 output tile (bi, bj) from the two 64-row slices of P in LDS, 4 x 4
-// outputs per thread.
+// 64 x 64 output tile (bi, bj) from the two 64-row slices of P in LDS; thread
+// (tx, ty) owns rows tx + 16u and columns ty + 16v, so that for each (u, v)
+// sixteen lanes update sixteen consecutive entries of one column.
 __global__ __launch_bounds__(256) void pg_chol_update_kernel(double* __restrict__ A, int n, int k0, int nb,
                                                              int rem) {
   const int bi = blockIdx.y, bj = blockIdx.x;
@@ -355,20 +425,35 @@ __global__ __launch_bounds__(256) void pg_chol_update_kernel(double* __restrict_
   __shared__ double Pj[kPgNb][kPgNb + 1];
   const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
   const int64_t col0 = (int64_t)k0 * n, row0 = k0 + nb;
-  for (int c = ty; c < nb; c += 16)
-    for (int q = tx; q < kPgNb; q += 16) {
-      const int ri = bi * kPgNb + q, rj = bj * kPgNb + q;
-      Pi[q][c] = ri < rem ? A[col0 + (int64_t)c * n + row0 + ri] : 0.0;
-      Pj[q][c] = rj < rem ? A[col0 + (int64_t)c * n + row0 + rj] : 0.0;
-    }
+  {
+    // all 32 loads in flight at once: clamped addresses, then zeroed where
+    // out of range (columns past nb are never read)
+    double vi[4][4], vj[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int c = min(ty + 16 * a, nb - 1), q = tx + 16 * e;
+        vi[a][e] = A[col0 + (int64_t)c * n + row0 + min(bi * kPgNb + q, rem - 1)];
+        vj[a][e] = A[col0 + (int64_t)c * n + row0 + min(bj * kPgNb + q, rem - 1)];
+      }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int c = ty + 16 * a, q = tx + 16 * e;
+        Pi[q][c] = bi * kPgNb + q < rem ? vi[a][e] : 0.0;
+        Pj[q][c] = bj * kPgNb + q < rem ? vj[a][e] : 0.0;
+      }
+  }
   __syncthreads();
   double acc[4][4] = {};
   for (int c = 0; c < nb; ++c) {
     double a[4], b[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      a[u] = Pi[4 * ty + u][c];
-      b[u] = Pj[4 * tx + u][c];
+      a[u] = Pi[tx + 16 * u][c];
+      b[u] = Pj[ty + 16 * u][c];
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -379,7 +464,7 @@ __global__ __launch_bounds__(256) void pg_chol_update_kernel(double* __restrict_
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int r = bi * kPgNb + 4 * ty + u, q = bj * kPgNb + 4 * tx + v;
+      const int r = bi * kPgNb + tx + 16 * u, q = bj * kPgNb + ty + 16 * v;
       if (r < rem && q <= r) {
         double* e = A + (int64_t)(row0 + q) * n + row0 + r;
         *e = *e - acc[u][v];
@@ -387,10 +472,89 @@ __global__ __launch_bounds__(256) void pg_chol_update_kernel(double* __restrict_
     }
 }
 
+// Forward substitution L y = g for the block column [k0, k0 + nb): every
+// workgroup solves the diagonal block itself (wavefront 0, lane r holding row
+// r of L_kk and g_r: y_j is taken from lane j, then g_r -= L_rj y_j in lanes
+// r > j), then subtracts L_ik y_k from its own share of the rows below, one
+// thread per row.  y goes to its own vector, so no workgroup reads an entry of
+// g that another one has already overwritten.
+__global__ __launch_bounds__(256) void pg_trsv_lower_kernel(const double* __restrict__ L, int n, int k0, int nb,
+                                                            double* __restrict__ g, double* __restrict__ y) {
+  __shared__ double ys[kPgNb];
+  const int t = threadIdx.x;
+  if (t < kPgNb) {
+    const int r = t, rc = min(r, nb - 1);
+    double l[kPgNb];
+#pragma unroll
+    for (int c = 0; c < kPgNb; ++c) l[c] = L[(int64_t)(k0 + min(c, nb - 1)) * n + (k0 + rc)];
+    const double rinv = 1.0 / L[(int64_t)(k0 + rc) * n + (k0 + rc)];
+    double v = g[k0 + rc];
+#pragma unroll
+    for (int j = 0; j < kPgNb; ++j) {
+      if (j < nb) {
+        const double yj = lane_value(v * rinv, j);
+        v = r == j ? yj : (r > j ? fma(-l[j], yj, v) : v);
+      }
+    }
+    ys[r] = v;
+    if (blockIdx.x == 0 && r < nb) y[k0 + r] = v;
+  }
+  __syncthreads();
+  const int row = k0 + nb + (int)blockIdx.x * 256 + t;
+  if (row >= n) return;
+  double lv[kPgNb];
+#pragma unroll
+  for (int c = 0; c < kPgNb; ++c) lv[c] = L[(int64_t)(k0 + min(c, nb - 1)) * n + row];
+  double acc = g[row];
+#pragma unroll
+  for (int c = 0; c < kPgNb; ++c)
+    if (c < nb) acc = fma(-lv[c], ys[c], acc);
+  g[row] = acc;
+}
+
+// Backward substitution L^T x = y for the block column [k0, k0 + nb), blocks
+// taken last to first: every workgroup solves the transposed diagonal block
+// (lane r holding column r of L_kk and y_r: x_j from lane j, then
+// y_r -= L_jr x_j in lanes r < j), then subtracts L_kj^T x_k from its share
+// of the rows above, one thread per row.  x goes to its own vector.
+__global__ __launch_bounds__(256) void pg_trsv_upper_kernel(const double* __restrict__ L, int n, int k0, int nb,
+                                                            double* __restrict__ y, double* __restrict__ x) {
+  __shared__ double xs[kPgNb];
+  const int t = threadIdx.x;
+  if (t < kPgNb) {
+    const int r = t, rc = min(r, nb - 1);
+    double u[kPgNb];
+#pragma unroll
+    for (int j = 0; j < kPgNb; ++j) u[j] = L[(int64_t)(k0 + rc) * n + (k0 + min(j, nb - 1))];
+    const double rinv = 1.0 / L[(int64_t)(k0 + rc) * n + (k0 + rc)];
+    double v = y[k0 + rc];
+#pragma unroll
+    for (int j = kPgNb - 1; j >= 0; --j) {
+      if (j < nb) {
+        const double xj = lane_value(v * rinv, j);
+        v = r == j ? xj : (r < j ? fma(-u[j], xj, v) : v);
+      }
+    }
+    xs[r] = v;
+    if (blockIdx.x == 0 && r < nb) x[k0 + r] = v;
+  }
+  __syncthreads();
+  const int row = (int)blockIdx.x * 256 + t;
+  if (row >= k0) return;
+  double lv[kPgNb];
+#pragma unroll
+  for (int c = 0; c < kPgNb; ++c) lv[c] = L[(int64_t)row * n + (k0 + min(c, nb - 1))];
+  double acc = y[row];
+#pragma unroll
+  for (int c = 0; c < kPgNb; ++c)
+    if (c < nb) acc = fma(-lv[c], xs[c], acc);
+  y[row] = acc;
+}
+
 // Pivot rule on the factor: failed factorisation, or some L_kk^2 <= 1e-12 max diag.
 __global__ __launch_bounds__(256) void pg_pivot_check_kernel(const double* __restrict__ L, int n,
                                                              const double* __restrict__ dmax,
-                                                             const rocblas_int* __restrict__ info,
+                                                             const int* __restrict__ info,
                                                              int* __restrict__ flag) {
   __shared__ int bad;
   if (threadIdx.x == 0) bad = *info != 0 ? 1 : 0;
@@ -424,13 +588,6 @@ bool rigid_ok(const double* T) {
 }
 
 }  // namespace
-
-namespace icp_rt {
-void pg_release(icp_ctx* c) {
-  if (c->solver) (void)rocblas_destroy_handle(static_cast<rocblas_handle>(c->solver));
-  c->solver = nullptr;
-}
-}  // namespace icp_rt
 
 extern "C" {
 
@@ -519,7 +676,7 @@ int icp_pose_graph_optimize(icp_ctx_t* ctx, int32_t n_nodes, double* poses, int3
   const size_t o_e = take(sizeof(PgEdge) * m);
   const size_t o_t = take(sizeof(double) * kTerms * m), o_tc = take(sizeof(double) * kTerms * m);
   const size_t o_h = take(sizeof(double) * (size_t)n * n), o_a = take(sizeof(double) * (size_t)n * n);
-  const size_t o_g = take(sizeof(double) * n), o_d = take(sizeof(double) * n);
+  const size_t o_g = take(sizeof(double) * n), o_d = take(sizeof(double) * n), o_y = take(sizeof(double) * n);
   const size_t o_b = take(sizeof(PgBlock) * blocks.size());
   const size_t o_hc = take(sizeof(int2) * std::max<size_t>(hcontrib.size(), 1));
   const size_t o_gc = take(sizeof(int2) * std::max<size_t>(gcontrib.size(), 1));
@@ -550,17 +707,8 @@ int icp_pose_graph_optimize(icp_ctx_t* ctx, int32_t n_nodes, double* poses, int3
   double* Fd = reinterpret_cast<double*>(dd + o_s);
   int* flag = reinterpret_cast<int*>(dd + o_s + 8);
   double* dmax = reinterpret_cast<double*>(dd + o_s + 16);
-  rocblas_int* info = reinterpret_cast<rocblas_int*>(dd + o_s + 24);
-  if (!c->solver) {
-    rocblas_handle h = nullptr;
-    if (rocblas_create_handle(&h) != rocblas_status_success)
-      return fail(ICP_E_DEVICE, "rocblas_create_handle failed");
-    c->solver = h;
-  }
-  rocblas_handle rb = static_cast<rocblas_handle>(c->solver);
-  if (rocblas_set_stream(rb, s) != rocblas_status_success ||
-      rocblas_set_pointer_mode(rb, rocblas_pointer_mode_host) != rocblas_status_success)
-    return fail(ICP_E_DEVICE, "rocblas_set_stream / rocblas_set_pointer_mode failed");
+  int* info = reinterpret_cast<int*>(dd + o_s + 24);
+  double* yv = reinterpret_cast<double*>(dd + o_y);
   const PgEdge* E = reinterpret_cast<const PgEdge*>(dd + o_e);
   const PgBlock* B = reinterpret_cast<const PgBlock*>(dd + o_b);
   const int2* HC = reinterpret_cast<const int2*>(dd + o_hc);
@@ -605,22 +753,36 @@ int icp_pose_graph_optimize(icp_ctx_t* ctx, int32_t n_nodes, double* poses, int3
     hipLaunchKernelGGL(pg_diag_max_kernel, dim3(1), dim3(256), 0, s, A, n, dmax);
     // A is symmetric: its row-major storage is also its column-major one.
     // Blocked right-looking Cholesky of its lower triangle.
-    HIP_TRY(hipMemsetAsync(info, 0, sizeof(rocblas_int), s), "memset");
+    HIP_TRY(hipMemsetAsync(info, 0, sizeof(int), s), "memset");
     for (int k0 = 0; k0 < n; k0 += kPgNb) {
       const int nb = std::min(kPgNb, n - k0), rem = n - k0 - nb;
-      hipLaunchKernelGGL(pg_chol_diag_kernel, dim3(1), dim3(256), 0, s, A, n, k0, nb, info);
+      hipLaunchKernelGGL(pg_chol_diag_kernel, dim3(1), dim3(kPgNb), 0, s, A, n, k0, nb, info);
       HIP_TRY(hipGetLastError(), "pose graph factorisation");
       if (rem == 0) break;
-      hipLaunchKernelGGL(pg_chol_panel_kernel, dim3((unsigned)((rem + 255) / 256)), dim3(256), 0, s, A, n, k0, nb,
-                         rem);
+      const dim3 pgrid((unsigned)((rem + kPgPanelRows - 1) / kPgPanelRows));
+      if (nb == kPgNb)
+        hipLaunchKernelGGL(pg_chol_panel_kernel<true>, pgrid, dim3(256), 0, s, A, n, k0, nb, rem);
+      else
+        hipLaunchKernelGGL(pg_chol_panel_kernel<false>, pgrid, dim3(256), 0, s, A, n, k0, nb, rem);
       HIP_TRY(hipGetLastError(), "pose graph factorisation");
       const unsigned tiles = (unsigned)((rem + kPgNb - 1) / kPgNb);
       hipLaunchKernelGGL(pg_chol_update_kernel, dim3(tiles, tiles), dim3(256), 0, s, A, n, k0, nb, rem);
       HIP_TRY(hipGetLastError(), "pose graph factorisation");
     }
     hipLaunchKernelGGL(pg_pivot_check_kernel, dim3(1), dim3(256), 0, s, A, n, dmax, info, flag);
-    if (rocsolver_dpotrs(rb, rocblas_fill_lower, n, 1, A, n, dv, n) != rocblas_status_success)
-      return fail(ICP_E_DEVICE, "rocsolver_dpotrs failed");
+    // L y = rhs block column by block column, then L^T x = y from the last
+    // block back; the right-hand side (dv) is consumed and receives x
+    for (int k0 = 0; k0 < n; k0 += kPgNb) {
+      const int nb = std::min(kPgNb, n - k0), rem = n - k0 - nb;
+      hipLaunchKernelGGL(pg_trsv_lower_kernel, dim3((unsigned)std::max(1, (rem + 255) / 256)), dim3(256), 0, s, A,
+                         n, k0, nb, dv, yv);
+    }
+    for (int k0 = ((n - 1) / kPgNb) * kPgNb; k0 >= 0; k0 -= kPgNb) {
+      const int nb = std::min(kPgNb, n - k0);
+      hipLaunchKernelGGL(pg_trsv_upper_kernel, dim3((unsigned)std::max(1, (k0 + 255) / 256)), dim3(256), 0, s, A,
+                         n, k0, nb, yv, dv);
+    }
+    HIP_TRY(hipGetLastError(), "pose graph solve");
     hipLaunchKernelGGL(pg_update_kernel, dim3((unsigned)((n_nodes + 63) / 64)), dim3(64), 0, s, P, dv,
                        n_nodes, Cn);
     HIP_TRY(hipGetLastError(), "pose graph step");

@@ -76,12 +76,10 @@ struct icp_ctx {
   icp_rt::Buf cs, tp, tn, sx, sy, sz, perm;
   // voxel downsampling: descriptors, scratch, multi-scale level clouds
   icp_rt::Buf vdesc, vflags, vstarts, lvl_src, lvl_tgt, lvl_tn;
-  // pose-graph optimisation: poses, edges, terms, normal equations; dense
-  // solver library handle (created on first use)
+  // pose-graph optimisation: poses, edges, terms, normal equations
   icp_rt::Buf pg;
   // RANSAC: hypothesis flags, survivors, validation partials, feature-match keys
   icp_rt::Buf rs;
-  void* solver = nullptr;
   void* host = nullptr;  // pinned staging
   size_t host_cap = 0;
   // kernel timing
@@ -106,8 +104,6 @@ struct DeviceGuard {
 int ctx_init(icp_ctx* c, int device, void* stream);
 // The given context, or this thread's default context of the current device.
 int resolve_ctx(icp_ctx* in, icp_ctx** out);
-// Releases the context's dense-solver handle (pose-graph optimisation).
-void pg_release(icp_ctx* c);
 // Cells per max_corr_dist along an axis for every grid this process builds.
 int grid_sub();
 void ctx_free(icp_ctx* c);

@@ -14,10 +14,11 @@
 // assembled block by block from host-built incidence lists (fixed order, no
 // atomics); F is a fixed-order reduction; the damped system is factorised by
 // a right-looking blocked Cholesky (64x64 diagonal blocks factorised by one
-// wavefront in registers, the panel solved one row per thread, the trailing
-// update in 64x64 tiles) and solved by blocked forward and backward
-// substitution, on the context's stream, with the pivot rule checked on the
-// factor; one thread per node applies the step.  The host keeps or refuses the
+// wavefront in registers, each inside the trailing update that precedes it;
+// the panel solved with four lanes per row; the trailing update in 64x64
+// tiles) and solved by blocked forward and backward substitution, on the
+// context's stream, with the pivot rule checked on the factor; one thread per
+// node applies the step.  The host keeps or refuses the
 // step from F alone.
 
 #include <math.h>
@@ -271,20 +272,15 @@ __global__ __launch_bounds__(256) void pg_diag_max_kernel(const double* __restri
 
 // Diagonal block [k0, k0 + nb) of the column-major lower factor, nb <= 64,
 // by one wavefront: lane r keeps row r of the block in registers.  Column by
-// column: the pivot's square root (read from the lane that holds it), the
-// column below it scaled by the reciprocal square root of the pivot (within
-// an ulp or two of dividing by the root) and published in LDS, and
-// the rank-1 update of every lane's row (entries right of the diagonal are
-// updated too and never stored).  A non-positive pivot records its 1-based
-// position in `info` (first one only), is replaced by 1 so that nothing
-// becomes NaN, and the run is flagged degenerate by the pivot rule afterwards.
+// column: the pivot (read from the lane that holds it) gives its reciprocal
+// square root, which scales the column below it (within an ulp or two of
+// dividing by the root), and every lane's row takes the rank-1 update, the
+// column's entries read from their lanes into scalar registers (entries right
+// of the diagonal are updated too and never stored).  A non-positive pivot
+// records its 1-based position in `info` (first one only), is replaced by 1
+// so that nothing becomes NaN, and the run is flagged degenerate by the pivot
+// rule afterwards.
 constexpr int kPgNb = 64;
-
-__device__ inline void pg_wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Value of lane `lane` (uniform) to the whole wavefront, read into scalar
 // registers (no LDS round trip).
@@ -295,10 +291,8 @@ __device__ inline double lane_value(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-__global__ __launch_bounds__(kPgNb) void pg_chol_diag_kernel(double* __restrict__ A, int n, int k0, int nb,
-                                                             int* __restrict__ info) {
-  __shared__ double col[kPgNb];
-  const int r = threadIdx.x;
+__device__ __forceinline__ void diag_factor(double* __restrict__ A, int n, int k0, int nb, int* __restrict__ info) {
+  const int r = threadIdx.x;  // the calling wavefront is threads 0..63
   // every load is issued before any is used: addresses are clamped into the
   // block and the entries outside its lower triangle are zeroed afterwards
   // (a load under a per-lane branch would be waited for at the branch)
@@ -313,22 +307,25 @@ __global__ __launch_bounds__(kPgNb) void pg_chol_diag_kernel(double* __restrict_
     if (j < nb) {
       const double d = lane_value(b[j], j);
       const bool bad = !(d > 0.0);
-      // the square root and its reciprocal are formed side by side, so the
-      // step's critical path holds one of them instead of both in turn
-      const double piv = bad ? 1.0 : sqrt(d);
+      // one reciprocal square root per pivot: the root itself is d / sqrt(d)
       const double inv = bad ? 1.0 : rsqrt(d);
+      const double piv = bad ? 1.0 : d * inv;
       if (bad && r == 0 && *info == 0) *info = k0 + j + 1;
       b[j] = r == j ? piv : b[j] * inv;
-      col[r] = b[j];
-      pg_wave_sync();
+      // column j of the other rows comes from their lanes through scalar
+      // registers, entry j + 1 (the next pivot's row) first
 #pragma unroll
-      for (int c = j + 1; c < kPgNb; ++c) b[c] = fma(-b[j], col[c], b[c]);
-      pg_wave_sync();
+      for (int c = j + 1; c < kPgNb; ++c) b[c] = fma(-b[j], lane_value(b[j], c), b[c]);
     }
   }
 #pragma unroll
   for (int c = 0; c < kPgNb; ++c)
     if (c < nb && r < nb && c <= r) A[(int64_t)(k0 + c) * n + (k0 + r)] = b[c];
+}
+
+__global__ __launch_bounds__(kPgNb) void pg_chol_diag_kernel(double* __restrict__ A, int n, int k0, int nb,
+                                                             int* __restrict__ info) {
+  diag_factor(A, n, k0, nb, info);
 }
 
 // Value of lane Q of each group of four lanes, to all four (a DPP quad
@@ -416,9 +413,11 @@ __global__ __launch_bounds__(256) void pg_chol_panel_kernel(double* __restrict__
 // k0 .. k0 + nb, rows below the block): block (bj, bi), bj <= bi, computes the
 // 64 x 64 output tile (bi, bj) from the two 64-row slices of P in LDS; thread
 // (tx, ty) owns rows tx + 16u and columns ty + 16v, so that for each (u, v)
-// sixteen lanes update sixteen consecutive entries of one column.
+// sixteen lanes update sixteen consecutive entries of one column.  Tile
+// (0, 0) is the next diagonal block: once updated, its first wavefront
+// factorises it, which hides that sequential step behind the other tiles.
 __global__ __launch_bounds__(256) void pg_chol_update_kernel(double* __restrict__ A, int n, int k0, int nb,
-                                                             int rem) {
+                                                             int rem, int* __restrict__ info) {
   const int bi = blockIdx.y, bj = blockIdx.x;
   if (bj > bi) return;  // upper tiles: nothing (uniform per block)
   __shared__ double Pi[kPgNb][kPgNb + 1];
@@ -470,6 +469,10 @@ __global__ __launch_bounds__(256) void pg_chol_update_kernel(double* __restrict_
         *e = *e - acc[u][v];
       }
     }
+  if (bi == 0 && bj == 0) {
+    __syncthreads();  // the tile's updated entries, written by all four waves
+    if (t < kPgNb) diag_factor(A, n, (int)row0, min(kPgNb, rem), info);
+  }
 }
 
 // Forward substitution L y = g for the block column [k0, k0 + nb): every
@@ -754,10 +757,11 @@ int icp_pose_graph_optimize(icp_ctx_t* ctx, int32_t n_nodes, double* poses, int3
     // A is symmetric: its row-major storage is also its column-major one.
     // Blocked right-looking Cholesky of its lower triangle.
     HIP_TRY(hipMemsetAsync(info, 0, sizeof(int), s), "memset");
+    // the first diagonal block here, every later one by the update before it
+    hipLaunchKernelGGL(pg_chol_diag_kernel, dim3(1), dim3(kPgNb), 0, s, A, n, 0, std::min(kPgNb, n), info);
+    HIP_TRY(hipGetLastError(), "pose graph factorisation");
     for (int k0 = 0; k0 < n; k0 += kPgNb) {
       const int nb = std::min(kPgNb, n - k0), rem = n - k0 - nb;
-      hipLaunchKernelGGL(pg_chol_diag_kernel, dim3(1), dim3(kPgNb), 0, s, A, n, k0, nb, info);
-      HIP_TRY(hipGetLastError(), "pose graph factorisation");
       if (rem == 0) break;
       const dim3 pgrid((unsigned)((rem + kPgPanelRows - 1) / kPgPanelRows));
       if (nb == kPgNb)
@@ -766,7 +770,7 @@ int icp_pose_graph_optimize(icp_ctx_t* ctx, int32_t n_nodes, double* poses, int3
         hipLaunchKernelGGL(pg_chol_panel_kernel<false>, pgrid, dim3(256), 0, s, A, n, k0, nb, rem);
       HIP_TRY(hipGetLastError(), "pose graph factorisation");
       const unsigned tiles = (unsigned)((rem + kPgNb - 1) / kPgNb);
-      hipLaunchKernelGGL(pg_chol_update_kernel, dim3(tiles, tiles), dim3(256), 0, s, A, n, k0, nb, rem);
+      hipLaunchKernelGGL(pg_chol_update_kernel, dim3(tiles, tiles), dim3(256), 0, s, A, n, k0, nb, rem, info);
       HIP_TRY(hipGetLastError(), "pose graph factorisation");
     }
     hipLaunchKernelGGL(pg_pivot_check_kernel, dim3(1), dim3(256), 0, s, A, n, dmax, info, flag);

@@ -395,7 +395,9 @@ __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
       const uint32_t bjc = inl ? bj : 0u;
       bp = ld4(a.tp, bjc);
       if (VAR == 1) bn = ld4(a.tn, bjc);
-      if (a.jprev) glb(a.jprev)[i] = inl ? bj : 0xffffffffu;
+      // the warm-start index is written back only where the match moved
+      const uint32_t nj = inl ? bj : 0xffffffffu;
+      if (a.jprev && nj != jp) glb(a.jprev)[i] = nj;
       if (WRITE) {
         const uint32_t oi = glb(a.sperm)[i];
         glb(a.idx_out)[oi] = inl ? (int32_t)bo : -1;

@@ -49,7 +49,7 @@ def test_consistent_graph_recovered(icp):
 
 
 @pytest.mark.parametrize("method", ["gn", "lm"])
-@pytest.mark.parametrize("n,closures", [(12, 6), (64, 40), (200, 150)])
+@pytest.mark.parametrize("n,closures", [(12, 6), (64, 40), (200, 150), (256, 256)])
 def test_noisy_graph_matches_oracle(icp, method, n, closures):
     d = synth.pose_graph(2 + n, n, closures)
     P, res = icp.pose_graph_optimize(d["init"], d["edges"], method, 100, 1e-13)

@@ -291,7 +291,10 @@ __device__ inline double lane_value(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-__device__ __forceinline__ void diag_factor(double* __restrict__ A, int n, int k0, int nb, int* __restrict__ info) {
+template <bool FULL>
+__device__ __forceinline__ void diag_factor_t(double* __restrict__ A, int n, int k0, int nb_arg,
+                                              int* __restrict__ info) {
+  const int nb = FULL ? kPgNb : nb_arg;
   const int r = threadIdx.x;  // the calling wavefront is threads 0..63
   // every load is issued before any is used: addresses are clamped into the
   // block and the entries outside its lower triangle are zeroed afterwards
@@ -302,25 +305,45 @@ __device__ __forceinline__ void diag_factor(double* __restrict__ A, int n, int k
   for (int c = 0; c < kPgNb; ++c) b[c] = A[(int64_t)(k0 + min(c, nb - 1)) * n + (k0 + rc)];
 #pragma unroll
   for (int c = 0; c < kPgNb; ++c) b[c] = c < nb && r < nb && c <= r ? b[c] : 0.0;
+  // one reciprocal square root per pivot (the root itself is d / sqrt(d)),
+  // formed without branches; pivot j + 1 is formed as soon as its entry has
+  // taken column j's update, so that its chain overlaps the rest of that
+  // update
+  double d = lane_value(b[0], 0);
+  bool bad = !(d > 0.0);
+  double inv = rsqrt(bad ? 1.0 : d);
+  double piv = bad ? 1.0 : d * inv;
+  int first_bad = -1;
 #pragma unroll
   for (int j = 0; j < kPgNb; ++j) {
-    if (j < nb) {
-      const double d = lane_value(b[j], j);
-      const bool bad = !(d > 0.0);
-      // one reciprocal square root per pivot: the root itself is d / sqrt(d)
-      const double inv = bad ? 1.0 : rsqrt(d);
-      const double piv = bad ? 1.0 : d * inv;
-      if (bad && r == 0 && *info == 0) *info = k0 + j + 1;
+    if (FULL || j < nb) {
+      first_bad = bad && first_bad < 0 ? j : first_bad;
       b[j] = r == j ? piv : b[j] * inv;
-      // column j of the other rows comes from their lanes through scalar
-      // registers, entry j + 1 (the next pivot's row) first
+      const double lj = b[j];
+      if (j + 1 < kPgNb) {
+        // column j of the other rows comes from their lanes through scalar
+        // registers
+        b[j + 1] = fma(-lj, lane_value(lj, j + 1), b[j + 1]);
+        d = lane_value(b[j + 1], j + 1);
+        bad = !(d > 0.0);
+        inv = rsqrt(bad ? 1.0 : d);
+        piv = bad ? 1.0 : d * inv;
 #pragma unroll
-      for (int c = j + 1; c < kPgNb; ++c) b[c] = fma(-b[j], lane_value(b[j], c), b[c]);
+        for (int c = j + 2; c < kPgNb; ++c) b[c] = fma(-lj, lane_value(lj, c), b[c]);
+      }
     }
   }
+  if (first_bad >= 0 && r == 0 && *info == 0) *info = k0 + first_bad + 1;
 #pragma unroll
   for (int c = 0; c < kPgNb; ++c)
     if (c < nb && r < nb && c <= r) A[(int64_t)(k0 + c) * n + (k0 + r)] = b[c];
+}
+
+__device__ __forceinline__ void diag_factor(double* __restrict__ A, int n, int k0, int nb, int* __restrict__ info) {
+  if (nb == kPgNb)
+    diag_factor_t<true>(A, n, k0, nb, info);
+  else
+    diag_factor_t<false>(A, n, k0, nb, info);
 }
 
 __global__ __launch_bounds__(kPgNb) void pg_chol_diag_kernel(double* __restrict__ A, int n, int k0, int nb,

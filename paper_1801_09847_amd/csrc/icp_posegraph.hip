@@ -13,8 +13,8 @@
 // f = e^T L e in float64; the dense normal equations over the free nodes are
 // assembled block by block from host-built incidence lists (fixed order, no
 // atomics); F is a fixed-order reduction; the damped system is factorised by
-// a right-looking blocked Cholesky (64x64 diagonal blocks factorised by one
-// wavefront in registers, each inside the trailing update that precedes it;
+// a right-looking blocked Cholesky (64x64 diagonal blocks factorised in
+// registers by four wavefronts, each inside the trailing update before it;
 // the panel solved with four lanes per row; the trailing update in 64x64
 // tiles) and solved by blocked forward and backward substitution, on the
 // context's stream, with the pivot rule checked on the factor; one thread per
@@ -271,15 +271,16 @@ __global__ __launch_bounds__(256) void pg_diag_max_kernel(const double* __restri
 }
 
 // Diagonal block [k0, k0 + nb) of the column-major lower factor, nb <= 64,
-// by one wavefront: lane r keeps row r of the block in registers.  Column by
-// column: the pivot (read from the lane that holds it) gives its reciprocal
-// square root, which scales the column below it (within an ulp or two of
-// dividing by the root), and every lane's row takes the rank-1 update, the
-// column's entries read from their lanes into scalar registers (entries right
-// of the diagonal are updated too and never stored).  A non-positive pivot
-// records its 1-based position in `info` (first one only), is replaced by 1
-// so that nothing becomes NaN, and the run is flagged degenerate by the pivot
-// rule afterwards.
+// by the four wavefronts of a workgroup: lane r keeps row r of the block and
+// wavefront w the columns 4m + w, in registers.  Column by column: the
+// wavefront holding it reads the pivot from its lane, forms its reciprocal
+// square root, scales the column below it (within an ulp or two of dividing
+// by the root) and publishes it in LDS; after one barrier every wavefront
+// applies the rank-1 update to its own columns (entries right of the
+// diagonal are updated too and never stored).  A non-positive pivot records
+// its 1-based position in `info` (first one only), is replaced by 1 so that
+// nothing becomes NaN, and the run is flagged degenerate by the pivot rule
+// afterwards.
 constexpr int kPgNb = 64;
 
 // Value of lane `lane` (uniform) to the whole wavefront, read into scalar
@@ -294,51 +295,52 @@ __device__ inline double lane_value(double v, int lane) {
 template <bool FULL>
 __device__ __forceinline__ void diag_factor_t(double* __restrict__ A, int n, int k0, int nb_arg,
                                               int* __restrict__ info) {
+  __shared__ __align__(16) double colbuf[2][4][16];  // column j: L_(4k+q),j at [j & 1][q][k]
   const int nb = FULL ? kPgNb : nb_arg;
-  const int r = threadIdx.x;  // the calling wavefront is threads 0..63
+  const int t = threadIdx.x, r = t & 63, w = t >> 6;  // row r; wave w holds columns 4k + w
   // every load is issued before any is used: addresses are clamped into the
   // block and the entries outside its lower triangle are zeroed afterwards
   // (a load under a per-lane branch would be waited for at the branch)
-  double b[kPgNb];
+  double b[16];
   const int rc = min(r, nb - 1);
 #pragma unroll
-  for (int c = 0; c < kPgNb; ++c) b[c] = A[(int64_t)(k0 + min(c, nb - 1)) * n + (k0 + rc)];
+  for (int k = 0; k < 16; ++k) b[k] = A[(int64_t)(k0 + min(4 * k + w, nb - 1)) * n + (k0 + rc)];
 #pragma unroll
-  for (int c = 0; c < kPgNb; ++c) b[c] = c < nb && r < nb && c <= r ? b[c] : 0.0;
-  // one reciprocal square root per pivot (the root itself is d / sqrt(d)),
-  // formed without branches; pivot j + 1 is formed as soon as its entry has
-  // taken column j's update, so that its chain overlaps the rest of that
-  // update
-  double d = lane_value(b[0], 0);
-  bool bad = !(d > 0.0);
-  double inv = rsqrt(bad ? 1.0 : d);
-  double piv = bad ? 1.0 : d * inv;
-  int first_bad = -1;
+  for (int k = 0; k < 16; ++k) {
+    const int c = 4 * k + w;
+    b[k] = c < nb && r < nb && c <= r ? b[k] : 0.0;
+  }
 #pragma unroll
   for (int j = 0; j < kPgNb; ++j) {
     if (FULL || j < nb) {
-      first_bad = bad && first_bad < 0 ? j : first_bad;
-      b[j] = r == j ? piv : b[j] * inv;
-      const double lj = b[j];
-      if (j + 1 < kPgNb) {
-        // column j of the other rows comes from their lanes through scalar
-        // registers
-        b[j + 1] = fma(-lj, lane_value(lj, j + 1), b[j + 1]);
-        d = lane_value(b[j + 1], j + 1);
-        bad = !(d > 0.0);
-        inv = rsqrt(bad ? 1.0 : d);
-        piv = bad ? 1.0 : d * inv;
+      const int kj = j >> 2, wj = j & 3, par = j & 1;
+      if (w == wj) {  // the wavefront that holds column j: pivot, scaling, publication
+        const double d = lane_value(b[kj], j);
+        const bool bad = !(d > 0.0);
+        const double inv = rsqrt(bad ? 1.0 : d);  // the root itself is d / sqrt(d)
+        const double piv = bad ? 1.0 : d * inv;
+        if (bad && r == 0 && *info == 0) *info = k0 + j + 1;
+        b[kj] = r == j ? piv : b[kj] * inv;
+        colbuf[par][r & 3][r >> 2] = b[kj];
+      }
+      __syncthreads();
+      const double lrj = colbuf[par][r & 3][r >> 2];
+      const double* cj = &colbuf[par][w][0];
 #pragma unroll
-        for (int c = j + 2; c < kPgNb; ++c) b[c] = fma(-lj, lane_value(lj, c), b[c]);
+      for (int k = kj; k < 16; ++k) {
+        const double nv = fma(-lrj, cj[k], b[k]);
+        b[k] = k > kj || w > wj ? nv : b[k];  // columns 4k + w > j only
       }
     }
   }
-  if (first_bad >= 0 && r == 0 && *info == 0) *info = k0 + first_bad + 1;
 #pragma unroll
-  for (int c = 0; c < kPgNb; ++c)
-    if (c < nb && r < nb && c <= r) A[(int64_t)(k0 + c) * n + (k0 + r)] = b[c];
+  for (int k = 0; k < 16; ++k) {
+    const int c = 4 * k + w;
+    if (c < nb && r < nb && c <= r) A[(int64_t)(k0 + c) * n + (k0 + r)] = b[k];
+  }
 }
 
+// All 256 threads of the workgroup take part.
 __device__ __forceinline__ void diag_factor(double* __restrict__ A, int n, int k0, int nb, int* __restrict__ info) {
   if (nb == kPgNb)
     diag_factor_t<true>(A, n, k0, nb, info);
@@ -346,8 +348,8 @@ __device__ __forceinline__ void diag_factor(double* __restrict__ A, int n, int k
     diag_factor_t<false>(A, n, k0, nb, info);
 }
 
-__global__ __launch_bounds__(kPgNb) void pg_chol_diag_kernel(double* __restrict__ A, int n, int k0, int nb,
-                                                             int* __restrict__ info) {
+__global__ __launch_bounds__(256) void pg_chol_diag_kernel(double* __restrict__ A, int n, int k0, int nb,
+                                                           int* __restrict__ info) {
   diag_factor(A, n, k0, nb, info);
 }
 
@@ -437,8 +439,8 @@ __global__ __launch_bounds__(256) void pg_chol_panel_kernel(double* __restrict__
 // 64 x 64 output tile (bi, bj) from the two 64-row slices of P in LDS; thread
 // (tx, ty) owns rows tx + 16u and columns ty + 16v, so that for each (u, v)
 // sixteen lanes update sixteen consecutive entries of one column.  Tile
-// (0, 0) is the next diagonal block: once updated, its first wavefront
-// factorises it, which hides that sequential step behind the other tiles.
+// (0, 0) is the next diagonal block: once updated, its workgroup factorises
+// it, which hides that sequential step behind the other tiles.
 __global__ __launch_bounds__(256) void pg_chol_update_kernel(double* __restrict__ A, int n, int k0, int nb,
                                                              int rem, int* __restrict__ info) {
   const int bi = blockIdx.y, bj = blockIdx.x;
@@ -494,7 +496,7 @@ __global__ __launch_bounds__(256) void pg_chol_update_kernel(double* __restrict_
     }
   if (bi == 0 && bj == 0) {
     __syncthreads();  // the tile's updated entries, written by all four waves
-    if (t < kPgNb) diag_factor(A, n, (int)row0, min(kPgNb, rem), info);
+    diag_factor(A, n, (int)row0, min(kPgNb, rem), info);
   }
 }
 
@@ -781,7 +783,7 @@ int icp_pose_graph_optimize(icp_ctx_t* ctx, int32_t n_nodes, double* poses, int3
     // Blocked right-looking Cholesky of its lower triangle.
     HIP_TRY(hipMemsetAsync(info, 0, sizeof(int), s), "memset");
     // the first diagonal block here, every later one by the update before it
-    hipLaunchKernelGGL(pg_chol_diag_kernel, dim3(1), dim3(kPgNb), 0, s, A, n, 0, std::min(kPgNb, n), info);
+    hipLaunchKernelGGL(pg_chol_diag_kernel, dim3(1), dim3(256), 0, s, A, n, 0, std::min(kPgNb, n), info);
     HIP_TRY(hipGetLastError(), "pose graph factorisation");
     for (int k0 = 0; k0 < n; k0 += kPgNb) {
       const int nb = std::min(kPgNb, n - k0), rem = n - k0 - nb;

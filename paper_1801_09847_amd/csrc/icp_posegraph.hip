@@ -541,42 +541,59 @@ __global__ __launch_bounds__(256) void pg_trsv_lower_kernel(const double* __rest
 }
 
 // Backward substitution L^T x = y for the block column [k0, k0 + nb), blocks
-// taken last to first: every workgroup solves the transposed diagonal block
-// (lane r holding column r of L_kk and y_r: x_j from lane j, then
-// y_r -= L_jr x_j in lanes r < j), then subtracts L_kj^T x_k from its share
-// of the rows above, one thread per row.  x goes to its own vector.
-__global__ __launch_bounds__(256) void pg_trsv_upper_kernel(const double* __restrict__ L, int n, int k0, int nb,
-                                                            double* __restrict__ y, double* __restrict__ x) {
+// taken last to first, one wavefront per workgroup: every workgroup solves
+// the transposed diagonal block (lane r holding column r of L_kk and y_r: x_j
+// from lane j, then y_r -= L_jr x_j in lanes r < j), then subtracts
+// L_kj^T x_k from its 64 rows above, one lane per row.  Both the block and the
+// rows are read along the factor's columns (coalesced) and transposed in LDS.
+// x goes to its own vector.
+__global__ __launch_bounds__(kPgNb) void pg_trsv_upper_kernel(const double* __restrict__ L, int n, int k0, int nb,
+                                                              double* __restrict__ y, double* __restrict__ x) {
+  __shared__ double T[kPgNb][kPgNb + 1];
   __shared__ double xs[kPgNb];
-  const int t = threadIdx.x;
-  if (t < kPgNb) {
-    const int r = t, rc = min(r, nb - 1);
-    double u[kPgNb];
+  const int r = threadIdx.x;
+  const int rc = min(r, nb - 1);
+  {
+    double v[kPgNb];  // element (rc, c) of the block
 #pragma unroll
-    for (int j = 0; j < kPgNb; ++j) u[j] = L[(int64_t)(k0 + rc) * n + (k0 + min(j, nb - 1))];
-    const double rinv = 1.0 / L[(int64_t)(k0 + rc) * n + (k0 + rc)];
-    double v = y[k0 + rc];
+    for (int c = 0; c < kPgNb; ++c) v[c] = L[(int64_t)(k0 + min(c, nb - 1)) * n + (k0 + rc)];
 #pragma unroll
-    for (int j = kPgNb - 1; j >= 0; --j) {
-      if (j < nb) {
-        const double xj = lane_value(v * rinv, j);
-        v = r == j ? xj : (r < j ? fma(-u[j], xj, v) : v);
-      }
-    }
-    xs[r] = v;
-    if (blockIdx.x == 0 && r < nb) x[k0 + r] = v;
+    for (int c = 0; c < kPgNb; ++c) T[r][c] = v[c];
   }
   __syncthreads();
-  const int row = (int)blockIdx.x * 256 + t;
-  if (row >= k0) return;
-  double lv[kPgNb];
+  double u[kPgNb];  // column r of the block: u[j] = L_jr
 #pragma unroll
-  for (int c = 0; c < kPgNb; ++c) lv[c] = L[(int64_t)row * n + (k0 + min(c, nb - 1))];
-  double acc = y[row];
+  for (int j = 0; j < kPgNb; ++j) u[j] = T[min(j, nb - 1)][rc];
+  const double rinv = 1.0 / T[rc][rc];
+  double v = y[k0 + rc];
 #pragma unroll
-  for (int c = 0; c < kPgNb; ++c)
-    if (c < nb) acc = fma(-lv[c], xs[c], acc);
-  y[row] = acc;
+  for (int j = kPgNb - 1; j >= 0; --j) {
+    if (j < nb) {
+      const double xj = lane_value(v * rinv, j);
+      v = r == j ? xj : (r < j ? fma(-u[j], xj, v) : v);
+    }
+  }
+  xs[r] = v;
+  if (blockIdx.x == 0 && r < nb) x[k0 + r] = v;
+  const int row0 = (int)blockIdx.x * kPgNb;
+  if (row0 >= k0) return;  // uniform: no rows above for this workgroup
+  {
+    double w[kPgNb];  // lane r: element (k0 + r, row0 + jj) of the factor
+#pragma unroll
+    for (int jj = 0; jj < kPgNb; ++jj) w[jj] = L[(int64_t)min(row0 + jj, k0 - 1) * n + (k0 + rc)];
+    __syncthreads();  // every lane is done reading the diagonal block from T
+#pragma unroll
+    for (int jj = 0; jj < kPgNb; ++jj) T[jj][r] = w[jj];
+  }
+  __syncthreads();
+  const int row = row0 + r;
+  if (row < k0) {
+    double acc = y[row];
+#pragma unroll
+    for (int c = 0; c < kPgNb; ++c)
+      if (c < nb) acc = fma(-T[r][c], xs[c], acc);
+    y[row] = acc;
+  }
 }
 
 // Pivot rule on the factor: failed factorisation, or some L_kk^2 <= 1e-12 max diag.
@@ -808,8 +825,8 @@ int icp_pose_graph_optimize(icp_ctx_t* ctx, int32_t n_nodes, double* poses, int3
     }
     for (int k0 = ((n - 1) / kPgNb) * kPgNb; k0 >= 0; k0 -= kPgNb) {
       const int nb = std::min(kPgNb, n - k0);
-      hipLaunchKernelGGL(pg_trsv_upper_kernel, dim3((unsigned)std::max(1, (k0 + 255) / 256)), dim3(256), 0, s, A,
-                         n, k0, nb, yv, dv);
+      hipLaunchKernelGGL(pg_trsv_upper_kernel, dim3((unsigned)std::max(1, (k0 + kPgNb - 1) / kPgNb)), dim3(kPgNb), 0,
+                         s, A, n, k0, nb, yv, dv);
     }
     HIP_TRY(hipGetLastError(), "pose graph solve");
     hipLaunchKernelGGL(pg_update_kernel, dim3((unsigned)((n_nodes + 63) / 64)), dim3(64), 0, s, P, dv,

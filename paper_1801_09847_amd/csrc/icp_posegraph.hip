@@ -16,10 +16,10 @@
 // a right-looking blocked Cholesky (64x64 diagonal blocks factorised in
 // registers by four wavefronts, each inside the trailing update before it;
 // the panel solved with four lanes per row; the trailing update in 64x64
-// tiles) and solved by blocked forward and backward substitution, on the
-// context's stream, with the pivot rule checked on the factor; one thread per
-// node applies the step.  The host keeps or refuses the
-// step from F alone.
+// tiles; the forward substitution rides along in the update) and solved by
+// blocked backward substitution, on the context's stream, with the pivot
+// rule checked on the factor; one thread per node applies the step.  The
+// host keeps or refuses the step from F alone.
 
 #include <math.h>
 
@@ -434,16 +434,83 @@ __global__ __launch_bounds__(256) void pg_chol_panel_kernel(double* __restrict__
     if (FULL || 4 * k + q < nb) row[(int64_t)(4 * k + q) * n] = b[k];
 }
 
+// Forward substitution L y = g, step for the block column [k0, k0 + nb), by
+// a whole workgroup of 256 threads: wavefront 0 solves the diagonal block
+// (lane r holding row r of L_kk and g_r: y_j is taken from lane j, then
+// g_r -= L_rj y_j in lanes r > j), then the workgroup subtracts L_ik y_k from
+// rows k0 + nb + first + t, t + stride, ... (one thread per row, coalesced
+// along the column).  y goes to its own vector, so no workgroup reads an
+// entry of g that another one has already overwritten.
+__device__ __forceinline__ void lower_solve_step(const double* __restrict__ L, int n, int k0, int nb,
+                                                 double* __restrict__ g, double* __restrict__ y, bool write_y,
+                                                 int first, int stride) {
+  // (rows of L are read in halves of 32 columns: few registers, so that the
+  // trailing-update kernel that also runs this keeps its occupancy)
+  constexpr int H = kPgNb / 2;
+  __shared__ double ys[kPgNb];
+  const int t = threadIdx.x;
+  if (t < kPgNb) {
+    const int r = t, rc = min(r, nb - 1);
+    const double rinv = 1.0 / L[(int64_t)(k0 + rc) * n + (k0 + rc)];
+    double v = g[k0 + rc];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      double l[H];
+#pragma unroll
+      for (int c = 0; c < H; ++c) l[c] = L[(int64_t)(k0 + min(h * H + c, nb - 1)) * n + (k0 + rc)];
+#pragma unroll
+      for (int jj = 0; jj < H; ++jj) {
+        const int j = h * H + jj;
+        if (j < nb) {
+          const double yj = lane_value(v * rinv, j);
+          v = r == j ? yj : (r > j ? fma(-l[jj], yj, v) : v);
+        }
+      }
+    }
+    ys[r] = v;
+    if (write_y && r < nb) y[k0 + r] = v;
+  }
+  __syncthreads();
+  for (int row = k0 + nb + first + t; row < n; row += stride) {
+    double acc = g[row];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      double lv[H];
+#pragma unroll
+      for (int c = 0; c < H; ++c) lv[c] = L[(int64_t)(k0 + min(h * H + c, nb - 1)) * n + row];
+#pragma unroll
+      for (int c = 0; c < H; ++c)
+        if (h * H + c < nb) acc = fma(-lv[c], ys[h * H + c], acc);
+    }
+    g[row] = acc;
+  }
+}
+
+// One forward-substitution step over a grid: every workgroup solves the
+// diagonal block itself and takes its own 256 rows below.
+__global__ __launch_bounds__(256) void pg_trsv_lower_kernel(const double* __restrict__ L, int n, int k0, int nb,
+                                                            double* __restrict__ g, double* __restrict__ y) {
+  lower_solve_step(L, n, k0, nb, g, y, blockIdx.x == 0, (int)blockIdx.x * 256, (int)gridDim.x * 256);
+}
+
 // Trailing update C -= P P^T (lower part) after a panel P (rem x nb, column
 // k0 .. k0 + nb, rows below the block): block (bj, bi), bj <= bi, computes the
 // 64 x 64 output tile (bi, bj) from the two 64-row slices of P in LDS; thread
 // (tx, ty) owns rows tx + 16u and columns ty + 16v, so that for each (u, v)
 // sixteen lanes update sixteen consecutive entries of one column.  Tile
 // (0, 0) is the next diagonal block: once updated, its workgroup factorises
-// it, which hides that sequential step behind the other tiles.
+// it, which hides that sequential step behind the other tiles.  An extra row
+// of workgroups (blockIdx.y == gridDim.x) carries, in its first workgroup,
+// the forward-substitution step of this block column, whose diagonal block
+// and panel are final by now.
 __global__ __launch_bounds__(256) void pg_chol_update_kernel(double* __restrict__ A, int n, int k0, int nb,
-                                                             int rem, int* __restrict__ info) {
+                                                             int rem, int* __restrict__ info, double* __restrict__ g,
+                                                             double* __restrict__ y) {
   const int bi = blockIdx.y, bj = blockIdx.x;
+  if (bi == (int)gridDim.x) {
+    if (bj == 0) lower_solve_step(A, n, k0, nb, g, y, true, 0, 256);
+    return;
+  }
   if (bj > bi) return;  // upper tiles: nothing (uniform per block)
   __shared__ double Pi[kPgNb][kPgNb + 1];
   __shared__ double Pj[kPgNb][kPgNb + 1];
@@ -498,46 +565,6 @@ __global__ __launch_bounds__(256) void pg_chol_update_kernel(double* __restrict_
     __syncthreads();  // the tile's updated entries, written by all four waves
     diag_factor(A, n, (int)row0, min(kPgNb, rem), info);
   }
-}
-
-// Forward substitution L y = g for the block column [k0, k0 + nb): every
-// workgroup solves the diagonal block itself (wavefront 0, lane r holding row
-// r of L_kk and g_r: y_j is taken from lane j, then g_r -= L_rj y_j in lanes
-// r > j), then subtracts L_ik y_k from its own share of the rows below, one
-// thread per row.  y goes to its own vector, so no workgroup reads an entry of
-// g that another one has already overwritten.
-__global__ __launch_bounds__(256) void pg_trsv_lower_kernel(const double* __restrict__ L, int n, int k0, int nb,
-                                                            double* __restrict__ g, double* __restrict__ y) {
-  __shared__ double ys[kPgNb];
-  const int t = threadIdx.x;
-  if (t < kPgNb) {
-    const int r = t, rc = min(r, nb - 1);
-    double l[kPgNb];
-#pragma unroll
-    for (int c = 0; c < kPgNb; ++c) l[c] = L[(int64_t)(k0 + min(c, nb - 1)) * n + (k0 + rc)];
-    const double rinv = 1.0 / L[(int64_t)(k0 + rc) * n + (k0 + rc)];
-    double v = g[k0 + rc];
-#pragma unroll
-    for (int j = 0; j < kPgNb; ++j) {
-      if (j < nb) {
-        const double yj = lane_value(v * rinv, j);
-        v = r == j ? yj : (r > j ? fma(-l[j], yj, v) : v);
-      }
-    }
-    ys[r] = v;
-    if (blockIdx.x == 0 && r < nb) y[k0 + r] = v;
-  }
-  __syncthreads();
-  const int row = k0 + nb + (int)blockIdx.x * 256 + t;
-  if (row >= n) return;
-  double lv[kPgNb];
-#pragma unroll
-  for (int c = 0; c < kPgNb; ++c) lv[c] = L[(int64_t)(k0 + min(c, nb - 1)) * n + row];
-  double acc = g[row];
-#pragma unroll
-  for (int c = 0; c < kPgNb; ++c)
-    if (c < nb) acc = fma(-lv[c], ys[c], acc);
-  g[row] = acc;
 }
 
 // Backward substitution L^T x = y for the block column [k0, k0 + nb), blocks
@@ -811,17 +838,19 @@ int icp_pose_graph_optimize(icp_ctx_t* ctx, int32_t n_nodes, double* poses, int3
       else
         hipLaunchKernelGGL(pg_chol_panel_kernel<false>, pgrid, dim3(256), 0, s, A, n, k0, nb, rem);
       HIP_TRY(hipGetLastError(), "pose graph factorisation");
+      // the trailing update also carries this block column's forward-
+      // substitution step (L y = rhs): dv is consumed, y collects
       const unsigned tiles = (unsigned)((rem + kPgNb - 1) / kPgNb);
-      hipLaunchKernelGGL(pg_chol_update_kernel, dim3(tiles, tiles), dim3(256), 0, s, A, n, k0, nb, rem, info);
+      hipLaunchKernelGGL(pg_chol_update_kernel, dim3(tiles, tiles + 1), dim3(256), 0, s, A, n, k0, nb, rem, info, dv,
+                         yv);
       HIP_TRY(hipGetLastError(), "pose graph factorisation");
     }
     hipLaunchKernelGGL(pg_pivot_check_kernel, dim3(1), dim3(256), 0, s, A, n, dmax, info, flag);
-    // L y = rhs block column by block column, then L^T x = y from the last
-    // block back; the right-hand side (dv) is consumed and receives x
-    for (int k0 = 0; k0 < n; k0 += kPgNb) {
-      const int nb = std::min(kPgNb, n - k0), rem = n - k0 - nb;
-      hipLaunchKernelGGL(pg_trsv_lower_kernel, dim3((unsigned)std::max(1, (rem + 255) / 256)), dim3(256), 0, s, A,
-                         n, k0, nb, dv, yv);
+    // the last block column's forward step, then L^T x = y from the last
+    // block back; dv receives x
+    {
+      const int k0 = ((n - 1) / kPgNb) * kPgNb;
+      hipLaunchKernelGGL(pg_trsv_lower_kernel, dim3(1), dim3(256), 0, s, A, n, k0, n - k0, dv, yv);
     }
     for (int k0 = ((n - 1) / kPgNb) * kPgNb; k0 >= 0; k0 -= kPgNb) {
       const int nb = std::min(kPgNb, n - k0);

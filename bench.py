@@ -92,6 +92,23 @@ def cpu_baseline(data, variant, passes, min_seconds=10.0):
                       f"with k-d tree, {dt:.1f} s wall incl. tree builds"}
 
 
+def ceilings_section(icp):
+    """Device ceilings measured in this process: unpacked vector issue rates
+    (lane operations per second) and streaming copy / read bandwidth over
+    1 GiB buffers (beyond the 256 MiB last-level cache) and over 64 MiB (held
+    in it)."""
+    out = {}
+    for kind, name in ((0, "f32_mul_add"), (1, "f32_fma"), (2, "f64_mul_add"), (3, "f64_fma")):
+        rate, ms = icp.measure_valu(kind)
+        out[f"valu_{name}_lane_ops_per_s"] = rate
+    for nbytes, kind, name in ((1 << 30, 0, "copy_1GiB"), (1 << 30, 1, "read_1GiB"),
+                               (64 << 20, 0, "copy_64MiB"), (64 << 20, 1, "read_64MiB")):
+        gbs, ms = icp.measure_copy(nbytes, kind)
+        out[f"{name}_gbs"] = gbs
+    print("bench: ceilings " + ", ".join(f"{k} {v:.4g}" for k, v in out.items()), file=sys.stderr, flush=True)
+    return out
+
+
 def robust_section(args, icp, np, torch, s, t, n, data, K, r, steps=3):
     """The same registration with the robust (IRLS) losses, scale 1 cm."""
     out = []
@@ -202,7 +219,7 @@ def normals_section(args, icp, synth, np, torch, data):
     return out
 
 
-def ransac_section(args, icp, synth, np, torch):
+def ransac_section(args, icp, synth, np, torch, valu_rate=None):
     """Global registration as in the paper's pairwise workflow: nearest-feature
     matching of 33-dimensional FPFH-shaped features, then RANSAC with
     ransac_n 4, edge length 0.9, distance 0.075 m, max_iteration 4e6 and
@@ -227,10 +244,10 @@ def ransac_section(args, icp, synth, np, torch):
         corr = icp.feature_match(fs, ft, ctx=ctx)
     torch.cuda.synchronize()
     fm = (time.perf_counter() - t0) / reps
-    # float32 subtract, multiply and add per dimension and pair.  Peak of
-    # non-FMA float32 operations: 256 CUs x 128 lanes x 2.4 GHz with packed
-    # float32 (the chip's ceiling), half that (64 lanes) for the unpacked
-    # instructions this library is built with
+    # float32 subtract, multiply and add per dimension and pair, one unpacked
+    # instruction each.  Peak: the chip's packed float32 rate (256 CUs x 128
+    # lanes x 2.4 GHz); the measured unpacked mul/add issue rate of this
+    # device (icp_measure_valu kind 0) beside it
     alu_peak = 256 * 128 * 2.4e9
     fm_ops = 3.0 * dim * ns * nt
     res = icp.ransac_register(s, t, corr, 0.075, ctx=ctx, **prm)
@@ -254,7 +271,9 @@ def ransac_section(args, icp, synth, np, torch):
            "feature_match": {"ms_per_call": fm * 1e3, "pairs_per_s": ns * nt / fm,
                              "roofline": {"bound": "alu", "achieved": fm_ops / fm / 1e12, "peak": alu_peak / 1e12,
                                           "unit": "Tops/s", "frac": fm_ops / fm / alu_peak,
-                                          "frac_of_unpacked_peak": fm_ops / fm / (alu_peak / 2)}},
+                                          "measured_unpacked_rate": valu_rate / 1e12 if valu_rate else None,
+                                          "frac_of_measured_unpacked_rate":
+                                              fm_ops / fm / valu_rate if valu_rate else None}},
            "ransac": {"ms_per_call": rs * 1e3, "n_iterations": res.n_iterations, "n_validated": res.n_validated,
                       "fitness": res.fitness, "inlier_rmse": res.inlier_rmse, "rot_err_deg": ang,
                       "trans_err_m": float(np.linalg.norm(res.T[:3, 3] - G[:3, 3])),
@@ -533,6 +552,8 @@ def main():
     ap.add_argument("--variant", default="point_to_plane", choices=sorted(ALG_BYTES))
     ap.add_argument("--precision", default="kahan32", choices=["kahan32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ceilings", action="store_true", help="skip the measured VALU / copy ceilings")
+    ap.add_argument("--ceilings-only", action="store_true", help="only measure and print the device ceilings")
     ap.add_argument("--cpu-passes", type=int, default=6)
     ap.add_argument("--no-batched", action="store_true", help="skip the 256-pair batched section")
     ap.add_argument("--batch-pairs", type=int, default=256)
@@ -571,6 +592,11 @@ def main():
         return
 
     from paper_1801_09847_amd import icp, synth
+
+    ceilings = None if args.no_ceilings else ceilings_section(icp)
+    if args.ceilings_only:
+        print(json.dumps({"ceilings": ceilings}), flush=True)
+        return
 
     desc, gen = WORKLOADS[args.workload]
     print(f"bench: generating {args.workload} ({desc})", file=sys.stderr, flush=True)
@@ -645,10 +671,14 @@ def main():
             "alg_bytes_per_launch": alg_bytes,
             "avg_launch_us": pass_us,
             "launches_timed": prof["pass_launches"],
+            "copy_ceiling_gbs": ceilings["copy_1GiB_gbs"] if ceilings else None,
+            "frac_of_copy_ceiling": achieved / ceilings["copy_1GiB_gbs"] if ceilings else None,
         },
         "result": {"fitness": res.fitness, "inlier_rmse": res.inlier_rmse, "n_iter": res.n_iter,
                    "status": res.status},
     }
+    if ceilings:
+        out["ceilings"] = ceilings
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(data, args.variant, args.cpu_passes)
@@ -660,7 +690,8 @@ def main():
     if not args.no_pose_graph and args.workload == "c3":
         out["pose_graph"] = pose_graph_section(args, icp, synth, np, torch)
     if not args.no_ransac and args.workload == "c3":
-        out["ransac"] = ransac_section(args, icp, synth, np, torch)
+        out["ransac"] = ransac_section(args, icp, synth, np, torch,
+                                       ceilings["valu_f32_mul_add_lane_ops_per_s"] if ceilings else None)
     if not args.no_batched:
         out["batched"] = batched_section(args, icp, synth, np, torch)
     if not args.no_served:

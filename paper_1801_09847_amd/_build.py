@@ -2,6 +2,7 @@
 next to this file (in-tree, so the built object travels with the sources)."""
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -11,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libicp.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["icp_kernels.hip", "icp_build.hip", "icp_api.hip", "icp_server.hip", "icp_posegraph.hip",
-           "icp_ransac.hip"]
+           "icp_ransac.hip", "icp_ceilings.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -25,17 +26,26 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    objs = []
+def build(verbose: bool = False, jobs: int | None = None) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    cmds, objs = [], []
     for src in SOURCES:
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-        cmd = [HIPCC, *FLAGS, "-I", os.path.join(HERE, "..", "include"), "-c",
-               os.path.join(CSRC, src), "-o", obj]
+        cmds.append([HIPCC, *FLAGS, "-I", os.path.join(HERE, "..", "include"), "-c",
+                     os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+    # one hipcc per translation unit, a few at a time (each takes several GB
+    # of memory at -O3 on the largest sources)
+    jobs = jobs or max(1, min(len(cmds), (os.cpu_count() or 2) // 2, 4))
+
+    def run(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
-        objs.append(obj)
+
+    with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
+        for f in [ex.submit(run, c) for c in cmds]:
+            f.result()
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, "-Wl,-z,defs"]
     if verbose:

@@ -328,8 +328,9 @@ typedef struct {
  *   max_iter >= 0; rel_tol finite, >= 0
  *   out      host result
  * Synchronous on the context's stream.  Errors: INVALID_ARG (bad sizes,
- * indices, non-finite or non-rigid transforms, non-finite information), OOM,
- * DEVICE; on errors the poses are untouched. */
+ * indices, non-finite or non-rigid transforms, non-finite information, an
+ * information matrix that is not exactly symmetric), OOM, DEVICE; on errors
+ * the poses are untouched. */
 int icp_pose_graph_optimize(icp_ctx_t *ctx, int32_t n_nodes, double *poses, int32_t n_edges,
                             const icp_pose_edge_t *edges, int32_t method, int32_t max_iter,
                             double rel_tol, icp_pose_graph_result_t *out);
@@ -500,6 +501,9 @@ typedef struct {
   int32_t host_memory;        /* 1: the three arrays are host memory */
   int32_t reserved;           /* must be 0 */
   uint64_t user_tag;
+  void *stream;               /* device inputs: the hipStream_t whose work so far
+                                 produces them (the copy waits for it), or NULL
+                                 when they are already complete */
 } icp_request_t;
 
 typedef struct {
@@ -520,14 +524,23 @@ int icp_server_create(const icp_server_cfg_t *cfg, icp_server_t **out);
 
 /* Copies the request's inputs (device-to-device or host-to-device) into
  * server memory before returning -- the caller may free its buffers at once
- * -- and queues it.  *ticket identifies the completion.  Thread-safe.
- * Errors: INVALID_ARG, TOO_LARGE (inputs alone exceed the budget), DEVICE. */
+ * -- and queues it.  The copy runs on the server's own stream: device inputs
+ * still being written by queued work must name that work's stream in
+ * req->stream (the copy is ordered after everything enqueued on it before
+ * this call); with stream NULL they must be complete.  *ticket identifies the
+ * completion.  Thread-safe.
+ * Errors: INVALID_ARG, TOO_LARGE (inputs alone exceed the budget), DEVICE
+ * (also once the server has stopped after a device error). */
 int icp_server_submit(icp_server_t *srv, const icp_request_t *req, uint64_t *ticket);
 
 /* Caller-driven mode: one server step (admission, level preparation,
  * iters_per_step iterations, retirement).  *n_busy (optional) receives the
  * number of queued + running requests after the step.  With a background
- * thread this is a no-op.  Errors: DEVICE (the server is then unusable). */
+ * thread this is a no-op.  Errors: DEVICE.  After a failed step (here or on
+ * the background thread) the server is stopped: every queued and running
+ * request completes at once with error ICP_E_DEVICE, and later submits and
+ * steps return ICP_E_DEVICE; only poll, wait (for the completions already
+ * posted) and destroy remain useful. */
 int icp_server_step(icp_server_t *srv, int32_t *n_busy);
 
 /* Moves up to cap finished requests' completions to out (host), in
@@ -535,8 +548,9 @@ int icp_server_step(icp_server_t *srv, int32_t *n_busy);
 int icp_server_poll(icp_server_t *srv, icp_completion_t *out, int32_t cap, int32_t *n_out);
 
 /* Blocks until `ticket` has completed and moves its completion to *out (in
- * caller-driven mode it runs steps itself).  Errors: NOT_FOUND (unknown or
- * already delivered ticket), DEVICE. */
+ * caller-driven mode it runs steps itself).  A request of a stopped server
+ * is delivered with error ICP_E_DEVICE.  Errors: NOT_FOUND (unknown or
+ * already delivered ticket), DEVICE (a step it ran failed). */
 int icp_server_wait(icp_server_t *srv, uint64_t ticket, icp_completion_t *out);
 
 /* Stops the server: requests not yet completed are completed with
@@ -568,6 +582,30 @@ int icp_ctx_set_profiling(icp_ctx_t *ctx, int enable);
 
 /* Copies the accumulated counters to *out (host).  Errors: INVALID_ARG. */
 int icp_ctx_get_profile(icp_ctx_t *ctx, icp_profile_t *out);
+
+/* ---- device ceilings (measurement support) ------------------------------
+ * Not part of the method: these run small dedicated kernels on `device` and
+ * return the rates that the library's kernels are compared against, taken on
+ * the same device in the same process.  Each allocates and frees its own
+ * buffers and stream, and blocks until done.
+ *
+ * icp_measure_valu: issue rate of unpacked vector arithmetic, in lane
+ * operations per second (one operation per lane per instruction), over
+ * 8 waves per SIMD of 8 independent dependency chains each.
+ *   kind 0  v_mul_f32 / v_add_f32 alternating
+ *   kind 1  v_fma_f32
+ *   kind 2  v_mul_f64 / v_add_f64 alternating
+ *   kind 3  v_fma_f64
+ * *best_ms (may be NULL) receives the fastest of five timed launches.
+ * Errors: INVALID_ARG (kind outside 0..3, lane_ops_per_s NULL), DEVICE. */
+int icp_measure_valu(int device, int kind, double *lane_ops_per_s, double *best_ms);
+
+/* icp_measure_copy: streaming bandwidth of device memory over a buffer of
+ * `bytes` (>= 1 MiB; choose it above the 256 MiB last-level cache to measure
+ * HBM).  kind 0: copy (read + write bytes counted), kind 1: read only (a
+ * per-thread sum is written, negligible).  *gb_per_s is bytes moved / fastest
+ * of five launches, in 1e9 B/s.  Errors: INVALID_ARG, OOM/DEVICE. */
+int icp_measure_copy(int device, int64_t bytes, int kind, double *gb_per_s, double *best_ms);
 
 #ifdef __cplusplus
 }

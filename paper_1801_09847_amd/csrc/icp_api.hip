@@ -60,7 +60,7 @@ void ctx_free(icp_ctx* c) {
   DeviceGuard g(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   Buf* bufs[] = {&c->desc, &c->bbox_part, &c->t_key, &c->t_rank, &c->scan_tmp, &c->s_hist,
-                 &c->cs, &c->tp, &c->tn, &c->sx, &c->sy, &c->sz, &c->perm, &c->vdesc,
+                 &c->cs, &c->occ_raw, &c->occ, &c->tp, &c->tn, &c->sx, &c->sy, &c->sz, &c->perm, &c->vdesc,
                  &c->vflags, &c->vstarts, &c->lvl_src, &c->lvl_tgt, &c->lvl_tn, &c->pg, &c->rs};
   for (Buf* b : bufs) b->release();
   for (Buf& b : c->sk) b.release();
@@ -241,6 +241,7 @@ Layout make_layout(int n, int64_t n_items, int64_t total_src, int64_t total_tile
   L.blk_s = take(sizeof(int64_t) * (n + 1));
   L.src_off = take(sizeof(int64_t) * (n + 1));
   L.blk_tab = take(sizeof(int64_t) * (n + 1));
+  L.blk_occ = take(sizeof(int64_t) * (n + 1));
   L.pargs = take(sizeof(PassArgs) * n);
   L.sargs = take(sizeof(SolveArgs) * n);
   L.states = take(sizeof(IterState) * n);
@@ -324,9 +325,12 @@ int plan_pairs(icp_ctx* c, int n, const PairIn* in, Prep* P, int* bad) {
   int64_t* bs = reinterpret_cast<int64_t*>(hh + L.blk_s);
   int64_t* so = reinterpret_cast<int64_t*>(hh + L.src_off);
   int64_t* bk = reinterpret_cast<int64_t*>(hh + L.blk_tab);
+  int64_t* bo2 = reinterpret_cast<int64_t*>(hh + L.blk_occ);
+  P->occ_off.assign(n + 1, 0);
   bt[0] = 0;
   bs[0] = 0;
   bk[0] = 0;
+  bo2[0] = 0;
   for (int p = 0; p < n; ++p) {
     const float* t = hbox + 16 * p;
     const float* q = t + 8;
@@ -340,14 +344,18 @@ int plan_pairs(icp_ctx* c, int n, const PairIn* in, Prep* P, int* bad) {
     bp[p] = BuildPair{in[p].src, in[p].tgt, in[p].tgt_n, in[p].n_src, in[p].n_tgt,
                       P->src_off[p], P->tgt_off[p], P->tab_off[p], P->g[p],
                       (double)q[0], (double)q[1], (double)q[2], 1.0 / hs,
-                      nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+                      nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                      P->occ_off[p], nullptr};
     bt[p + 1] = bt[p] + (in[p].n_tgt + 255) / 256;
     bs[p + 1] = bs[p] + (in[p].n_src + 255) / 256;
     bk[p + 1] = bk[p] + ((int64_t)P->g[p].ncell + 1 + 255) / 256;
+    P->occ_off[p + 1] = P->occ_off[p] + occ_words(P->g[p]);
+    bo2[p + 1] = bo2[p] + (int64_t)((occ_words(P->g[p]) + 255) / 256);
     so[p] = P->src_off[p];
   }
   so[n] = P->src_off[n];
   P->total_tab = P->tab_off[n];
+  P->total_occ = P->occ_off[n];
   if (P->total_tab >= (uint64_t)UINT32_MAX)
     return fail(ICP_E_TOO_LARGE, "grid tables of one call exceed 2^32 cells");
   P->sub = P->g[0].sub;
@@ -371,7 +379,9 @@ int build_pairs(icp_ctx* c, Prep* P, const PairDst* dst) {
   const int64_t hist_cap = radix_hist_needed(P->total_src);
   HIP_TRY(c->cs.ensure(4 * (size_t)P->total_tab), "alloc");
   HIP_TRY(c->perm.ensure(4 * (size_t)P->total_src), "alloc");
+  HIP_TRY(c->occ_raw.ensure(4 * (size_t)std::max<uint64_t>(P->total_occ, 1)), "alloc");
   if (!dst) {
+    HIP_TRY(c->occ.ensure(4 * (size_t)std::max<uint64_t>(P->total_occ, 1)), "alloc");
     HIP_TRY(c->tp.ensure(16 * (size_t)P->total_tgt), "alloc");
     if (normals) HIP_TRY(c->tn.ensure(16 * (size_t)P->total_tgt), "alloc");
     HIP_TRY(c->sx.ensure(4 * (size_t)P->total_src), "alloc");
@@ -392,6 +402,7 @@ int build_pairs(icp_ctx* c, Prep* P, const PairDst* dst) {
       bp[p].sy_dst = dst[p].sy;
       bp[p].sz_dst = dst[p].sz;
       bp[p].perm_dst = dst[p].perm ? dst[p].perm : c->perm.as<uint32_t>() + P->src_off[p];
+      bp[p].occ_dst = dst[p].occ;
     } else {
       bp[p].cs_dst = c->cs.as<uint32_t>() + P->tab_off[p];
       bp[p].tp_dst = c->tp.as<float4>() + P->tgt_off[p];
@@ -400,17 +411,25 @@ int build_pairs(icp_ctx* c, Prep* P, const PairDst* dst) {
       bp[p].sy_dst = c->sy.as<float>() + P->src_off[p];
       bp[p].sz_dst = c->sz.as<float>() + P->src_off[p];
       bp[p].perm_dst = c->perm.as<uint32_t>() + P->src_off[p];
+      bp[p].occ_dst = c->occ.as<uint32_t>() + P->occ_off[p];
     }
   }
   HIP_TRY(hipMemcpyAsync(dd + L.pairs, hh + L.pairs, L.pargs - L.pairs, hipMemcpyHostToDevice, s),
           "upload");
   const BuildPair* dbp = reinterpret_cast<const BuildPair*>(dd + L.pairs);
+  HIP_TRY(launch_occ_clear(c->occ_raw.as<uint32_t>(), P->total_occ, s), "occupancy clear");
   HIP_TRY(launch_seg_targets(dbp, n, reinterpret_cast<const int64_t*>(dd + L.blk_t), bt[n],
                              reinterpret_cast<const int64_t*>(dd + L.blk_tab), bk[n],
                              P->total_tab, c->cs.as<uint32_t>(), c->t_key.as<uint32_t>(),
                              c->t_rank.as<uint32_t>(), c->scan_tmp.as<uint32_t>(), scan_cap,
-                             dst != nullptr, s),
+                             dst != nullptr, c->occ_raw.as<uint32_t>(), s),
           "target grid");
+  {
+    const int64_t* bo2 = reinterpret_cast<const int64_t*>(hh + L.blk_occ);
+    HIP_TRY(launch_occ_dilate(dbp, n, reinterpret_cast<const int64_t*>(dd + L.blk_occ), bo2[n],
+                              c->occ_raw.as<uint32_t>(), s),
+            "occupancy dilation");
+  }
   SortBufs sb;
   for (int k = 0; k < 2; ++k) {
     sb.klo[k] = c->sk[k].as<uint32_t>();
@@ -445,6 +464,7 @@ PassArgs pass_args(icp_ctx* c, const Prep& P, int p, double r, bool with_jprev, 
   a.tp = c->tp.as<float4>() + P.tgt_off[p];
   a.tn = normals ? c->tn.as<float4>() + P.tgt_off[p] : nullptr;
   a.cs = c->cs.as<uint32_t>() + P.tab_off[p];
+  a.occ = c->occ.as<uint32_t>() + P.occ_off[p];
   a.g = P.g[p];
   a.r2f = (float)(r * r);
   a.inv_h2 = (float)(P.g[p].inv_h * P.g[p].inv_h);

@@ -291,11 +291,13 @@ __device__ inline int cell_of(float p, double o, double inv_h, int dim) {
 // Cell key of every target point (global: offset by the pair's table) and its
 // rank among the points of its cell (order of arrival; the search breaks ties
 // by original index, so the order inside a cell never matters).
+// With occ_raw, the cell's bit is also set in the pair's raw occupancy bitmap.
 __global__ __launch_bounds__(256) void seg_target_key_kernel(const BuildPair* __restrict__ pairs, int n,
                                                              const int64_t* __restrict__ blk_off,
                                                              uint32_t* __restrict__ counts,
                                                              uint32_t* __restrict__ key,
-                                                             uint32_t* __restrict__ rank) {
+                                                             uint32_t* __restrict__ rank,
+                                                             uint32_t* __restrict__ occ_raw) {
   const int p = find_segment(blk_off, n, blockIdx.x);
   const BuildPair& bp = pairs[p];
   const int64_t i = (int64_t)(blockIdx.x - blk_off[p]) * 256 + threadIdx.x;
@@ -308,7 +310,51 @@ __global__ __launch_bounds__(256) void seg_target_key_kernel(const BuildPair* __
   const uint32_t k = ((uint32_t)cz * (uint32_t)g.dy + (uint32_t)cy) * (uint32_t)g.dx + (uint32_t)cx;
   const uint32_t gk = (uint32_t)bp.tab_off + k;
   key[bp.tgt_off + i] = gk;
-  rank[bp.tgt_off + i] = atomicAdd(&counts[gk], 1u);
+  const uint32_t rk = atomicAdd(&counts[gk], 1u);
+  rank[bp.tgt_off + i] = rk;
+  // the first point to reach a cell marks it (one atomic per occupied cell)
+  if (rk == 0 && occ_raw && bp.occ_dst) {
+    const uint64_t w = bp.occ_off + ((uint64_t)cz * (uint64_t)g.dy + (uint64_t)cy) * occ_row_words(g.dx) +
+                       ((uint32_t)cx >> 5);
+    atomicOr(&occ_raw[w], 1u << (cx & 31));
+  }
+}
+
+// Dilation of each pair's raw occupancy bitmap over the 27-cell
+// neighbourhood: word (z, y, wi) of the result is the OR over the rows
+// (y + dy, z + dz), |dy|, |dz| <= 1, inside the grid, of the row's words
+// wi - 1 .. wi + 1 spread by one bit to each side.
+__global__ __launch_bounds__(256) void occ_dilate_kernel(const BuildPair* __restrict__ pairs, int n,
+                                                         const int64_t* __restrict__ blk_off,
+                                                         const uint32_t* __restrict__ raw) {
+  const int p = find_segment(blk_off, n, blockIdx.x);
+  const BuildPair& bp = pairs[p];
+  const GridDesc g = bp.g;
+  const uint32_t W = occ_row_words(g.dx);
+  const int64_t w = (int64_t)(blockIdx.x - blk_off[p]) * 256 + threadIdx.x;
+  if (!bp.occ_dst || (uint64_t)w >= occ_words(g)) return;
+  const int64_t row = w / W;
+  const int wi = (int)(w - row * W);
+  const int y = (int)(row % g.dy), z = (int)(row / g.dy);
+  const uint32_t* base = raw + bp.occ_off;
+  uint32_t d = 0;
+  for (int dz = -1; dz <= 1; ++dz) {
+    const int zz = z + dz;
+    if (zz < 0 || zz >= g.dz) continue;
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int yy = y + dy;
+      if (yy < 0 || yy >= g.dy) continue;
+      const uint32_t* r = base + ((int64_t)zz * g.dy + yy) * W;
+      const uint32_t c = r[wi];
+      const uint32_t l = wi > 0 ? r[wi - 1] : 0u;
+      const uint32_t h = wi + 1 < (int)W ? r[wi + 1] : 0u;
+      // bit j of the row word covers x = 32 wi + j: its x - 1 neighbour is
+      // bit j - 1 (or bit 31 of the word before), its x + 1 neighbour bit
+      // j + 1 (or bit 0 of the word after)
+      d |= c | (c << 1) | (c >> 1) | (l >> 31) | (h << 31);
+    }
+  }
+  bp.occ_dst[w] = d;
 }
 
 // After the scan, the concatenated tables hold each cell's first position
@@ -697,11 +743,11 @@ hipError_t launch_seg_targets(const BuildPair* pairs, int n, const int64_t* blk_
                               int64_t total_blocks, const int64_t* tab_blk_off,
                               int64_t tab_blocks, uint64_t total_tab, uint32_t* counts,
                               uint32_t* key, uint32_t* rank, uint32_t* scan_tmp, int64_t scan_cap,
-                              bool copy_tables, hipStream_t s) {
+                              bool copy_tables, uint32_t* occ_raw, hipStream_t s) {
   hipError_t e = hipMemsetAsync(counts, 0, sizeof(uint32_t) * (size_t)total_tab, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(seg_target_key_kernel, dim3((unsigned)total_blocks), dim3(256), 0, s, pairs, n,
-                     blk_off, counts, key, rank);
+                     blk_off, counts, key, rank, occ_raw);
   e = scan_exclusive(counts, (int64_t)total_tab, scan_tmp, scan_cap, pairs, n, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(seg_target_scatter_kernel, dim3((unsigned)total_blocks), dim3(256), 0, s, pairs,
@@ -709,6 +755,18 @@ hipError_t launch_seg_targets(const BuildPair* pairs, int n, const int64_t* blk_
   if (copy_tables)
     hipLaunchKernelGGL(seg_table_copy_kernel, dim3((unsigned)tab_blocks), dim3(256), 0, s, pairs, n,
                        tab_blk_off, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_occ_clear(uint32_t* occ_raw, uint64_t total_occ, hipStream_t s) {
+  return hipMemsetAsync(occ_raw, 0, sizeof(uint32_t) * (size_t)total_occ, s);
+}
+
+hipError_t launch_occ_dilate(const BuildPair* pairs, int n, const int64_t* occ_blk_off, int64_t occ_blocks,
+                             const uint32_t* occ_raw, hipStream_t s) {
+  if (occ_blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(occ_dilate_kernel, dim3((unsigned)occ_blocks), dim3(256), 0, s, pairs, n, occ_blk_off,
+                     occ_raw);
   return hipGetLastError();
 }
 

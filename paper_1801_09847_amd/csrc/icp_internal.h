@@ -7,7 +7,7 @@
 namespace icp {
 
 constexpr int kBlock = 256;        // threads per block of the pass kernel
-constexpr int kTile = 512;         // queries per block of the pass kernel (2 per thread)
+constexpr int kTile = 256;         // queries per block of the pass kernel (one per thread)
 constexpr int kNumSums = 29;       // 21 (J^T J upper) + 6 (J^T r) + sum d2 + count
 constexpr int kSumD2 = 27;
 constexpr int kSumCount = 28;
@@ -23,6 +23,16 @@ struct GridDesc {
   uint32_t ncell;  // dx * dy * dz
   int32_t sub;     // 1 or 2
 };
+
+// Occupancy bitmap over a grid, one bit per cell, rows of the x axis padded
+// to whole 32-bit words: the bit of cell (x, y, z) is bit (x & 31) of word
+// (z * dy + y) * occ_row_words(dx) + (x >> 5).  The pass reads the dilated
+// map, whose bit is set when any of the 27 cells around the cell holds a
+// target point.
+__host__ __device__ inline uint32_t occ_row_words(int32_t dx) { return ((uint32_t)dx + 31u) >> 5; }
+__host__ __device__ inline uint64_t occ_words(const GridDesc& g) {
+  return (uint64_t)g.dy * (uint64_t)g.dz * occ_row_words(g.dx);
+}
 
 // Device-resident loop state of one registration.
 struct IterState {
@@ -48,6 +58,7 @@ struct PassArgs {
   const float4* tp;       // cell-ordered target (x, y, z, bit pattern of original index)
   const float4* tn;       // cell-ordered target normals (nx, ny, nz, 0)
   const uint32_t* cs;     // cell start table, ncell + 1 entries (positions into tp)
+  const uint32_t* occ;    // optional dilated occupancy bitmap of the grid (occ_words(g) words)
   GridDesc g;
   float r2f;              // (float)(max_corr_dist^2)
   float inv_h2;           // (float)(inv_h^2)
@@ -170,6 +181,8 @@ struct BuildPair {
   float* sy_dst;
   float* sz_dst;
   uint32_t* perm_dst;            // n_src: ordered position -> original source index
+  uint64_t occ_off;              // first word of the pair's raw bitmap in the call's scratch
+  uint32_t* occ_dst;             // dilated occupancy bitmap (occ_words(g) words), or null
 };
 
 struct SortBufs {
@@ -194,7 +207,15 @@ hipError_t launch_seg_targets(const BuildPair* pairs, int n, const int64_t* blk_
                               int64_t total_blocks, const int64_t* tab_blk_off,
                               int64_t tab_blocks, uint64_t total_tab, uint32_t* counts,
                               uint32_t* key, uint32_t* rank, uint32_t* scan_tmp, int64_t scan_cap,
-                              bool copy_tables, hipStream_t s);
+                              bool copy_tables, uint32_t* occ_raw, hipStream_t s);
+// Dilated occupancy bitmaps of every pair that has an occ_dst: occ_raw is the
+// call's concatenated raw bitmap (total_occ words, zeroed by this call and
+// filled by the target key pass, so this runs before launch_seg_targets and
+// launch_occ_dilate after it); occ_blk_off: per-pair block offsets over the
+// raw words (256 words a block).
+hipError_t launch_occ_clear(uint32_t* occ_raw, uint64_t total_occ, hipStream_t s);
+hipError_t launch_occ_dilate(const BuildPair* pairs, int n, const int64_t* occ_blk_off, int64_t occ_blocks,
+                             const uint32_t* occ_raw, hipStream_t s);
 hipError_t launch_seg_sources(const BuildPair* pairs, int n, const int64_t* blk_off,
                               int64_t total_blocks, const int64_t* src_off, int64_t total,
                               SortBufs sb, uint32_t* hist, int64_t hist_cap, hipStream_t s);

@@ -159,11 +159,15 @@ __device__ inline F loss_weight(int kind, F k, F s) {
 // a lane are staged in LDS and scanned as a single flattened loop so that the
 // wavefront runs max(candidates) iterations instead of a sum over rows of the
 // per-row maximum.
+// Cell of a query (clamped to R + 1 cells around the grid) and its position
+// inside the cell, from the float32 query in float64.
+struct QueryCell {
+  int cx, cy, cz;
+  float fx, fy, fz;
+};
+
 template <int R>
-__device__ inline uint32_t stage_rows(const PassArgs& a, float q32x, float q32y, float q32z,
-                                      uint2* lane_ranges, uint64_t best) {
-  constexpr int W = 2 * R + 1;
-  const GridDesc& g = a.g;
+__device__ inline QueryCell query_cell(const GridDesc& g, float q32x, float q32y, float q32z) {
   const double lo = -(double)R - 1.0;
   double ux = ((double)q32x - g.ox) * g.inv_h;
   double uy = ((double)q32y - g.oy) * g.inv_h;
@@ -172,8 +176,35 @@ __device__ inline uint32_t stage_rows(const PassArgs& a, float q32x, float q32y,
   uy = fmin(fmax(uy, lo), (double)g.dy + R);
   uz = fmin(fmax(uz, lo), (double)g.dz + R);
   const double flx = floor(ux), fly = floor(uy), flz = floor(uz);
-  const int cx = (int)flx, cy = (int)fly, cz = (int)flz;
-  const float fx = (float)(ux - flx), fy = (float)(uy - fly), fz = (float)(uz - flz);
+  QueryCell c;
+  c.cx = (int)flx; c.cy = (int)fly; c.cz = (int)flz;
+  c.fx = (float)(ux - flx); c.fy = (float)(uy - fly); c.fz = (float)(uz - flz);
+  return c;
+}
+
+// Whether any target lies in the 27 cells around the query's cell, from the
+// dilated occupancy bitmap.  The cell is clamped into the grid first: along
+// each axis the clamped cell's neighbours include every in-grid neighbour of
+// the query's own cell, so a clear bit proves that the query has no
+// candidate (with R = 1; for R = 2 the bitmap is not used).
+__device__ inline bool occupied_neighbourhood(const PassArgs& a, const QueryCell& c) {
+  const GridDesc& g = a.g;
+  // a cell more than one cell outside the grid has no neighbour in it
+  if (c.cx < -1 || c.cx > g.dx || c.cy < -1 || c.cy > g.dy || c.cz < -1 || c.cz > g.dz) return false;
+  const uint32_t x = (uint32_t)min(max(c.cx, 0), g.dx - 1);
+  const uint32_t y = (uint32_t)min(max(c.cy, 0), g.dy - 1);
+  const uint32_t z = (uint32_t)min(max(c.cz, 0), g.dz - 1);
+  const uint32_t w = (z * (uint32_t)g.dy + y) * occ_row_words(g.dx) + (x >> 5);
+  return (ld_cell(a.occ, w) >> (x & 31u)) & 1u;
+}
+
+template <int R>
+__device__ inline uint32_t stage_rows(const PassArgs& a, const QueryCell& qc, uint2* lane_ranges,
+                                      uint64_t best) {
+  constexpr int W = 2 * R + 1;
+  const GridDesc& g = a.g;
+  const int cx = qc.cx, cy = qc.cy, cz = qc.cz;
+  const float fx = qc.fx, fy = qc.fy, fz = qc.fz;
 
   // squared gaps (in cells) from the query to the slab of offset d, lowered by
   // a safety margin; slabs outside the grid get an infinite gap
@@ -250,6 +281,12 @@ __device__ inline uint32_t stage_rows(const PassArgs& a, float q32x, float q32y,
   return total;
 }
 
+template <int R>
+__device__ inline uint32_t stage_rows(const PassArgs& a, float q32x, float q32y, float q32z,
+                                      uint2* lane_ranges, uint64_t best) {
+  return stage_rows<R>(a, query_cell<R>(a.g, q32x, q32y, q32z), lane_ranges, best);
+}
+
 // Scans the `total` candidates of the lane's staged ranges in order, keeping
 // the smallest (d^2, original index) key.
 __device__ inline void scan_ranges(const PassArgs& a, float q32x, float q32y, float q32z,
@@ -280,12 +317,12 @@ __device__ inline void scan_ranges(const PassArgs& a, float q32x, float q32y, fl
 }
 
 // Per-wave LDS region: during the search it holds the lanes' candidate ranges
-// ([slot][lane] uint2), during the reduction the transposed terms
-// ([value][lane] float, or [value][lane] double for half of the values).
-template <int R>
+// ([slot][lane] uint2), during the reduction half of the transposed terms
+// ([value][lane], 14 float or 14 double values).
+template <int R, int PREC = 0>
 struct WaveScratch {
   static constexpr int kRangeWords = (2 * R + 1) * (2 * R + 1) * kWave * 2;
-  static constexpr int kTermWords = 28 * kWave;
+  static constexpr int kTermWords = 14 * kWave * (PREC == 0 ? 1 : 2);
   static constexpr int kWords = kRangeWords > kTermWords ? kRangeWords : kTermWords;
 };
 
@@ -295,26 +332,33 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One pass over a tile of kRounds * kBlock queries per block: correspondence,
-// per-correspondence J^T J / J^T r terms, and their sum.
+// One pass over a tile of kRounds * kBlock queries per block (one query per
+// thread and round): correspondence, per-correspondence J^T J / J^T r terms,
+// and their sum.
 //
-// Latency: each round's source point, warm-start index and warm-start target
-// point are loaded one round ahead, so a round waits on memory only for its
-// candidate rows, its candidates and (for an inlier) the matched normal.
+// Latency: with several rounds, each round's source point, warm-start index
+// and warm-start target point are loaded one round ahead.  A query whose
+// 27-cell neighbourhood holds no target (dilated occupancy bitmap) skips the
+// row search, and a wave without any correspondence skips the terms and the
+// reduction.
 //
 // Reduction (float32 Kahan mode): each lane adds its own queries' 28 terms
 // over the rounds in float32; after the last round the lanes write them to
-// the wave's LDS region transposed ([term][lane]) and lane L (< 56) adds the
-// 32 entries (L & 1) * 32.. of term L >> 1 with Kahan compensation.  Float64
-// mode does the transposed sum every round, in float64.  The two halves and
-// the block's waves are then merged in a fixed order and one float64 partial
-// per term is written, so results do not depend on timing.
+// the wave's LDS region transposed ([term][lane], 14 terms at a time) and
+// lane L (< 56) adds 16 entries of term L >> 2 with Kahan compensation, the
+// four quarters merging by TwoSum.  Float64 mode does the transposed sum
+// every round, in float64.  The block's waves are then merged in a fixed
+// order and one float64 partial per term is written, so results do not
+// depend on timing.
 template <int VAR, int PREC, bool WRITE, int R, bool ROBUST>
 __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
-  __shared__ __align__(16) uint32_t scratch[kBlock / kWave][WaveScratch<R>::kWords];
-  __shared__ float red_s[kBlock / kWave][kNumSums];
-  __shared__ float red_c[kBlock / kWave][kNumSums];
-  __shared__ double red_d[kBlock / kWave][kNumSums];
+  // float32 mode merges (sum, compensation) pairs, float64 mode plain sums
+  constexpr int kRedS = PREC == 0 ? kNumSums : 1;
+  constexpr int kRedD = PREC == 0 ? 1 : kNumSums;
+  __shared__ __align__(16) uint32_t scratch[kBlock / kWave][WaveScratch<R, PREC>::kWords];
+  __shared__ float red_s[kBlock / kWave][kRedS];
+  __shared__ float red_c[kBlock / kWave][kRedS];
+  __shared__ double red_d[kBlock / kWave][kRedD];
   __shared__ uint32_t red_n[kBlock / kWave];
   double T[12];
 #pragma unroll
@@ -330,6 +374,7 @@ __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
   for (int k = 0; k < 28; ++k) lacc[k] = 0.0f;
   double acc_d0 = 0.0, acc_d1 = 0.0; // float64 mode: terms lane>>2 and 14 + (lane>>2), quarter lane&3
   uint32_t cnt = 0;
+  bool wave_any = false;  // some query of this wave had a correspondence (wave-uniform)
 
   const int64_t tile = (int64_t)tile_index * (kRounds * kBlock);
   // Prefetches are unconditional so that no branch forces an early wait on
@@ -382,7 +427,11 @@ __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
           bj = jp;
         }
       }
-      total = stage_rows<R>(a, q32x, q32y, q32z, lane_ranges, best);
+      const QueryCell qc = query_cell<R>(a.g, q32x, q32y, q32z);
+      // queries whose 27-cell neighbourhood holds no target skip the row
+      // search (the whole wave, when all of its queries do)
+      const bool nb = (R == 1 && a.occ) ? occupied_neighbourhood(a, qc) : true;
+      if (nb) total = stage_rows<R>(a, qc, lane_ranges, best);
     }
     // the next round's warm-start point: its index arrived with this round's
     // candidate rows, and the load overlaps the candidate scan
@@ -404,9 +453,13 @@ __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
         glb(a.d2_out)[oi] = inl ? bd : INFINITY;
       }
     }
-    cnt += (uint32_t)__popcll(__ballot(inl));
+    const uint64_t inl_mask = __ballot(inl);
+    cnt += (uint32_t)__popcll(inl_mask);
+    wave_any = wave_any || inl_mask != 0;
 
-    if (PREC == 0) {
+    // a wave without any correspondence adds nothing (every term is zero)
+    if (inl_mask == 0) {
+    } else if constexpr (PREC == 0) {
       // a query without a correspondence adds exact zeros: point-to-plane
       // terms vanish with a zero residual and normal, point-to-point terms
       // (which hold constants) are selected away
@@ -473,35 +526,56 @@ __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
   }
 
   // merge within the wave, then across the block's waves, in a fixed order
-  if (PREC == 0) {
-    wave_sync();  // the last search's LDS ranges are dead from here on
+  if constexpr (PREC == 0) {
+    // Kahan over the wave's lanes, 14 terms at a time through LDS: in half h
+    // lane L < 56 sums the 16 entries (L & 3) * 16.. of term 14 h + (L >> 2)
+    // with compensation; the four quarters merge by TwoSum (quarters 0+1 and
+    // 2+3, then the two pairs).  A wave that saw no correspondence holds
+    // only zeros and skips the sums.
+    float s_h[2] = {0.f, 0.f}, c_h[2] = {0.f, 0.f};
+    if (wave_any) {
 #pragma unroll
-    for (int k = 0; k < 28; ++k) xf[k * kWave + lane] = lacc[k];
-    wave_sync();
-    float acc_s = 0.f, acc_c = 0.f;  // Kahan: term lane>>1, half lane&1
-    if (lane < 56) {
-      const float4* src = reinterpret_cast<const float4*>(xf + (lane >> 1) * kWave + (lane & 1) * 32);
+      for (int half = 0; half < 2; ++half) {
+        wave_sync();  // the last search's ranges (or the previous half) are dead from here on
 #pragma unroll
-      for (int m = 0; m < 8; ++m) {
-        const float4 x4 = src[m];
-        const float xs[4] = {x4.x, x4.y, x4.z, x4.w};
+        for (int k = 0; k < 14; ++k) xf[k * kWave + lane] = lacc[14 * half + k];
+        wave_sync();
+        float acc_s = 0.f, acc_c = 0.f;
+        if (lane < 56) {
+          const float4* src = reinterpret_cast<const float4*>(xf + (lane >> 2) * kWave + (lane & 3) * 16);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const float y = xs[e] - acc_c;
-          const float t = acc_s + y;
-          acc_c = (t - acc_s) - y;
-          acc_s = t;
+          for (int m = 0; m < 4; ++m) {
+            const float4 x4 = src[m];
+            const float xs[4] = {x4.x, x4.y, x4.z, x4.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const float y = xs[e] - acc_c;
+              const float t = acc_s + y;
+              acc_c = (t - acc_s) - y;
+              acc_s = t;
+            }
+          }
         }
+#pragma unroll
+        for (int off = 1; off <= 2; off <<= 1) {
+          const float so = __shfl_xor(acc_s, off, kWave);
+          const float co = __shfl_xor(acc_c, off, kWave);
+          float s2, e;
+          // the lower quarter is the first operand, so both lanes of a pair
+          // form the same (s2, c2)
+          if (lane & off) two_sum(so, acc_s, s2, e); else two_sum(acc_s, so, s2, e);
+          acc_c = ((lane & off) ? (co + acc_c) : (acc_c + co)) + e;
+          acc_s = s2;
+        }
+        s_h[half] = acc_s;
+        c_h[half] = acc_c;
       }
     }
-    const float so = __shfl_xor(acc_s, 1, kWave);
-    const float co = __shfl_xor(acc_c, 1, kWave);
-    float s2, e;
-    two_sum(acc_s, so, s2, e);
-    const float c2 = (acc_c + co) + e;
-    if (lane < 56 && (lane & 1) == 0) {
-      red_s[w][lane >> 1] = s2;
-      red_c[w][lane >> 1] = c2;
+    if (lane < 56 && (lane & 3) == 0) {
+      red_s[w][lane >> 2] = s_h[0];
+      red_c[w][lane >> 2] = c_h[0];
+      red_s[w][14 + (lane >> 2)] = s_h[1];
+      red_c[w][14 + (lane >> 2)] = c_h[1];
     }
   } else {
     double d0 = acc_d0 + __shfl_xor(acc_d0, 1, kWave);
@@ -518,7 +592,7 @@ __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
   if (threadIdx.x < 28) {
     const int k = threadIdx.x;
     double out;
-    if (PREC == 0) {
+    if constexpr (PREC == 0) {
       float S = red_s[0][k], C = red_c[0][k];
       for (int ww = 1; ww < kBlock / kWave; ++ww) {
         float t2, e;

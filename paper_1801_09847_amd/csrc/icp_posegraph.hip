@@ -682,6 +682,12 @@ int icp_pose_graph_optimize(icp_ctx_t* ctx, int32_t n_nodes, double* poses, int3
     if (!rigid_ok(e.Z)) return fail(ICP_E_INVALID_ARG, "edge " + std::to_string(k) + ": Z is not a finite rigid transform");
     for (int q = 0; q < 36; ++q)
       if (!std::isfinite(e.information[q])) return fail(ICP_E_INVALID_ARG, "edge " + std::to_string(k) + ": information not finite");
+    // the factorisation reads one triangle of H: an asymmetric information
+    // matrix would silently solve other normal equations than F's
+    for (int a = 0; a < 6; ++a)
+      for (int b = a + 1; b < 6; ++b)
+        if (e.information[6 * a + b] != e.information[6 * b + a])
+          return fail(ICP_E_INVALID_ARG, "edge " + std::to_string(k) + ": information matrix is not symmetric");
   }
   int rc;
   icp_ctx* c = nullptr;

@@ -74,6 +74,8 @@ struct icp_ctx {
   icp_rt::Buf sk[6];  // sort buffers: klo[2], khi[2], val[2]
   // prepared pairs (concatenated)
   icp_rt::Buf cs, tp, tn, sx, sy, sz, perm;
+  // occupancy bitmaps: raw (scratch of a build) and dilated (read by the pass)
+  icp_rt::Buf occ_raw, occ;
   // voxel downsampling: descriptors, scratch, multi-scale level clouds
   icp_rt::Buf vdesc, vflags, vstarts, lvl_src, lvl_tgt, lvl_tn;
   // pose-graph optimisation: poses, edges, terms, normal equations
@@ -133,7 +135,7 @@ struct PairIn {
 // Byte offsets of one call's descriptors; the same layout is used in pinned
 // host staging and in the context's `desc` device buffer.
 struct Layout {
-  size_t clouds, blk_bbox, pairs, blk_t, blk_s, src_off, blk_tab;  // preparation
+  size_t clouds, blk_bbox, pairs, blk_t, blk_s, src_off, blk_tab, blk_occ;  // preparation
   size_t pargs, sargs, states, items;                                // loop header
   size_t header_end;                                                 // end of uploaded part
   size_t bbox_out, jprev, part, red;                                 // device only
@@ -146,8 +148,10 @@ struct Prep {
   std::vector<GridDesc> g;
   std::vector<int64_t> src_off, tgt_off, tile_off;
   std::vector<uint64_t> tab_off;
+  std::vector<uint64_t> occ_off;  // per pair: first word of its raw occupancy bitmap
   int64_t total_src = 0, total_tgt = 0, total_tiles = 0;
   uint64_t total_tab = 0;
+  uint64_t total_occ = 0;
   int sub = 1;
   bool normals = false;
 };
@@ -161,6 +165,7 @@ struct PairDst {
   float* sy;
   float* sz;
   uint32_t* perm;
+  uint32_t* occ;  // occ_words(g), or null: no occupancy bitmap
 };
 
 // Boxes, finiteness and grid sizes of n pairs (one synchronisation).  On a

@@ -133,6 +133,10 @@ struct icp_server {
   void* solve_args[1] = {nullptr};
   uint64_t fault_tag = 0;
   bool fault_on = false;
+  // host-forced step failure (failure-handling tests): step number fault_step
+  // returns ICP_E_DEVICE before any device work
+  int64_t fault_step = -1;
+  int64_t step_count = 0;
   // bookkeeping (mu)
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -277,7 +281,8 @@ int prepare_level(icp_server* s, std::vector<Req*>& list, std::vector<std::pair<
   std::vector<size_t> need(list.size());
   for (size_t k = 0; k < list.size(); ++k) {
     const int64_t tiles = tiles_of(list[k]->lns);
-    need[k] = align256(4 * ((size_t)P.g[k].ncell + 1)) + 2 * align256(16 * (size_t)list[k]->lnt) +
+    need[k] = align256(4 * ((size_t)P.g[k].ncell + 1)) + align256(4 * (size_t)occ_words(P.g[k])) +
+              2 * align256(16 * (size_t)list[k]->lnt) +
               4 * align256(4 * (size_t)list[k]->lns) + align256(sizeof(double) * kNumSums * tiles) +
               align256(sizeof(IterState));
   }
@@ -351,6 +356,7 @@ int prepare_level(icp_server* s, std::vector<Req*>& list, std::vector<std::pair<
       return q;
     };
     dst[k].cs = reinterpret_cast<uint32_t*>(take(4 * ((size_t)P.g[k].ncell + 1)));
+    dst[k].occ = reinterpret_cast<uint32_t*>(take(4 * (size_t)occ_words(P.g[k])));
     dst[k].tp = reinterpret_cast<float4*>(take(16 * (size_t)r->lnt));
     dst[k].tn = reinterpret_cast<float4*>(take(16 * (size_t)r->lnt));
     dst[k].sx = reinterpret_cast<float*>(take(4 * (size_t)r->lns));
@@ -370,6 +376,7 @@ int prepare_level(icp_server* s, std::vector<Req*>& list, std::vector<std::pair<
     a.tp = dst[k].tp;
     a.tn = plane ? dst[k].tn : nullptr;
     a.cs = dst[k].cs;
+    a.occ = dst[k].occ;
     a.g = P.g[k];
     a.r2f = (float)(rr * rr);
     a.inv_h2 = (float)(P.g[k].inv_h * P.g[k].inv_h);
@@ -390,10 +397,40 @@ int prepare_level(icp_server* s, std::vector<Req*>& list, std::vector<std::pair<
   return ICP_SUCCESS;
 }
 
-// One server step.  Only one step runs at a time (step_mu).
+// Stops a server after a failed step (mu not held): every queued and running
+// request completes with ICP_E_DEVICE and waiters wake up.
+void stop_broken(icp_server* s) {
+  std::lock_guard<std::mutex> g(s->mu);
+  s->broken = true;
+  for (Req* r : s->queue) complete(s, r, ICP_E_DEVICE, nullptr);
+  s->queue.clear();
+  for (Req* r : s->active) complete(s, r, ICP_E_DEVICE, nullptr);
+  s->active.clear();
+  s->cv_done.notify_all();
+}
+
+int server_step_body(icp_server* s, int32_t* n_busy);
+
+// One server step.  Only one step runs at a time (step_mu).  Any failure
+// stops the server (stop_broken).
 int server_step(icp_server* s, int32_t* n_busy) {
   std::lock_guard<std::mutex> step_lock(s->step_mu);
   if (s->broken) return fail(ICP_E_DEVICE, "server stopped after a device error");
+  int rc;
+  if (s->fault_step >= 0 && s->step_count == s->fault_step)
+    rc = fail(ICP_E_DEVICE, "step failure forced by ICP_FAULT_INJECT_STEP");
+  else
+    rc = server_step_body(s, n_busy);
+  s->step_count += 1;
+  if (rc != ICP_SUCCESS) {
+    const std::string msg = g_last_error;
+    stop_broken(s);
+    g_last_error = msg;
+  }
+  return rc;
+}
+
+int server_step_body(icp_server* s, int32_t* n_busy) {
   icp_ctx* c = s->ctx;
   DeviceGuard dg(c->device);
   std::vector<Req*> prep, upload;
@@ -434,10 +471,7 @@ int server_step(icp_server* s, int32_t* n_busy) {
   }
   int rc;
   std::vector<std::pair<Req*, int>> failed;
-  if (!prep.empty() && (rc = prepare_level(s, prep, failed)) != 0) {
-    s->broken = true;
-    return rc;
-  }
+  if (!prep.empty() && (rc = prepare_level(s, prep, failed)) != 0) return rc;
   if (!failed.empty()) {
     std::lock_guard<std::mutex> g(s->mu);
     for (auto& f : failed) {
@@ -643,6 +677,7 @@ int icp_server_create(const icp_server_cfg_t* cfg, icp_server_t** out) {
     s->fault_on = true;
     s->fault_tag = strtoull(f, nullptr, 10);
   }
+  if (const char* f = getenv("ICP_FAULT_INJECT_STEP")) s->fault_step = strtoll(f, nullptr, 10);
   if ((rc = build_graph(s)) != 0) return bail(rc);
   if (k.background_thread) s->worker = std::thread(worker_loop, s);
   *out = s;
@@ -696,7 +731,11 @@ int icp_server_submit(icp_server_t* s, const icp_request_t* q, uint64_t* ticket)
   DeviceGuard dg(s->ctx->device);
   const hipMemcpyKind kind = q->host_memory ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
   hipError_t e = hipSuccess;
-  if (on_device) {
+  // the copy starts after the work that produces the inputs (submit blocks
+  // until its copy is done anyway)
+  if (!q->host_memory && q->stream) e = hipStreamSynchronize(static_cast<hipStream_t>(q->stream));
+  if (e != hipSuccess) {
+  } else if (on_device) {
     e = hipMemcpyAsync(r->src, q->src_xyz, 12 * (size_t)r->n_src, kind, s->copy_stream);
     if (e == hipSuccess) e = hipMemcpyAsync(r->tgt, q->tgt_xyz, 12 * (size_t)r->n_tgt, kind, s->copy_stream);
     if (e == hipSuccess && plane)

@@ -82,7 +82,7 @@ class icp_request_t(C.Structure):
     _fields_ = [("src_xyz", C.c_void_p), ("tgt_xyz", C.c_void_p), ("tgt_normals", C.c_void_p),
                 ("n_src", C.c_int64), ("n_tgt", C.c_int64), ("T_init", C.c_double * 16),
                 ("rel_tol", C.c_double), ("spacing", C.c_double), ("host_memory", C.c_int32),
-                ("reserved", C.c_int32), ("user_tag", C.c_uint64)]
+                ("reserved", C.c_int32), ("user_tag", C.c_uint64), ("stream", C.c_void_p)]
 
 
 class icp_completion_t(C.Structure):
@@ -164,6 +164,8 @@ def lib():
         L.icp_server_poll.argtypes = [vp, C.POINTER(icp_completion_t), i32, C.POINTER(C.c_int32)]
         L.icp_server_wait.argtypes = [vp, C.c_uint64, C.POINTER(icp_completion_t)]
         L.icp_server_destroy.argtypes = [vp]
+        L.icp_measure_valu.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.icp_measure_copy.argtypes = [C.c_int, i64, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.icp_ctx_set_profiling.argtypes = [vp, C.c_int]
         L.icp_ctx_get_profile.argtypes = [vp, C.POINTER(icp_profile_t)]
         for name in ("icp_ctx_create", "icp_ctx_destroy", "icp_register", "icp_correspondences",
@@ -173,7 +175,7 @@ def lib():
                      "icp_pose_graph_optimize", "icp_feature_match", "icp_ransac_validate", "icp_compute_fpfh",
                      "icp_ransac_register",
                      "icp_server_create", "icp_server_submit", "icp_server_step", "icp_server_poll",
-                     "icp_server_wait", "icp_server_destroy"):
+                     "icp_server_wait", "icp_server_destroy", "icp_measure_valu", "icp_measure_copy"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -183,6 +185,20 @@ def _check(rc: int) -> None:
     if rc != ICP_SUCCESS:
         L = lib()
         raise IcpError(rc, f"{L.icp_strerror(rc).decode()}: {L.icp_last_error().decode()}")
+
+
+def measure_valu(kind: int, device: int = 0) -> tuple[float, float]:
+    """(lane operations per second, best launch ms) of icp_measure_valu."""
+    rate, ms = C.c_double(), C.c_double()
+    _check(lib().icp_measure_valu(int(device), int(kind), C.byref(rate), C.byref(ms)))
+    return rate.value, ms.value
+
+
+def measure_copy(nbytes: int, kind: int = 0, device: int = 0) -> tuple[float, float]:
+    """(GB/s, best launch ms) of icp_measure_copy."""
+    rate, ms = C.c_double(), C.c_double()
+    _check(lib().icp_measure_copy(int(device), int(nbytes), int(kind), C.byref(rate), C.byref(ms)))
+    return rate.value, ms.value
 
 
 def _pose(T) -> np.ndarray:
@@ -627,6 +643,10 @@ class Server:
             q.src_xyz, q.n_src = _dev_pts(src, "src")
             q.tgt_xyz, q.n_tgt = _dev_pts(tgt, "tgt")
             q.tgt_normals = _dev_pts(tgt_normals, "tgt_normals")[0] if tgt_normals is not None else None
+            # the server's copy is ordered after the work queued on the
+            # producing (torch's current) stream
+            import torch
+            q.stream = torch.cuda.current_stream(src.device).cuda_stream
         q.T_init[:] = [float(x) for x in _pose(np.eye(4) if T_init is None else T_init)]
         q.rel_tol, q.spacing, q.host_memory, q.reserved, q.user_tag = float(rel_tol), float(spacing), int(host), 0, int(tag)
         t = C.c_uint64()

@@ -172,6 +172,7 @@ def test_pose_graph_validation():
         (np.array([eye, eye]), [(1, 1, eye, np.eye(6))], {}),      # self edge
         (np.array([eye, eye]), [(0, 1, eye * 2, np.eye(6))], {}),  # not rigid
         (np.array([eye, eye]), [(0, 1, eye, np.full((6, 6), np.nan))], {}),
+        (np.array([eye, eye]), [(0, 1, eye, np.eye(6) + np.triu(np.ones((6, 6)), 1) * 1e-3)], {}),  # asymmetric
         (np.array([eye, eye]), good, {"method": 7}),
         (np.array([eye, eye]), good, {"max_iter": -1}),
     ):

@@ -4,7 +4,10 @@ Bar: neighbourhood sizes bit-exact (integer); normals within 1e-6 rad of the
 oracle's wherever the least eigenvector is well defined (relative eigengap
 (l1 - l0) / (l0 + l1 + l2) > 1e-6), same orientation wherever the point does
 not lie within 1e-6 of the viewpoint's plane through it; zero exactly where
-fewer than three neighbours exist; unit length elsewhere.
+fewer than three neighbours exist; unit length elsewhere; where the least
+eigenvector is not unique (duplicates, lattices, collinear or identical
+points) the normal lies in the least eigenspace of the neighbourhood
+covariance (n^T C n <= l0 + 1e-6 tr C).
 
 Tolerance: both sides form the covariance in float64 from float32 points and
 differ only in summation order and in the (shifted one-pass vs centred
@@ -44,6 +47,32 @@ def _angle(a, b):
     return np.arctan2(np.linalg.norm(np.cross(a, b), axis=-1), np.abs(np.sum(a * b, axis=-1)))
 
 
+def _neighbourhood(P, i, radius, max_nn):
+    """Hybrid neighbourhood of point i by brute force: the max_nn smallest
+    (pinned float32 squared distance, index) within radius."""
+    d = P - P[i]
+    d2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+    r2 = np.float32(radius * radius)
+    cand = np.nonzero(d2 <= r2)[0]
+    order = np.lexsort((cand, d2[cand]))
+    return cand[order[:max_nn]]
+
+
+def _least_eigenspace_ok(P, sel, N, radius, max_nn, which):
+    """For the points `which` (positions into sel) whose least eigenvector is
+    not unique: the normal must lie in the least eigenspace of the
+    neighbourhood covariance C, n^T C n <= l0 + 1e-6 tr C (a direction along
+    a collinear neighbourhood, say, has n^T C n = l2 and fails)."""
+    for k in which:
+        nb = _neighbourhood(P, sel[k], radius, max_nn)
+        X = P[nb].astype(np.float64)
+        X = X - X.mean(0)
+        C = X.T @ X / len(nb)
+        l0 = np.linalg.eigvalsh(C)[0]
+        n = N[k].astype(np.float64)
+        assert n @ C @ n <= l0 + 1e-6 * np.trace(C) + 1e-300, (k, n @ C @ n, l0, np.trace(C))
+
+
 def check(icp, oracle_lib, P, radius, max_nn, view, queries=None, label=""):
     P = np.ascontiguousarray(P, np.float32)
     print(f"\n[normals] {label} n={len(P)} radius={radius} max_nn={max_nn}", flush=True)
@@ -66,6 +95,8 @@ def check(icp, oracle_lib, P, radius, max_nn, view, queries=None, label=""):
         facing = np.abs(np.sum(oN.astype(np.float64) * vp, 1)) > 1e-6 * np.linalg.norm(vp, axis=1)
         both = ok & facing
         assert np.all(np.sum(N[both].astype(np.float64) * oN[both], 1) > 0)
+    ill = np.nonzero(~few & ~ok)[0]
+    _least_eigenspace_ok(P, sel, N, radius, max_nn, ill)
     print(f"[normals] {label}: {ok.sum()} compared, {few.sum()} with < 3 neighbours, "
           f"{(~few & ~ok).sum()} ill-conditioned, counts {cnt.min()}..{cnt.max()}", flush=True)
     return cnt
@@ -104,6 +135,12 @@ def test_duplicates_ties_and_tiny_clouds(icp, oracle_lib):
     check(icp, oracle_lib, lat, 0.6, 4, (0.3, 0.2, 5.0), label="lattice ties")
     for n in (1, 2, 3, 4, 7):
         check(icp, oracle_lib, rng.uniform(0, 0.01, (n, 3)), 0.1, 30, (0.0, 0.0, 1.0), label=f"n={n}")
+    # collinear neighbourhoods: the normal must be perpendicular to the line
+    t = np.arange(40, dtype=np.float64)[:, None] * 0.01
+    line = np.float32([0.1, 0.2, 0.3]) + t * np.float64([0.6, 0.0, 0.8])
+    check(icp, oracle_lib, line, 0.05, 30, (1.0, 1.0, 1.0), label="collinear")
+    N = icp.estimate_normals(_dev(line), 0.05, 30, (1.0, 1.0, 1.0)).cpu().numpy().astype(np.float64)
+    assert np.abs(N @ np.float64([0.6, 0.0, 0.8])).max() < 1e-5
 
 
 def test_identical_points(icp):

@@ -84,3 +84,30 @@ def test_disconnected_node_is_degenerate(icp):
     np.testing.assert_array_equal(P, d["init"])
     O, F0, F, steps, status = opg.optimize(list(d["init"]), edges, "gn", 10, 0.0)
     assert status == opg.DEGENERATE and steps == 0
+
+
+def test_disconnected_node_beyond_first_block_is_degenerate(icp):
+    """A free node with no edge beyond the first 64 unknowns: its zero pivot
+    is found by the diagonal factorisation fused into the trailing update
+    (not by the first diagonal block), and the run stops degenerate."""
+    d = synth.pose_graph(8, 30, 10)
+    lost = 20  # unknowns 114..119, in the second 64-column block
+    edges = [e for e in d["edges"] if lost not in (e[0], e[1])]
+    P, res = icp.pose_graph_optimize(d["init"], edges, "lm", 10, 0.0)
+    assert res["status"] == icp.ICP_DEGENERATE and res["steps"] == 0
+    np.testing.assert_array_equal(P, d["init"])
+    O, F0, F, steps, status = opg.optimize(list(d["init"]), edges, "lm", 10, 0.0)
+    assert status == opg.DEGENERATE and steps == 0
+
+
+@pytest.mark.parametrize("method", ["gn", "lm"])
+def test_graph_with_whole_last_block(icp, method):
+    """33 nodes: 32 free nodes, 192 unknowns, so the last 64-column block of
+    the factorisation is full."""
+    d = synth.pose_graph(9, 33, 20)
+    P, res = icp.pose_graph_optimize(d["init"], d["edges"], method, 100, 1e-13)
+    O, F0, F, steps, status = opg.optimize(list(d["init"]), d["edges"], method, 100, 1e-13)
+    ang, dt = _worst(P, O)
+    assert abs(res["F_final"] - F) <= 1e-9 * F
+    assert ang <= 1e-8 and dt <= 1e-8
+    assert res["status"] != icp.ICP_DEGENERATE

@@ -194,3 +194,54 @@ def test_server_robust_equals_multiscale_robust(icp, requests, loss, k):
     assert differs >= len(requests) - 1
     srv.close()
 
+
+
+@pytest.mark.parametrize("background", [False, True])
+def test_server_stops_after_failed_step(icp, requests, monkeypatch, background):
+    """A failed step (forced from the host by ICP_FAULT_INJECT_STEP, before any
+    device work) stops the server: every queued and running request is
+    delivered with ICP_E_DEVICE instead of waiting forever, and later submits
+    and steps are refused with ICP_E_DEVICE."""
+    monkeypatch.setenv("ICP_FAULT_INJECT_STEP", "1")
+    srv = icp.Server(VOX, ITS, max_slots=2, budget_bytes=1 << 30, iters_per_step=2,
+                     background_thread=background)
+    monkeypatch.delenv("ICP_FAULT_INJECT_STEP")
+    tickets = [srv.submit(dev(d["src"]), dev(d["tgt"]), dev(d["tgt_normals"]), spacing=d["spacing"], tag=k)
+               for k, d in enumerate(requests[:4])]
+    if not background:
+        srv.step()  # step 0 runs normally
+        with pytest.raises(icp.IcpError) as e:
+            srv.step()  # step 1 fails
+        assert e.value.code == icp.ICP_E_DEVICE
+    t0 = time.monotonic()
+    errors = [srv.wait(t).error for t in tickets]
+    assert time.monotonic() - t0 < 30.0
+    assert errors.count(icp.ICP_E_DEVICE) >= 3  # a request can finish in step 0 only if tiny
+    assert all(e in (0, icp.ICP_E_DEVICE) for e in errors)
+    d = requests[2]
+    with pytest.raises(icp.IcpError) as e:
+        srv.submit(dev(d["src"]), dev(d["tgt"]), dev(d["tgt_normals"]), spacing=d["spacing"])
+    assert e.value.code == icp.ICP_E_DEVICE
+    if not background:
+        with pytest.raises(icp.IcpError) as e:
+            srv.step()
+        assert e.value.code == icp.ICP_E_DEVICE
+    srv.close()
+
+
+def test_server_submit_orders_after_producer_stream(icp, requests):
+    """Inputs written by work still queued on the caller's stream are copied
+    only after it: the result equals the plain call on the final inputs."""
+    d = requests[1]
+    plain = _plain(icp, d)
+    srv = icp.Server(VOX, ITS, max_slots=2, budget_bytes=1 << 30)
+    final, tgt, nrm = dev(d["src"]), dev(d["tgt"]), dev(d["tgt_normals"])
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        src = torch.zeros((len(d["src"]), 3), dtype=torch.float32, device="cuda")
+        torch.cuda._sleep(20_000_000)  # keeps the stream busy (milliseconds) before the write below
+        src.copy_(final, non_blocking=True)
+        t = srv.submit(src, tgt, nrm, spacing=d["spacing"])
+    _same(srv.wait(t), plain)
+    srv.close()

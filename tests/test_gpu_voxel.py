@@ -76,10 +76,12 @@ def test_voxel_downsample_edges(icp, oracle_lib):
     assert e.value.code == icp.ICP_E_NONFINITE
 
 
-@pytest.mark.parametrize("seed", [0, 1])
-def test_multiscale_matches_oracle(icp, oracle_lib, seed):
+@pytest.mark.parametrize("seed,n_fixed", [(0, None), (1, None), (2, 450_000)])
+def test_multiscale_matches_oracle(icp, oracle_lib, seed, n_fixed):
+    """Requests of the served workload's recipe: two at their own size capped
+    at 60k, one at 450k points (the upper end of the request sizes)."""
     n, o = synth.c5_request_size(seed)
-    n = min(n, 60000)
+    n = min(n, 60000) if n_fixed is None else n_fixed
     d = synth.room_pair_random(10_000 + seed, n, n, overlap=o)
     sp = np.sqrt(d["area"] / n)
     vox = [0.04, 0.02, 0.01]

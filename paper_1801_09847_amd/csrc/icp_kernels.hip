@@ -376,35 +376,18 @@ __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
   uint32_t cnt = 0;
   bool wave_any = false;  // some query of this wave had a correspondence (wave-uniform)
 
-  const int64_t tile = (int64_t)tile_index * (kRounds * kBlock);
-  // Prefetches are unconditional so that no branch forces an early wait on
-  // them: a lane past the end of the source reads the last point, and an
-  // absent warm-start index reads target entry 0; such values are never used.
-  const int64_t last = (int64_t)a.n_src - 1;
-  float nsx, nsy, nsz;
-  uint32_t njp;
+  static_assert(kRounds == 1, "one query per thread");
   {
-    const int64_t i0 = min(tile + (int64_t)threadIdx.x, last);
-    nsx = glb(a.sx)[i0]; nsy = glb(a.sy)[i0]; nsz = glb(a.sz)[i0];
-    njp = a.jprev ? glb(a.jprev)[i0] : 0xffffffffu;
-  }
-  float4 npw = ld4(a.tp, njp != 0xffffffffu ? njp : 0u);
-
-  for (int round = 0; round < kRounds; ++round) {
-    const int64_t i = tile + round * kBlock + threadIdx.x;
-    const float ssx = nsx, ssy = nsy, ssz = nsz;
-    const uint32_t jp = njp;
-    const float4 pw = npw;
-    // the next round's source point and warm-start index (in the last round
-    // the lane rereads its own point, which is then ignored)
-    {
-      const int64_t in = min(round + 1 < kRounds ? i + kBlock : i, last);
-      nsx = glb(a.sx)[in]; nsy = glb(a.sy)[in]; nsz = glb(a.sz)[in];
-      njp = a.jprev ? glb(a.jprev)[in] : 0xffffffffu;
-    }
+    const int64_t i = (int64_t)tile_index * kTile + threadIdx.x;
+    // The warm-start point load is unconditional so that no branch forces an
+    // early wait on it: a lane without a warm start (or past the end of the
+    // source) reads target entry 0, which is never used.
+    const int64_t ic = min(i, (int64_t)a.n_src - 1);
+    const float ssx = glb(a.sx)[ic], ssy = glb(a.sy)[ic], ssz = glb(a.sz)[ic];
+    const uint32_t jp = (a.jprev && i < a.n_src) ? glb(a.jprev)[ic] : 0xffffffffu;
+    const float4 pw = ld4(a.tp, jp != 0xffffffffu ? jp : 0u);
 
     bool inl = false;
-    float4 bp = make_float4(0.f, 0.f, 0.f, 0.f), bn = make_float4(0.f, 0.f, 0.f, 0.f);
     uint32_t bj = 0xffffffffu;
     double q64x = 0.0, q64y = 0.0, q64z = 0.0;
     float q32x = 0.f, q32y = 0.f, q32z = 0.f;
@@ -417,8 +400,14 @@ __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
       t = T[4] * sx; t = t + T[5] * sy; t = t + T[6] * sz; q64y = t + T[7];
       t = T[8] * sx; t = t + T[9] * sy; t = t + T[10] * sz; q64z = t + T[11];
       q32x = (float)q64x; q32y = (float)q64y; q32z = (float)q64z;
+      const QueryCell qc = query_cell<R>(a.g, q32x, q32y, q32z);
+      // queries whose 27-cell neighbourhood holds no target skip the row
+      // search (the whole wave, when all of its queries do)
+      const bool nb = (R == 1 && a.occ) ? occupied_neighbourhood(a, qc) : true;
       if (jp != 0xffffffffu) {
-        // warm start: the previous pass's match bounds this pass's distance
+        // warm start: a target point (the previous pass's match) bounds this
+        // pass's distance; any target would do, so an index left over from an
+        // earlier pass is as valid as a fresh one
         const float dx = q32x - pw.x, dy = q32y - pw.y, dz = q32z - pw.z;
         float d2 = dx * dx + dy * dy;
         d2 = d2 + dz * dz;
@@ -427,26 +416,16 @@ __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
           bj = jp;
         }
       }
-      const QueryCell qc = query_cell<R>(a.g, q32x, q32y, q32z);
-      // queries whose 27-cell neighbourhood holds no target skip the row
-      // search (the whole wave, when all of its queries do)
-      const bool nb = (R == 1 && a.occ) ? occupied_neighbourhood(a, qc) : true;
       if (nb) total = stage_rows<R>(a, qc, lane_ranges, best);
     }
-    // the next round's warm-start point: its index arrived with this round's
-    // candidate rows, and the load overlaps the candidate scan
-    npw = ld4(a.tp, njp != 0xffffffffu ? njp : 0u);
+    scan_ranges(a, q32x, q32y, q32z, lane_ranges, total, best, bj);
     if (i < a.n_src) {
-      scan_ranges(a, q32x, q32y, q32z, lane_ranges, total, best, bj);
       const float bd = __uint_as_float((uint32_t)(best >> 32));
       const uint32_t bo = (uint32_t)best;
       inl = best != ~0ull && bd <= a.r2f;
-      const uint32_t bjc = inl ? bj : 0u;
-      bp = ld4(a.tp, bjc);
-      if (VAR == 1) bn = ld4(a.tn, bjc);
-      // the warm-start index is written back only where the match moved
-      const uint32_t nj = inl ? bj : 0xffffffffu;
-      if (a.jprev && nj != jp) glb(a.jprev)[i] = nj;
+      // the warm-start index is written back only where a match is found at
+      // another position (a query that loses its match keeps the old index)
+      if (a.jprev && inl && bj != jp) glb(a.jprev)[i] = bj;
       if (WRITE) {
         const uint32_t oi = glb(a.sperm)[i];
         glb(a.idx_out)[oi] = inl ? (int32_t)bo : -1;
@@ -457,7 +436,14 @@ __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
     cnt += (uint32_t)__popcll(inl_mask);
     wave_any = wave_any || inl_mask != 0;
 
-    // a wave without any correspondence adds nothing (every term is zero)
+    // a wave without any correspondence adds nothing (every term is zero);
+    // the matched point and normal are loaded only by waves that use them
+    float4 bp = make_float4(0.f, 0.f, 0.f, 0.f), bn = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (inl_mask != 0) {
+      const uint32_t bjc = inl ? bj : 0u;
+      bp = ld4(a.tp, bjc);
+      if (VAR == 1) bn = ld4(a.tn, bjc);
+    }
     if (inl_mask == 0) {
     } else if constexpr (PREC == 0) {
       // a query without a correspondence adds exact zeros: point-to-plane
@@ -613,10 +599,28 @@ __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
   }
 }
 
+// Block -> tile order.  Blocks are handed to the eight XCDs in turn (block b
+// to XCD b mod 8), each with its own L2; consecutive Morton-ordered tiles
+// share target cells, so each XCD takes runs of kXcdRun consecutive tiles:
+// within a group of 8 kXcdRun blocks, block r works on tile
+// (r mod 8) kXcdRun + r div 8.  Groups rotate over the XCDs, which keeps the
+// work balanced when the busy tiles are clustered.  A bijection on the
+// tiles; the last partial group keeps the identity.
+#ifndef ICP_XCD_RUN
+#define ICP_XCD_RUN 16
+#endif
+constexpr uint32_t kXcdRun = ICP_XCD_RUN;
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t n) {
+  constexpr uint32_t G = 8 * kXcdRun;
+  if (kXcdRun <= 1 || b >= (n / G) * G) return b;
+  const uint32_t r = b % G;
+  return (b - r) + (r % 8) * kXcdRun + r / 8;
+}
+
 template <int VAR, int PREC, bool WRITE, int R, bool ROBUST>
 __global__ __launch_bounds__(kBlock) void pass_kernel(PassArgs a) {
   if (glb(a.st)->done) return;
-  pass_tile<VAR, PREC, WRITE, R, ROBUST>(a, blockIdx.x);
+  pass_tile<VAR, PREC, WRITE, R, ROBUST>(a, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // Batched form: block b handles tile items[b].y of pair items[b].x.  Tiles and
@@ -739,7 +743,7 @@ __global__ __launch_bounds__(256) void validate_reduce_kernel(ValidateArgs v) {
 template <int VAR, int PREC, int R, bool ROBUST = false>
 __global__ __launch_bounds__(kBlock) void batch_pass_kernel(const PassArgs* __restrict__ pairs,
                                                             const uint2* __restrict__ items) {
-  const uint2 it = items[blockIdx.x];
+  const uint2 it = items[xcd_tile(blockIdx.x, gridDim.x)];
   const PassArgs a = pairs[it.x];  // by value: uniform, kept in scalar registers
   if (glb(a.st)->done) return;
   pass_tile<VAR, PREC, false, R, ROBUST>(a, it.y);

@@ -431,6 +431,24 @@ int icp_compute_fpfh(icp_ctx_t *ctx, const float *pts, const float *normals, int
 int icp_feature_match(icp_ctx_t *ctx, const float *src_feat, int64_t n_src, const float *tgt_feat,
                       int64_t n_tgt, int32_t dim, int32_t *match_out, float *dist_out);
 
+/* icp_feature_match without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, results and errors as
+ * icp_feature_match, with the context replaced by a stream:
+ *   hip_stream  hipStream_t the kernels are enqueued on (NULL: the null
+ *               stream) on the calling thread's current device
+ * The call is asynchronous: it only enqueues kernels (no allocation, no
+ * memset, no synchronisation), and match_out / dist_out are complete when
+ * that stream's work is.  Its scratch (one 64-bit key per source feature) is
+ * a static device array of 2^20 keys (8 MiB) that each device holds for the
+ * life of the process: n_src > 2^20 gives ICP_E_TOO_LARGE.  Every call on a
+ * device shares that array, so calls that may overlap on one device (other
+ * streams, other threads) race and must be serialised by the caller.  The
+ * first call on a device looks the array's address up (hipGetSymbolAddress).
+ * Errors: INVALID_ARG, TOO_LARGE, DEVICE. */
+int icp_feature_match_noalloc(const float *src_feat, int64_t n_src, const float *tgt_feat, int64_t n_tgt,
+                              int32_t dim, int32_t *match_out, float *dist_out, void *hip_stream);
+
 /* Scores n_hyp given transforms (the validation step).
  *   src_xyz, tgt_xyz  device (n, 3) float32; 1 <= n_src <= 2^23
  *   T                 host (n_hyp, 16) rigid transforms, n_hyp 1 .. 65535

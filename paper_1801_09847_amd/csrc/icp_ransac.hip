@@ -16,6 +16,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 
 #include "icp_runtime.h"
@@ -523,6 +524,34 @@ int check_features(const float* f, int64_t n, const char* name) {
   return ICP_SUCCESS;
 }
 
+// ---- no-allocation feature match -----------------------------------------
+// The scratch of icp_feature_match_noalloc: one 64-bit (distance, index) key
+// per source feature, in a file-scope device array that every call on a
+// device shares (each device holds its own copy).  Host code never names the
+// array as a device address: its address on each device is looked up once,
+// with that device current, and kept in g_noalloc_ptr.
+constexpr int64_t kNoAllocMaxSrc = int64_t(1) << 20;  // 8 MiB of keys
+static __device__ __align__(256) unsigned long long scratch[kNoAllocMaxSrc];
+constexpr int kNoAllocMaxDevices = 64;
+std::mutex g_noalloc_mu;
+unsigned long long* g_noalloc_ptr[kNoAllocMaxDevices] = {};
+
+// The scratch address on the current device (looked up on its first use).
+int noalloc_scratch(unsigned long long** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= kNoAllocMaxDevices) return fail(ICP_E_DEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(ICP_E_DEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    g_noalloc_ptr[dev] = static_cast<unsigned long long*>(p);
+  }
+  *out = g_noalloc_ptr[dev];
+  return ICP_SUCCESS;
+}
+
 int check_radius(double r) {
   if (!(r > 0.0) || !std::isfinite(r) || !std::isfinite((float)(r * r)) || !((float)(r * r) > 0.0f))
     return fail(ICP_E_INVALID_ARG, "max_corr_dist must be > 0 with a finite, non-zero float32 square");
@@ -666,6 +695,30 @@ int icp_feature_match(icp_ctx_t* ctx, const float* src_feat, int64_t n_src, cons
                                dist_out, c->stream),
           "feature match");
   HIP_TRY(hipStreamSynchronize(c->stream), "sync");
+  return ICP_SUCCESS;
+}
+
+int icp_feature_match_noalloc(const float* src_feat, int64_t n_src, const float* tgt_feat, int64_t n_tgt,
+                              int32_t dim, int32_t* match_out, float* dist_out, void* hip_stream) {
+  int rc;
+  if ((rc = check_features(src_feat, n_src, "src_feat")) != 0) return rc;
+  if ((rc = check_features(tgt_feat, n_tgt, "tgt_feat")) != 0) return rc;
+  if (dim < 1 || dim > kMaxFeatureDim)
+    return fail(ICP_E_INVALID_ARG, "dim must be in [1, " + std::to_string(kMaxFeatureDim) + "]");
+  if (n_src > 0 && !match_out) return fail(ICP_E_INVALID_ARG, "match_out is NULL");
+  if ((reinterpret_cast<uintptr_t>(match_out) & 3u) || (reinterpret_cast<uintptr_t>(dist_out) & 3u))
+    return fail(ICP_E_INVALID_ARG, "output pointer is not 4-byte aligned");
+  if (n_src > kNoAllocMaxSrc)
+    return fail(ICP_E_TOO_LARGE, "icp_feature_match_noalloc: n_src exceeds " + std::to_string(kNoAllocMaxSrc) +
+                                     " (the size of its static scratch)");
+  if ((double)n_tgt * dim > 9.2e18) return fail(ICP_E_TOO_LARGE, "feature array too large");
+  unsigned long long* keys = nullptr;
+  if ((rc = noalloc_scratch(&keys)) != 0) return rc;
+  if (n_src == 0) return ICP_SUCCESS;
+  // the keys are initialised by a fill kernel (not a memset) inside the launch
+  HIP_TRY(launch_feature_match(src_feat, n_src, tgt_feat, n_tgt, dim, keys, match_out, dist_out,
+                               static_cast<hipStream_t>(hip_stream)),
+          "feature match");
   return ICP_SUCCESS;
 }
 

@@ -155,6 +155,7 @@ def lib():
                                               dbl, C.POINTER(icp_pose_graph_result_t)]
         L.icp_compute_fpfh.argtypes = [vp, vp, vp, i64, dbl, i32, vp, vp]
         L.icp_feature_match.argtypes = [vp, vp, i64, vp, i64, i32, vp, vp]
+        L.icp_feature_match_noalloc.argtypes = [vp, i64, vp, i64, i32, vp, vp, vp]
         L.icp_ransac_validate.argtypes = [vp, vp, i64, vp, i64, dbl, i32, vp, vp, vp]
         L.icp_ransac_register.argtypes = [vp, vp, i64, vp, i64, vp, C.POINTER(icp_ransac_params_t),
                                           C.POINTER(icp_ransac_result_t), C.POINTER(icp_ransac_trace_t)]
@@ -172,7 +173,7 @@ def lib():
                      "icp_normal_equations", "icp_ctx_set_profiling", "icp_ctx_get_profile",
                      "icp_register_batch", "icp_register_batch_robust", "icp_voxel_downsample", "icp_register_multiscale", "icp_register_multiscale_robust",
                      "icp_estimate_normals", "icp_register_robust", "icp_normal_equations_robust",
-                     "icp_pose_graph_optimize", "icp_feature_match", "icp_ransac_validate", "icp_compute_fpfh",
+                     "icp_pose_graph_optimize", "icp_feature_match", "icp_feature_match_noalloc", "icp_ransac_validate", "icp_compute_fpfh",
                      "icp_ransac_register",
                      "icp_server_create", "icp_server_submit", "icp_server_step", "icp_server_poll",
                      "icp_server_wait", "icp_server_destroy", "icp_measure_valu", "icp_measure_copy"):
@@ -470,6 +471,13 @@ def feature_match(src_feat, tgt_feat, ctx: Context | None = None, with_dist=Fals
                                    tgt_feat.shape[0], int(src_feat.shape[1]), match.data_ptr(),
                                    dist.data_ptr() if dist is not None else None))
     return (match, dist) if with_dist else match
+
+
+def icp_feature_match_noalloc(src_ptr, n_src, tgt_ptr, n_tgt, dim, match_ptr, dist_ptr, hip_stream) -> None:
+    """Raw no-allocation feature match: enqueues on hip_stream (an int handle
+    or None) into caller-provided outputs; complete when that stream is."""
+    _check(lib().icp_feature_match_noalloc(src_ptr, int(n_src), tgt_ptr, int(n_tgt), int(dim), match_ptr,
+                                           dist_ptr, hip_stream))
 
 
 def ransac_validate(src, tgt, max_corr_dist, Ts, ctx: Context | None = None):

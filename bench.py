@@ -109,6 +109,84 @@ def ceilings_section(icp):
     return out
 
 
+def oracle_timing(np, d, variant, threads, reps):
+    """CPU-baseline leg: wall time of the FP64 oracle's whole registration of
+    pair d (k-d tree build included) on `threads` host threads, median of reps."""
+    import oracle
+    oracle.build(force=False)
+    prev = oracle.num_threads()
+    oracle.set_num_threads(threads)
+    ts = []
+    try:
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            r = oracle.icp_register(d["src"], d["tgt"], d["tgt_normals"], np.eye(4), d["max_corr_dist"],
+                                    d["max_iter"], 0.0, variant=variant)
+            ts.append(time.perf_counter() - t0)
+    finally:
+        oracle.set_num_threads(prev)
+    return float(np.median(ts)), r
+
+
+def config_section(args, icp, synth, np, torch, c3=None):
+    """The other single-pair configurations: C1 (5k/5k heightfield), C2
+    (300k/300k room) point-to-plane and C3 (2M/2M room) point-to-point, each
+    end to end per registration call (grid build included, median of steps),
+    its pass kernel's algorithmic bandwidth and grid-build rate, and the
+    oracle's whole registration on all host threads and on one thread."""
+    out = {}
+    cases = [("c1_point_to_plane", "c1_heightfield", "point_to_plane", 7, 3, True),
+             ("c2_point_to_plane", "c2_room", "point_to_plane", 7, 3, True),
+             ("c3_point_to_point", "c3_room", "point_to_point", 5, 1, False)]
+    ncores = len(os.sched_getaffinity(0))
+    for name, gen, variant, steps, oreps, one_thread in cases:
+        d = c3 if (gen == "c3_room" and c3 is not None) else getattr(synth, gen)(0)
+        dev = torch.device("cuda:0")
+        s, t, n = (torch.from_numpy(d[k]).to(dev) for k in ("src", "tgt", "tgt_normals"))
+        ctx = icp.Context(0)
+        K, r = d["max_iter"], d["max_corr_dist"]
+        icp.register(s, t, n, np.eye(4), r, K, 0.0, variant, args.precision, ctx=ctx)
+        torch.cuda.synchronize()
+        walls = []
+        for k in range(steps):
+            if k == steps - 1:
+                ctx.set_profiling(True)
+            t0 = time.perf_counter()
+            res = icp.register(s, t, n, np.eye(4), r, K, 0.0, variant, args.precision, ctx=ctx)
+            walls.append(time.perf_counter() - t0)
+        prof = ctx.profile()
+        ctx.close()
+        wall = float(np.median(walls))
+        evals = (res.n_iter + 1) * len(d["src"])
+        pass_us = prof["pass_ms"] * 1e3 / max(1, prof["pass_launches"])
+        alg = ALG_BYTES[variant] * len(d["src"])
+        # grid build: 52 B per target point (read xyz + normal, write the
+        # cell-ordered point and its index), source ordering included in the time
+        build_gbs = 52.0 * prof["build_points"] / (prof["build_ms"] * 1e-3) / 1e9 if prof["build_ms"] > 0 else None
+        e = {"n_src": len(d["src"]), "n_tgt": len(d["tgt"]), "max_corr_dist": r, "passes": res.n_iter + 1,
+             "ms_per_registration": wall * 1e3, "corr_evals_per_s": evals / wall,
+             "pass_avg_us": pass_us, "pass_alg_gbs": alg / (pass_us * 1e-6) / 1e9,
+             "pass_frac_of_8tbs": alg / (pass_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+             "build_ms": prof["build_ms"], "build_alg_gbs": build_gbs,
+             "fitness": res.fitness, "inlier_rmse": res.inlier_rmse}
+        if not args.no_cpu_baseline:
+            ta, o = oracle_timing(np, d, variant, ncores, oreps)
+            dR = np.linalg.norm(res.T[:3, :3] - o.T[:3, :3])
+            e["oracle"] = {"threads": ncores, "s_per_registration": ta, "corr_evals_per_s": evals / ta,
+                           "pose_error_rad": float(2 * np.arcsin(min(1.0, dR / (2 * np.sqrt(2))))),
+                           "pose_error_m": float(np.linalg.norm(res.T[:3, 3] - o.T[:3, 3])),
+                           "n_inliers_equal": bool(res.n_inliers == o.n_inliers)}
+            if one_thread:
+                t1, _ = oracle_timing(np, d, variant, 1, 1)
+                e["oracle"]["s_per_registration_1_thread"] = t1
+                e["oracle"]["n_core_over_1_core"] = t1 / ta
+        out[name] = e
+        print(f"bench: {name}: {e['corr_evals_per_s']:.3e} corr-evals/s, pass {pass_us:.1f} us, "
+              f"{wall * 1e3:.2f} ms per registration", file=sys.stderr, flush=True)
+        del s, t, n
+    return out
+
+
 def robust_section(args, icp, np, torch, s, t, n, data, K, r, steps=3):
     """The same registration with the robust (IRLS) losses, scale 1 cm."""
     out = []
@@ -351,7 +429,7 @@ def ransac_section(args, icp, synth, np, torch, valu_rate=None):
     return out
 
 
-def batched_section(args, icp, synth, np, torch, oracle_sample=8):
+def batched_section(args, icp, synth, np, torch, oracle_sample=32):
     """C4: 256 independent pairs, sizes log-uniform in [2k, 200k], one batched
     call vs the same pairs through the plain per-pair call."""
     print("bench: generating 256 batched pairs", file=sys.stderr, flush=True)
@@ -365,6 +443,7 @@ def batched_section(args, icp, synth, np, torch, oracle_sample=8):
                        "U(0.5, 0.9), r = max(3 cm, 2 sqrt(A/N)), point-to-plane, 30 iterations, "
                        "rel_tol 1e-6",
            "pairs": len(data), "points_src_total": int(sum(len(d["src"]) for d in data))}
+    oracle_res = {}
     for prec in ("kahan32", "f64"):
         descs = [icp.make_pair(*t, np.eye(4), d["max_corr_dist"], d["max_iter"], d["rel_tol"])
                  for t, d in zip(tens, data)]
@@ -398,8 +477,10 @@ def batched_section(args, icp, synth, np, torch, oracle_sample=8):
             idx = sorted(range(len(data)), key=lambda k: len(data[k]["src"]))[::len(data) // oracle_sample][:oracle_sample]
             for k in idx:
                 d = data[k]
-                o = oracle.icp_register(d["src"], d["tgt"], d["tgt_normals"], np.eye(4), d["max_corr_dist"],
-                                        d["max_iter"], d["rel_tol"])
+                if k not in oracle_res:  # the FP64 oracle's result does not depend on the GPU precision
+                    oracle_res[k] = oracle.icp_register(d["src"], d["tgt"], d["tgt_normals"], np.eye(4),
+                                                        d["max_corr_dist"], d["max_iter"], d["rel_tol"])
+                o = oracle_res[k]
                 g = res[k]
                 dR = np.linalg.norm(g.T[:3, :3] - o.T[:3, :3])
                 ang = 2 * np.arcsin(min(1.0, dR / (2 * np.sqrt(2))))
@@ -407,19 +488,21 @@ def batched_section(args, icp, synth, np, torch, oracle_sample=8):
                              "trans_m": float(np.linalg.norm(g.T[:3, 3] - o.T[:3, 3])),
                              "rmse_diff": g.inlier_rmse - o.inlier_rmse,
                              "n_iter": [g.n_iter, o.n_iter], "n_in": [g.n_inliers, o.n_inliers]})
-            entry["pose_error_vs_oracle_sample"] = errs
+            entry["pose_error_vs_oracle"] = {
+                "pairs": len(errs), "max_rot_rad": max(e["rot_rad"] for e in errs),
+                "max_trans_m": max(e["trans_m"] for e in errs),
+                "max_abs_rmse_diff": max(abs(e["rmse_diff"]) for e in errs),
+                "n_iter_equal": sum(e["n_iter"][0] == e["n_iter"][1] for e in errs),
+                "n_inliers_equal": sum(e["n_in"][0] == e["n_in"][1] for e in errs)}
         out[prec] = entry
         print(f"bench: batched {prec}: {tb*1e3:.1f} ms vs plain {tp*1e3:.1f} ms", file=sys.stderr, flush=True)
     ctx.close()
     return out
 
 
-def _gen_c5(q):
+def _gen_c5_scene(k):
     from paper_1801_09847_amd import synth
-    import math
-    d = synth.c5_request(q)
-    return {"src": d["src"], "tgt": d["tgt"], "tgt_normals": d["tgt_normals"],
-            "spacing": math.sqrt(d["area"] / len(d["tgt"]))}
+    return synth.c5_scene(k)
 
 
 def _gen_c4(p):
@@ -433,51 +516,81 @@ def parallel_generate(fn, items, workers=8):
         return list(ex.map(fn, items))
 
 
+def served_accuracy(icp, np, torch, reqs, qs, results, vox, its):
+    """CPU-baseline leg of the served section: the FP64 oracle's multi-scale
+    registration of the requests qs, against the GPU results given for them
+    (pose error in rad / m)."""
+    import oracle
+    oracle.build(force=False)
+    rot, trans = [], []
+    for q in qs:
+        (s, t, n), spacing, _ = reqs[q]
+        dists = [2.0 * max(v, spacing) for v in vox]
+        o = oracle.register_multiscale(s.cpu().numpy(), t.cpu().numpy(), n.cpu().numpy(), np.eye(4),
+                                       list(vox), list(its), dists)
+        T = results[q].T
+        dR = np.linalg.norm(T[:3, :3] - o.T[:3, :3])
+        rot.append(2.0 * np.arcsin(min(1.0, dR / (2.0 * np.sqrt(2.0)))))
+        trans.append(float(np.linalg.norm(T[:3, 3] - o.T[:3, 3])))
+    return {"requests": len(qs), "max_rot_rad": float(max(rot)), "median_rot_rad": float(np.median(rot)),
+            "max_trans_m": float(max(trans)), "median_trans_m": float(np.median(trans))}
+
+
 def served_section(args, icp, np, torch):
-    """C5: requests (sizes log-uniform in [5k, 500k], room pairs, overlap
-    U(0.5, 0.9)) arriving as a Poisson process; multi-scale ICP (voxel 4/2/1 cm,
-    30/20/10 iterations, max_corr_dist 2 max(voxel, spacing)), point-to-plane.
+    """C5: 2000 distinct requests (sizes log-uniform in [5k, 500k], overlap
+    U(0.5, 0.9), each cut from a pool of room scenes with its own subsample,
+    crop and motion, synth.c5_request_pooled), arriving as a Poisson process at
+    rates swept over multiples of the plain path's measured pairs/s until the
+    server saturates; multi-scale ICP (voxel 4/2/1 cm, 30/20/10 iterations,
+    max_corr_dist 2 max(voxel, spacing)), point-to-plane, FP32-Kahan.
     Served: icp_server with a background thread.  Plain: the same requests
-    back to back through icp_register_multiscale."""
+    back to back through icp_register_multiscale; its latency under each
+    arrival trace is the FIFO replay of its measured service times.  Pose error
+    against the FP64 oracle on a subsample, for both forms."""
     import threading
     from paper_1801_09847_amd import synth
     vox, its = (0.04, 0.02, 0.01), (30, 20, 10)
-    print(f"bench: generating {args.served_pool} served requests", file=sys.stderr, flush=True)
-    pool = parallel_generate(_gen_c5, range(args.served_pool))
-    dev = torch.device("cuda:0")
-    tens = [(torch.from_numpy(d["src"]).to(dev), torch.from_numpy(d["tgt"]).to(dev),
-             torch.from_numpy(d["tgt_normals"]).to(dev)) for d in pool]
-    torch.cuda.synchronize()
     n_req = args.served_requests
-    order = [q % len(pool) for q in range(n_req)]
+    print(f"bench: served: {args.served_scenes} scenes, {n_req} requests", file=sys.stderr, flush=True)
+    scenes = parallel_generate(_gen_c5_scene, range(args.served_scenes))
+    dev = torch.device("cuda:0")
+    scenes_t = [{k: torch.from_numpy(np.ascontiguousarray(sc[k])).to(dev) for k in ("tgt", "tgt_normals", "src")}
+                for sc in scenes]
+    reqs = []
+    n_pts = 0
+    for q in range(n_req):
+        d = synth.c5_request_pooled_torch(q, scenes, scenes_t)
+        reqs.append(((d["src"], d["tgt"], d["tgt_normals"]), d["spacing"], d["meta"]["n"]))
+        n_pts += d["meta"]["n"]
+    del scenes_t
+    torch.cuda.synchronize()
     ctx = icp.Context(0)
 
-    def plain_one(k):
-        d = pool[k]
-        dists = [2.0 * max(v, d["spacing"]) for v in vox]
-        return icp.register_multiscale(*tens[k], np.eye(4), vox, its, dists, 0.0, ctx=ctx)
+    def plain_one(q):
+        t, spacing, _ = reqs[q]
+        dists = [2.0 * max(v, spacing) for v in vox]
+        return icp.register_multiscale(*t, np.eye(4), vox, its, dists, 0.0, ctx=ctx)
 
-    for k in range(min(4, len(pool))):
-        plain_one(k)
+    for q in range(4):
+        plain_one(q)
     torch.cuda.synchronize()
-    service = []
-    plain_res = {}
+    service, plain_res = [], []
     t0 = time.perf_counter()
-    for k in order:
+    for q in range(n_req):
         a = time.perf_counter()
-        r = plain_one(k)
+        plain_res.append(plain_one(q))
         service.append(time.perf_counter() - a)
-        plain_res.setdefault(k, r)
     plain_total = time.perf_counter() - t0
     plain_rate = n_req / plain_total
-    out = {"workload": f"{n_req} requests cycled over {len(pool)} distinct room pairs, sizes "
-                       "log-uniform in [5k, 500k], multi-scale 4/2/1 cm x 30/20/10 iterations, "
-                       "point-to-plane, Poisson arrivals",
+    out = {"workload": f"{n_req} distinct requests (synth.c5_request_pooled over {args.served_scenes} room "
+                       f"scenes, mean {n_pts / n_req:.0f} points), sizes log-uniform in [5k, 500k], overlap "
+                       "U(0.5, 0.9), multi-scale 4/2/1 cm x 30/20/10 iterations, point-to-plane, Poisson arrivals",
            "plain_pairs_per_s": plain_rate, "plain_ms_total": plain_total * 1e3,
            "server": {"max_slots": args.served_slots, "iters_per_step": args.served_iters_per_step,
                       "budget_bytes": args.served_budget}, "rates": []}
     print(f"bench: plain {plain_rate:.1f} pairs/s", file=sys.stderr, flush=True)
     rng = np.random.Generator(np.random.PCG64(12345))
+    served_res = None
     for mult in args.served_rates:
         rate = mult * plain_rate
         gaps = rng.exponential(1.0 / rate, n_req)
@@ -485,9 +598,8 @@ def served_section(args, icp, np, torch):
         srv = icp.Server(vox, its, corr_factor=2.0, max_slots=args.served_slots,
                          budget_bytes=args.served_budget, iters_per_step=args.served_iters_per_step,
                          background_thread=True)
-        warm = srv.submit(*tens[0], spacing=pool[0]["spacing"])
+        warm = srv.submit(*reqs[0][0], spacing=reqs[0][1])
         srv.wait(warm)
-        tickets = {}
         base_ns = [0]
 
         def client():
@@ -498,8 +610,7 @@ def served_section(args, icp, np, torch):
                 now = time.monotonic_ns()
                 if target > now:
                     time.sleep((target - now) / 1e9)
-                k = order[q]
-                tickets[srv.submit(*tens[k], spacing=pool[k]["spacing"], tag=q)] = q
+                srv.submit(*reqs[q][0], spacing=reqs[q][1], tag=q)
 
         th = threading.Thread(target=client)
         th.start()
@@ -511,17 +622,18 @@ def served_section(args, icp, np, torch):
             done += got
         th.join()
         srv.close()
-        lat = []
-        mismatch = 0
-        last_done = 0
+        lat, mismatch, last_done = [], 0, 0
+        res_q = [None] * n_req
         for c in done:
             q = c.user_tag
-            arr_ns = base_ns[0] + int(arrivals[q] * 1e9)
-            lat.append((c.t_done_ns - arr_ns) / 1e6)
+            res_q[q] = c.result
+            lat.append((c.t_done_ns - (base_ns[0] + int(arrivals[q] * 1e9))) / 1e6)
             last_done = max(last_done, c.t_done_ns)
-            p = plain_res[order[q]]
+            p = plain_res[q]
             if c.error or not np.array_equal(c.result.T, p.T) or c.result.n_iter != p.n_iter:
                 mismatch += 1
+        if served_res is None:
+            served_res = res_q
         served_rate = n_req / ((last_done - base_ns[0]) / 1e9)
         # plain latency under the same arrivals: FIFO single server with the measured service times
         t_free, plat = 0.0, []
@@ -539,6 +651,15 @@ def served_section(args, icp, np, torch):
         print(f"bench: served x{mult}: {served_rate:.1f} pairs/s p50 {entry['p50_ms']:.1f} ms "
               f"p99 {entry['p99_ms']:.1f} ms (plain p50 {entry['plain_p50_ms']:.1f} p99 "
               f"{entry['plain_p99_ms']:.1f})", file=sys.stderr, flush=True)
+        if served_rate < 0.8 * rate:
+            break  # saturated: higher offered rates only lengthen the queue
+    out["saturated_pairs_per_s"] = max(e["served_pairs_per_s"] for e in out["rates"])
+    out["speedup_vs_plain"] = out["saturated_pairs_per_s"] / plain_rate
+    if args.served_oracle > 0:
+        qs = list(range(0, n_req, max(1, n_req // args.served_oracle)))[:args.served_oracle]
+        print(f"bench: served: oracle on {len(qs)} requests", file=sys.stderr, flush=True)
+        out["oracle_pose_error"] = {"plain": served_accuracy(icp, np, torch, reqs, qs, plain_res, vox, its),
+                                    "served": served_accuracy(icp, np, torch, reqs, qs, served_res, vox, its)}
     ctx.close()
     return out
 
@@ -561,11 +682,14 @@ def main():
     ap.add_argument("--no-served", action="store_true", help="skip the served (request server) section")
     ap.add_argument("--no-normals", action="store_true", help="skip the normal-estimation section")
     ap.add_argument("--no-robust", action="store_true", help="skip the robust-loss section")
+    ap.add_argument("--no-configs", action="store_true", help="skip the C1 / C2 / C3 point-to-point section")
     ap.add_argument("--no-pose-graph", action="store_true", help="skip the pose-graph section")
     ap.add_argument("--no-ransac", action="store_true", help="skip the RANSAC global-registration section")
-    ap.add_argument("--served-requests", type=int, default=400)
-    ap.add_argument("--served-pool", type=int, default=64)
-    ap.add_argument("--served-rates", type=float, nargs="+", default=[1.0, 8.0])
+    ap.add_argument("--served-requests", type=int, default=2000)
+    ap.add_argument("--served-scenes", type=int, default=8)
+    ap.add_argument("--served-rates", type=float, nargs="+", default=[0.25, 0.5, 1.0, 2.0, 4.0, 8.0, 16.0])
+    ap.add_argument("--served-oracle", type=int, default=50,
+                    help="requests checked against the FP64 oracle (both forms); 0 skips")
     ap.add_argument("--served-slots", type=int, default=128)
     ap.add_argument("--served-iters-per-step", type=int, default=5)
     ap.add_argument("--served-budget", type=int, default=64 << 30)
@@ -676,6 +800,11 @@ def main():
         },
         "result": {"fitness": res.fitness, "inlier_rmse": res.inlier_rmse, "n_iter": res.n_iter,
                    "status": res.status},
+        # grid build + source ordering of the timed step: 52 algorithmic bytes
+        # per target point (xyz + normal in, cell-ordered point + index out)
+        "grid_build": {"ms": prof["build_ms"], "target_points": prof["build_points"],
+                       "alg_gbs": 52.0 * prof["build_points"] / (prof["build_ms"] * 1e-3) / 1e9
+                       if prof["build_ms"] > 0 else None},
     }
     if ceilings:
         out["ceilings"] = ceilings
@@ -684,6 +813,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline(data, args.variant, args.cpu_passes)
     if not args.no_robust:
         out["robust"] = robust_section(args, icp, np, torch, s, t, n, data, K, r)
+    if not args.no_configs and args.workload == "c3":
+        out["configs"] = config_section(args, icp, synth, np, torch, c3=data)
     del s, t, n
     if not args.no_normals and args.workload == "c3":
         out["normals"] = normals_section(args, icp, synth, np, torch, data)

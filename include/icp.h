@@ -592,6 +592,9 @@ typedef struct {
   double validate_ms;        /* RANSAC validation launches (pass and per-hypothesis sum) */
   int64_t validate_launches;
   int64_t validate_evals;    /* hypotheses x source points scored */
+  double build_ms;           /* grid and source-order builds of registration calls */
+  int64_t builds;
+  int64_t build_points;      /* target points built (summed over the calls' pairs) */
 } icp_profile_t;
 
 /* Enables (1) or disables (0) kernel timing on ctx; resets the counters.

@@ -68,6 +68,8 @@ void ctx_free(icp_ctx* c) {
   c->host = nullptr;
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   c->ev.clear();
+  for (hipEvent_t& e : c->ev_build)
+    if (e) (void)hipEventDestroy(e), e = nullptr;
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   c->stream = nullptr;
 }
@@ -417,6 +419,11 @@ int build_pairs(icp_ctx* c, Prep* P, const PairDst* dst) {
   HIP_TRY(hipMemcpyAsync(dd + L.pairs, hh + L.pairs, L.pargs - L.pairs, hipMemcpyHostToDevice, s),
           "upload");
   const BuildPair* dbp = reinterpret_cast<const BuildPair*>(dd + L.pairs);
+  if (c->profiling) {
+    for (hipEvent_t& e : c->ev_build)
+      if (!e) HIP_TRY(hipEventCreate(&e), "hipEventCreate");
+    HIP_TRY(hipEventRecord(c->ev_build[0], s), "hipEventRecord");
+  }
   HIP_TRY(launch_occ_clear(c->occ_raw.as<uint32_t>(), P->total_occ, s), "occupancy clear");
   HIP_TRY(launch_seg_targets(dbp, n, reinterpret_cast<const int64_t*>(dd + L.blk_t), bt[n],
                              reinterpret_cast<const int64_t*>(dd + L.blk_tab), bk[n],
@@ -440,6 +447,10 @@ int build_pairs(icp_ctx* c, Prep* P, const PairDst* dst) {
                              reinterpret_cast<const int64_t*>(dd + L.src_off), P->total_src, sb,
                              c->s_hist.as<uint32_t>(), hist_cap, s),
           "source order");
+  if (c->profiling) {
+    HIP_TRY(hipEventRecord(c->ev_build[1], s), "hipEventRecord");
+    c->build_pending = P->total_tgt;
+  }
   return ICP_SUCCESS;
 }
 
@@ -497,6 +508,13 @@ int collect_profile(icp_ctx* c, int counted_passes, int64_t evals) {
   HIP_TRY(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]), "hipEventElapsedTime");
   c->prof.call_ms += ms;
   c->prof.calls += 1;
+  if (c->build_pending) {
+    HIP_TRY(hipEventElapsedTime(&ms, c->ev_build[0], c->ev_build[1]), "hipEventElapsedTime");
+    c->prof.build_ms += ms;
+    c->prof.builds += 1;
+    c->prof.build_points += c->build_pending;
+    c->build_pending = 0;
+  }
   return ICP_SUCCESS;
 }
 
@@ -777,6 +795,7 @@ int icp_ctx_set_profiling(icp_ctx_t* ctx, int enable) {
   if (!ctx) return fail(ICP_E_INVALID_ARG, "ctx is NULL");
   ctx->profiling = enable != 0;
   ctx->prof = icp_profile_t{};
+  ctx->build_pending = 0;
   return ICP_SUCCESS;
 }
 

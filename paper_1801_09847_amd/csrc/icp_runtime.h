@@ -87,6 +87,8 @@ struct icp_ctx {
   // kernel timing
   bool profiling = false;
   std::vector<hipEvent_t> ev;  // [0] call start, [1] call end, [2+2k]/[3+2k] around pass k
+  hipEvent_t ev_build[2] = {nullptr, nullptr};  // around the last build (profiling)
+  int64_t build_pending = 0;   // target points of a timed build not yet collected
   icp_profile_t prof{};
 };
 

@@ -423,6 +423,104 @@ def c5_request(q: int, lo: float = 5e3, hi: float = 5e5) -> dict:
     return d
 
 
+def c5_scene(k: int, n_max: int = 500_000, noise: float = 0.002) -> dict:
+    """Scene ``k`` of the served workload's pool (seed 20000+k): a 6x4x3 m room
+    with 20 boxes and 10 spheres, its target surface sampled at the largest
+    request size (``n_max`` points, exact normals, N(0, noise^2) positions) and
+    an independent source surface sampling twice as dense, both in random
+    order.  Requests are cut from these samplings by ``c5_request_pooled``."""
+    seed = 20_000 + k
+    scene = room_scene(seed, 6.0, 4.0, 3.0, 20, 10)
+    rt, rs = _rng(seed, "tgt"), _rng(seed, "src")
+    tp, tn, area = room_surface_random(scene, rt, n_max)
+    tp = tp + rt.normal(0.0, noise, tp.shape)
+    sp, _, _ = room_surface_random(scene, rs, 2 * n_max + 64)
+    sp = sp + rs.normal(0.0, noise, sp.shape)
+    return {"tgt": tp, "tgt_normals": tn, "src": sp, "area": float(area)}
+
+
+def _c5_pool_params(q: int, scenes: list):
+    """Random choices of pooled request q: size, overlap, scene, offsets, side."""
+    n, o = c5_request_size(q)
+    rng = _rng(10_000 + q, "c5-pool")
+    k = int(rng.integers(len(scenes)))
+    N = len(scenes[k]["tgt"])
+    n = min(n, N)
+    off = int(rng.integers(N))
+    from_low = bool(rng.integers(0, 2))
+    kk = min(n - 1, max(0, int(round(o * n)) - 1))
+    return n, o, rng, k, off, from_low, kk
+
+
+def _c5_motion(rng, lo, hi) -> np.ndarray:
+    """Random motion of a pooled request: rotation <= 10 deg about the centre
+    of the source's bounding box, translation <= 10 cm (the box centre is an
+    exact function of the points, unlike a centroid's rounded sum)."""
+    return random_motion(rng, 10.0, 0.10, (np.asarray(lo, np.float64) + np.asarray(hi, np.float64)) / 2.0)
+
+
+def c5_request_pooled(q: int, scenes: list) -> dict:
+    """Served request ``q`` (seed 10000+q) cut from a pool of scenes: its size
+    n and overlap o come from ``c5_request_size``; the target is n points of a
+    scene's target sampling taken from a random offset of its random order (a
+    random subsample), the source the first n points, from a random offset of
+    the scene's source sampling, inside the x-slab from a random end wall that
+    holds a fraction o of those target points, moved by a random motion
+    (``_c5_motion``).  Returns float32 clouds, the target spacing sqrt(A / n)
+    and the motion.  ``c5_request_pooled_torch`` computes the same arrays
+    with torch (e.g. on the GPU)."""
+    n, o, rng, k, off, from_low, kk = _c5_pool_params(q, scenes)
+    P = scenes[k]
+    N = len(P["tgt"])
+    idx = (off + np.arange(n)) % N
+    tp, tn = P["tgt"][idx], P["tgt_normals"][idx]
+    xs = np.sort(tp[:, 0])
+    cut = xs[kk] if from_low else xs[n - 1 - kk]
+    sx = np.ascontiguousarray(P["src"][:, 0])
+    M = len(sx)
+    soff = int(rng.integers(M))
+    order = (soff + np.arange(M)) % M
+    inside = sx[order] <= cut if from_low else sx[order] >= cut
+    sp = P["src"][order[np.nonzero(inside)[0][:n]]]
+    G = _c5_motion(rng, sp.min(axis=0), sp.max(axis=0))
+    moved = np.empty_like(sp)
+    for a in range(3):
+        moved[:, a] = ((G[a, 0] * sp[:, 0] + G[a, 1] * sp[:, 1]) + G[a, 2] * sp[:, 2]) + G[a, 3]
+    return {"src": _f32(moved), "tgt": _f32(tp), "tgt_normals": _f32(tn),
+            "spacing": math.sqrt(P["area"] / n), "G": G, "T_gt": np.linalg.inv(G),
+            "meta": {"q": q, "n": n, "overlap": o, "from_low": from_low, "scene": k}}
+
+
+def c5_request_pooled_torch(q: int, scenes: list, scenes_t: list) -> dict:
+    """``c5_request_pooled`` with the array work in torch: scenes_t[k] holds
+    the float64 tensors "tgt", "tgt_normals", "src" (any device) of
+    scenes[k].  Every step is a selection or one rounding of the same
+    float64 operation, so the float32 clouds equal the numpy ones bit for bit."""
+    import torch
+    n, o, rng, k, off, from_low, kk = _c5_pool_params(q, scenes)
+    P, T = scenes[k], scenes_t[k]
+    dev = T["tgt"].device
+    N = T["tgt"].shape[0]
+    idx = (off + torch.arange(n, device=dev)) % N
+    tp, tn = T["tgt"][idx], T["tgt_normals"][idx]
+    xs = torch.sort(tp[:, 0]).values
+    cut = xs[kk] if from_low else xs[n - 1 - kk]
+    M = T["src"].shape[0]
+    soff = int(rng.integers(M))
+    order = (soff + torch.arange(M, device=dev)) % M
+    sx = T["src"][order, 0]
+    inside = sx <= cut if from_low else sx >= cut
+    sp = T["src"][order[torch.nonzero(inside).flatten()[:n]]]
+    G = _c5_motion(rng, sp.min(dim=0).values.cpu().numpy(), sp.max(dim=0).values.cpu().numpy())
+    cols = []
+    for a in range(3):
+        cols.append(((G[a, 0] * sp[:, 0] + G[a, 1] * sp[:, 1]) + G[a, 2] * sp[:, 2]) + G[a, 3])
+    moved = torch.stack(cols, dim=1)
+    return {"src": moved.float().contiguous(), "tgt": tp.float().contiguous(),
+            "tgt_normals": tn.float().contiguous(), "spacing": math.sqrt(P["area"] / n), "G": G,
+            "T_gt": np.linalg.inv(G), "meta": {"q": q, "n": n, "overlap": o, "from_low": from_low, "scene": k}}
+
+
 def poisson_arrivals(n: int, rate: float, seed: int = 0) -> np.ndarray:
     """Arrival times (s) of a Poisson process of ``rate`` requests/s."""
     rng = _rng(seed, "arrivals")

@@ -1,5 +1,6 @@
 """Generator determinism and shape checks (inputs shared by oracle and GPU tests)."""
 import numpy as np
+import pytest
 
 from paper_1801_09847_amd import synth
 
@@ -76,3 +77,21 @@ def test_bench_refuses_several_gpus():
     r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode != 0 and "one GPU" in (r.stdout + r.stderr)
+
+
+def test_pooled_served_requests_numpy_equals_torch():
+    """The served workload's requests are cut from a scene pool by a numpy
+    definition and, in the benchmark, by the same steps in torch on the GPU;
+    on the CPU the two give the same float32 clouds bit for bit."""
+    torch = pytest.importorskip("torch")
+    scenes = [synth.c5_scene(k, n_max=40_000) for k in range(2)]
+    st = [{k: torch.from_numpy(np.ascontiguousarray(s[k])) for k in ("tgt", "tgt_normals", "src")}
+          for s in scenes]
+    for q in range(6):
+        a = synth.c5_request_pooled(q, scenes)
+        b = synth.c5_request_pooled_torch(q, scenes, st)
+        for key in ("src", "tgt", "tgt_normals"):
+            np.testing.assert_array_equal(a[key], b[key].numpy())
+        assert a["spacing"] == b["spacing"] and np.array_equal(a["G"], b["G"])
+        n = a["meta"]["n"]
+        assert len(a["tgt"]) == n and 0 < len(a["src"]) <= n

@@ -27,12 +27,21 @@ STATUS_OK, STATUS_CONVERGED, STATUS_DEGENERATE = 0, 1, 2
 _VARIANTS = {"point_to_point": 0, "point_to_plane": 1, 0: 0, 1: 1}
 
 
-def build(force: bool = True) -> str:
-    """Compile ``oracle.cpp`` into ``liboracle.so`` next to it (g++, FP64, no FMA contraction)."""
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile ``oracle.cpp`` into ``liboracle.so`` next to it (g++, FP64, no FMA
+    contraction).  sanitize: clang++ with AddressSanitizer and
+    UndefinedBehaviorSanitizer (the runtime must be preloaded; CPU test runs)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math",
-                               "-fopenmp", "-shared", "-fPIC", "-o", tmp, _SRC])
+        if sanitize:
+            cmd = ["/opt/rocm/llvm/bin/clang++", "-std=c++17", "-O1", "-g", "-ffp-contract=off", "-fopenmp",
+                   "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer",
+                   "-shared-libsan", "-shared", "-fPIC", "-o", tmp, _SRC,
+                   "-Wl,-rpath,/opt/rocm/llvm/lib"]
+        else:
+            cmd = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math",
+                   "-fopenmp", "-shared", "-fPIC", "-o", tmp, _SRC]
+        subprocess.check_call(cmd)
         os.replace(tmp, _LIB)
     return _LIB
 

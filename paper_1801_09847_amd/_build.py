@@ -26,12 +26,23 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, jobs: int | None = None) -> str:
+# Host-side AddressSanitizer + UndefinedBehaviorSanitizer (CPU test runs only:
+# the device code is built as usual; every -fsanitize applies to the host
+# compilation alone).
+SANITIZE_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+SANITIZE_LINK = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-shared-libsan"]
+ASAN_RUNTIME = "/opt/rocm/llvm/lib/clang/22/lib/linux/libclang_rt.asan-x86_64.so"
+
+
+def build(verbose: bool = False, jobs: int | None = None, sanitize: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     cmds, objs = [], []
+    extra = SANITIZE_HOST if sanitize else []
     for src in SOURCES:
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-        cmds.append([HIPCC, *FLAGS, "-I", os.path.join(HERE, "..", "include"), "-c",
+        cmds.append([HIPCC, *FLAGS, *extra, "-I", os.path.join(HERE, "..", "include"), "-c",
                      os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     # one hipcc per translation unit, a few at a time (each takes several GB
@@ -47,7 +58,8 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
         for f in [ex.submit(run, c) for c in cmds]:
             f.result()
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, "-Wl,-z,defs"]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs,
+           *(SANITIZE_LINK if sanitize else ["-Wl,-z,defs"])]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
@@ -56,5 +68,5 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
+    build(verbose="-v" in sys.argv, sanitize="--sanitize" in sys.argv)
     print(LIB)

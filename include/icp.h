@@ -617,8 +617,11 @@ int icp_ctx_get_profile(icp_ctx_t *ctx, icp_profile_t *out);
  *   kind 1  v_fma_f32
  *   kind 2  v_mul_f64 / v_add_f64 alternating
  *   kind 3  v_fma_f64
+ *   kind 4  v_sub_f32 / v_mul_f32 / v_add_f32 of a 36-dimensional squared
+ *           distance, two queries against a target in scalar registers (many
+ *           independent instructions per wave: the highest unpacked rate)
  * *best_ms (may be NULL) receives the fastest of five timed launches.
- * Errors: INVALID_ARG (kind outside 0..3, lane_ops_per_s NULL), DEVICE. */
+ * Errors: INVALID_ARG (kind outside 0..4, lane_ops_per_s NULL), DEVICE. */
 int icp_measure_valu(int device, int kind, double *lane_ops_per_s, double *best_ms);
 
 /* icp_measure_copy: streaming bandwidth of device memory over a buffer of

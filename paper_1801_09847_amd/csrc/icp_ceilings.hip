@@ -69,6 +69,35 @@ __global__ __launch_bounds__(256) void valu_fma_kernel(float* out, int iters, fl
   out[blockIdx.x * blockDim.x + threadIdx.x] = (float)s;
 }
 
+// kind 4: the squared-distance pattern of a 36-dimensional feature comparison
+// (per dimension one v_sub, one v_mul and one v_add for each of two queries
+// against a target held in scalar registers): many independent instructions
+// per wave, the shape in which the SIMDs reach their highest unpacked rate.
+__global__ __launch_bounds__(256) void valu_distance_kernel(float* out, const float* __restrict__ tg,
+                                                            int iters) {
+  float q0[36], q1[36];
+#pragma unroll
+  for (int k = 0; k < 36; ++k) {
+    q0[k] = (float)(threadIdx.x + k) * 1e-3f;
+    q1[k] = (float)(3 * threadIdx.x + k) * 1e-3f;
+  }
+  float b0 = 1e30f, b1 = 1e30f;
+  for (int it = 0; it < iters; ++it) {
+    const float* t = tg + (it & 63) * 36;
+    float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+    for (int k = 0; k < 36; ++k) {
+      const float tk = t[k];
+      const float d0 = q0[k] - tk, d1 = q1[k] - tk;
+      s0 = s0 + d0 * d0;
+      s1 = s1 + d1 * d1;
+    }
+    b0 = fminf(b0, s0);
+    b1 = fminf(b1, s1);
+  }
+  out[blockIdx.x * blockDim.x + threadIdx.x] = b0 + b1;
+}
+
 __global__ __launch_bounds__(256) void copy_kernel(const float4* __restrict__ src, float4* __restrict__ dst,
                                                    int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -103,7 +132,7 @@ struct Scoped {
 }  // namespace
 
 extern "C" int icp_measure_valu(int device, int kind, double* lane_ops_per_s, double* best_ms) {
-  if (!lane_ops_per_s || kind < 0 || kind > 3) return icp_rt::fail(ICP_E_INVALID_ARG, "icp_measure_valu: bad argument");
+  if (!lane_ops_per_s || kind < 0 || kind > 4) return icp_rt::fail(ICP_E_INVALID_ARG, "icp_measure_valu: bad argument");
   HIP_TRY(hipSetDevice(device), "hipSetDevice");
   int n_cu = 0;
   HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device), "hipDeviceGetAttribute");
@@ -116,14 +145,19 @@ extern "C" int icp_measure_valu(int device, int kind, double* lane_ops_per_s, do
   const int blocks = n_cu * 8;
   const int iters = 2048;
   HIP_TRY(hipMalloc(&z.a, (size_t)blocks * 256 * sizeof(float)), "hipMalloc");
+  HIP_TRY(hipMalloc(&z.b, 64 * 36 * sizeof(float)), "hipMalloc");
+  HIP_TRY(hipMemsetAsync(z.b, 0, 64 * 36 * sizeof(float), z.s), "hipMemsetAsync");
   float* out = static_cast<float*>(z.a);
+  const float* tg = static_cast<const float*>(z.b);
   const float a = 0.999f, b = 1e-3f;
+  const int dist_iters = iters / 8;
   auto launch = [&]() {
     switch (kind) {
       case 0: valu_chain_kernel<0><<<blocks, 256, 0, z.s>>>(out, iters, a, b); break;
       case 1: valu_fma_kernel<1><<<blocks, 256, 0, z.s>>>(out, iters, a, b); break;
       case 2: valu_chain_kernel<2><<<blocks, 256, 0, z.s>>>(out, iters, a, b); break;
-      default: valu_fma_kernel<3><<<blocks, 256, 0, z.s>>>(out, iters, a, b); break;
+      case 3: valu_fma_kernel<3><<<blocks, 256, 0, z.s>>>(out, iters, a, b); break;
+      default: valu_distance_kernel<<<blocks, 256, 0, z.s>>>(out, tg, dist_iters); break;
     }
   };
   launch();  // warm-up (clocks ramp, code object loads)
@@ -138,8 +172,10 @@ extern "C" int icp_measure_valu(int device, int kind, double* lane_ops_per_s, do
     HIP_TRY(hipEventElapsedTime(&ms, z.e0, z.e1), "hipEventElapsedTime");
     if (ms < best) best = ms;
   }
-  // lane operations: two per chain per trip
-  const double ops = (double)blocks * 256.0 * iters * kChains * 2.0;
+  // lane operations: two per chain per trip; the distance pattern six per
+  // dimension per trip
+  const double ops = kind == 4 ? (double)blocks * 256.0 * dist_iters * 36.0 * 6.0
+                               : (double)blocks * 256.0 * iters * kChains * 2.0;
   *lane_ops_per_s = ops / (best * 1e-3);
   if (best_ms) *best_ms = best;
   return ICP_SUCCESS;

@@ -182,20 +182,22 @@ __device__ inline QueryCell query_cell(const GridDesc& g, float q32x, float q32y
   return c;
 }
 
-// Whether any target lies in the 27 cells around the query's cell, from the
-// dilated occupancy bitmap.  The cell is clamped into the grid first: along
-// each axis the clamped cell's neighbours include every in-grid neighbour of
-// the query's own cell, so a clear bit proves that the query has no
-// candidate (with R = 1; for R = 2 the bitmap is not used).
-__device__ inline bool occupied_neighbourhood(const PassArgs& a, const QueryCell& c) {
+// The dilated-occupancy-bitmap word and bit of a query's cell: the bit is set
+// when any target lies in the 27 cells around it.  The cell is clamped into
+// the grid first: along each axis the clamped cell's neighbours include every
+// in-grid neighbour of the query's own cell, so a clear bit proves that the
+// query has no candidate (with R = 1; for R = 2 the bitmap is not used).
+// Returns false (no word to read, no candidate) for a cell more than one cell
+// outside the grid, which has no neighbour in it.
+__device__ inline bool occupancy_word(const PassArgs& a, const QueryCell& c, uint32_t* word, uint32_t* bit) {
   const GridDesc& g = a.g;
-  // a cell more than one cell outside the grid has no neighbour in it
   if (c.cx < -1 || c.cx > g.dx || c.cy < -1 || c.cy > g.dy || c.cz < -1 || c.cz > g.dz) return false;
   const uint32_t x = (uint32_t)min(max(c.cx, 0), g.dx - 1);
   const uint32_t y = (uint32_t)min(max(c.cy, 0), g.dy - 1);
   const uint32_t z = (uint32_t)min(max(c.cz, 0), g.dz - 1);
-  const uint32_t w = (z * (uint32_t)g.dy + y) * occ_row_words(g.dx) + (x >> 5);
-  return (ld_cell(a.occ, w) >> (x & 31u)) & 1u;
+  *word = (z * (uint32_t)g.dy + y) * occ_row_words(g.dx) + (x >> 5);
+  *bit = 1u << (x & 31u);
+  return true;
 }
 
 template <int R>
@@ -376,15 +378,66 @@ __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
   uint32_t cnt = 0;
   bool wave_any = false;  // some query of this wave had a correspondence (wave-uniform)
 
-  static_assert(kRounds == 1, "one query per thread");
+  // Phase 1, for all kRounds queries of the thread at once (their loads in
+  // flight together): source point and warm-start index, then the query's
+  // cell and its bit in the dilated occupancy bitmap.  Phase 2 searches, one
+  // query at a time, only the queries whose neighbourhood holds a target; a
+  // wave none of whose lanes has one for a round skips that round entirely.
+  constexpr int Q = kRounds;
+  const int64_t base = (int64_t)tile_index * kTile + threadIdx.x;
+  float ssx[Q], ssy[Q], ssz[Q];
+  uint32_t jpq[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int64_t i = base + (int64_t)q * kBlock;
+    const int64_t ic = min(i, (int64_t)a.n_src - 1);
+    ssx[q] = glb(a.sx)[ic]; ssy[q] = glb(a.sy)[ic]; ssz[q] = glb(a.sz)[ic];
+    jpq[q] = (a.jprev && i < a.n_src) ? glb(a.jprev)[ic] : 0xffffffffu;
+  }
+  uint32_t nbmask = 0;  // bit q: query q lies in the source and has a target in its 27 cells
   {
-    const int64_t i = (int64_t)tile_index * kTile + threadIdx.x;
+    uint32_t word[Q], bit[Q];
+    bool inside[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      word[q] = 0u;
+      bit[q] = 0u;
+      inside[q] = base + (int64_t)q * kBlock < (int64_t)a.n_src;
+      if (R == 1 && a.occ) {
+        const double sx = ssx[q], sy = ssy[q], sz = ssz[q];
+        double t;
+        t = T[0] * sx; t = t + T[1] * sy; t = t + T[2] * sz; const float qx = (float)(t + T[3]);
+        t = T[4] * sx; t = t + T[5] * sy; t = t + T[6] * sz; const float qy = (float)(t + T[7]);
+        t = T[8] * sx; t = t + T[9] * sy; t = t + T[10] * sz; const float qz = (float)(t + T[11]);
+        const QueryCell qc = query_cell<R>(a.g, qx, qy, qz);
+        uint32_t w = 0u;
+        if (occupancy_word(a, qc, &w, &bit[q])) word[q] = ld_cell(a.occ, w);
+      } else {
+        word[q] = bit[q] = 1u;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+      if (inside[q] && (word[q] & bit[q]) != 0u) nbmask |= 1u << q;
+  }
+
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int64_t i = base + (int64_t)q * kBlock;
+    const bool nb = (nbmask >> q) & 1u;
+    if (__ballot(nb) == 0) {
+      // no query of this round has a candidate: no correspondence
+      if (WRITE && i < a.n_src) {
+        const uint32_t oi = glb(a.sperm)[i];
+        glb(a.idx_out)[oi] = -1;
+        glb(a.d2_out)[oi] = INFINITY;
+      }
+      continue;
+    }
+    const uint32_t jp = jpq[q];
     // The warm-start point load is unconditional so that no branch forces an
     // early wait on it: a lane without a warm start (or past the end of the
     // source) reads target entry 0, which is never used.
-    const int64_t ic = min(i, (int64_t)a.n_src - 1);
-    const float ssx = glb(a.sx)[ic], ssy = glb(a.sy)[ic], ssz = glb(a.sz)[ic];
-    const uint32_t jp = (a.jprev && i < a.n_src) ? glb(a.jprev)[ic] : 0xffffffffu;
     const float4 pw = ld4(a.tp, jp != 0xffffffffu ? jp : 0u);
 
     bool inl = false;
@@ -394,16 +447,12 @@ __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
     uint64_t best = ~0ull;
     uint32_t total = 0;
     if (i < a.n_src) {
-      const double sx = ssx, sy = ssy, sz = ssz;
+      const double sx = ssx[q], sy = ssy[q], sz = ssz[q];
       double t;
       t = T[0] * sx; t = t + T[1] * sy; t = t + T[2] * sz; q64x = t + T[3];
       t = T[4] * sx; t = t + T[5] * sy; t = t + T[6] * sz; q64y = t + T[7];
       t = T[8] * sx; t = t + T[9] * sy; t = t + T[10] * sz; q64z = t + T[11];
       q32x = (float)q64x; q32y = (float)q64y; q32z = (float)q64z;
-      const QueryCell qc = query_cell<R>(a.g, q32x, q32y, q32z);
-      // queries whose 27-cell neighbourhood holds no target skip the row
-      // search (the whole wave, when all of its queries do)
-      const bool nb = (R == 1 && a.occ) ? occupied_neighbourhood(a, qc) : true;
       if (jp != 0xffffffffu) {
         // warm start: a target point (the previous pass's match) bounds this
         // pass's distance; any target would do, so an index left over from an
@@ -416,7 +465,7 @@ __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
           bj = jp;
         }
       }
-      if (nb) total = stage_rows<R>(a, qc, lane_ranges, best);
+      if (nb) total = stage_rows<R>(a, query_cell<R>(a.g, q32x, q32y, q32z), lane_ranges, best);
     }
     scan_ranges(a, q32x, q32y, q32z, lane_ranges, total, best, bj);
     if (i < a.n_src) {

@@ -191,6 +191,40 @@ def config_section(args, icp, synth, np, torch, c3=None):
     return out
 
 
+def far_outlier_section(args, icp, synth, np, torch, data, base, base_pass_us, steps=3):
+    """The headline pair with 1 % of its target points copied about 100 m away
+    (a box ~200 m wide: the grid takes the hashed cell table): pass time
+    against the outlier-free pair's, and the result against its result (the
+    same matches, so the same bits)."""
+    f = synth.with_far_outliers(data, seed=0)
+    dev = torch.device("cuda:0")
+    s, t, n = (torch.from_numpy(f[k]).to(dev) for k in ("src", "tgt", "tgt_normals"))
+    ctx = icp.Context(0)
+    K, r = data["max_iter"], data["max_corr_dist"]
+    icp.register(s, t, n, np.eye(4), r, K, 0.0, args.variant, args.precision, ctx=ctx)
+    torch.cuda.synchronize()
+    walls = []
+    for k in range(steps):
+        if k == steps - 1:
+            ctx.set_profiling(True)
+        t0 = time.perf_counter()
+        res = icp.register(s, t, n, np.eye(4), r, K, 0.0, args.variant, args.precision, ctx=ctx)
+        walls.append(time.perf_counter() - t0)
+    prof = ctx.profile()
+    ctx.close()
+    pass_us = prof["pass_ms"] * 1e3 / max(1, prof["pass_launches"])
+    out = {"n_tgt": len(f["tgt"]), "far_copies": len(f["tgt"]) - len(data["tgt"]), "far_dist_m": 100.0,
+           "hashed_grids": prof["hashed_grids"], "ms_per_registration": float(np.median(walls)) * 1e3,
+           "pass_avg_us": pass_us, "pass_ratio_vs_outlier_free": pass_us / base_pass_us,
+           "build_ms": prof["build_ms"],
+           "result_identical_to_outlier_free": bool(np.array_equal(res.T, base.T) and res.n_iter == base.n_iter
+                                                    and res.n_inliers == base.n_inliers)}
+    print(f"bench: far outliers: pass {pass_us:.1f} us ({out['pass_ratio_vs_outlier_free']:.2f}x), "
+          f"identical {out['result_identical_to_outlier_free']}", file=sys.stderr, flush=True)
+    del s, t, n
+    return out
+
+
 def robust_section(args, icp, np, torch, s, t, n, data, K, r, steps=3):
     """The same registration with the robust (IRLS) losses, scale 1 cm."""
     out = []
@@ -687,6 +721,8 @@ def main():
     ap.add_argument("--no-normals", action="store_true", help="skip the normal-estimation section")
     ap.add_argument("--no-robust", action="store_true", help="skip the robust-loss section")
     ap.add_argument("--no-configs", action="store_true", help="skip the C1 / C2 / C3 point-to-point section")
+    ap.add_argument("--no-far-outliers", action="store_true",
+                    help="skip the far-outlier (hashed cell table) section")
     ap.add_argument("--no-pose-graph", action="store_true", help="skip the pose-graph section")
     ap.add_argument("--no-ransac", action="store_true", help="skip the RANSAC global-registration section")
     ap.add_argument("--served-requests", type=int, default=2000)
@@ -817,6 +853,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline(data, args.variant, args.cpu_passes)
     if not args.no_robust:
         out["robust"] = robust_section(args, icp, np, torch, s, t, n, data, K, r)
+    if not args.no_far_outliers:
+        out["far_outliers"] = far_outlier_section(args, icp, synth, np, torch, data, res, pass_us)
     if not args.no_configs and args.workload == "c3":
         out["configs"] = config_section(args, icp, synth, np, torch, c3=data)
     del s, t, n

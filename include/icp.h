@@ -595,6 +595,7 @@ typedef struct {
   double build_ms;           /* grid and source-order builds of registration calls */
   int64_t builds;
   int64_t build_points;      /* target points built (summed over the calls' pairs) */
+  int64_t hashed_grids;      /* pairs whose target grid got a hashed cell table */
 } icp_profile_t;
 
 /* Enables (1) or disables (0) kernel timing on ctx; resets the counters.

@@ -196,15 +196,27 @@ int grid_sub() {
   return kDefaultSub;
 }
 
+// ICP_GRID_HASH=1 (debugging and tests only) gives every grid that may be
+// hashed a hashed table, whatever its extent; results must not change.
+bool grid_force_hash() {
+  const char* e = getenv("ICP_GRID_HASH");
+  return e && atoi(e) == 1;
+}
+
 // Grid over a target box: cell edge h >= r (1 + 2^-10) / sub so that every
 // point within r of a query lies in the (2 sub + 1)^3 cells around the query's
-// cell.  The dense table is capped at max(2^24, 32 n_tgt) cells; a larger
-// extent grows h (still exact: any h above the bound works, only the candidate
-// count changes).
-GridDesc make_grid(const float* mn, const float* mx, double r, int64_t n_tgt) {
+// cell.  The dense table is capped at max(2^24, 32 n_tgt) cells.  A larger
+// box gets a hashed table of 16 n_tgt slots (rounded up to a power of two, at
+// least 2^16) at the same h when the call's kernels accept one (`hashed_ok`),
+// else a grown h (still exact: any h above the bound works, only the
+// candidate count changes).  A hashed grid still grows h if an axis would
+// exceed 2^24 cells.
+GridDesc make_grid(const float* mn, const float* mx, double r, int64_t n_tgt, bool hashed_ok) {
   // below 2^30 entries: the pass addresses the table with 32-bit byte offsets
   const double cap = std::min<double>(1073741824.0 - 1024.0, std::max<double>(16777216.0, 32.0 * (double)n_tgt));
+  const double axis_cap = 16777216.0;
   const int sub = grid_sub();
+  const bool force = hashed_ok && grid_force_hash();
   double h = r * (1.0 + 1.0 / 1024.0) * grid_scale() / sub;
   GridDesc g{};
   for (int it = 0; it < 64; ++it) {
@@ -212,15 +224,25 @@ GridDesc make_grid(const float* mn, const float* mx, double r, int64_t n_tgt) {
     double d[3];
     for (int a = 0; a < 3; ++a) d[a] = floor(((double)mx[a] - (double)mn[a]) * inv_h) + 1.0;
     const double cells = d[0] * d[1] * d[2];
-    if (cells <= cap) {
+    const double dmax = std::max(d[0], std::max(d[1], d[2]));
+    const bool dense = cells <= cap && !force;
+    const bool hashed = !dense && hashed_ok && dmax <= axis_cap;
+    if (dense || hashed) {
       g.ox = mn[0]; g.oy = mn[1]; g.oz = mn[2];
       g.inv_h = inv_h;
       g.dx = (int32_t)d[0]; g.dy = (int32_t)d[1]; g.dz = (int32_t)d[2];
-      g.ncell = (uint32_t)cells;
       g.sub = sub;
+      g.hashed = hashed ? 1 : 0;
+      if (dense) {
+        g.ncell = (uint32_t)cells;
+      } else {
+        uint32_t slots = 1u << 16;
+        while ((double)slots < 16.0 * (double)n_tgt && slots < (1u << 29)) slots <<= 1;
+        g.ncell = slots;
+      }
       return g;
     }
-    h *= std::cbrt(cells / cap) * 1.001;
+    h *= (hashed_ok ? dmax / axis_cap : std::cbrt(cells / cap)) * 1.001;
   }
   return g;  // unreachable for finite inputs
 }
@@ -336,7 +358,7 @@ int plan_pairs(icp_ctx* c, int n, const PairIn* in, Prep* P, int* bad) {
   for (int p = 0; p < n; ++p) {
     const float* t = hbox + 16 * p;
     const float* q = t + 8;
-    P->g[p] = make_grid(t, t + 3, in[p].r, in[p].n_tgt);
+    P->g[p] = make_grid(t, t + 3, in[p].r, in[p].n_tgt, in[p].hashed_ok);
     P->tab_off[p + 1] = P->tab_off[p] + (uint64_t)P->g[p].ncell + 1;
     double ext = 0.0;
     for (int a = 0; a < 3; ++a) ext = std::max(ext, (double)q[3 + a] - (double)q[a]);
@@ -431,6 +453,12 @@ int build_pairs(icp_ctx* c, Prep* P, const PairDst* dst) {
                              c->t_rank.as<uint32_t>(), c->scan_tmp.as<uint32_t>(), scan_cap,
                              dst != nullptr, c->occ_raw.as<uint32_t>(), s),
           "target grid");
+  bool any_hashed = false;
+  for (int p = 0; p < n; ++p) any_hashed = any_hashed || P->g[p].hashed;
+  if (any_hashed)
+    HIP_TRY(launch_hashed_occ(dbp, n, reinterpret_cast<const int64_t*>(dd + L.blk_t), bt[n],
+                              c->occ_raw.as<uint32_t>(), s),
+            "hashed occupancy");
   {
     const int64_t* bo2 = reinterpret_cast<const int64_t*>(hh + L.blk_occ);
     HIP_TRY(launch_occ_dilate(dbp, n, reinterpret_cast<const int64_t*>(dd + L.blk_occ), bo2[n],
@@ -450,6 +478,7 @@ int build_pairs(icp_ctx* c, Prep* P, const PairDst* dst) {
   if (c->profiling) {
     HIP_TRY(hipEventRecord(c->ev_build[1], s), "hipEventRecord");
     c->build_pending = P->total_tgt;
+    for (int p = 0; p < n; ++p) c->prof.hashed_grids += P->g[p].hashed;
   }
   return ICP_SUCCESS;
 }
@@ -827,7 +856,7 @@ int icp_register_robust(icp_ctx_t* ctx, const float* src_xyz, int64_t n_src, con
   if ((rc = resolve_ctx(ctx, &c)) != 0) return rc;
   DeviceGuard dg(c->device);
   const bool plane = variant == ICP_POINT_TO_PLANE;
-  const PairIn in{src_xyz, n_src, tgt_xyz, plane ? tgt_normals : nullptr, n_tgt, max_corr_dist};
+  const PairIn in{src_xyz, n_src, tgt_xyz, plane ? tgt_normals : nullptr, n_tgt, max_corr_dist, true};
   Prep P;
   if ((rc = prepare_pairs(c, 1, &in, &P)) != 0) return rc;
   LoopIn li{T_init, max_corr_dist, max_iter, rel_tol};
@@ -872,7 +901,7 @@ int icp_register_batch_robust(icp_ctx_t* ctx, const icp_pair_t* pairs, int32_t n
   for (int p = 0; p < n_pairs; ++p) {
     const icp_pair_t& q = pairs[p];
     in[p] = PairIn{q.src_xyz, q.n_src, q.tgt_xyz, plane ? q.tgt_normals : nullptr, q.n_tgt,
-                   q.max_corr_dist};
+                   q.max_corr_dist, true};
     li[p] = LoopIn{q.T_init, q.max_corr_dist, q.max_iter, q.rel_tol, loss, loss_k};
   }
   Prep P;
@@ -1007,7 +1036,7 @@ int icp_register_multiscale_robust(icp_ctx_t* ctx, const float* src_xyz, int64_t
       ns = cnt[0];
       nt = cnt[1];
     }
-    const PairIn in{s, ns, t, tn, nt, max_corr_dist[l]};
+    const PairIn in{s, ns, t, tn, nt, max_corr_dist[l], true};
     Prep P;
     if ((rc = prepare_pairs(c, 1, &in, &P)) != 0) return rc;
     const LoopIn li{T, max_corr_dist[l], max_iter[l], rel_tol, loss, loss_k};
@@ -1031,7 +1060,7 @@ int icp_correspondences(icp_ctx_t* ctx, const float* src_xyz, int64_t n_src, con
   icp_ctx* c = nullptr;
   if ((rc = resolve_ctx(ctx, &c)) != 0) return rc;
   DeviceGuard dg(c->device);
-  const PairIn in{src_xyz, n_src, tgt_xyz, nullptr, n_tgt, max_corr_dist};
+  const PairIn in{src_xyz, n_src, tgt_xyz, nullptr, n_tgt, max_corr_dist, true};
   Prep P;
   if ((rc = prepare_pairs(c, 1, &in, &P)) != 0) return rc;
   return single_pass(c, P, max_corr_dist, T, false, ICP_POINT_TO_POINT, ICP_PREC_F32_KAHAN_F64,
@@ -1061,7 +1090,7 @@ int icp_normal_equations_robust(icp_ctx_t* ctx, const float* src_xyz, int64_t n_
   if ((rc = resolve_ctx(ctx, &c)) != 0) return rc;
   DeviceGuard dg(c->device);
   const bool plane = variant == ICP_POINT_TO_PLANE;
-  const PairIn in{src_xyz, n_src, tgt_xyz, plane ? tgt_normals : nullptr, n_tgt, max_corr_dist};
+  const PairIn in{src_xyz, n_src, tgt_xyz, plane ? tgt_normals : nullptr, n_tgt, max_corr_dist, true};
   Prep P;
   if ((rc = prepare_pairs(c, 1, &in, &P)) != 0) return rc;
   IterState st;

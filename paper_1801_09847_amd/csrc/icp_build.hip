@@ -288,8 +288,8 @@ __device__ inline int cell_of(float p, double o, double inv_h, int dim) {
   return (int)floor(u);
 }
 
-// Cell key of every target point (global: offset by the pair's table) and its
-// rank among the points of its cell (order of arrival; the search breaks ties
+// Cell key of every target point (global: offset by the pair's table; dense
+// or hashed as the pair's grid says) and its rank among the points of its key (order of arrival; the search breaks ties
 // by original index, so the order inside a cell never matters).
 // With occ_raw, the cell's bit is also set in the pair's raw occupancy bitmap.
 __global__ __launch_bounds__(256) void seg_target_key_kernel(const BuildPair* __restrict__ pairs, int n,
@@ -307,21 +307,63 @@ __global__ __launch_bounds__(256) void seg_target_key_kernel(const BuildPair* __
   const int cx = min(max(cell_of(t[0], g.ox, g.inv_h, g.dx), 0), g.dx - 1);
   const int cy = min(max(cell_of(t[1], g.oy, g.inv_h, g.dy), 0), g.dy - 1);
   const int cz = min(max(cell_of(t[2], g.oz, g.inv_h, g.dz), 0), g.dz - 1);
-  const uint32_t k = ((uint32_t)cz * (uint32_t)g.dy + (uint32_t)cy) * (uint32_t)g.dx + (uint32_t)cx;
+  const uint32_t k = g.hashed ? hashed_slot(g, cx, cy, cz)
+                             : ((uint32_t)cz * (uint32_t)g.dy + (uint32_t)cy) * (uint32_t)g.dx + (uint32_t)cx;
   const uint32_t gk = (uint32_t)bp.tab_off + k;
   key[bp.tgt_off + i] = gk;
   const uint32_t rk = atomicAdd(&counts[gk], 1u);
   rank[bp.tgt_off + i] = rk;
   // the first point to reach a cell marks it (one atomic per occupied cell)
-  if (rk == 0 && occ_raw && bp.occ_dst) {
+  if (rk == 0 && occ_raw && bp.occ_dst && !g.hashed) {
     const uint64_t w = bp.occ_off + ((uint64_t)cz * (uint64_t)g.dy + (uint64_t)cy) * occ_row_words(g.dx) +
                        ((uint32_t)cx >> 5);
     atomicOr(&occ_raw[w], 1u << (cx & 31));
   }
 }
 
+// Occupancy of a hashed grid, dilated as it is built: after the scatter, the
+// first point of each cell among its slot's points (slots are shared, ranks
+// count per slot) sets the slots of the in-grid cells around its cell, per
+// row one mask for each run that the row's x segment touches (a run's slots
+// are consecutive bits of one word).
+__global__ __launch_bounds__(256) void seg_hashed_occ_kernel(const BuildPair* __restrict__ pairs, int n,
+                                                             const int64_t* __restrict__ blk_off,
+                                                             uint32_t* __restrict__ occ_raw) {
+  const int p = find_segment(blk_off, n, blockIdx.x);
+  const BuildPair& bp = pairs[p];
+  const int64_t j = (int64_t)(blockIdx.x - blk_off[p]) * 256 + threadIdx.x;
+  const GridDesc g = bp.g;
+  if (!g.hashed || !bp.occ_dst || j >= bp.n_tgt) return;
+  auto cell = [&](const float4& q, int* c) {
+    c[0] = min(max(cell_of(q.x, g.ox, g.inv_h, g.dx), 0), g.dx - 1);
+    c[1] = min(max(cell_of(q.y, g.oy, g.inv_h, g.dy), 0), g.dy - 1);
+    c[2] = min(max(cell_of(q.z, g.oz, g.inv_h, g.dz), 0), g.dz - 1);
+  };
+  int c[3];
+  cell(bp.tp_dst[j], c);
+  const uint32_t slot0 = hashed_slot(g, c[0], c[1], c[2]);
+  for (int64_t k = bp.cs_dst[slot0]; k < j; ++k) {
+    int o[3];
+    cell(bp.tp_dst[k], o);
+    if (o[0] == c[0] && o[1] == c[1] && o[2] == c[2]) return;  // not the cell's first point
+  }
+  const int x0 = max(c[0] - 1, 0), x1 = min(c[0] + 1, g.dx - 1);
+  const int xs = x1 & ~(kHashRun - 1);  // first x of x1's run
+  for (int z = max(c[2] - 1, 0); z <= min(c[2] + 1, g.dz - 1); ++z)
+    for (int y = max(c[1] - 1, 0); y <= min(c[1] + 1, g.dy - 1); ++y)
+      for (int part = 0; part < 2; ++part) {
+        if (part == 1 && xs <= x0) break;
+        const int a = part == 0 ? x0 : xs;
+        const int b = (part == 0 && xs > x0) ? xs - 1 : x1;
+        const uint32_t slot = hashed_slot(g, a, y, z);
+        const uint32_t mask = (uint32_t)((1ull << (b - a + 1)) - 1ull) << (slot & 31u);
+        atomicOr(&occ_raw[bp.occ_off + (slot >> 5)], mask);
+      }
+}
+
 // Dilation of each pair's raw occupancy bitmap over the 27-cell
-// neighbourhood: word (z, y, wi) of the result is the OR over the rows
+// neighbourhood (a hashed grid's map is dilated as it is built and only
+// copied): word (z, y, wi) of the result is the OR over the rows
 // (y + dy, z + dz), |dy|, |dz| <= 1, inside the grid, of the row's words
 // wi - 1 .. wi + 1 spread by one bit to each side.
 __global__ __launch_bounds__(256) void occ_dilate_kernel(const BuildPair* __restrict__ pairs, int n,
@@ -333,6 +375,10 @@ __global__ __launch_bounds__(256) void occ_dilate_kernel(const BuildPair* __rest
   const uint32_t W = occ_row_words(g.dx);
   const int64_t w = (int64_t)(blockIdx.x - blk_off[p]) * 256 + threadIdx.x;
   if (!bp.occ_dst || (uint64_t)w >= occ_words(g)) return;
+  if (g.hashed) {  // dilated as it was built
+    bp.occ_dst[w] = raw[bp.occ_off + w];
+    return;
+  }
   const int64_t row = w / W;
   const int wi = (int)(w - row * W);
   const int y = (int)(row % g.dy), z = (int)(row / g.dy);
@@ -760,6 +806,14 @@ hipError_t launch_seg_targets(const BuildPair* pairs, int n, const int64_t* blk_
 
 hipError_t launch_occ_clear(uint32_t* occ_raw, uint64_t total_occ, hipStream_t s) {
   return hipMemsetAsync(occ_raw, 0, sizeof(uint32_t) * (size_t)total_occ, s);
+}
+
+hipError_t launch_hashed_occ(const BuildPair* pairs, int n, const int64_t* blk_off, int64_t total_blocks,
+                             uint32_t* occ_raw, hipStream_t s) {
+  if (total_blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(seg_hashed_occ_kernel, dim3((unsigned)total_blocks), dim3(256), 0, s, pairs, n, blk_off,
+                     occ_raw);
+  return hipGetLastError();
 }
 
 hipError_t launch_occ_dilate(const BuildPair* pairs, int n, const int64_t* occ_blk_off, int64_t occ_blocks,

@@ -13,25 +13,60 @@ constexpr int kSumD2 = 27;
 constexpr int kSumCount = 28;
 
 // Uniform voxel grid over the target: cell = floor((p - origin) * inv_h) per
-// axis in float64; dense key = (cz * dy + cy) * dx + cx.  The cell edge is
-// >= r (1 + 2^-10) / sub, so a query's candidates lie in the (2 sub + 1)^3
-// cells around its own.
+// axis in float64.  The cell edge is >= r (1 + 2^-10) / sub, so a query's
+// candidates lie in the (2 sub + 1)^3 cells around its own.  The cell table
+// holds, for each key, the first position of its points in the key-ordered
+// target (ncell + 1 entries).
+//   dense:  key = (cz * dy + cy) * dx + cx, one entry per cell of the box;
+//   hashed: for boxes whose dense table would be too large (a few far
+//           outliers, say), key = hashed_slot(cx, cy, cz) over ncell slots
+//           (a power of two).  Distinct cells may share a slot: a lookup then
+//           yields extra target points, which the distance test sorts out,
+//           and never misses one.
 struct GridDesc {
   double ox, oy, oz;
   double inv_h;
   int32_t dx, dy, dz;
-  uint32_t ncell;  // dx * dy * dz
-  int32_t sub;     // 1 or 2
+  uint32_t ncell;   // dense: dx * dy * dz; hashed: number of slots
+  int32_t sub;      // 1 or 2
+  int32_t hashed;   // 0 dense, 1 hashed
 };
 
-// Occupancy bitmap over a grid, one bit per cell, rows of the x axis padded
-// to whole 32-bit words: the bit of cell (x, y, z) is bit (x & 31) of word
-// (z * dy + y) * occ_row_words(dx) + (x >> 5).  The pass reads the dilated
-// map, whose bit is set when any of the 27 cells around the cell holds a
-// target point.
+// Hashed keys: the cells of a run of kHashRun consecutive x (same y, z, x
+// aligned to the run) take kHashRun consecutive slots at a hashed position,
+// so the cells [x0, x1] of one run form one slot range and one range of the
+// target.  A row segment of at most 2 sub + 1 <= kHashRun cells spans at most
+// two runs.
+constexpr int kHashRunBits = 5;
+constexpr int kHashRun = 1 << kHashRunBits;
+__host__ __device__ inline uint32_t hashed_slot(const GridDesc& g, int32_t x, int32_t y, int32_t z) {
+  uint32_t h = ((uint32_t)x >> kHashRunBits) * 0x9E3779B1u;
+  h ^= (uint32_t)y * 0x85EBCA77u;
+  h ^= (uint32_t)z * 0xC2B2AE3Du;
+  // finalising mix (xor-shift / odd multiply rounds) so that the low bits
+  // depend on every input bit
+  h ^= h >> 15;
+  h *= 0x2C1B3C6Du;
+  h ^= h >> 12;
+  h *= 0x297A2D39u;
+  h ^= h >> 15;
+  const uint32_t runs = g.ncell >> kHashRunBits;
+  return ((h & (runs - 1u)) << kHashRunBits) | ((uint32_t)x & (uint32_t)(kHashRun - 1));
+}
+
+// Occupancy bitmap of a grid, read by the pass through the dilated map, whose
+// bit for a cell is set when any of the 27 cells around it holds a target
+// point.
+//   dense:  one bit per cell, rows of the x axis padded to whole 32-bit words:
+//           the bit of cell (x, y, z) is bit (x & 31) of word
+//           (z * dy + y) * occ_row_words(dx) + (x >> 5);
+//   hashed: one bit per slot (bit s & 31 of word s >> 5 for slot s); each
+//           occupied cell sets the bits of its 27 neighbours' slots, so a
+//           clear bit still proves an empty neighbourhood (cells that share a
+//           slot can only set more bits).
 __host__ __device__ inline uint32_t occ_row_words(int32_t dx) { return ((uint32_t)dx + 31u) >> 5; }
 __host__ __device__ inline uint64_t occ_words(const GridDesc& g) {
-  return (uint64_t)g.dy * (uint64_t)g.dz * occ_row_words(g.dx);
+  return g.hashed ? (uint64_t)(g.ncell >> 5) : (uint64_t)g.dy * (uint64_t)g.dz * occ_row_words(g.dx);
 }
 
 // Device-resident loop state of one registration.
@@ -216,6 +251,11 @@ hipError_t launch_seg_targets(const BuildPair* pairs, int n, const int64_t* blk_
 hipError_t launch_occ_clear(uint32_t* occ_raw, uint64_t total_occ, hipStream_t s);
 hipError_t launch_occ_dilate(const BuildPair* pairs, int n, const int64_t* occ_blk_off, int64_t occ_blocks,
                              const uint32_t* occ_raw, hipStream_t s);
+// Dilated occupancy of the pairs with hashed grids, into the raw words (after
+// launch_seg_targets, before launch_occ_dilate; blk_off: per-pair blocks over
+// the targets, as for launch_seg_targets).
+hipError_t launch_hashed_occ(const BuildPair* pairs, int n, const int64_t* blk_off, int64_t total_blocks,
+                             uint32_t* occ_raw, hipStream_t s);
 hipError_t launch_seg_sources(const BuildPair* pairs, int n, const int64_t* blk_off,
                               int64_t total_blocks, const int64_t* src_off, int64_t total,
                               SortBufs sb, uint32_t* hist, int64_t hist_cap, hipStream_t s);

@@ -195,14 +195,32 @@ __device__ inline bool occupancy_word(const PassArgs& a, const QueryCell& c, uin
   const uint32_t x = (uint32_t)min(max(c.cx, 0), g.dx - 1);
   const uint32_t y = (uint32_t)min(max(c.cy, 0), g.dy - 1);
   const uint32_t z = (uint32_t)min(max(c.cz, 0), g.dz - 1);
+  if (g.hashed) {
+    const uint32_t slot = hashed_slot(g, (int32_t)x, (int32_t)y, (int32_t)z);
+    *word = slot >> 5;
+    *bit = 1u << (slot & 31u);
+    return true;
+  }
   *word = (z * (uint32_t)g.dy + y) * occ_row_words(g.dx) + (x >> 5);
   *bit = 1u << (x & 31u);
   return true;
 }
 
+// Whether the x cells [cx - R, cx + R] (clamped to the grid) of a query span
+// two runs of a hashed grid.
+template <int R>
+__device__ inline bool hashed_straddle(const GridDesc& g, int cx) {
+  const int lo = max(cx - R, 0), hi = min(cx + R, g.dx - 1);
+  return lo <= hi && (hi & ~(kHashRun - 1)) > lo;
+}
+
+// Dense grid: one range per surviving row.  Hashed grid: a row segment lies
+// in one run of kHashRun cells or straddles two; part 0 stages each row's
+// range in its first run, part 1 the rest of the straddling rows (the caller
+// scans part 0 before it stages part 1 into the same slots).
 template <int R>
 __device__ inline uint32_t stage_rows(const PassArgs& a, const QueryCell& qc, uint2* lane_ranges,
-                                      uint64_t best) {
+                                      uint64_t best, int part = 0) {
   constexpr int W = 2 * R + 1;
   const GridDesc& g = a.g;
   const int cx = qc.cx, cy = qc.cy, cz = qc.cz;
@@ -238,6 +256,8 @@ __device__ inline uint32_t stage_rows(const PassArgs& a, const QueryCell& qc, ui
     xlo_c[d] = max(cx - d, 0);
     xhi_c[d] = min(cx + d, g.dx - 1);
   }
+  // hashed grids: first x of the run holding the neighbourhood's last cell
+  const int xsplit = xhi_c[R] & ~(kHashRun - 1);
   const uint32_t sdx = (uint32_t)g.dx, sdxdy = (uint32_t)g.dx * (uint32_t)g.dy;
   // row index of (cy, cz); rows of out-of-grid slabs wrap but are never loaded
   uint32_t base = ((uint32_t)cz * (uint32_t)g.dy + (uint32_t)cy) * sdx;
@@ -263,10 +283,31 @@ __device__ inline uint32_t stage_rows(const PassArgs& a, const QueryCell& qc, ui
         if (gyz <= thi[d]) xhi = xhi_c[d];
       }
       ok[k] = gyz <= thr && xlo <= xhi;
-      if (ok[k]) {
-        const uint32_t row = base + (uint32_t)dz * sdxdy + (uint32_t)dy * sdx;
-        beg[k] = ld_cell(a.cs, row + (uint32_t)xlo);
-        end_[k] = ld_cell(a.cs, row + (uint32_t)xhi + 1u);
+      if (!g.hashed) {
+        if (part != 0) ok[k] = false;
+        if (ok[k]) {
+          const uint32_t row = base + (uint32_t)dz * sdxdy + (uint32_t)dy * sdx;
+          beg[k] = ld_cell(a.cs, row + (uint32_t)xlo);
+          end_[k] = ld_cell(a.cs, row + (uint32_t)xhi + 1u);
+        }
+      } else {
+        // the split is fixed per query (the first x of the run that holds
+        // the neighbourhood's last cell), not per bound: part 1 runs with the
+        // bound that part 0 has tightened, which may narrow [xlo, xhi], and
+        // must still cover every cell that part 0 did not
+        int x0 = xlo, x1 = xhi;
+        if (part == 0) {
+          if (xsplit > xlo_c[R]) x1 = min(xhi, xsplit - 1);
+        } else {
+          ok[k] = ok[k] && xsplit > xlo_c[R];
+          x0 = max(xlo, xsplit);
+        }
+        ok[k] = ok[k] && x0 <= x1;
+        if (ok[k]) {
+          const uint32_t slot = hashed_slot(g, x0, cy + dy, cz + dz);
+          beg[k] = ld_cell(a.cs, slot);
+          end_[k] = ld_cell(a.cs, slot + (uint32_t)(x1 - x0) + 1u);
+        }
       }
     }
   }
@@ -468,6 +509,16 @@ __device__ void pass_tile(const PassArgs& a, uint32_t tile_index) {
       if (nb) total = stage_rows<R>(a, query_cell<R>(a.g, q32x, q32y, q32z), lane_ranges, best);
     }
     scan_ranges(a, q32x, q32y, q32z, lane_ranges, total, best, bj);
+    if (a.g.hashed) {
+      // the second runs of straddling row segments (waves whose queries all
+      // lie inside single runs skip this)
+      const QueryCell qc = query_cell<R>(a.g, q32x, q32y, q32z);
+      const bool straddle = i < a.n_src && nb && hashed_straddle<R>(a.g, qc.cx);
+      if (__ballot(straddle) != 0) {
+        const uint32_t total1 = straddle ? stage_rows<R>(a, qc, lane_ranges, best, 1) : 0u;
+        scan_ranges(a, q32x, q32y, q32z, lane_ranges, total1, best, bj);
+      }
+    }
     if (i < a.n_src) {
       const float bd = __uint_as_float((uint32_t)(best >> 32));
       const uint32_t bo = (uint32_t)best;

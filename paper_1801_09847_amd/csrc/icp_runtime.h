@@ -132,6 +132,7 @@ struct PairIn {
   const float* tgt_n;  // null: point-to-point (normals neither checked nor gathered)
   int64_t n_tgt;
   double r;
+  bool hashed_ok = false;  // the call's kernels accept a hashed grid (the pass does)
 };
 
 // Byte offsets of one call's descriptors; the same layout is used in pinned

@@ -263,7 +263,7 @@ int prepare_level(icp_server* s, std::vector<Req*>& list, std::vector<std::pair<
     if (list.empty()) return ICP_SUCCESS;
     in.clear();
     for (Req* r : list)
-      in.push_back(PairIn{r->ls, r->lns, r->lt, r->ltn, r->lnt, level_dist(s, r, r->level)});
+      in.push_back(PairIn{r->ls, r->lns, r->lt, r->ltn, r->lnt, level_dist(s, r, r->level), true});
     int bad = -1;
     rc = plan_pairs(c, (int)list.size(), in.data(), &P, &bad);
     if (rc == ICP_E_NONFINITE && bad >= 0) {
@@ -340,7 +340,7 @@ int prepare_level(icp_server* s, std::vector<Req*>& list, std::vector<std::pair<
     list.resize(fit);
     in.clear();
     for (Req* r : list)
-      in.push_back(PairIn{r->ls, r->lns, r->lt, r->ltn, r->lnt, level_dist(s, r, r->level)});
+      in.push_back(PairIn{r->ls, r->lns, r->lt, r->ltn, r->lnt, level_dist(s, r, r->level), true});
     int bad = -1;
     if ((rc = plan_pairs(c, (int)list.size(), in.data(), &P, &bad)) != 0) return rc;
   }
@@ -356,7 +356,7 @@ int prepare_level(icp_server* s, std::vector<Req*>& list, std::vector<std::pair<
       return q;
     };
     dst[k].cs = reinterpret_cast<uint32_t*>(take(4 * ((size_t)P.g[k].ncell + 1)));
-    dst[k].occ = reinterpret_cast<uint32_t*>(take(4 * (size_t)occ_words(P.g[k])));
+    dst[k].occ = occ_words(P.g[k]) ? reinterpret_cast<uint32_t*>(take(4 * (size_t)occ_words(P.g[k]))) : nullptr;
     dst[k].tp = reinterpret_cast<float4*>(take(16 * (size_t)r->lnt));
     dst[k].tn = reinterpret_cast<float4*>(take(16 * (size_t)r->lnt));
     dst[k].sx = reinterpret_cast<float*>(take(4 * (size_t)r->lns));

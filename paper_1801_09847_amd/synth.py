@@ -393,6 +393,27 @@ def c3_room(seed: int = 0) -> dict:
     return d
 
 
+def with_far_outliers(d: dict, seed: int = 0, frac: float = 0.01, dist: float = 100.0) -> dict:
+    """The pair with ``frac`` of its target points copied ``dist`` metres away
+    from the target's box centre (uniform directions, with their normals) and
+    appended to the target: a box ~2 dist wide, most of it empty.  The
+    original target points keep their indices; no source point comes within
+    any correspondence distance of the copies."""
+    rng = _rng(seed, "far_outliers")
+    tgt, nrm = d["tgt"], d["tgt_normals"]
+    m = max(1, int(round(frac * len(tgt))))
+    pick = rng.choice(len(tgt), size=m, replace=False)
+    u = rng.normal(size=(m, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    centre = 0.5 * (tgt.min(axis=0).astype(np.float64) + tgt.max(axis=0).astype(np.float64))
+    far = centre + dist * u + (tgt[pick].astype(np.float64) - centre) * 0.01
+    out = dict(d)
+    out["tgt"] = _f32(np.concatenate([tgt, far]))
+    out["tgt_normals"] = _f32(np.concatenate([nrm, nrm[pick]]))
+    out["meta"] = dict(d.get("meta", {}), far_outliers=m, far_dist=dist)
+    return out
+
+
 def loguniform_size(rng: np.random.Generator, lo: float, hi: float) -> int:
     return int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
 

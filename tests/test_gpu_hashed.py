@@ -1,0 +1,143 @@
+"""GPU parity of the hashed cell table, used for target boxes whose dense table
+would be too large.
+
+A target with 1 % of its points copied about 100 m away (synth.with_far_outliers)
+has a box about 200 m wide: at r = 3 cm its dense table would need ~1e11
+cells, so the grid takes the hashed table at the nominal cell edge.
+
+Bars:
+  * correspondences bit-exact against the oracle (indices and pinned float32
+    distances), with the table forced to hashed on ordinary pairs
+    (ICP_GRID_HASH=1, which must not change any result) and on far-outlier
+    targets;
+  * the far-outlier registration bit-identical to that of the same pair
+    without the copies (no query comes near them, so every match, term and
+    sum is the same), and within 1e-5 rad / 1e-6 m of the oracle's with equal
+    inlier and iteration counts;
+  * batched: a far-outlier pair next to ordinary ones gives its alone result.
+The pass time with the hashed table is printed next to the dense one.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1801_09847_amd import synth
+
+sys.path.insert(0, os.path.dirname(__file__))
+from cases import adversarial_sets, pose_error  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def icp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1801_09847_amd import icp as m
+    m.lib()
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _hashed_count(icp, fn):
+    ctx = icp.Context(0)
+    ctx.set_profiling(True)
+    out = fn(ctx)
+    prof = ctx.profile()
+    ctx.close()
+    return out, prof
+
+
+@pytest.mark.parametrize("sub", ["1", "2"])
+def test_adversarial_forced_hash_bit_exact(icp, oracle_lib, sub, monkeypatch):
+    monkeypatch.setenv("ICP_GRID_HASH", "1")
+    monkeypatch.setenv("ICP_GRID_SUB", sub)
+    for name, src, tgt, r in adversarial_sets():
+        idx, d2 = icp.correspondences(dev(src), np.eye(4), dev(tgt), r)
+        oi, of, _ = oracle_lib.correspondences(src, np.eye(4), tgt, r, search=1)
+        np.testing.assert_array_equal(idx.cpu().numpy().astype(np.int64), oi, err_msg=name)
+        np.testing.assert_array_equal(d2.cpu().numpy().view(np.uint32), of.view(np.uint32), err_msg=name)
+
+
+@pytest.mark.parametrize("sub", ["1", "2"])
+def test_c1_forced_hash_equals_dense(icp, oracle_lib, sub, monkeypatch):
+    monkeypatch.setenv("ICP_GRID_SUB", sub)
+    d = synth.c1_heightfield(0)
+    s, t, n = dev(d["src"]), dev(d["tgt"]), dev(d["tgt_normals"])
+    dense = icp.register(s, t, n, np.eye(4), 0.05, 30)
+    monkeypatch.setenv("ICP_GRID_HASH", "1")
+    rng = np.random.default_rng(5)
+    from test_gpu_parity import _small_T
+    for T in (np.eye(4), d["T_gt"], _small_T(rng, 5.0, 0.03), _small_T(rng, 5.0, 0.03) @ d["T_gt"]):
+        idx, d2 = icp.correspondences(s, T, t, 0.05)
+        oi, of, _ = oracle_lib.correspondences(d["src"], T, d["tgt"], 0.05)
+        np.testing.assert_array_equal(idx.cpu().numpy().astype(np.int64), oi)
+        np.testing.assert_array_equal(d2.cpu().numpy().view(np.uint32), of.view(np.uint32))
+    hashed, prof = _hashed_count(icp, lambda ctx: icp.register(s, t, n, np.eye(4), 0.05, 30, ctx=ctx))
+    assert prof["hashed_grids"] == 1
+    assert np.array_equal(dense.T, hashed.T)
+    assert (dense.n_iter, dense.n_inliers, dense.fitness, dense.inlier_rmse) == \
+        (hashed.n_iter, hashed.n_inliers, hashed.fitness, hashed.inlier_rmse)
+
+
+@pytest.fixture(scope="module")
+def far_c2():
+    d = synth.c2_room(0)
+    return d, synth.with_far_outliers(d, seed=0)
+
+
+@pytest.mark.parametrize("variant", ["point_to_plane", "point_to_point"])
+def test_far_outliers_registration(icp, oracle_lib, far_c2, variant):
+    d, f = far_c2
+    r, K = d["max_corr_dist"], d["max_iter"]
+    s = dev(d["src"])
+    t0, n0 = dev(d["tgt"]), dev(d["tgt_normals"])
+    t1, n1 = dev(f["tgt"]), dev(f["tgt_normals"])
+    reg = lambda t, n: (lambda ctx: icp.register(s, t, n, np.eye(4), r, K, 0.0, variant, ctx=ctx))
+    icp.register(s, t1, n1, np.eye(4), r, K, 0.0, variant)  # warm-up (code objects, buffers)
+    base, p0 = _hashed_count(icp, reg(t0, n0))
+    far, p1 = _hashed_count(icp, reg(t1, n1))
+    assert p0["hashed_grids"] == 0 and p1["hashed_grids"] == 1
+    us0 = p0["pass_ms"] * 1e3 / p0["pass_launches"]
+    us1 = p1["pass_ms"] * 1e3 / p1["pass_launches"]
+    print(f"\n{variant}: pass {us0:.1f} us dense (outlier-free), {us1:.1f} us hashed "
+          f"({len(f['tgt']) - len(d['tgt'])} far copies), ratio {us1 / us0:.2f}")
+    assert np.array_equal(base.T, far.T)
+    assert (base.n_iter, base.n_inliers, base.status) == (far.n_iter, far.n_inliers, far.status)
+    o = oracle_lib.icp_register(f["src"], f["tgt"], f["tgt_normals"], np.eye(4), r, K, variant=variant,
+                                search=2)
+    ang, dt = pose_error(far.T, o.T)
+    assert far.n_inliers == o.n_inliers and far.n_iter == o.n_iter and far.status == o.status
+    assert ang <= 1e-5 and dt <= 1e-6, (ang, dt)
+    # the matches at the final pose, bit-exact on a sample
+    idx, d2 = icp.correspondences(s, far.T, t1, r)
+    idx, d2 = idx.cpu().numpy().astype(np.int64), d2.cpu().numpy()
+    sel = np.random.default_rng(3).choice(len(d["src"]), 20000, replace=False)
+    oi, of, _ = oracle_lib.correspondences(d["src"][sel], far.T, f["tgt"], r, search=2)
+    np.testing.assert_array_equal(idx[sel], oi)
+    m = oi >= 0
+    np.testing.assert_array_equal(d2[sel][m].view(np.uint32), of[m].view(np.uint32))
+
+
+def test_far_outliers_batch_equals_alone(icp):
+    pairs = []
+    for k in range(3):
+        d = synth.c1_heightfield(k)
+        if k == 1:
+            d = synth.with_far_outliers(d, seed=k)
+        pairs.append(d)
+    tens = [(dev(d["src"]), dev(d["tgt"]), dev(d["tgt_normals"])) for d in pairs]
+    descs = [icp.make_pair(*t, np.eye(4), 0.05, 20, 0.0) for t in tens]
+    mix, prof = _hashed_count(icp, lambda ctx: icp.register_batch(descs, ctx=ctx))
+    assert prof["hashed_grids"] == 1
+    for k in range(3):
+        alone = icp.register_batch([descs[k]])[0]
+        assert np.array_equal(mix[k].T, alone.T), k
+        assert (mix[k].n_iter, mix[k].n_inliers) == (alone.n_iter, alone.n_inliers)

@@ -95,3 +95,17 @@ def test_pooled_served_requests_numpy_equals_torch():
         assert a["spacing"] == b["spacing"] and np.array_equal(a["G"], b["G"])
         n = a["meta"]["n"]
         assert len(a["tgt"]) == n and 0 < len(a["src"]) <= n
+
+
+def test_far_outliers_keep_the_target():
+    d = synth.c1_heightfield(0)
+    f = synth.with_far_outliers(d, seed=0, frac=0.01, dist=100.0)
+    n = len(d["tgt"])
+    assert len(f["tgt"]) == n + 50 and len(f["tgt_normals"]) == n + 50
+    assert np.array_equal(f["tgt"][:n], d["tgt"]) and np.array_equal(f["src"], d["src"])
+    centre = 0.5 * (d["tgt"].min(0) + d["tgt"].max(0))
+    far = np.linalg.norm(f["tgt"][n:] - centre, axis=1)
+    assert np.all(far > 95.0) and np.all(far < 105.0)
+    # reproducible
+    g = synth.with_far_outliers(d, seed=0, frac=0.01, dist=100.0)
+    assert np.array_equal(f["tgt"], g["tgt"])

@@ -274,7 +274,7 @@ Layout make_layout(int n, int64_t n_items, int64_t total_src, int64_t total_tile
   L.bbox_out = take(sizeof(float) * 16 * n);
   L.jprev = take(sizeof(uint32_t) * (size_t)total_src);
   L.part = take(sizeof(double) * kNumSums * (size_t)total_tiles);
-  L.red = take(sizeof(double) * kNumSums * 64);  // segment sums of a single pair's solve
+  L.red = take(sizeof(double) * kNumSums * kSegs);  // segment sums of a single pair's solve
   L.total = align256(off);
   return L;
 }

@@ -11,6 +11,11 @@ constexpr int kTile = 256;         // queries per block of the pass kernel (one 
 constexpr int kNumSums = 29;       // 21 (J^T J upper) + 6 (J^T r) + sum d2 + count
 constexpr int kSumD2 = 27;
 constexpr int kSumCount = 28;
+// Segments of a pair's tile partials in the two-level reduction (the reduce
+// kernel's blocks; the solve adds the segment sums): 64, or kSegs for pairs
+// of more than 4096 tiles.  Segment sums are stored with a stride of kSegs.
+constexpr int kSegs = 256;
+__host__ __device__ inline int segs_of(int n_blocks) { return n_blocks > 4096 ? kSegs : 64; }
 
 // Uniform voxel grid over the target: cell = floor((p - origin) * inv_h) per
 // axis in float64.  The cell edge is >= r (1 + 2^-10) / sub, so a query's
@@ -301,7 +306,7 @@ hipError_t launch_normals(const NormalArgs& a, int sub, hipStream_t s);
 hipError_t launch_pass(const PassArgs& a, int variant, int precision, bool write_corr, hipStream_t s);
 // Scores of a.n_hyp <= kMaxValidateHyp hypotheses (pass kernel and reduction).
 hipError_t launch_validate(const ValidateArgs& a, int sub, hipStream_t s);
-// Solve of one pair.  `red` (kNumSums * 64 doubles of scratch, or null) lets
+// Solve of one pair.  `red` (kNumSums * kSegs doubles of scratch, or null) lets
 // a pair of many pass blocks reduce its partials with many blocks first; the
 // result is the same bits either way.
 hipError_t launch_solve(const SolveArgs& a, double* red, hipStream_t s);

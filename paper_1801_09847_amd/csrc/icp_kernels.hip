@@ -958,18 +958,18 @@ __device__ void apply_exp(const double* xi, double* T) {
 }
 
 // Two-level partial sum, for pairs of more than kTwoLevel pass blocks: the
-// blocks are cut into kSegs segments of ceil(n / kSegs) consecutive blocks; a
-// segment's sum is taken by 8 lanes (lane j adds blocks j, j + 8, ... of the
-// segment in order, then a fixed xor-shuffle tree), and the solve then adds
-// the kSegs segment sums.  A single pair's segment sums come from a separate
-// many-block kernel (one block's bandwidth would bound the solve); the batched
-// solve computes them in-block with the same function, so a pair gets the
-// same bits in both forms.
-constexpr int kSegs = 64;
+// blocks are cut into S = segs_of(n) segments of ceil(n / S) consecutive
+// blocks; a segment's sum is taken by 8 lanes (lane j adds blocks j, j + 8,
+// ... of the segment in order, then a fixed xor-shuffle tree), and the solve
+// then adds the S segment sums.  A single pair's segment sums come from a
+// separate many-block kernel (one block's bandwidth would bound the solve);
+// the batched solve computes them in-block with the same function, so a pair
+// gets the same bits in both forms.
 constexpr int kTwoLevel = 512;
 
 __device__ double segment_sum(const ICP_G double* row, int n_blocks, int s, int j) {
-  const int len = (n_blocks + kSegs - 1) / kSegs;
+  const int segs = segs_of(n_blocks);
+  const int len = (n_blocks + segs - 1) / segs;
   const int b1 = min(n_blocks, (s + 1) * len);
   double acc = 0.0;
   for (int b = s * len + j; b < b1; b += 8) acc = acc + row[b];
@@ -1011,15 +1011,16 @@ __device__ void solve_body(const SolveArgs& a, const double* red) {
   if (a.n_blocks <= kTwoLevel) {
     if (v < kNumSums) acc = row_share(glb(a.part) + (int64_t)v * a.n_blocks, a.n_blocks, g);
   } else if (red) {
-    if (v < kNumSums) acc = row_share(glb(red) + v * kSegs, kSegs, g);
+    if (v < kNumSums) acc = row_share(glb(red) + v * kSegs, segs_of(a.n_blocks), g);
   } else {
-    for (int idx = t >> 3; idx < kNumSums * kSegs; idx += (int)(blockDim.x >> 3)) {
-      const int vv = idx / kSegs;
-      const double x = segment_sum(glb(a.part) + (int64_t)vv * a.n_blocks, a.n_blocks, idx % kSegs, t & 7);
-      if ((t & 7) == 0) sred[idx] = x;
+    const int segs = segs_of(a.n_blocks);
+    for (int idx = t >> 3; idx < kNumSums * segs; idx += (int)(blockDim.x >> 3)) {
+      const int vv = idx / segs, sg = idx % segs;
+      const double x = segment_sum(glb(a.part) + (int64_t)vv * a.n_blocks, a.n_blocks, sg, t & 7);
+      if ((t & 7) == 0) sred[vv * kSegs + sg] = x;
     }
     __syncthreads();
-    if (v < kNumSums) acc = row_share(static_cast<const double*>(sred) + v * kSegs, kSegs, g);
+    if (v < kNumSums) acc = row_share(static_cast<const double*>(sred) + v * kSegs, segs, g);
   }
 #pragma unroll
   for (int off = 16; off > 0; off >>= 1) acc = acc + __shfl_xor(acc, off, kWave);
@@ -1659,7 +1660,7 @@ hipError_t launch_validate(const ValidateArgs& a, int sub, hipStream_t s) {
 
 hipError_t launch_solve(const SolveArgs& a, double* red, hipStream_t s) {
   if (red && a.n_blocks > kTwoLevel) {
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3(kSegs), dim3(256), 0, s, a, red);
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)segs_of(a.n_blocks)), dim3(256), 0, s, a, red);
   } else {
     red = nullptr;
   }

@@ -103,10 +103,19 @@ const char *icp_last_error(void);
 
 /* Creates a context on `device` bound to `hip_stream` (a hipStream_t; NULL
  * makes the context create and own a default-priority stream).  The context
- * owns its device workspace, which grows on demand and is reused across calls.
+ * owns its device workspace:
+ *   arena_bytes == 0: buffers grow on demand (hipMalloc inside the calls that
+ *                     need more than before) and are reused across calls;
+ *   arena_bytes > 0:  one device allocation of arena_bytes now, and pinned
+ *                     host staging of arena_bytes / 256 (at least 16 MiB, at
+ *                     most 256 MiB); every call carves its buffers from
+ *                     them afresh and allocates nothing, and a call that
+ *                     does not fit returns ICP_E_OOM (the context stays
+ *                     usable).  A 2M/2M point-to-plane registration needs
+ *                     about 0.5 GB.
  * *out receives the handle.  Errors: INVALID_ARG (out NULL, bad device),
- * DEVICE. */
-int icp_ctx_create(int device, void *hip_stream, icp_ctx_t **out);
+ * OOM (arena), DEVICE. */
+int icp_ctx_create(int device, void *hip_stream, size_t arena_bytes, icp_ctx_t **out);
 
 /* Releases the context and all device memory it owns.  NULL is a no-op. */
 int icp_ctx_destroy(icp_ctx_t *ctx);

@@ -41,7 +41,7 @@ int hip_fail(hipError_t e, const char* what) {
   return fail(code, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-int ctx_init(icp_ctx* c, int device, void* stream) {
+int ctx_init(icp_ctx* c, int device, void* stream, size_t arena_bytes) {
   c->device = device;
   DeviceGuard g(device);
   if (!g.ok) return fail(ICP_E_DEVICE, "cannot select device " + std::to_string(device));
@@ -51,19 +51,28 @@ int ctx_init(icp_ctx* c, int device, void* stream) {
     HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking), "hipStreamCreate");
     c->own_stream = true;
   }
-  HIP_TRY(hipHostMalloc(&c->host, kHostBytes, hipHostMallocDefault), "hipHostMalloc");
-  c->host_cap = kHostBytes;
+  size_t host_bytes = kHostBytes;
+  if (arena_bytes > 0) {
+    // one device allocation for the context's life; pinned staging sized
+    // with it (a call's descriptors and results are far smaller than its
+    // device buffers)
+    HIP_TRY(hipMalloc(reinterpret_cast<void**>(&c->arena.base), arena_bytes), "hipMalloc (arena)");
+    c->arena.size = arena_bytes;
+    c->fixed = true;
+    for_each_buf(c, [c](Buf& b) { b.arena = &c->arena; });
+    host_bytes = std::min<size_t>(std::max<size_t>(arena_bytes / 256, (size_t)16 << 20), (size_t)256 << 20);
+  }
+  HIP_TRY(hipHostMalloc(&c->host, host_bytes, hipHostMallocDefault), "hipHostMalloc");
+  c->host_cap = host_bytes;
   return ICP_SUCCESS;
 }
 
 void ctx_free(icp_ctx* c) {
   DeviceGuard g(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
-  Buf* bufs[] = {&c->desc, &c->bbox_part, &c->t_key, &c->t_rank, &c->scan_tmp, &c->s_hist,
-                 &c->cs, &c->occ_raw, &c->occ, &c->tp, &c->tn, &c->sx, &c->sy, &c->sz, &c->perm, &c->vdesc,
-                 &c->vflags, &c->vstarts, &c->lvl_src, &c->lvl_tgt, &c->lvl_tn, &c->pg, &c->rs};
-  for (Buf* b : bufs) b->release();
-  for (Buf& b : c->sk) b.release();
+  for_each_buf(c, [](Buf& b) { b.release(); });
+  if (c->arena.base) (void)hipFree(c->arena.base);
+  c->arena = Arena{};
   if (c->host) (void)hipHostFree(c->host);
   c->host = nullptr;
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
@@ -91,6 +100,11 @@ thread_local DefaultCtx g_default;
 int resolve_ctx(icp_ctx* in, icp_ctx** out) {
   if (in) {
     *out = in;
+    // a new call: the arena's buffers are carved afresh
+    if (in->fixed) {
+      in->arena.top = 0;
+      ++in->arena.epoch;
+    }
     return ICP_SUCCESS;
   }
   int dev = 0;
@@ -112,6 +126,9 @@ int resolve_ctx(icp_ctx* in, icp_ctx** out) {
 
 int ensure_host(icp_ctx* c, size_t bytes) {
   if (bytes <= c->host_cap) return ICP_SUCCESS;
+  if (c->fixed)
+    return fail(ICP_E_OOM, "call needs " + std::to_string(bytes) + " bytes of pinned staging; the context's is " +
+                               std::to_string(c->host_cap) + " (arena_bytes / 256, at least 16 MiB)");
   HIP_TRY(hipStreamSynchronize(c->stream), "sync");
   if (c->host) (void)hipHostFree(c->host);
   c->host = nullptr;
@@ -797,13 +814,13 @@ const char* icp_strerror(int code) {
 
 const char* icp_last_error(void) { return g_last_error.c_str(); }
 
-int icp_ctx_create(int device, void* hip_stream, icp_ctx_t** out) {
+int icp_ctx_create(int device, void* hip_stream, size_t arena_bytes, icp_ctx_t** out) {
   if (!out) return fail(ICP_E_INVALID_ARG, "out is NULL");
   int n = 0;
   HIP_TRY(hipGetDeviceCount(&n), "hipGetDeviceCount");
   if (device < 0 || device >= n) return fail(ICP_E_INVALID_ARG, "device index out of range");
   icp_ctx* c = new icp_ctx();
-  const int rc = ctx_init(c, device, hip_stream);
+  const int rc = ctx_init(c, device, hip_stream, arena_bytes);
   if (rc != ICP_SUCCESS) {
     ctx_free(c);
     delete c;

@@ -26,11 +26,42 @@ int hip_fail(hipError_t e, const char* what);
     if (e_ != hipSuccess) return ::icp_rt::hip_fail(e_, what); \
   } while (0)
 
-// A device buffer that only grows (reused across calls).
+// Fixed device arena of a context created with arena_bytes > 0: the
+// buffers of a call are carved from it in turn (a bump pointer that the
+// start of every call resets), so calls allocate no device memory, and a call
+// whose buffers do not fit fails with ICP_E_OOM.  Resetting at the start of a
+// call is safe: every kernel of the context runs on its stream, so the next
+// call's work is ordered after the previous call's.
+struct Arena {
+  char* base = nullptr;
+  size_t size = 0;
+  size_t top = 0;
+  uint64_t epoch = 1;  // call counter: a buffer carved in an older call is stale
+};
+
+// A device buffer: without an arena it only grows (hipMalloc, reused across
+// calls); with one it is carved from the arena once per call.
 struct Buf {
   void* p = nullptr;
   size_t cap = 0;
+  Arena* arena = nullptr;
+  uint64_t epoch = 0;
   hipError_t ensure(size_t bytes) {
+    if (arena) {
+      if (p && bytes <= cap && epoch == arena->epoch) return hipSuccess;
+      const size_t off = (arena->top + 255) & ~(size_t)255;
+      const size_t want = std::max<size_t>(bytes, 256);
+      if (off > arena->size || want > arena->size - off) {
+        p = nullptr;
+        cap = 0;
+        return hipErrorOutOfMemory;
+      }
+      p = arena->base + off;
+      cap = want;
+      epoch = arena->epoch;
+      arena->top = off + want;
+      return hipSuccess;
+    }
     if (bytes <= cap && p) return hipSuccess;
     if (p) {
       hipError_t e = hipFree(p);
@@ -48,7 +79,7 @@ struct Buf {
     return hipSuccess;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p && !arena) (void)hipFree(p);
     p = nullptr;
     cap = 0;
   }
@@ -84,6 +115,9 @@ struct icp_ctx {
   icp_rt::Buf rs;
   void* host = nullptr;  // pinned staging
   size_t host_cap = 0;
+  // fixed device arena (arena_bytes > 0 at creation), else growing buffers
+  icp_rt::Arena arena;
+  bool fixed = false;
   // kernel timing
   bool profiling = false;
   std::vector<hipEvent_t> ev;  // [0] call start, [1] call end, [2+2k]/[3+2k] around pass k
@@ -105,7 +139,16 @@ struct DeviceGuard {
   }
 };
 
-int ctx_init(icp_ctx* c, int device, void* stream);
+int ctx_init(icp_ctx* c, int device, void* stream, size_t arena_bytes = 0);
+// Every buffer of a context (arena wiring, release).
+template <class F>
+void for_each_buf(icp_ctx* c, F f) {
+  Buf* bufs[] = {&c->desc, &c->bbox_part, &c->t_key, &c->t_rank, &c->scan_tmp, &c->s_hist,
+                 &c->cs, &c->occ_raw, &c->occ, &c->tp, &c->tn, &c->sx, &c->sy, &c->sz, &c->perm, &c->vdesc,
+                 &c->vflags, &c->vstarts, &c->lvl_src, &c->lvl_tgt, &c->lvl_tn, &c->pg, &c->rs};
+  for (Buf* b : bufs) f(*b);
+  for (Buf& b : c->sk) f(b);
+}
 // The given context, or this thread's default context of the current device.
 int resolve_ctx(icp_ctx* in, icp_ctx** out);
 // Cells per max_corr_dist along an axis for every grid this process builds.

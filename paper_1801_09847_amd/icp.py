@@ -130,7 +130,7 @@ def lib():
         L.icp_strerror.restype = C.c_char_p
         L.icp_strerror.argtypes = [C.c_int]
         L.icp_last_error.restype = C.c_char_p
-        L.icp_ctx_create.argtypes = [C.c_int, vp, C.POINTER(vp)]
+        L.icp_ctx_create.argtypes = [C.c_int, vp, C.c_size_t, C.POINTER(vp)]
         L.icp_ctx_destroy.argtypes = [vp]
         L.icp_register.argtypes = [vp, vp, i64, vp, vp, i64, vp, dbl, i32, dbl, i32, i32,
                                    C.POINTER(icp_result_t)]
@@ -213,9 +213,9 @@ def icp_version() -> str:
     return lib().icp_version().decode()
 
 
-def icp_ctx_create(device: int, hip_stream: int | None) -> int:
+def icp_ctx_create(device: int, hip_stream: int | None, arena_bytes: int = 0) -> int:
     h = C.c_void_p()
-    _check(lib().icp_ctx_create(int(device), hip_stream or None, C.byref(h)))
+    _check(lib().icp_ctx_create(int(device), hip_stream or None, int(arena_bytes), C.byref(h)))
     return h.value
 
 
@@ -292,15 +292,16 @@ def _dev_pts(t, name):
 
 class Context:
     """Owns an icp_ctx_t bound to a device and a HIP stream (default: torch's
-    current stream of that device)."""
+    current stream of that device); arena_bytes > 0 gives it one fixed device
+    arena, from which every call carves its buffers without allocating."""
 
-    def __init__(self, device: int = 0, stream=None):
+    def __init__(self, device: int = 0, stream=None, arena_bytes: int = 0):
         import torch
         if stream is None:
             stream = torch.cuda.current_stream(device)
         self.device = device
         self.stream = stream
-        self.handle = icp_ctx_create(device, stream.cuda_stream if stream is not None else None)
+        self.handle = icp_ctx_create(device, stream.cuda_stream if stream is not None else None, arena_bytes)
 
     def set_profiling(self, enable: bool) -> None:
         _check(lib().icp_ctx_set_profiling(self.handle, 1 if enable else 0))

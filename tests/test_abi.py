@@ -96,7 +96,7 @@ def test_null_out_and_hooks_validation():
     with pytest.raises(icp.IcpError) as e:
         icp.icp_normal_equations(None, FAKE, 10, T, FAKE, None, 10, 0.1, 1, 0)
     assert e.value.code == icp.ICP_E_INVALID_ARG
-    rc = L.icp_ctx_create(0, None, None)
+    rc = L.icp_ctx_create(0, None, 0, None)
     assert rc == icp.ICP_E_INVALID_ARG
     assert L.icp_ctx_destroy(None) == 0
 

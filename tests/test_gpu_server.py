@@ -245,3 +245,33 @@ def test_server_submit_orders_after_producer_stream(icp, requests):
         t = srv.submit(src, tgt, nrm, spacing=d["spacing"])
     _same(srv.wait(t), plain)
     srv.close()
+
+
+def test_server_far_outlier_request_equals_plain(icp, requests):
+    """A request whose target has 1 % of its points 100 m away takes hashed
+    cell tables at every level, in the server as alone."""
+    reqs = [requests[0], synth.with_far_outliers(requests[1], seed=1), requests[4]]
+    reqs[1]["spacing"] = requests[1]["spacing"]
+    ctx = icp.Context(0)
+    ctx.set_profiling(True)
+    d = reqs[1]
+    dists = [2.0 * max(v, d["spacing"]) for v in VOX]
+    icp.register_multiscale(dev(d["src"]), dev(d["tgt"]), dev(d["tgt_normals"]), np.eye(4), VOX, ITS, dists,
+                            ctx=ctx)
+    assert ctx.profile()["hashed_grids"] == len(VOX)
+    ctx.close()
+    plain = [_plain(icp, d) for d in reqs]
+    srv = icp.Server(VOX, ITS, max_slots=4, budget_bytes=1 << 30, iters_per_step=3)
+    tickets = {}
+    for k, d in enumerate(reqs):
+        tickets[srv.submit(dev(d["src"]), dev(d["tgt"]), dev(d["tgt_normals"]), spacing=d["spacing"], tag=k)] = k
+    done = []
+    for _ in range(500):
+        srv.step()
+        done += srv.poll()
+        if len(done) == len(reqs):
+            break
+    srv.close()
+    assert len(done) == len(reqs)
+    for c in done:
+        _same(c, plain[tickets[c.ticket]])

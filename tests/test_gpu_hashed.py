@@ -141,3 +141,22 @@ def test_far_outliers_batch_equals_alone(icp):
         alone = icp.register_batch([descs[k]])[0]
         assert np.array_equal(mix[k].T, alone.T), k
         assert (mix[k].n_iter, mix[k].n_inliers) == (alone.n_iter, alone.n_inliers)
+
+
+@pytest.mark.parametrize("far", [1.0e3, 1.0e6])
+def test_extreme_extent_bit_exact(icp, oracle_lib, far):
+    """One target point 1 km or 1000 km away: the hashed table holds the box
+    at the nominal cell edge (1 km) or, past 2^24 cells per axis, at a grown
+    one (1000 km); either way the matches are the oracle's."""
+    rng = np.random.default_rng(7)
+    for name, src, tgt, r in adversarial_sets():
+        t = np.concatenate([tgt, np.array([[far, -0.5 * far, 0.25 * far]], np.float32)])
+        T = np.eye(4)
+        T[:3, 3] = rng.uniform(-0.01, 0.01, 3)
+        ctx = icp.Context(0)
+        ctx.set_profiling(True)
+        idx, d2 = icp.correspondences(dev(src), T, dev(t), r, ctx=ctx)
+        ctx.close()
+        oi, of, _ = oracle_lib.correspondences(src, T, t, r, search=1)
+        np.testing.assert_array_equal(idx.cpu().numpy().astype(np.int64), oi, err_msg=name)
+        np.testing.assert_array_equal(d2.cpu().numpy().view(np.uint32), of.view(np.uint32), err_msg=name)

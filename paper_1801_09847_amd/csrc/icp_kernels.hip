@@ -1111,12 +1111,20 @@ __global__ void gather_states_kernel(const SolveArgs* __restrict__ arr, int n, I
 // A query's candidates are staged as row ranges exactly as in the pass.  Up to
 // three scans follow, each with eight candidate loads in flight per lane:
 // count the points within the radius; only when that exceeds max_nn, a
-// max-heap of max_nn keys in LDS (this lane's column of the block's heap
-// array) finds the max_nn-th smallest key; then the covariance sums over the
-// keys not above it.  (A single scan that pushes every point within the
+// max-heap of the max_nn smallest squared distances (32-bit, this lane's
+// column of the block's heap array in LDS) finds the max_nn-th smallest
+// distance t; then the covariance sums over the points with d^2 <= t.  The
+// neighbourhood is the max_nn smallest (d^2, index) keys: the heap's entries
+// below t are all the points closer than t, and its entries equal to t are
+// how many of the points at exactly t belong to it.  The third scan counts
+// the points at t; in the rare case that there are more than that, the
+// belonging ones are the smallest indices among them, found by one more heap
+// pass over indices, and the sums are taken again with that rule.  (A 64-bit
+// key heap halves the blocks that fit in a CU's LDS and took 3.06 against
+// 2.26 ms on 2M points; a single scan that pushes every point within the
 // radius through a heap of (key, position) entries and gathers the
-// neighbourhood from it measured slower: the heap traffic, not the candidate
-// loads, is the cost, and the common sparse case then pays it too.)
+// neighbourhood from it measured slower still: the heap traffic, not the
+// candidate loads, is the cost.)
 
 // Visits the `total` candidates of the lane's staged ranges in order, loading
 // kChunk of them before using any.
@@ -1212,7 +1220,7 @@ __device__ inline void least_eigvec3(double (&a)[3][3], double out[3]) {
 
 template <int R>
 __global__ __launch_bounds__(kNormBlock) void normals_kernel(NormalArgs na) {
-  extern __shared__ uint64_t nheap[];  // [max_nn][kNormBlock]: each lane's heap is a column
+  extern __shared__ uint32_t nheap[];  // [max_nn][kNormBlock]: each lane's heap is a column
   __shared__ __align__(16) uint32_t nscratch[kNormBlock / kWave][WaveScratch<R>::kRangeWords];
   const int w = threadIdx.x / kWave, lane = lane_id();
   uint2* lane_ranges = reinterpret_cast<uint2*>(nscratch[w]) + lane;
@@ -1238,64 +1246,90 @@ __global__ __launch_bounds__(kNormBlock) void normals_kernel(NormalArgs na) {
     within += dist2(p) <= r2f ? 1u : 0u;
   });
   const uint32_t K = (uint32_t)na.max_nn;
-  uint64_t kth = ~0ull;
+  uint32_t* H = nheap + threadIdx.x;  // H[k * kNormBlock]
+  // Max-heap of the K smallest of a stream of 32-bit values (squared
+  // distance bits, or indices); non-negative float bits order as integers.
+  auto heap_push = [&](uint32_t& size, uint32_t cap, uint32_t key) {
+    if (size < cap) {
+      uint32_t at = size++;
+      while (at > 0) {  // sift up
+        const uint32_t up = (at - 1) >> 1;
+        const uint32_t hu = H[up * kNormBlock];
+        if (hu >= key) break;
+        H[at * kNormBlock] = hu;
+        at = up;
+      }
+      H[at * kNormBlock] = key;
+    } else if (key < H[0]) {
+      uint32_t at = 0;
+      for (;;) {  // sift down from the root
+        const uint32_t l = 2 * at + 1;
+        if (l >= cap) break;
+        uint32_t c = l;
+        uint32_t hc = H[l * kNormBlock];
+        if (l + 1 < cap) {
+          const uint32_t hr = H[(l + 1) * kNormBlock];
+          if (hr > hc) {
+            c = l + 1;
+            hc = hr;
+          }
+        }
+        if (hc <= key) break;
+        H[at * kNormBlock] = hc;
+        at = c;
+      }
+      H[at * kNormBlock] = key;
+    }
+  };
+  // selection: d^2 bits below t, or equal to t with index at most tidx
+  uint32_t t = 0xffffffffu, tidx = 0xffffffffu, need = 0;
   if (within > K) {
-    uint64_t* H = nheap + threadIdx.x;  // H[k * kNormBlock]
     uint32_t size = 0;
     for_each_candidate(na.tp, lane_ranges, total, [&](const float4& p, uint32_t) {
       const float d2 = dist2(p);
-      if (!(d2 <= r2f)) return;
-      const uint64_t key = ((uint64_t)__float_as_uint(d2) << 32) | (uint64_t)__float_as_uint(p.w);
-      if (size < K) {
-        uint32_t at = size++;
-        while (at > 0) {  // sift up
-          const uint32_t up = (at - 1) >> 1;
-          const uint64_t hu = H[up * kNormBlock];
-          if (hu >= key) break;
-          H[at * kNormBlock] = hu;
-          at = up;
-        }
-        H[at * kNormBlock] = key;
-      } else if (key < H[0]) {
-        uint32_t at = 0;
-        for (;;) {  // sift down from the root
-          const uint32_t l = 2 * at + 1;
-          if (l >= K) break;
-          uint32_t c = l;
-          uint64_t hc = H[l * kNormBlock];
-          if (l + 1 < K) {
-            const uint64_t hr = H[(l + 1) * kNormBlock];
-            if (hr > hc) {
-              c = l + 1;
-              hc = hr;
-            }
-          }
-          if (hc <= key) break;
-          H[at * kNormBlock] = hc;
-          at = c;
-        }
-        H[at * kNormBlock] = key;
-      }
+      if (d2 <= r2f) heap_push(size, K, __float_as_uint(d2));
     });
-    kth = H[0];
+    t = H[0];
+    for (uint32_t k = 0; k < K; ++k) need += H[k * kNormBlock] == t ? 1u : 0u;
   }
 
   // float64 sums of the selected points, relative to the query point
   double s1x = 0.0, s1y = 0.0, s1z = 0.0;
   double sxx = 0.0, sxy = 0.0, sxz = 0.0, syy = 0.0, syz = 0.0, szz = 0.0;
-  uint32_t m = 0;
-  for_each_candidate(na.tp, lane_ranges, total, [&](const float4& p, uint32_t) {
-    const float d2 = dist2(p);
-    if (!(d2 <= r2f)) return;
-    const uint64_t key = ((uint64_t)__float_as_uint(d2) << 32) | (uint64_t)__float_as_uint(p.w);
-    if (key > kth) return;
-    const double dx = (double)p.x - (double)qx, dy = (double)p.y - (double)qy,
-                 dz = (double)p.z - (double)qz;
-    s1x += dx; s1y += dy; s1z += dz;
-    sxx += dx * dx; sxy += dx * dy; sxz += dx * dz;
-    syy += dy * dy; syz += dy * dz; szz += dz * dz;
-    ++m;
-  });
+  uint32_t m = 0, at_t = 0;
+  auto sums = [&](bool count_ties) {
+    s1x = s1y = s1z = 0.0;
+    sxx = sxy = sxz = syy = syz = szz = 0.0;
+    m = 0;
+    for_each_candidate(na.tp, lane_ranges, total, [&](const float4& p, uint32_t) {
+      const float d2 = dist2(p);
+      if (!(d2 <= r2f)) return;
+      const uint32_t db = __float_as_uint(d2);
+      if (db > t) return;
+      if (db == t) {
+        if (count_ties) ++at_t;
+        if (__float_as_uint(p.w) > tidx) return;
+      }
+      const double dx = (double)p.x - (double)qx, dy = (double)p.y - (double)qy,
+                   dz = (double)p.z - (double)qz;
+      s1x += dx; s1y += dy; s1z += dz;
+      sxx += dx * dx; sxy += dx * dy; sxz += dx * dz;
+      syy += dy * dy; syz += dy * dz; szz += dz * dz;
+      ++m;
+    });
+  };
+  sums(within > K);
+  if (within > K && at_t > need) {
+    // more points at exactly t than belong: the `need` smallest indices
+    // among them, the largest of which is the root of a heap of that size
+    uint32_t size = 0;
+    for_each_candidate(na.tp, lane_ranges, total, [&](const float4& p, uint32_t) {
+      const float d2 = dist2(p);
+      if (d2 <= r2f && __float_as_uint(d2) == t) heap_push(size, need, __float_as_uint(p.w));
+    });
+    tidx = H[0];
+    sums(false);
+  }
   double nrm[3] = {0.0, 0.0, 0.0};
   if (m >= 3) {
     const double inv = 1.0 / (double)m;
@@ -1695,7 +1729,7 @@ hipError_t launch_normals(const NormalArgs& a, int sub, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
   if (a.max_nn < 1 || a.max_nn > kMaxNormalNN) return hipErrorInvalidValue;
   const dim3 grid((unsigned)ceil_div(a.n, kNormBlock)), block(kNormBlock);
-  const size_t heap = sizeof(uint64_t) * (size_t)a.max_nn * kNormBlock;
+  const size_t heap = sizeof(uint32_t) * (size_t)a.max_nn * kNormBlock;
   if (sub == 2)
     hipLaunchKernelGGL(normals_kernel<2>, grid, block, heap, s, a);
   else

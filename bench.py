@@ -842,6 +842,11 @@ def main():
                    "status": res.status},
         # grid build + source ordering of the timed step: 52 algorithmic bytes
         # per target point (xyz + normal in, cell-ordered point + index out)
+        # the ICP loop alone (first to last pass launch of the profiled step,
+        # HIP events on the context stream): every pass and solve, no build
+        "loop_only": {"ms": prof["call_ms"] / max(1, prof["calls"]),
+                      "corr_evals_per_s": (res.n_iter + 1) * len(data["src"]) /
+                      (prof["call_ms"] / max(1, prof["calls"]) * 1e-3) if prof["call_ms"] > 0 else None},
         "grid_build": {"ms": prof["build_ms"], "target_points": prof["build_points"],
                        "alg_gbs": 52.0 * prof["build_points"] / (prof["build_ms"] * 1e-3) / 1e9
                        if prof["build_ms"] > 0 else None},

@@ -321,11 +321,14 @@ __global__ __launch_bounds__(256) void seg_target_key_kernel(const BuildPair* __
   }
 }
 
-// Occupancy of a hashed grid, dilated as it is built: after the scatter, the
-// first point of each cell among its slot's points (slots are shared, ranks
-// count per slot) sets the slots of the in-grid cells around its cell, per
-// row one mask for each run that the row's x segment touches (a run's slots
-// are consecutive bits of one word).
+// Occupancy of a hashed grid, dilated as it is built: after the scatter, a
+// point sets the slots of the in-grid cells around its cell, per row one mask
+// for each run that the row's x segment touches (a run's slots are
+// consecutive bits of one word), unless one of the (at most 64) points before
+// it among its slot's points lies in the same cell.  The first point of every
+// cell always sets them, and setting a bit twice changes nothing, so the bound
+// only limits the work per point (a cell of many points costs each of them
+// 64 comparisons).
 __global__ __launch_bounds__(256) void seg_hashed_occ_kernel(const BuildPair* __restrict__ pairs, int n,
                                                              const int64_t* __restrict__ blk_off,
                                                              uint32_t* __restrict__ occ_raw) {
@@ -342,7 +345,8 @@ __global__ __launch_bounds__(256) void seg_hashed_occ_kernel(const BuildPair* __
   int c[3];
   cell(bp.tp_dst[j], c);
   const uint32_t slot0 = hashed_slot(g, c[0], c[1], c[2]);
-  for (int64_t k = bp.cs_dst[slot0]; k < j; ++k) {
+  const int64_t first = bp.cs_dst[slot0];
+  for (int64_t k = j - 64 > first ? j - 64 : first; k < j; ++k) {
     int o[3];
     cell(bp.tp_dst[k], o);
     if (o[0] == c[0] && o[1] == c[1] && o[2] == c[2]) return;  // not the cell's first point

@@ -160,3 +160,21 @@ def test_extreme_extent_bit_exact(icp, oracle_lib, far):
         oi, of, _ = oracle_lib.correspondences(src, T, t, r, search=1)
         np.testing.assert_array_equal(idx.cpu().numpy().astype(np.int64), oi, err_msg=name)
         np.testing.assert_array_equal(d2.cpu().numpy().view(np.uint32), of.view(np.uint32), err_msg=name)
+
+
+def test_hashed_many_points_in_one_cell(icp, oracle_lib, monkeypatch):
+    """20k copies of one target point among 5k others, hashed table forced:
+    the build stays linear (each point compares with at most 64 earlier
+    points of its slot) and the matches are the oracle's."""
+    monkeypatch.setenv("ICP_GRID_HASH", "1")
+    rng = np.random.default_rng(11)
+    tgt = np.concatenate([rng.uniform(0, 1, (5000, 3)), np.tile([[0.5, 0.5, 0.5]], (20000, 1))]).astype(np.float32)
+    tgt = tgt[rng.permutation(len(tgt))]
+    src = rng.uniform(0.4, 0.6, (3000, 3)).astype(np.float32)
+    ctx = icp.Context(0)
+    ctx.set_profiling(True)
+    idx, d2 = icp.correspondences(dev(src), np.eye(4), dev(tgt), 0.03, ctx=ctx)
+    ctx.close()
+    oi, of, _ = oracle_lib.correspondences(src, np.eye(4), tgt, 0.03, search=1)
+    np.testing.assert_array_equal(idx.cpu().numpy().astype(np.int64), oi)
+    np.testing.assert_array_equal(d2.cpu().numpy().view(np.uint32), of.view(np.uint32))

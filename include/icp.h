@@ -113,6 +113,8 @@ const char *icp_last_error(void);
  *                     does not fit returns ICP_E_OOM (the context stays
  *                     usable).  A 2M/2M point-to-plane registration needs
  *                     about 0.5 GB.
+ * A context serves one call at a time: calls on one context from several
+ * threads must be serialised by the caller (use one context per thread).
  * *out receives the handle.  Errors: INVALID_ARG (out NULL, bad device),
  * OOM (arena), DEVICE. */
 int icp_ctx_create(int device, void *hip_stream, size_t arena_bytes, icp_ctx_t **out);

@@ -607,6 +607,7 @@ typedef struct {
   int64_t builds;
   int64_t build_points;      /* target points built (summed over the calls' pairs) */
   int64_t hashed_grids;      /* pairs whose target grid got a hashed cell table */
+  int64_t fine_grids;        /* pairs whose grid took two cells per radius */
 } icp_profile_t;
 
 /* Enables (1) or disables (0) kernel timing on ctx; resets the counters.

@@ -205,12 +205,27 @@ double grid_scale() {
 }
 
 // Cells per max_corr_dist along an axis (1: 27-cell neighbourhood, 2: 125
-// smaller cells).  ICP_GRID_SUB overrides the default (debugging and tests).
-int grid_sub() {
+// smaller cells).  ICP_GRID_SUB overrides the default and the density choice
+// (debugging and tests).
+int grid_sub_env() {
   const char* e = getenv("ICP_GRID_SUB");
   if (e && atoi(e) == 1) return 1;
   if (e && atoi(e) == 2) return 2;
-  return kDefaultSub;
+  return 0;
+}
+
+int grid_sub() {
+  const int e = grid_sub_env();
+  return e ? e : kDefaultSub;
+}
+
+// True when the target holds at least kFineSubPoints points per cell of the
+// one-cell-per-radius grid over its box.
+bool dense_target(const float* mn, const float* mx, double r, int64_t n_tgt) {
+  const double inv_h = 1.0 / (r * (1.0 + 1.0 / 1024.0) * grid_scale());
+  double cells = 1.0;
+  for (int a = 0; a < 3; ++a) cells *= floor(((double)mx[a] - (double)mn[a]) * inv_h) + 1.0;
+  return (double)n_tgt >= kFineSubPoints * cells;
 }
 
 // ICP_GRID_HASH=1 (debugging and tests only) gives every grid that may be
@@ -228,11 +243,10 @@ bool grid_force_hash() {
 // else a grown h (still exact: any h above the bound works, only the
 // candidate count changes).  A hashed grid still grows h if an axis would
 // exceed 2^24 cells.
-GridDesc make_grid(const float* mn, const float* mx, double r, int64_t n_tgt, bool hashed_ok) {
+GridDesc make_grid(const float* mn, const float* mx, double r, int64_t n_tgt, bool hashed_ok, int sub) {
   // below 2^30 entries: the pass addresses the table with 32-bit byte offsets
   const double cap = std::min<double>(1073741824.0 - 1024.0, std::max<double>(16777216.0, 32.0 * (double)n_tgt));
   const double axis_cap = 16777216.0;
-  const int sub = grid_sub();
   const bool force = hashed_ok && grid_force_hash();
   double h = r * (1.0 + 1.0 / 1024.0) * grid_scale() / sub;
   GridDesc g{};
@@ -372,10 +386,20 @@ int plan_pairs(icp_ctx* c, int n, const PairIn* in, Prep* P, int* bad) {
   bs[0] = 0;
   bk[0] = 0;
   bo2[0] = 0;
+  // one cell size per call (the batched kernels take it as a template
+  // argument): two cells per radius only if every pair allows it and has a
+  // dense target
+  int sub = grid_sub();
+  if (!grid_sub_env()) {
+    bool fine = true;
+    for (int p = 0; p < n && fine; ++p)
+      fine = in[p].fine_ok && dense_target(hbox + 16 * p, hbox + 16 * p + 3, in[p].r, in[p].n_tgt);
+    if (fine) sub = 2;
+  }
   for (int p = 0; p < n; ++p) {
     const float* t = hbox + 16 * p;
     const float* q = t + 8;
-    P->g[p] = make_grid(t, t + 3, in[p].r, in[p].n_tgt, in[p].hashed_ok);
+    P->g[p] = make_grid(t, t + 3, in[p].r, in[p].n_tgt, in[p].hashed_ok, sub);
     P->tab_off[p + 1] = P->tab_off[p] + (uint64_t)P->g[p].ncell + 1;
     double ext = 0.0;
     for (int a = 0; a < 3; ++a) ext = std::max(ext, (double)q[3 + a] - (double)q[a]);
@@ -495,7 +519,10 @@ int build_pairs(icp_ctx* c, Prep* P, const PairDst* dst) {
   if (c->profiling) {
     HIP_TRY(hipEventRecord(c->ev_build[1], s), "hipEventRecord");
     c->build_pending = P->total_tgt;
-    for (int p = 0; p < n; ++p) c->prof.hashed_grids += P->g[p].hashed;
+    for (int p = 0; p < n; ++p) {
+      c->prof.hashed_grids += P->g[p].hashed;
+      c->prof.fine_grids += P->g[p].sub == 2;
+    }
   }
   return ICP_SUCCESS;
 }
@@ -873,7 +900,7 @@ int icp_register_robust(icp_ctx_t* ctx, const float* src_xyz, int64_t n_src, con
   if ((rc = resolve_ctx(ctx, &c)) != 0) return rc;
   DeviceGuard dg(c->device);
   const bool plane = variant == ICP_POINT_TO_PLANE;
-  const PairIn in{src_xyz, n_src, tgt_xyz, plane ? tgt_normals : nullptr, n_tgt, max_corr_dist, true};
+  const PairIn in{src_xyz, n_src, tgt_xyz, plane ? tgt_normals : nullptr, n_tgt, max_corr_dist, true, true};
   Prep P;
   if ((rc = prepare_pairs(c, 1, &in, &P)) != 0) return rc;
   LoopIn li{T_init, max_corr_dist, max_iter, rel_tol};
@@ -918,7 +945,7 @@ int icp_register_batch_robust(icp_ctx_t* ctx, const icp_pair_t* pairs, int32_t n
   for (int p = 0; p < n_pairs; ++p) {
     const icp_pair_t& q = pairs[p];
     in[p] = PairIn{q.src_xyz, q.n_src, q.tgt_xyz, plane ? q.tgt_normals : nullptr, q.n_tgt,
-                   q.max_corr_dist, true};
+                   q.max_corr_dist, true, true};
     li[p] = LoopIn{q.T_init, q.max_corr_dist, q.max_iter, q.rel_tol, loss, loss_k};
   }
   Prep P;
@@ -1053,7 +1080,7 @@ int icp_register_multiscale_robust(icp_ctx_t* ctx, const float* src_xyz, int64_t
       ns = cnt[0];
       nt = cnt[1];
     }
-    const PairIn in{s, ns, t, tn, nt, max_corr_dist[l], true};
+    const PairIn in{s, ns, t, tn, nt, max_corr_dist[l], true, true};
     Prep P;
     if ((rc = prepare_pairs(c, 1, &in, &P)) != 0) return rc;
     const LoopIn li{T, max_corr_dist[l], max_iter[l], rel_tol, loss, loss_k};
@@ -1077,7 +1104,7 @@ int icp_correspondences(icp_ctx_t* ctx, const float* src_xyz, int64_t n_src, con
   icp_ctx* c = nullptr;
   if ((rc = resolve_ctx(ctx, &c)) != 0) return rc;
   DeviceGuard dg(c->device);
-  const PairIn in{src_xyz, n_src, tgt_xyz, nullptr, n_tgt, max_corr_dist, true};
+  const PairIn in{src_xyz, n_src, tgt_xyz, nullptr, n_tgt, max_corr_dist, true, true};
   Prep P;
   if ((rc = prepare_pairs(c, 1, &in, &P)) != 0) return rc;
   return single_pass(c, P, max_corr_dist, T, false, ICP_POINT_TO_POINT, ICP_PREC_F32_KAHAN_F64,
@@ -1107,7 +1134,7 @@ int icp_normal_equations_robust(icp_ctx_t* ctx, const float* src_xyz, int64_t n_
   if ((rc = resolve_ctx(ctx, &c)) != 0) return rc;
   DeviceGuard dg(c->device);
   const bool plane = variant == ICP_POINT_TO_PLANE;
-  const PairIn in{src_xyz, n_src, tgt_xyz, plane ? tgt_normals : nullptr, n_tgt, max_corr_dist, true};
+  const PairIn in{src_xyz, n_src, tgt_xyz, plane ? tgt_normals : nullptr, n_tgt, max_corr_dist, true, true};
   Prep P;
   if ((rc = prepare_pairs(c, 1, &in, &P)) != 0) return rc;
   IterState st;

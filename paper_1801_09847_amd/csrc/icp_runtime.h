@@ -91,6 +91,11 @@ struct Buf {
 
 constexpr size_t kHostBytes = 4096;
 constexpr int kDefaultSub = 1;
+// A call whose kernels allow it takes two cells per radius when each target
+// holds at least this many points per cell of the one-cell-per-radius grid
+// (over the whole box): the smaller cells then cut the candidates each query
+// scans by more than the extra rows cost.
+constexpr double kFineSubPoints = 2.0;
 
 }  // namespace icp_rt
 
@@ -151,7 +156,8 @@ void for_each_buf(icp_ctx* c, F f) {
 }
 // The given context, or this thread's default context of the current device.
 int resolve_ctx(icp_ctx* in, icp_ctx** out);
-// Cells per max_corr_dist along an axis for every grid this process builds.
+// Cells per max_corr_dist along an axis for grids without a density choice
+// (the environment override, else the default).
 int grid_sub();
 void ctx_free(icp_ctx* c);
 int ensure_host(icp_ctx* c, size_t bytes);
@@ -176,6 +182,7 @@ struct PairIn {
   int64_t n_tgt;
   double r;
   bool hashed_ok = false;  // the call's kernels accept a hashed grid (the pass does)
+  bool fine_ok = false;    // the call may take two cells per radius for a dense target
 };
 
 // Byte offsets of one call's descriptors; the same layout is used in pinned

@@ -95,7 +95,7 @@ class icp_profile_t(C.Structure):
     _fields_ = [("pass_ms", C.c_double), ("pass_launches", C.c_int64), ("pass_points", C.c_int64),
                 ("call_ms", C.c_double), ("calls", C.c_int64), ("validate_ms", C.c_double),
                 ("validate_launches", C.c_int64), ("validate_evals", C.c_int64), ("build_ms", C.c_double),
-                ("builds", C.c_int64), ("build_points", C.c_int64), ("hashed_grids", C.c_int64)]
+                ("builds", C.c_int64), ("build_points", C.c_int64), ("hashed_grids", C.c_int64), ("fine_grids", C.c_int64)]
 
 
 class icp_ransac_params_t(C.Structure):

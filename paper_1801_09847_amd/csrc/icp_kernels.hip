@@ -1001,7 +1001,19 @@ __device__ double row_share(Ptr p, int n, int g) {
 // `red` when given, else computed here) and updates its loop state.
 __device__ void solve_body(const SolveArgs& a, const double* red) {
   ICP_G IterState* st = glb(a.st);
-  if (st->done) return;
+  // the converged flag and thread 0's loop state are loaded together with the
+  // partials (one memory round trip); the partials read after convergence
+  // are discarded
+  const int done = st->done;
+  int k = 0;
+  int64_t n_prev = 0;
+  double e_prev = 0.0, T[12];
+  if (threadIdx.x == 0) {
+    k = st->k;
+    n_prev = st->n_prev;
+    e_prev = st->e_prev;
+    for (int m = 0; m < 12; ++m) T[m] = st->T[m];
+  }
   __shared__ double sums[kNumSums];
   __shared__ double sred[kNumSums * kSegs];
   // term v = t / 32 is summed by 32 threads (half a wave), each over its
@@ -1010,9 +1022,12 @@ __device__ void solve_body(const SolveArgs& a, const double* red) {
   double acc = 0.0;
   if (a.n_blocks <= kTwoLevel) {
     if (v < kNumSums) acc = row_share(glb(a.part) + (int64_t)v * a.n_blocks, a.n_blocks, g);
+    if (done) return;
   } else if (red) {
     if (v < kNumSums) acc = row_share(glb(red) + v * kSegs, segs_of(a.n_blocks), g);
+    if (done) return;
   } else {
+    if (done) return;
     const int segs = segs_of(a.n_blocks);
     for (int idx = t >> 3; idx < kNumSums * segs; idx += (int)(blockDim.x >> 3)) {
       const int vv = idx / segs, sg = idx % segs;
@@ -1038,22 +1053,19 @@ __device__ void solve_body(const SolveArgs& a, const double* red) {
     st->rmse = ek;
     return;
   }
-  const int k = st->k;
   int status = -1;
   if (nk == 0) {
     status = 2;
   } else if (k == a.max_iter) {
     status = 0;
-  } else if (k >= 1 && fabs((double)(nk - st->n_prev)) <= a.rel_tol * (double)st->n_prev &&
-             fabs(ek - st->e_prev) <= a.rel_tol * st->e_prev) {
+  } else if (k >= 1 && fabs((double)(nk - n_prev)) <= a.rel_tol * (double)n_prev &&
+             fabs(ek - e_prev) <= a.rel_tol * e_prev) {
     status = 1;
   } else {
     double xi[6];
     if (!cholesky_solve6(sums, sums + 21, xi)) {
       status = 2;
     } else {
-      double T[12];
-      for (int m = 0; m < 12; ++m) T[m] = st->T[m];
       apply_exp(xi, T);
       for (int m = 0; m < 12; ++m) st->T[m] = T[m];
     }
@@ -1076,11 +1088,11 @@ __global__ __launch_bounds__(1024) void solve_kernel(SolveArgs a, const double* 
 // Segment sums of a single pair's block partials (two-level form): block s
 // computes segment s of every term.
 __global__ __launch_bounds__(256) void reduce_partials_kernel(SolveArgs a, double* red) {
-  if (glb(a.st)->done) return;
+  const int done = glb(a.st)->done;  // loaded with the partials; checked before the store
   const int t = threadIdx.x, v = t >> 3;
   if (v < kNumSums) {
     const double x = segment_sum(glb(a.part) + (int64_t)v * a.n_blocks, a.n_blocks, blockIdx.x, t & 7);
-    if ((t & 7) == 0) glb(red)[v * kSegs + blockIdx.x] = x;
+    if ((t & 7) == 0 && !done) glb(red)[v * kSegs + blockIdx.x] = x;
   }
 }
 

@@ -172,6 +172,7 @@ def config_section(args, icp, synth, np, torch, c3=None):
              "pass_avg_us": pass_us, "pass_alg_gbs": alg / (pass_us * 1e-6) / 1e9,
              "pass_frac_of_8tbs": alg / (pass_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
              "build_ms": prof["build_ms"], "build_alg_gbs": build_gbs,
+             "grid": {"cells_per_radius": 2 if prof["fine_grids"] else 1, "hashed": prof["hashed_grids"] > 0},
              "fitness": res.fitness, "inlier_rmse": res.inlier_rmse}
         if not args.no_cpu_baseline:
             ta, o = oracle_timing(np, d, variant, ncores, oreps)
@@ -849,7 +850,8 @@ def main():
                       (prof["call_ms"] / max(1, prof["calls"]) * 1e-3) if prof["call_ms"] > 0 else None},
         "grid_build": {"ms": prof["build_ms"], "target_points": prof["build_points"],
                        "alg_gbs": 52.0 * prof["build_points"] / (prof["build_ms"] * 1e-3) / 1e9
-                       if prof["build_ms"] > 0 else None},
+                       if prof["build_ms"] > 0 else None,
+                       "cells_per_radius": 2 if prof["fine_grids"] else 1, "hashed": prof["hashed_grids"] > 0},
     }
     if ceilings:
         out["ceilings"] = ceilings
